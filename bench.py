@@ -1,0 +1,184 @@
+"""Benchmark: Gauss-Newton Hessian matvecs per second on one MI355X.
+
+Workload (the headline configuration): one image pair on a 256 x 256 periodic grid, n_t = 16 RK2
+steps, H2 seminorm with the mass-source constraint (beta_v = 1e-3, beta_w = 1e-4), FP32 transport and
+FFTs, FP64 spectral assembly and Krylov vectors.  Synthetic inputs (seeded blob-plus-texture template,
+band-limited velocity scaled to CFL 0.8); the reference image is the template transported by that
+velocity, computed on the GPU.
+
+A step is one PCG iteration of Alg. 2 at a fixed linearisation point: one GN Hessian matvec
+(incremental state solve forward, GN incremental adjoint solve backward, body-force quadrature,
+regularisation + projection assembly), one preconditioner application and the FP64 PCG inner
+products and vector updates.  ``value`` = steps per second = matvecs per second.
+
+Also reported: the dominant kernel's achieved HBM bandwidth against the 8 TB/s peak (hipEvents around
+back-to-back launches of that kernel on the library's stream), the time to ||g||/||g(0)|| <= 1e-2 of
+the plain solver on the same workload, matvec throughput and roofline fraction at 1024^2 / n_t = 32,
+and the FP64 CPU oracle timed on the host cores on a bounded sample (rank 0 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def setup(config: int, precision: str = "fp32"):
+    import numpy as np
+    import torch
+    import synthdata as sd
+    from paper_1503_00757_amd import Problem
+
+    w = sd.make_workload(config)
+    dev = torch.device("cuda:0")
+    mT = torch.tensor(w.mT, device=dev)
+    # reference image: the template transported by v* (state solve on the GPU)
+    P0 = Problem(mT, mT.clone(), w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, precision)
+    mR = P0.state_forward(torch.tensor(w.vstar, device=dev))
+    P0.close()
+    P = Problem(mT, mR, w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, precision)
+    vlin = torch.tensor(0.5 * w.vstar, device=dev)
+    vt = torch.tensor(w.vtilde, device=dev)
+    return w, P, vlin, vt
+
+
+def bench_pcg(P, vlin, steps, warmup):
+    import torch
+    g, _ = P.gradient(vlin, want_J=False)
+    rhs = -g
+    if warmup > 0:
+        P.pcg(rhs, eta=0.0, max_iters=warmup, fixed_iters=warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it, _ = P.pcg(rhs, eta=0.0, max_iters=steps, fixed_iters=steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert it == steps
+    return dt
+
+
+def bench_matvec(P, vt, reps):
+    import torch
+    out = P.vec()
+    P.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def roofline(P, reps=200):
+    """Dominant kernel: the incremental-adjoint stage-2 row pass (reads 9 and writes 3 fields)."""
+    ms, by = P.time_pass(0, reps)
+    achieved = by / (ms * 1e-3) / 1e9
+    return {"kernel": "row_pass_kernel<float,N,1,OP_A2> (incremental adjoint stage 2, row pass)",
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": by, "us_per_launch": round(ms * 1e3, 3)}
+
+
+def bench_solve(P):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v, st = P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"seconds": round(dt, 4), "newton_iters": st["newton_iters"], "pcg_iters": st["pcg_iters"],
+            "n_matvec": st["n_matvec"], "n_pde": st["n_pde"], "g_rel": st["g_rel"], "status": st["status"]}
+
+
+def cpu_baseline(budget_s=12.0):
+    """The FP64 oracle's GN matvec on the host cores (bounded sample of the same workload)."""
+    import numpy as np
+    import synthdata as sd
+    from oracle import Grid, Params, reduced, transport, spectral
+    w = sd.make_workload(2)
+    p = Params(w.n1, w.n2, w.nt, w.norm, w.constraint, w.beta_v, w.beta_w)
+    g = Grid(w.n1, w.n2)
+    spectral.set_workers(-1)
+    mR = transport.state_forward(g, p, w.mT, w.vstar).m[-1]
+    lin = reduced.gradient(g, p, w.mT, mR, 0.5 * w.vstar)
+    reduced.hessian_matvec(g, p, lin, w.vtilde)   # warm-up
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        reduced.hessian_matvec(g, p, lin, w.vtilde)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt > budget_s or n >= 200:
+            break
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": round(n / dt, 3), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} FP64 oracle GN matvecs (numpy/scipy.fft, all cores) on the 256^2, n_t=16 workload "
+                      f"at its linearisation point, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the solve and 1024^2 measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the single-pair path "
+              "does not shard across GPUs; see the design notes for how it would)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    print(f"[bench] 256^2 nt=16 setup", file=sys.stderr, flush=True)
+    w, P, vlin, vt = setup(2)
+    dt = bench_pcg(P, vlin, args.steps, args.warmup)
+    print(f"[bench] pcg {args.steps} steps {dt:.3f}s", file=sys.stderr, flush=True)
+    rl = roofline(P)
+    extras = {}
+    if not args.no_extras:
+        extras["matvec_only_per_s"] = round(1.0 / bench_matvec(P, vt, 50), 2)
+        print("[bench] solve", file=sys.stderr, flush=True)
+        extras["solve_to_grel_1e-2_plain"] = bench_solve(P)
+    P.close()
+    if not args.no_extras:
+        print("[bench] 1024^2 nt=32", file=sys.stderr, flush=True)
+        w3, P3, vlin3, vt3 = setup(3)
+        P3.gradient(vlin3, want_J=False)
+        t3 = bench_matvec(P3, vt3, 10)
+        nn = w3.n1 * w3.n2
+        bmodel = (248 * w3.nt + 112) * nn
+        rl3 = roofline(P3, 100)
+        P3.close()
+        extras["c3_1024sq_nt32"] = {"matvecs_per_s": round(1.0 / t3, 2), "ms_per_matvec": round(t3 * 1e3, 3),
+                                    "model_bytes_per_matvec": bmodel,
+                                    "model_frac_of_8TBs": round(bmodel / t3 / 8e12, 4),
+                                    "dominant_kernel": rl3}
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+    out = {
+        "metric": "GN Hessian matvecs/s at 256^2", "value": round(args.steps / dt, 2), "unit": "matvecs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2: one pair, 256x256 periodic grid, n_t=16, H2 + mass source, beta_v=1e-3, "
+                               "beta_w=1e-4; FP32 transport/FFT, FP64 assembly and PCG; step = one PCG "
+                               "iteration (1 GN matvec + preconditioner + FP64 PCG updates)",
+                   "n1": 256, "n2": 256, "nt": 16},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * regnk.h -- C ABI of the MI355X (gfx950) reduced-space Gauss-Newton-Krylov library for 2D
+ * diffeomorphic image registration (Mang & Biros, "Constrained H1-regularization schemes for
+ * diffeomorphic image registration", SIAM J. Imaging Sci. 9(3), 2016).
+ *
+ * Problem (Sec. 2, eq. (opt-prob-v)): find a stationary velocity v on the periodic domain
+ * [0, 2 pi)^2 that minimises
+ *     J[v] = 1/2 ||m_R - m_1||^2 + 1/2 beta_v |v|^2_V + gamma 1/2 beta_w ||div v||^2_{H1}
+ * subject to the transport equation d_t m + grad m . v = 0, m(0) = m_T (eq. (transport-eq)) and,
+ * for gamma = 1, the divergence constraint (eq. (constraint-divv)), which is eliminated through the
+ * projection K of Sec. 3.3, eq. (project-body-force).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: reg_status (REG_OK = 0).  No C++ exception crosses the ABI; on error
+ *    reg_last_error() returns a thread-local message.
+ *  - Array arguments are DEVICE pointers (HIP global memory) owned by the caller.  They must stay
+ *    valid until the call's work on the problem's stream has finished.  Calls that return host
+ *    scalars synchronise that stream before returning; the others only enqueue work.
+ *  - Layout: a scalar field is double[n1][n2], row-major (i2 fastest), sample (i1, i2) at
+ *    x = (2 pi i1 / n1, 2 pi i2 / n2).  A vector field is double[2][n1][n2] (component-major).
+ *  - Every velocity-like input (v, v~, r) has its Nyquist row and column (k1 = n1/2, k2 = n2/2)
+ *    removed before use, and every velocity-like output has none (spectral derivatives use the
+ *    Nyquist wavenumber 0 so that they are exactly skew-symmetric).
+ *  - Sizes: n1, n2 powers of two in [8, 2048]; nt >= 1; beta_v > 0; beta_w > 0 exactly when
+ *    constraint == REG_MASS_SOURCE.  Anything else is REG_EINVAL.
+ */
+#ifndef REGNK_H
+#define REGNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    REG_OK = 0,
+    REG_EINVAL = -1,      /* bad argument, size or parameter combination */
+    REG_ENOMEM = -2,      /* workspace too small */
+    REG_EDEVICE = -3,     /* a HIP runtime call failed */
+    REG_ENOTCONV = -4,    /* line search failed / iteration limit with a failure condition */
+    REG_ENONFINITE = -5,  /* a reduction produced NaN or Inf */
+    REG_ESTATE = -6       /* Hessian matvec requested before any linearisation point was set */
+} reg_status;
+
+/* Seminorm on v (Sec. 2, eq. (reg-v)); A = -Lap (H1) or Lap^2 (H2), eq. (var-reg-v). */
+enum { REG_H1 = 1, REG_H2 = 2 };
+/* Constraint on div v (Sec. 2): gamma = 0; gamma = 1 with w = 0 (incompressible); gamma = 1 with a
+ * mass source w penalised by its H1 norm (eq. (reg-w)), beta_w > 0. */
+enum { REG_UNCONSTRAINED = 0, REG_DIVFREE = 1, REG_MASS_SOURCE = 2 };
+/* Arithmetic of the transport solves and FFTs: FP64 throughout, or FP32 transport with FP64
+ * spectral assembly, reductions and Krylov vectors. */
+enum { REG_FP64 = 0, REG_FP32_TRANSPORT = 1 };
+/* Time quadrature of the body forces (Sec. 4): REG_ADJ_DISCRETE uses the quadrature that is the
+ * exact transpose of the discrete RK2 forward map (exact gradient, symmetric Hessian);
+ * REG_ADJ_PAPER uses the trapezoidal rule as printed. */
+enum { REG_ADJ_DISCRETE = 0, REG_ADJ_PAPER = 1 };
+
+typedef struct {
+    int32_t n1, n2;       /* grid (powers of two, 8..2048) */
+    int32_t nt;           /* RK2 time steps on [0, 1] */
+    int32_t norm;         /* REG_H1 | REG_H2 */
+    int32_t constraint;   /* REG_UNCONSTRAINED | REG_DIVFREE | REG_MASS_SOURCE */
+    int32_t precision;    /* REG_FP64 | REG_FP32_TRANSPORT */
+    int32_t adjoint;      /* REG_ADJ_DISCRETE | REG_ADJ_PAPER */
+    int32_t reserved;     /* must be 0 */
+    double beta_v;        /* weight of the v seminorm (> 0) */
+    double beta_w;        /* weight of the mass-source norm (> 0 iff REG_MASS_SOURCE) */
+} reg_params;
+
+typedef struct reg_problem reg_problem;   /* opaque handle */
+
+/* Bytes of device workspace a problem with these parameters needs (host-only, no device work). */
+reg_status reg_workspace_bytes(const reg_params* params, size_t* bytes);
+
+/* Create a problem.  m_T (template) and m_R (reference) are device scalar fields; they are copied
+ * into `workspace` (device memory of at least reg_workspace_bytes bytes, 256-byte aligned, owned
+ * by the caller and kept alive until reg_destroy).  The template is used as given (callers
+ * normalise intensities to [0, 1] as in Sec. 4).  All work is enqueued on `hip_stream`
+ * (hipStream_t; NULL = default stream).  The library allocates no device memory of its own. */
+reg_status reg_create(const reg_params* params, const double* m_T, const double* m_R,
+                      void* workspace, size_t workspace_bytes, void* hip_stream,
+                      reg_problem** out);
+
+/* Release the handle (the workspace stays the caller's). */
+reg_status reg_destroy(reg_problem* h);
+
+/* Change the stream subsequent calls enqueue on. */
+reg_status reg_set_stream(reg_problem* h, void* hip_stream);
+
+/* Deformed template m_1 = m(t = 1): one state solve forward in time (Sec. 3.3, eq. (state-eq-elim),
+ * RK2 as in Sec. 4).  v: device vector field; m1: device scalar field (output). */
+reg_status reg_state_forward(reg_problem* h, const double* v, double* m1);
+
+/* Objective J(v) of Sec. 2, eq. (objective): one state solve.  J_host: host double (output);
+ * terms3_host (nullable): host double[3] = {data, reg_v, reg_w}.  Synchronises the stream. */
+reg_status reg_objective(reg_problem* h, const double* v, double* J_host, double* terms3_host);
+
+/* Reduced gradient g = beta_v A v + K[b], b = int_0^1 lam grad m dt (Sec. 3.3, eq. (control-eq-elim)):
+ * state solve forward, adjoint solve backward (eq. (adj-eq-elim)) and the body-force quadrature.
+ * Also makes v the linearisation point of later Hessian matvecs (the state trajectory and its
+ * gradients stay in the workspace).  g: device vector field (output); J_host (nullable) receives
+ * J(v) (then the stream is synchronised). */
+reg_status reg_gradient(reg_problem* h, const double* v, double* g, double* J_host);
+
+/* Gauss-Newton reduced Hessian matvec at the current linearisation point (Sec. 3.3,
+ * eq. (inc-control-eq-elim) with B = A and L = K; Gauss-Newton as in Sec. 4: the lam terms are
+ * dropped):  H v~ = beta_v A v~ + K[b~], where b~ = int_0^1 lam~ grad m dt comes from one incremental
+ * state solve forward (eq. (inc-state-eq-elim)) and one incremental adjoint solve backward
+ * (eq. (inc-adj-eq-elim)).  vtilde, Hvtilde: device vector fields (may not alias).
+ * REG_ESTATE if no linearisation point has been set by reg_gradient / reg_solve. */
+reg_status reg_hessian_matvec(reg_problem* h, const double* vtilde, double* Hvtilde);
+
+/* Preconditioner of App. E.2: z = (beta_v A)^{-1} r, with the kernel of A (the mean, k = 0)
+ * scaled by 1/beta_v.  r, z: device vector fields (may alias). */
+reg_status reg_precond_apply(reg_problem* h, const double* r, double* z);
+
+/* Newton step of Alg. 2: PCG on H x = rhs at the current linearisation point, x_0 = 0, stopping at
+ * ||r|| <= eta ||rhs|| or after max_iters iterations; fixed_iters > 0 runs exactly that many.
+ * For REG_MASS_SOURCE the PCG inner product is <K^{-1} a, b>, in which H is self-adjoint.
+ * x: device vector field (output).  iters_host, relres_host: host outputs (nullable).
+ * Synchronises the stream. */
+reg_status reg_pcg(reg_problem* h, const double* rhs, double eta, int32_t max_iters,
+                   int32_t fixed_iters, double* x, int32_t* iters_host, double* relres_host);
+
+typedef struct {
+    int32_t max_newton;       /* outer iterations (Alg. 1) */
+    int32_t max_pcg;          /* inner iterations per Newton step (Alg. 2) */
+    int32_t fixed_pcg_iters;  /* > 0: exactly this many PCG iterations, no forcing-term test */
+    int32_t max_backtracks;   /* Armijo halvings before REG_ENOTCONV */
+    double gtol_rel;          /* stop when ||g(v_k)|| / ||g(0)|| <= gtol_rel */
+    double armijo_c1;         /* sufficient-decrease constant (1e-4) */
+    double armijo_rho;        /* backtracking factor (0.5) */
+    const double* v0;         /* nullable device vector field: warm start */
+} reg_solve_opts;
+
+typedef struct {
+    int32_t newton_iters, pcg_iters, n_matvec, n_pde, backtracks, status;
+    double g0_norm;           /* ||g(0)|| at v = 0 (also for a warm start) */
+    double g_rel;             /* final ||g|| / ||g(0)|| */
+    double J;                 /* final objective */
+} reg_solve_stats;
+
+/* Alg. 1: globalised inexact reduced-space Gauss-Newton-Krylov solve from v0 (or 0): PCG Newton
+ * steps (Alg. 2, forcing term eta_k = min(1/2, sqrt(||g_k|| / ||g(0)||))) and Armijo backtracking
+ * (Sec. 4).  v_out: device vector field (output); stats_host: host (nullable).  Leaves the final
+ * v as the linearisation point.  Synchronises the stream. */
+reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
+                     reg_solve_stats* stats_host);
+
+/* Measurement hook: launch one of the library's passes `reps` times back to back on the problem's
+ * stream at the current linearisation point and report the mean device time per launch (hipEvents
+ * around the launches) and the compulsory HBM bytes that pass moves per launch.
+ * which: 0 incremental-adjoint stage-2 row pass (the busiest pass), 1 incremental-state stage-2 row
+ * pass, 2 incremental-adjoint stage-2 column pass, 3 incremental-state stage-2 column pass.
+ * Synchronises the stream. */
+reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms_per_launch_host,
+                         double* bytes_per_launch_host);
+
+/* Thread-local description of the last error (never NULL). */
+const char* reg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REGNK_H */

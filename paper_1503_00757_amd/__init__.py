@@ -1,0 +1,16 @@
+"""MI355X (gfx950) reduced-space Gauss-Newton-Krylov registration library (Python binding).
+
+The compute path is the C-ABI library ``libregnk.so`` (hand-written HIP kernels); this package only
+marshals arguments to it.  ``ffi`` holds the raw C functions with the names of ``include/regnk.h``;
+``Problem`` is a convenience wrapper that keeps the workspace and device vectors in torch tensors.
+There is no CPU fallback: if the library is not built, importing ``ffi.lib()`` raises.
+"""
+from .ffi import (  # noqa: F401
+    RegParams, RegSolveOpts, RegSolveStats, RegError, lib, library_path,
+    REG_H1, REG_H2, REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE, REG_FP64, REG_FP32_TRANSPORT,
+    REG_ADJ_DISCRETE, REG_ADJ_PAPER,
+    reg_workspace_bytes, reg_create, reg_destroy, reg_set_stream, reg_state_forward, reg_objective,
+    reg_gradient, reg_hessian_matvec, reg_precond_apply, reg_pcg, reg_solve, reg_time_pass,
+    reg_last_error,
+)
+from .problem import Problem  # noqa: F401

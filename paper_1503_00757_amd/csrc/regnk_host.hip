@@ -1,0 +1,852 @@
+// Host side of the registration library: C ABI, workspace layout, and the drivers that sequence
+// the device passes into the state / adjoint / incremental solves, the Hessian matvec, the gradient,
+// the objective, PCG (Alg. 2) and the Newton loop (Alg. 1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "regnk.h"
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+using namespace regnk;
+
+// ---------------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------------
+static thread_local std::string g_err = "no error";
+
+static reg_status fail(reg_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define CK(call)                                                                               \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(REG_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+#define CKS(call)                                                                              \
+    do {                                                                                       \
+        reg_status s_ = (call);                                                                \
+        if (s_ != REG_OK) return s_;                                                           \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int NFIELD = 7;    // scalar scratch fields in transport precision
+constexpr int NPCG = 7;      // x, r, z, kr, s, st, kst
+constexpr int NSCAL = 16;
+
+struct Layout {
+    size_t total = 0;
+    size_t take(size_t bytes) {
+        size_t off = total;
+        total += (bytes + 255) & ~size_t(255);
+        return off;
+    }
+};
+
+struct Offsets {
+    size_t mT, mR, vT, vw, vtT, traj, fld[NFIELD], B, Bt;
+    size_t tw1f, tw2f, tw1d, tw2d;
+    size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal;
+    size_t total;
+};
+
+bool is_pow2_in_range(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
+
+reg_status check_params(const reg_params* p) {
+    if (!p) return fail(REG_EINVAL, "params is NULL");
+    if (!is_pow2_in_range(p->n1) || !is_pow2_in_range(p->n2))
+        return fail(REG_EINVAL, "n1=%d n2=%d: grid sizes must be powers of two in [8, 2048]", p->n1, p->n2);
+    if (p->nt < 1 || p->nt > 4096) return fail(REG_EINVAL, "nt=%d out of range [1, 4096]", p->nt);
+    if (p->norm != REG_H1 && p->norm != REG_H2) return fail(REG_EINVAL, "norm=%d", p->norm);
+    if (p->constraint < REG_UNCONSTRAINED || p->constraint > REG_MASS_SOURCE)
+        return fail(REG_EINVAL, "constraint=%d", p->constraint);
+    if (p->precision != REG_FP64 && p->precision != REG_FP32_TRANSPORT)
+        return fail(REG_EINVAL, "precision=%d", p->precision);
+    if (p->adjoint != REG_ADJ_DISCRETE && p->adjoint != REG_ADJ_PAPER)
+        return fail(REG_EINVAL, "adjoint=%d", p->adjoint);
+    if (p->reserved != 0) return fail(REG_EINVAL, "reserved must be 0");
+    if (!(p->beta_v > 0.0) || !std::isfinite(p->beta_v)) return fail(REG_EINVAL, "beta_v must be > 0");
+    const bool ms = p->constraint == REG_MASS_SOURCE;
+    if (ms && !(p->beta_w > 0.0 && std::isfinite(p->beta_w)))
+        return fail(REG_EINVAL, "beta_w must be > 0 for the mass-source model");
+    if (!ms && p->beta_w != 0.0) return fail(REG_EINVAL, "beta_w must be 0 unless constraint is REG_MASS_SOURCE");
+    return REG_OK;
+}
+
+Offsets layout(const reg_params* p) {
+    Offsets o{};
+    Layout L;
+    const size_t nn = (size_t)p->n1 * p->n2;
+    const size_t ts = p->precision == REG_FP64 ? 8 : 4;
+    o.mT = L.take(nn * ts);
+    o.mR = L.take(nn * ts);
+    o.vT = L.take(2 * nn * ts);
+    o.vw = L.take(2 * nn * ts);
+    o.vtT = L.take(2 * nn * ts);
+    o.traj = L.take((size_t)(2 * p->nt + 1) * 2 * nn * ts);
+    for (int i = 0; i < NFIELD; ++i) o.fld[i] = L.take(nn * ts);
+    o.B = L.take(2 * nn * ts);
+    o.Bt = L.take(2 * nn * ts);
+    o.tw1f = L.take(p->n1 * 8);
+    o.tw2f = L.take(p->n2 * 8);
+    o.tw1d = L.take(p->n1 * 16);
+    o.tw2d = L.take(p->n2 * 16);
+    o.v64 = L.take(2 * nn * 8);
+    o.vtrial = L.take(2 * nn * 8);
+    o.g64 = L.take(2 * nn * 8);
+    o.kg64 = L.take(2 * nn * 8);
+    o.vt64 = L.take(2 * nn * 8);
+    o.tmp0 = L.take(2 * nn * 8);
+    o.tmp1 = L.take(2 * nn * 8);
+    o.vcur = L.take(2 * nn * 8);
+    o.vtry = L.take(2 * nn * 8);
+    o.rhs = L.take(2 * nn * 8);
+    for (int i = 0; i < NPCG; ++i) o.pcg[i] = L.take(2 * nn * 8);
+    o.spec = L.take(4 * (size_t)p->n1 * (p->n2 / 2) * 16);
+    o.partial = L.take(4 * RED_BLOCKS * 8);
+    o.scal = L.take(NSCAL * 8);
+    o.total = L.total;
+    return o;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Problem handle
+// ---------------------------------------------------------------------------------------------
+struct reg_problem {
+    reg_params p;
+    hipStream_t stream;
+    int n1, n2, nt;
+    long nn;
+    bool f64;
+    char* ws;
+    Offsets o;
+    bool linearized = false;
+    bool matvec_done = false;
+    SpecParams sp;
+    double h1h2;
+
+    template <typename X>
+    X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
+    double* pcg(int i) const { return at<double>(o.pcg[i]); }
+    double* scal() const { return at<double>(o.scal); }
+    double* partial() const { return at<double>(o.partial); }
+    cpx<double>* spec() const { return at<cpx<double>>(o.spec); }
+};
+
+namespace {
+
+// ---- typed views ------------------------------------------------------------------------------
+template <typename T>
+struct TV {
+    const reg_problem* P;
+    T* mT() const { return P->at<T>(P->o.mT); }
+    T* mR() const { return P->at<T>(P->o.mR); }
+    T* vT() const { return P->at<T>(P->o.vT); }
+    T* vw() const { return P->at<T>(P->o.vw); }
+    T* vtT() const { return P->at<T>(P->o.vtT); }
+    T* G(int slot) const { return P->at<T>(P->o.traj) + (size_t)slot * 2 * P->nn; }
+    T* F(int i) const { return P->at<T>(P->o.fld[i]); }
+    T* B() const { return P->at<T>(P->o.B); }
+    T* Bt() const { return P->at<T>(P->o.Bt); }
+    const cpx<T>* tw1() const;
+    const cpx<T>* tw2() const;
+};
+template <>
+const cpx<float>* TV<float>::tw1() const { return P->at<cpx<float>>(P->o.tw1f); }
+template <>
+const cpx<float>* TV<float>::tw2() const { return P->at<cpx<float>>(P->o.tw2f); }
+template <>
+const cpx<double>* TV<double>::tw1() const { return P->at<cpx<double>>(P->o.tw1d); }
+template <>
+const cpx<double>* TV<double>::tw2() const { return P->at<cpx<double>>(P->o.tw2d); }
+
+// Gradient-trajectory slots: G_j at slot j (j = 0..nt), G*_j at slot nt + 1 + j (j < nt).
+inline int slot_G(const reg_problem* P, int j) { (void)P; return j; }
+inline int slot_Gs(const reg_problem* P, int j) { return P->nt + 1 + j; }
+
+template <typename T>
+PassArgs<T> base_args(const reg_problem* P, int axis) {
+    TV<T> tv{P};
+    PassArgs<T> a{};
+    a.n1 = P->n1;
+    a.n2 = P->n2;
+    a.nn = P->nn;
+    a.h = T(1.0 / P->nt);
+    a.tw = axis == 2 ? tv.tw2() : tv.tw1();
+    return a;
+}
+
+template <typename T>
+reg_status pass(const reg_problem* P, int op, int axis, const PassArgs<T>& a) {
+    CK(launch_pass<T>(op, axis, a, P->stream));
+    return REG_OK;
+}
+
+// ---- state solve forward (eq. (state-eq-elim)) ----------------------------------------------------
+// v: transport-precision velocity (2 nn).  store: write G_j, G*_j (and G_nt in paper mode) to the
+// trajectory.  m1: output field.  lam1 (nullable): lam(1) = m_R - m_1.
+template <typename T>
+reg_status state_forward(reg_problem* P, const T* v, bool store, T* m1, T* lam1) {
+    TV<T> tv{P};
+    const long nn = P->nn;
+    const T* cur = tv.mT();
+    T* Fa = tv.F(0);
+    T* Fb = tv.F(3);
+    T* Fp = tv.F(1);
+    T* Fs = tv.F(2);
+    for (int j = 0; j < P->nt; ++j) {
+        const bool last = j == P->nt - 1;
+        T* nxt = last ? m1 : (cur == Fa ? Fb : Fa);
+        T* G = store ? tv.G(slot_G(P, j)) : nullptr;
+        T* Gs = store ? tv.G(slot_Gs(P, j)) : nullptr;
+        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
+        r.U = cur; r.V = v + nn; r.OUT = Fp; r.GOUT = G;
+        CKS(pass<T>(P, OP_S1, 2, r));
+        c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs; c.GOUT = G;
+        CKS(pass<T>(P, OP_S1, 1, c));
+        r = base_args<T>(P, 2); c = base_args<T>(P, 1);
+        r.U = Fs; r.X = cur; r.V = v + nn; r.OUT = Fp; r.GOUT = Gs;
+        CKS(pass<T>(P, OP_S2, 2, r));
+        c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt; c.GOUT = Gs;
+        if (last) { c.OUT2 = lam1; c.MR = tv.mR(); }
+        CKS(pass<T>(P, OP_S2, 1, c));
+        cur = nxt;
+    }
+    if (store && P->p.adjoint == REG_ADJ_PAPER) {   // G_{n_t} for the trapezoid end point
+        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
+        r.U = m1; r.GOUT = tv.G(slot_G(P, P->nt));
+        CKS(pass<T>(P, OP_GRAD, 2, r));
+        c.U = m1; c.GOUT = tv.G(slot_G(P, P->nt));
+        CKS(pass<T>(P, OP_GRAD, 1, c));
+    }
+    return REG_OK;
+}
+
+// ---- adjoint solve backward (eq. (adj-eq-elim)); also the GN incremental adjoint ------------------
+// lamT: terminal value (field, read only).  B: body force (vector, overwritten) in the selected
+// quadrature, using the stored trajectory.
+template <typename T>
+reg_status adjoint_backward(reg_problem* P, const T* v, const T* lamT, T* B) {
+    TV<T> tv{P};
+    const long nn = P->nn;
+    const T h = T(1.0 / P->nt);
+    const bool paper = P->p.adjoint == REG_ADJ_PAPER;
+    const T* cur = lamT;
+    T* La = tv.F(0);
+    T* Lb = tv.F(3);
+    T* Fp = tv.F(1);
+    T* Fs = tv.F(2);
+    for (int j = P->nt - 1; j >= 0; --j) {
+        const bool first = j == P->nt - 1;
+        T* nxt = (cur == La) ? Lb : La;
+        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
+        r.U = cur; r.V = v + nn; r.OUT = Fp;
+        if (paper) {
+            r.B = B; r.G = tv.G(slot_G(P, j + 1));
+            r.bw = (j + 1 == P->nt) ? T(0.5) * h : h;
+            r.flags = first ? F_FIRST : 0;
+        }
+        CKS(pass<T>(P, OP_A1, 2, r));
+        c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs;
+        CKS(pass<T>(P, OP_A1, 1, c));
+        r = base_args<T>(P, 2); c = base_args<T>(P, 1);
+        r.U = Fs; r.X = cur; r.V = v + nn; r.OUT = Fp;
+        if (!paper) {
+            r.B = B; r.G = tv.G(slot_G(P, j)); r.G2 = tv.G(slot_Gs(P, j));
+            r.bw = T(0.5) * h;
+            r.flags = first ? F_FIRST : 0;
+        }
+        CKS(pass<T>(P, OP_A2, 2, r));
+        c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt;
+        CKS(pass<T>(P, OP_A2, 1, c));
+        cur = nxt;
+    }
+    if (paper) CK(launch_body_end<T>(nn, T(0.5) * h, cur, tv.G(slot_G(P, 0)), B, P->stream));
+    return REG_OK;
+}
+
+// ---- incremental state forward (eq. (inc-state-eq-elim)); writes lam~(1) = -m~(1) -----------------
+template <typename T>
+reg_status inc_state_forward(reg_problem* P, const T* v, const T* vt, T* lamt1) {
+    TV<T> tv{P};
+    const long nn = P->nn;
+    const bool paper = P->p.adjoint == REG_ADJ_PAPER;
+    T* Ma = tv.F(0);
+    T* Mb = tv.F(3);
+    T* Fp = tv.F(1);
+    T* Fs = tv.F(2);
+    const T* cur = nullptr;   // m~_0 = 0
+    for (int j = 0; j < P->nt; ++j) {
+        const bool last = j == P->nt - 1;
+        T* nxt = last ? lamt1 : (cur == Ma ? Mb : Ma);
+        const T* Gsrc2 = paper ? tv.G(slot_G(P, j + 1)) : tv.G(slot_Gs(P, j));
+        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
+        if (j == 0) {
+            // m~*_0 = -h v~ . G_0 is formed on the fly by both passes
+            r.flags = F_ZERO; r.VT = vt; r.G2 = tv.G(slot_G(P, 0)); r.G = Gsrc2; r.V = v + nn; r.OUT = Fp;
+            CKS(pass<T>(P, OP_I2, 2, r));
+            c.flags = F_ZERO | (last ? F_NEG : 0); c.VT = vt; c.G2 = tv.G(slot_G(P, 0)); c.V = v; c.X = Fp;
+            c.OUT = nxt;
+            CKS(pass<T>(P, OP_I2, 1, c));
+        } else {
+            r.U = cur; r.V = v + nn; r.VT = vt; r.G = tv.G(slot_G(P, j)); r.OUT = Fp;
+            CKS(pass<T>(P, OP_I1, 2, r));
+            c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs;
+            CKS(pass<T>(P, OP_I1, 1, c));
+            r = base_args<T>(P, 2); c = base_args<T>(P, 1);
+            r.U = Fs; r.X = cur; r.V = v + nn; r.VT = vt; r.G = Gsrc2; r.OUT = Fp;
+            CKS(pass<T>(P, OP_I2, 2, r));
+            c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt; c.flags = last ? F_NEG : 0;
+            CKS(pass<T>(P, OP_I2, 1, c));
+        }
+        cur = nxt;
+    }
+    return REG_OK;
+}
+
+// ---- spectral helpers (FP64) ------------------------------------------------------------------
+template <typename TI>
+reg_status spec_fwd(reg_problem* P, int field, const TI* in) {
+    cpx<double>* sp = P->spec() + (size_t)(2 * field) * P->n1 * (P->n2 / 2);
+    CK(launch_spec_row_fwd<TI>(P->sp, in, (const TI*)nullptr, sp, P->at<cpx<double>>(P->o.tw2d), P->stream));
+    return REG_OK;
+}
+reg_status spec_col(reg_problem* P, int mode, bool have_y, bool want2) {
+    CK(launch_spec_col(P->sp, mode, have_y, want2, P->spec(), P->at<cpx<double>>(P->o.tw1d), P->stream));
+    return REG_OK;
+}
+template <typename TO>
+reg_status spec_inv(reg_problem* P, int field, double* out_d, TO* out_t) {
+    CK(launch_spec_row_inv<TO>(P->sp, field, P->spec(), out_d, out_t, P->at<cpx<double>>(P->o.tw2d),
+                               P->stream));
+    return REG_OK;
+}
+
+// Nyquist projection of a caller vector field: out_d (double, nullable), out_t (T, nullable)
+template <typename T>
+reg_status project(reg_problem* P, const double* in, double* out_d, T* out_t) {
+    CKS(spec_fwd<double>(P, 0, in));
+    CKS(spec_col(P, SPEC_PROJ, false, false));
+    CKS(spec_inv<T>(P, 0, out_d, out_t));
+    return REG_OK;
+}
+
+// Host-read reductions ---------------------------------------------------------------------------
+reg_status fetch(reg_problem* P, int k, double* out) {
+    CK(hipMemcpyAsync(out, P->scal(), sizeof(double) * k, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    return REG_OK;
+}
+
+reg_status dots(reg_problem* P, int k, const double* const* a, const double* const* b, double* out) {
+    CK(launch_dots<double>(k, a, b, 2 * P->nn, P->partial(), P->scal(), P->stream));
+    return fetch(P, k, out);
+}
+
+// Regularisation terms 1/2 beta_v <v, A v> and 1/2 beta_w <div v, (1 - Lap) div v> of a projected v.
+reg_status reg_terms(reg_problem* P, const double* v64, double* rv, double* rw) {
+    double* t0 = P->at<double>(P->o.tmp0);
+    double* t1 = P->at<double>(P->o.tmp1);
+    const bool ms = P->p.constraint == REG_MASS_SOURCE;
+    CKS(spec_fwd<double>(P, 0, v64));
+    CKS(spec_col(P, SPEC_REG, false, ms));
+    CKS(spec_inv<double>(P, 0, t0, (double*)nullptr));
+    if (ms) CKS(spec_inv<double>(P, 1, t1, (double*)nullptr));
+    const double* a[2] = {v64, v64};
+    const double* b[2] = {t0, t1};
+    double r[2] = {0, 0};
+    CKS(dots(P, ms ? 2 : 1, a, b, r));
+    *rv = 0.5 * P->h1h2 * r[0];
+    *rw = ms ? 0.5 * P->h1h2 * r[1] : 0.0;
+    return REG_OK;
+}
+
+template <typename T>
+reg_status data_term(reg_problem* P, const T* m1, double* out) {
+    TV<T> tv{P};
+    CK(launch_sqdiff<T>(tv.mR(), m1, P->nn, P->partial(), P->scal(), P->stream));
+    double s = 0;
+    CKS(fetch(P, 1, &s));
+    *out = P->h1h2 * s;
+    return REG_OK;
+}
+
+// ---- objective --------------------------------------------------------------------------------
+template <typename T>
+reg_status objective_t(reg_problem* P, const double* v, double* J, double* terms) {
+    TV<T> tv{P};
+    double* vp = P->at<double>(P->o.vtrial);
+    CKS(project<T>(P, v, vp, tv.vw()));
+    CKS(state_forward<T>(P, tv.vw(), false, tv.F(4), nullptr));
+    double d = 0, rv = 0, rw = 0;
+    CKS(data_term<T>(P, tv.F(4), &d));
+    CKS(reg_terms(P, vp, &rv, &rw));
+    *J = d + rv + rw;
+    if (terms) { terms[0] = d; terms[1] = rv; terms[2] = rw; }
+    if (!std::isfinite(*J)) return fail(REG_ENONFINITE, "objective is not finite");
+    return REG_OK;
+}
+
+// ---- gradient (sets the linearisation point) --------------------------------------------------
+// g = F_Nyq[beta_v A v + K b]; also K^{-1} g for the mass-source model (kg, nullable).
+template <typename T>
+reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, double* Jout) {
+    TV<T> tv{P};
+    double* v64 = P->at<double>(P->o.v64);
+    P->linearized = false;
+    P->matvec_done = false;
+    CKS(project<T>(P, v, v64, tv.vT()));
+    CKS(state_forward<T>(P, tv.vT(), true, tv.F(4), tv.F(5)));
+    double d = 0, rv = 0, rw = 0;
+    if (Jout) {
+        CKS(data_term<T>(P, tv.F(4), &d));
+        CKS(reg_terms(P, v64, &rv, &rw));
+    }
+    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(5), tv.B()));
+    CKS(spec_fwd<double>(P, 0, v64));
+    CKS(spec_fwd<T>(P, 1, tv.B()));
+    const bool ms = P->p.constraint == REG_MASS_SOURCE;
+    CKS(spec_col(P, SPEC_HESS, true, ms && kg));
+    CKS(spec_inv<double>(P, 0, g, (double*)nullptr));
+    if (ms && kg) CKS(spec_inv<double>(P, 1, kg, (double*)nullptr));
+    if (Jout) {
+        *Jout = d + rv + rw;
+        if (!std::isfinite(*Jout)) return fail(REG_ENONFINITE, "objective is not finite");
+    }
+    P->linearized = true;
+    return REG_OK;
+}
+
+// ---- GN Hessian matvec on a projected FP64 input ------------------------------------------------
+template <typename T>
+reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kout) {
+    TV<T> tv{P};
+    if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
+    CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
+    CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), tv.F(5)));
+    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(5), tv.Bt()));
+    CKS(spec_fwd<double>(P, 0, vt64));
+    CKS(spec_fwd<T>(P, 1, tv.Bt()));
+    CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
+    CKS(spec_inv<double>(P, 0, out, (double*)nullptr));
+    if (kout) CKS(spec_inv<double>(P, 1, kout, (double*)nullptr));
+    P->matvec_done = true;
+    return REG_OK;
+}
+
+reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
+    CKS(spec_fwd<double>(P, 0, r));
+    CKS(spec_col(P, SPEC_PREC, false, kr != nullptr));
+    CKS(spec_inv<double>(P, 0, z, (double*)nullptr));
+    if (kr) CKS(spec_inv<double>(P, 1, kr, (double*)nullptr));
+    return REG_OK;
+}
+
+// ---- PCG (Alg. 2) -----------------------------------------------------------------------------
+enum { PX = 0, PR, PZ, PKR, PS, PST, PKST };
+
+template <typename T>
+reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, int fixed_iters, double* xout,
+                 int* iters, double* relres, int* nmv) {
+    const long n = 2 * P->nn;
+    const bool W = P->p.constraint == REG_MASS_SOURCE;
+    double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
+    double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
+    CK(hipMemcpyAsync(r, rhs, n * 8, hipMemcpyDeviceToDevice, P->stream));
+    CK(launch_fill(n, 0.0, x, P->stream));
+    CKS(precond_t(P, r, z, W ? kr : nullptr));
+    CK(hipMemcpyAsync(s, z, n * 8, hipMemcpyDeviceToDevice, P->stream));
+    double v2[2];
+    {
+        const double* a[2] = {W ? kr : r, r};
+        const double* b[2] = {z, r};
+        CKS(dots(P, 2, a, b, v2));
+    }
+    double rz = v2[0];
+    const double r0 = std::sqrt(v2[1]);
+    double rn = r0;
+    const int nit = fixed_iters > 0 ? fixed_iters : max_iters;
+    int l = 0;
+    while (l < nit) {
+        CKS(matvec_t<T>(P, s, st, W ? kst : nullptr));
+        if (nmv) ++*nmv;
+        double sHs = 0;
+        {
+            const double* a[1] = {s};
+            const double* b[1] = {W ? kst : st};
+            CKS(dots(P, 1, a, b, &sHs));
+        }
+        ++l;
+        if (!std::isfinite(sHs)) return fail(REG_ENONFINITE, "PCG: <s, H s> is not finite");
+        if (!(sHs > 0.0)) {
+            if (l == 1) CK(hipMemcpyAsync(x, s, n * 8, hipMemcpyDeviceToDevice, P->stream));
+            break;
+        }
+        const double kappa = rz / sHs;
+        CK(launch_add_scaled(n, x, kappa, s, x, P->stream));
+        CK(launch_add_scaled(n, r, -kappa, st, r, P->stream));
+        // preconditioned residual first, so that one synchronisation returns ||r||^2 and <r, z>_W
+        CKS(precond_t(P, r, z, W ? kr : nullptr));
+        {
+            const double* a[2] = {r, W ? kr : r};
+            const double* b[2] = {r, z};
+            CKS(dots(P, 2, a, b, v2));
+        }
+        rn = std::sqrt(v2[0]);
+        if (!std::isfinite(rn)) return fail(REG_ENONFINITE, "PCG: residual is not finite");
+        if (fixed_iters == 0 && rn <= eta * r0) break;
+        if (l >= nit) break;
+        const double mu = v2[1] / rz;
+        rz = v2[1];
+        CK(launch_axpby(n, 1.0, z, mu, s, P->stream));   // s = z + mu s
+    }
+    if (xout != x) CK(hipMemcpyAsync(xout, x, n * 8, hipMemcpyDeviceToDevice, P->stream));
+    if (iters) *iters = l;
+    if (relres) *relres = r0 > 0 ? rn / r0 : 0.0;
+    return REG_OK;
+}
+
+// ---- Newton (Alg. 1) --------------------------------------------------------------------------
+template <typename T>
+reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_solve_stats* st) {
+    const long n = 2 * P->nn;
+    reg_solve_stats S{};
+    const bool W = P->p.constraint == REG_MASS_SOURCE;
+    double* v = P->at<double>(P->o.vcur);       // current iterate
+    double* g = P->at<double>(P->o.g64);
+    double* kg = P->at<double>(P->o.kg64);
+    double* vt = P->at<double>(P->o.vt64);       // Newton step
+    double* trial = P->at<double>(P->o.vtry);    // line-search trial point
+    double* rhs = P->at<double>(P->o.rhs);
+    double J = 0;
+    // g(0) at v = 0 for the relative gradient (also with a warm start)
+    CK(launch_fill(n, 0.0, v, P->stream));
+    CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
+    S.n_pde += 2;
+    double gg = 0;
+    {
+        const double* a[1] = {g};
+        CKS(dots(P, 1, a, a, &gg));
+    }
+    const double g0 = std::sqrt(gg);
+    S.g0_norm = g0;
+    if (o->v0) {
+        CK(hipMemcpyAsync(v, o->v0, n * 8, hipMemcpyDeviceToDevice, P->stream));
+        CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
+        S.n_pde += 2;
+        const double* a[1] = {g};
+        CKS(dots(P, 1, a, a, &gg));
+    }
+    CK(hipMemcpyAsync(v, P->at<double>(P->o.v64), n * 8, hipMemcpyDeviceToDevice, P->stream));
+    int k = 0;
+    reg_status status = REG_OK;
+    double grel = 0;
+    while (true) {
+        grel = g0 > 0 ? std::sqrt(gg) / g0 : 0.0;
+        if (!std::isfinite(grel) || !std::isfinite(J)) { status = REG_ENONFINITE; break; }
+        if (grel <= o->gtol_rel || k >= o->max_newton) break;
+        const double eta = std::min(0.5, std::sqrt(grel));
+        CK(launch_fill(n, 0.0, rhs, P->stream));
+        CK(launch_axpby(n, -1.0, g, 0.0, rhs, P->stream));   // rhs = -g
+        int its = 0;
+        double rr = 0;
+        CKS(pcg_t<T>(P, rhs, eta, o->max_pcg, o->fixed_pcg_iters, vt, &its, &rr, &S.n_matvec));
+        S.n_pde += 2 * its;
+        S.pcg_iters += its;
+        double slope = 0;
+        {
+            const double* a[1] = {W ? kg : g};
+            const double* b[1] = {vt};
+            CKS(dots(P, 1, a, b, &slope));
+        }
+        slope *= P->h1h2;
+        double alpha = 1.0;
+        bool accepted = false;
+        int nbt = 0;
+        if (slope < 0.0) {
+            for (nbt = 0; nbt <= o->max_backtracks; ++nbt) {
+                CK(launch_add_scaled(n, v, alpha, vt, trial, P->stream));
+                double Jt = 0;
+                reg_status s = objective_t<T>(P, trial, &Jt, nullptr);
+                S.n_pde += 1;
+                if (s != REG_OK && s != REG_ENONFINITE) return s;
+                if (s == REG_OK && Jt <= J + o->armijo_c1 * alpha * slope) { accepted = true; break; }
+                alpha *= o->armijo_rho;
+            }
+        }
+        if (nbt > o->max_backtracks) nbt = o->max_backtracks;
+        S.backtracks += nbt;
+        if (!accepted) { status = REG_ENOTCONV; break; }
+        CK(launch_add_scaled(n, v, alpha, vt, v, P->stream));
+        CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
+        S.n_pde += 2;
+        {
+            const double* a[1] = {g};
+            CKS(dots(P, 1, a, a, &gg));
+        }
+        ++k;
+    }
+    S.newton_iters = k;
+    S.g_rel = grel;
+    S.J = J;
+    S.status = status;
+    CK(hipMemcpyAsync(vout, P->at<double>(P->o.v64), n * 8, hipMemcpyDeviceToDevice, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    if (st) *st = S;
+    if (status == REG_ENOTCONV) return fail(REG_ENOTCONV, "Armijo line search failed after %d backtracks", o->max_backtracks);
+    if (status == REG_ENONFINITE) return fail(REG_ENONFINITE, "non-finite gradient or objective");
+    return REG_OK;
+}
+
+// ---- measurement hook ---------------------------------------------------------------------------
+template <typename T>
+reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes) {
+    TV<T> tv{P};
+    if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
+    const long nn = P->nn;
+    const int j = P->nt > 1 ? P->nt / 2 : 0;
+    const bool paper = P->p.adjoint == REG_ADJ_PAPER;
+    PassArgs<T> a;
+    int op, axis;
+    double fields;
+    switch (which) {
+        case 0:   // incremental adjoint, stage 2, row pass (body-force accumulation)
+            a = base_args<T>(P, 2);
+            a.U = tv.F(2); a.X = tv.F(0); a.V = tv.vT() + nn; a.OUT = tv.F(1);
+            if (!paper) { a.B = tv.Bt(); a.G = tv.G(slot_G(P, j)); a.G2 = tv.G(slot_Gs(P, j)); a.bw = T(0.5 / P->nt); }
+            op = OP_A2; axis = 2; fields = paper ? 4 : 12;
+            break;
+        case 1:   // incremental state, stage 2, row pass
+            a = base_args<T>(P, 2);
+            a.U = tv.F(2); a.X = tv.F(0); a.V = tv.vT() + nn; a.VT = tv.vtT();
+            a.G = paper ? tv.G(slot_G(P, j + 1)) : tv.G(slot_Gs(P, j)); a.OUT = tv.F(1);
+            op = OP_I2; axis = 2; fields = 8;
+            break;
+        case 2:   // incremental adjoint, stage 2, column pass
+            a = base_args<T>(P, 1);
+            a.U = tv.F(2); a.V = tv.vT(); a.X = tv.F(1); a.OUT = tv.F(6);
+            op = OP_A2; axis = 1; fields = 4;
+            break;
+        case 3:   // incremental state, stage 2, column pass
+            a = base_args<T>(P, 1);
+            a.U = tv.F(2); a.V = tv.vT(); a.X = tv.F(1); a.OUT = tv.F(6);
+            op = OP_I2; axis = 1; fields = 4;
+            break;
+        default:
+            return fail(REG_EINVAL, "unknown pass %d", which);
+    }
+    if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    CKS(pass<T>(P, op, axis, a));   // warm-up
+    CK(hipEventRecord(e0, P->stream));
+    for (int i = 0; i < reps; ++i) CKS(pass<T>(P, op, axis, a));
+    CK(hipEventRecord(e1, P->stream));
+    CK(hipEventSynchronize(e1));
+    float t = 0;
+    CK(hipEventElapsedTime(&t, e0, e1));
+    CK(hipEventDestroy(e0));
+    CK(hipEventDestroy(e1));
+    *ms = (double)t / reps;
+    *bytes = fields * (double)nn * sizeof(T);
+    return REG_OK;
+}
+
+void twiddles(int n, std::vector<cpx<float>>& f, std::vector<cpx<double>>& d) {
+    f.resize(n);
+    d.resize(n);
+    for (int m = 0; m < n; ++m) {
+        const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+        const double c = (double)cosl(ang), s = (double)sinl(ang);
+        d[m] = {c, s};
+        f[m] = {(float)c, (float)s};
+    }
+}
+
+#define DISPATCH(P, call_f, call_d) ((P)->f64 ? (call_d) : (call_f))
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char* reg_last_error(void) { return g_err.c_str(); }
+
+reg_status reg_workspace_bytes(const reg_params* params, size_t* bytes) {
+    CKS(check_params(params));
+    if (!bytes) return fail(REG_EINVAL, "bytes is NULL");
+    *bytes = layout(params).total;
+    return REG_OK;
+}
+
+reg_status reg_create(const reg_params* params, const double* m_T, const double* m_R, void* workspace,
+                      size_t workspace_bytes, void* hip_stream, reg_problem** out) {
+    CKS(check_params(params));
+    if (!out || !m_T || !m_R || !workspace) return fail(REG_EINVAL, "NULL argument");
+    if (((uintptr_t)workspace & 255) != 0) return fail(REG_EINVAL, "workspace must be 256-byte aligned");
+    Offsets o = layout(params);
+    if (workspace_bytes < o.total)
+        return fail(REG_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", workspace_bytes, o.total);
+    reg_problem* P = new (std::nothrow) reg_problem();
+    if (!P) return fail(REG_ENOMEM, "host allocation failed");
+    P->p = *params;
+    P->stream = (hipStream_t)hip_stream;
+    P->n1 = params->n1;
+    P->n2 = params->n2;
+    P->nt = params->nt;
+    P->nn = (long)params->n1 * params->n2;
+    P->f64 = params->precision == REG_FP64;
+    P->ws = (char*)workspace;
+    P->o = o;
+    P->sp = SpecParams{params->n1, params->n2, params->norm, params->constraint, params->beta_v, params->beta_w};
+    P->h1h2 = (2.0 * M_PI / params->n1) * (2.0 * M_PI / params->n2);
+    std::vector<cpx<float>> f1, f2;
+    std::vector<cpx<double>> d1, d2;
+    twiddles(P->n1, f1, d1);
+    twiddles(P->n2, f2, d2);
+    auto cleanup = [&](reg_status s) { delete P; return s; };
+#define CKC(call)                                                                                       \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return cleanup(fail(REG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)));           \
+    } while (0)
+    CKC(hipMemcpyAsync(P->ws + o.tw1f, f1.data(), f1.size() * sizeof(f1[0]), hipMemcpyHostToDevice, P->stream));
+    CKC(hipMemcpyAsync(P->ws + o.tw2f, f2.data(), f2.size() * sizeof(f2[0]), hipMemcpyHostToDevice, P->stream));
+    CKC(hipMemcpyAsync(P->ws + o.tw1d, d1.data(), d1.size() * sizeof(d1[0]), hipMemcpyHostToDevice, P->stream));
+    CKC(hipMemcpyAsync(P->ws + o.tw2d, d2.data(), d2.size() * sizeof(d2[0]), hipMemcpyHostToDevice, P->stream));
+    if (P->f64) {
+        CKC(launch_convert<double>(P->nn, m_T, P->at<double>(o.mT), P->stream));
+        CKC(launch_convert<double>(P->nn, m_R, P->at<double>(o.mR), P->stream));
+    } else {
+        CKC(launch_convert<float>(P->nn, m_T, P->at<float>(o.mT), P->stream));
+        CKC(launch_convert<float>(P->nn, m_R, P->at<float>(o.mR), P->stream));
+    }
+    // inputs must be finite
+    {
+        const double* a[2] = {m_T, m_R};
+        CKC(launch_dots<double>(2, a, a, P->nn, P->partial(), P->scal(), P->stream));
+        double r[2];
+        CKC(hipMemcpyAsync(r, P->scal(), sizeof r, hipMemcpyDeviceToHost, P->stream));
+        CKC(hipStreamSynchronize(P->stream));
+        if (!std::isfinite(r[0]) || !std::isfinite(r[1]))
+            return cleanup(fail(REG_EINVAL, "m_T or m_R contains non-finite values"));
+    }
+#undef CKC
+    *out = P;
+    return REG_OK;
+}
+
+reg_status reg_destroy(reg_problem* h) {
+    delete h;
+    return REG_OK;
+}
+
+reg_status reg_set_stream(reg_problem* h, void* hip_stream) {
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    h->stream = (hipStream_t)hip_stream;
+    return REG_OK;
+}
+
+reg_status reg_state_forward(reg_problem* h, const double* v, double* m1) {
+    if (!h || !v || !m1) return fail(REG_EINVAL, "NULL argument");
+    if (h->f64) {
+        TV<double> tv{h};
+        CKS(project<double>(h, v, h->at<double>(h->o.vtrial), tv.vw()));
+        CKS(state_forward<double>(h, tv.vw(), false, tv.F(4), nullptr));
+        CK(hipMemcpyAsync(m1, tv.F(4), h->nn * 8, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        TV<float> tv{h};
+        CKS(project<float>(h, v, h->at<double>(h->o.vtrial), tv.vw()));
+        CKS(state_forward<float>(h, tv.vw(), false, tv.F(4), nullptr));
+        CK(launch_widen<float>(h->nn, tv.F(4), m1, h->stream));
+    }
+    return REG_OK;
+}
+
+reg_status reg_objective(reg_problem* h, const double* v, double* J_host, double* terms3_host) {
+    if (!h || !v || !J_host) return fail(REG_EINVAL, "NULL argument");
+    return DISPATCH(h, objective_t<float>(h, v, J_host, terms3_host), objective_t<double>(h, v, J_host, terms3_host));
+}
+
+reg_status reg_gradient(reg_problem* h, const double* v, double* g, double* J_host) {
+    if (!h || !v || !g) return fail(REG_EINVAL, "NULL argument");
+    return DISPATCH(h, gradient_t<float>(h, v, g, nullptr, J_host), gradient_t<double>(h, v, g, nullptr, J_host));
+}
+
+reg_status reg_hessian_matvec(reg_problem* h, const double* vtilde, double* Hv) {
+    if (!h || !vtilde || !Hv) return fail(REG_EINVAL, "NULL argument");
+    if (vtilde == Hv) return fail(REG_EINVAL, "vtilde and Hvtilde may not alias");
+    if (!h->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
+    double* vt64 = h->at<double>(h->o.vt64);
+    if (h->f64) {
+        CKS(project<double>(h, vtilde, vt64, (double*)nullptr));
+        return matvec_t<double>(h, vt64, Hv, nullptr);
+    }
+    CKS(project<float>(h, vtilde, vt64, (float*)nullptr));
+    return matvec_t<float>(h, vt64, Hv, nullptr);
+}
+
+reg_status reg_precond_apply(reg_problem* h, const double* r, double* z) {
+    if (!h || !r || !z) return fail(REG_EINVAL, "NULL argument");
+    return precond_t(h, r, z, nullptr);
+}
+
+reg_status reg_pcg(reg_problem* h, const double* rhs, double eta, int32_t max_iters, int32_t fixed_iters,
+                   double* x, int32_t* iters_host, double* relres_host) {
+    if (!h || !rhs || !x) return fail(REG_EINVAL, "NULL argument");
+    if (!h->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
+    if (max_iters < 0 || fixed_iters < 0 || (max_iters == 0 && fixed_iters == 0))
+        return fail(REG_EINVAL, "iteration limits");
+    double* r = h->at<double>(h->o.tmp1);
+    CKS(project<double>(h, rhs, r, (double*)nullptr));
+    int it = 0;
+    double rr = 0;
+    reg_status s = DISPATCH(h, pcg_t<float>(h, r, eta, max_iters, fixed_iters, x, &it, &rr, nullptr),
+                            pcg_t<double>(h, r, eta, max_iters, fixed_iters, x, &it, &rr, nullptr));
+    if (s != REG_OK) return s;
+    CK(hipStreamSynchronize(h->stream));
+    if (iters_host) *iters_host = it;
+    if (relres_host) *relres_host = rr;
+    return REG_OK;
+}
+
+reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out, reg_solve_stats* stats_host) {
+    if (!h || !opts || !v_out) return fail(REG_EINVAL, "NULL argument");
+    if (opts->max_newton < 0 || opts->max_pcg < 1 || opts->fixed_pcg_iters < 0 || opts->max_backtracks < 0 ||
+        !(opts->armijo_rho > 0 && opts->armijo_rho < 1) || !(opts->armijo_c1 > 0 && opts->armijo_c1 < 1))
+        return fail(REG_EINVAL, "bad solve options");
+    return DISPATCH(h, solve_t<float>(h, opts, v_out, stats_host), solve_t<double>(h, opts, v_out, stats_host));
+}
+
+reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes) {
+    if (!h || !ms || !bytes) return fail(REG_EINVAL, "NULL argument");
+    return DISPATCH(h, time_pass_t<float>(h, which, reps, ms, bytes), time_pass_t<double>(h, which, reps, ms, bytes));
+}
+
+}  // extern "C"

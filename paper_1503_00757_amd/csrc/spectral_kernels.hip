@@ -1,0 +1,300 @@
+// Two-dimensional Fourier multipliers in FP64: the Hessian / gradient assembly
+// beta_v A v + K[b] (Sec. 3.3, eqs. (control-eq-elim), (inc-control-eq-elim)), the preconditioner
+// (beta_v A)^{-1} (App. E.2), the Nyquist projection and the regularisation terms of the objective.
+//
+// Three passes over a half spectrum that omits the Nyquist column (it is projected out anyway):
+//   row forward  : each row of a vector field, packed as comp0 + i comp1, is transformed along x2 and
+//                  split into the half spectra of the two real components (k2 = 0..n2/2-1);
+//   column       : per column k2, FFT along x1 of every needed component, the (2x2) multiplier of the
+//                  mode, inverse FFT along x1 -- in place, each block owns whole columns;
+//   row inverse  : the two half spectra of a result are recombined into one complex row, inverse
+//                  transformed along x2; real part -> component 0, imaginary part -> component 1.
+//
+// Symbols (k~ = integer wavenumber with Nyquist -> 0, |k|^2 = k~1^2 + k~2^2):
+//   A^ = |k|^2 (H1) or |k|^4 (H2)                                  eq. (var-reg-v)
+//   K^ = I - c(k) k k^T/|k|^2, c = 0 (no constraint), 1 (w = 0), 1/M^ (mass source) with
+//   M^ = 1 + beta_v A^ / (beta_w |k|^2 (|k|^2 + 1))                 eq. (project-body-force)
+//   K^{-1} = I + c'(k) k k^T/|k|^2, c' = 1/(M^ - 1)                   (mass source only)
+//   P^ = beta_v A^, or beta_v where A^ = 0                          App. E.2
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace regnk {
+
+template <int N>
+constexpr int spec_fpw() { return (N / 4) >= 64 ? 1 : 64 / (N / 4); }
+template <int N>
+constexpr int spec_nf() { return (N / 4) >= 128 ? 1 : ((N / 4) >= 32 ? 2 : 128 / (N / 4)); }
+
+// ---------------------------------------------------------------------------------------------
+template <typename TI, int N, int FPW>
+__global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const TI* __restrict__ in0,
+                                                                  const TI* __restrict__ in1,
+                                                                  cpx<double>* __restrict__ spec,
+                                                                  const cpx<double>* __restrict__ tw) {
+    constexpr int Q = N / 4, H = N / 2;
+    constexpr int L = LdsSize<N>::value;
+    __shared__ cpx<double> lds[FPW][2][L];
+    const int f = threadIdx.x / Q, t = threadIdx.x % Q;
+    const int i1 = blockIdx.x * FPW + f;
+    const bool valid = i1 < n1;
+    const int field = blockIdx.y;
+    const TI* in = field ? in1 : in0;
+    const long nn = (long)n1 * N;
+    const long row = (long)(valid ? i1 : 0) * N;
+    cpx<double> x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = t + r * Q;
+        x[r] = valid ? cpx<double>{(double)in[row + e], (double)in[nn + row + e]} : cpx<double>{0.0, 0.0};
+    }
+    int buf = 0;
+    fft4<double, N, false>(x, lds[f][0], lds[f][1], t, tw, buf);
+    cpx<double>* o = buf ? lds[f][1] : lds[f][0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[lpad(t + r * Q)] = x[r];
+    __syncthreads();
+    if (!valid) return;
+    const long hn = (long)n1 * H;
+    cpx<double>* s0 = spec + (long)(2 * field) * hn + (long)i1 * H;
+    cpx<double>* s1 = s0 + hn;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int e = t + r * Q;   // < N/2
+        const cpx<double> z = x[r];
+        const cpx<double> zc = o[lpad((N - e) & (N - 1))];
+        // Z_e = A_e + i B_e, conj(Z_{N-e}) = A_e - i B_e  (A, B spectra of the real components)
+        const double dx = z.x - zc.x, dy = z.y + zc.y;   // Z_e - conj(Z_{N-e})
+        s0[e] = {0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y)};
+        s1[e] = {0.5 * dy, -0.5 * dx};
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+struct ModeCoef {
+    double a;     // A^
+    double kk;    // |k|^2
+    double p11, p12, p22;   // k k^T / |k|^2
+};
+
+template <int N, int NF>
+__global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int mode, int have_y, int want2,
+                                                              cpx<double>* __restrict__ spec,
+                                                              const cpx<double>* __restrict__ tw) {
+    constexpr int Q = N / 4;
+    constexpr int L = LdsSize<N>::value;
+    __shared__ cpx<double> lds[NF][2][L];
+    const int f = threadIdx.x % NF, t = threadIdx.x / NF;
+    const int H = p.n2 / 2;
+    const int k2 = blockIdx.x * NF + f;
+    const bool valid = k2 < H;
+    const long hn = (long)N * H;
+    const long col = valid ? k2 : 0;
+    cpx<double> X0[4], X1[4], Y0[4], Y1[4];
+    int buf = 0;
+    auto load_fft = [&](int comp, cpx<double>(&x)[4]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long idx = comp * hn + (long)(t + r * Q) * H + col;
+            x[r] = valid ? spec[idx] : cpx<double>{0.0, 0.0};
+        }
+        fft4<double, N, false>(x, lds[f][0], lds[f][1], t, tw, buf);
+    };
+    load_fft(0, X0);
+    load_fft(1, X1);
+    if (have_y) {
+        load_fft(2, Y0);
+        load_fft(3, Y1);
+    }
+    const double scale = 1.0 / ((double)N * (double)p.n2);
+    const double k2d = (double)k2;
+    cpx<double> O0[4], O1[4], P0[4], P1[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = t + r * Q;
+        const double k1 = (double)kwave<N>(e);
+        const double kk = k1 * k1 + k2d * k2d;
+        const double A = (p.norm == 1) ? kk : kk * kk;
+        const double ik = kk > 0.0 ? 1.0 / kk : 0.0;
+        const double p11 = k1 * k1 * ik, p12 = k1 * k2d * ik, p22 = k2d * k2d * ik;
+        double c = 0.0, ci = 0.0;   // K = I - c P, K^{-1} = I + ci P
+        if (kk > 0.0) {
+            if (p.constraint == 1) {
+                c = 1.0;
+            } else if (p.constraint == 2) {
+                const double q = p.beta_v * A / (p.beta_w * kk * (kk + 1.0));   // M^ - 1
+                c = 1.0 / (1.0 + q);
+                ci = 1.0 / q;
+            }
+        }
+        const bool zero = (e == N / 2);   // Nyquist row of x1: projected out
+        cpx<double> x0 = X0[r], x1 = X1[r];
+        cpx<double> o0{0, 0}, o1{0, 0}, q0{0, 0}, q1{0, 0};
+        if (mode == SPEC_PROJ) {
+            o0 = x0;
+            o1 = x1;
+        } else if (mode == SPEC_HESS) {
+            const cpx<double> y0 = Y0[r], y1 = Y1[r];
+            const double ba = p.beta_v * A;
+            // K y
+            const cpx<double> ky0 = {y0.x - c * (p11 * y0.x + p12 * y1.x), y0.y - c * (p11 * y0.y + p12 * y1.y)};
+            const cpx<double> ky1 = {y1.x - c * (p12 * y0.x + p22 * y1.x), y1.y - c * (p12 * y0.y + p22 * y1.y)};
+            o0 = {ba * x0.x + ky0.x, ba * x0.y + ky0.y};
+            o1 = {ba * x1.x + ky1.x, ba * x1.y + ky1.y};
+            // K^{-1}(beta_v A x + K y) = beta_v A K^{-1} x + y
+            const cpx<double> kx0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
+            const cpx<double> kx1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
+            q0 = {ba * kx0.x + y0.x, ba * kx0.y + y0.y};
+            q1 = {ba * kx1.x + y1.x, ba * kx1.y + y1.y};
+        } else if (mode == SPEC_PREC) {
+            const double pinv = 1.0 / (p.beta_v * (A > 0.0 ? A : 1.0));
+            o0 = {x0.x * pinv, x0.y * pinv};
+            o1 = {x1.x * pinv, x1.y * pinv};
+            q0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
+            q1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
+        } else {   // SPEC_REG: beta_v A v and beta_w (1 + |k|^2) k k^T v
+            const double ba = p.beta_v * A;
+            o0 = {ba * x0.x, ba * x0.y};
+            o1 = {ba * x1.x, ba * x1.y};
+            const double w = p.beta_w * (1.0 + kk) * kk;
+            q0 = {w * (p11 * x0.x + p12 * x1.x), w * (p11 * x0.y + p12 * x1.y)};
+            q1 = {w * (p12 * x0.x + p22 * x1.x), w * (p12 * x0.y + p22 * x1.y)};
+        }
+        const double sc = zero ? 0.0 : scale;
+        O0[r] = {o0.x * sc, o0.y * sc};
+        O1[r] = {o1.x * sc, o1.y * sc};
+        P0[r] = {q0.x * sc, q0.y * sc};
+        P1[r] = {q1.x * sc, q1.y * sc};
+    }
+    auto ifft_store = [&](int comp, cpx<double>(&x)[4]) {
+        fft4<double, N, true>(x, lds[f][0], lds[f][1], t, tw, buf);
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) spec[comp * hn + (long)(t + r * Q) * H + col] = x[r];
+        }
+    };
+    ifft_store(0, O0);
+    ifft_store(1, O1);
+    if (want2) {
+        ifft_store(2, P0);
+        ifft_store(3, P1);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+template <typename TO, int N, int FPW>
+__global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const cpx<double>* __restrict__ spec,
+                                                                  double* __restrict__ out_d,
+                                                                  TO* __restrict__ out_t,
+                                                                  const cpx<double>* __restrict__ tw) {
+    constexpr int Q = N / 4, H = N / 2;
+    constexpr int L = LdsSize<N>::value;
+    __shared__ cpx<double> lds[FPW][2][L];
+    const int f = threadIdx.x / Q, t = threadIdx.x % Q;
+    const int i1 = blockIdx.x * FPW + f;
+    const bool valid = i1 < n1;
+    const long hn = (long)n1 * H;
+    const cpx<double>* s0 = spec + (long)(valid ? i1 : 0) * H;
+    const cpx<double>* s1 = s0 + hn;
+    cpx<double> x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = t + r * Q;
+        cpx<double> z{0.0, 0.0};
+        if (valid && e != H) {
+            if (e < H) {
+                const cpx<double> a = s0[e], b = s1[e];
+                z = {a.x - b.y, a.y + b.x};
+            } else {
+                const cpx<double> a = s0[N - e], b = s1[N - e];
+                z = {a.x + b.y, b.x - a.y};
+            }
+        }
+        x[r] = z;
+    }
+    int buf = 0;
+    fft4<double, N, true>(x, lds[f][0], lds[f][1], t, tw, buf);
+    if (!valid) return;
+    const long nn = (long)n1 * N;
+    const long row = (long)i1 * N;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = t + r * Q;
+        if (out_d) {
+            out_d[row + e] = x[r].x;
+            out_d[nn + row + e] = x[r].y;
+        }
+        if (out_t) {
+            out_t[row + e] = (TO)x[r].x;
+            out_t[nn + row + e] = (TO)x[r].y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+template <typename TI>
+hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1, cpx<double>* spec,
+                               const cpx<double>* tw2, hipStream_t s) {
+    const int nf = in1 ? 2 : 1;
+#define ROWF(NN)                                                                                       \
+    case NN: {                                                                                         \
+        constexpr int FPW = spec_fpw<NN>();                                                            \
+        hipLaunchKernelGGL((spec_row_fwd_kernel<TI, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf),      \
+                           dim3(FPW * NN / 4), 0, s, p.n1, in0, in1, spec, tw2);                       \
+        break;                                                                                         \
+    }
+    switch (p.n2) {
+        ROWF(8) ROWF(16) ROWF(32) ROWF(64) ROWF(128) ROWF(256) ROWF(512) ROWF(1024) ROWF(2048)
+        default: return hipErrorInvalidValue;
+    }
+#undef ROWF
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
+                           const cpx<double>* tw1, hipStream_t s) {
+    const int H = p.n2 / 2;
+#define COLF(NN)                                                                                       \
+    case NN: {                                                                                         \
+        constexpr int NF = spec_nf<NN>();                                                              \
+        hipLaunchKernelGGL((spec_col_kernel<NN, NF>), dim3((H + NF - 1) / NF), dim3(NF * NN / 4), 0,  \
+                           s, p, mode, (int)have_y, (int)want2, spec, tw1);                            \
+        break;                                                                                         \
+    }
+    switch (p.n1) {
+        COLF(8) COLF(16) COLF(32) COLF(64) COLF(128) COLF(256) COLF(512) COLF(1024) COLF(2048)
+        default: return hipErrorInvalidValue;
+    }
+#undef COLF
+    return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>* spec, double* out_d,
+                               TO* out_t, const cpx<double>* tw2, hipStream_t s) {
+    const cpx<double>* sp = spec + (long)(2 * field) * p.n1 * (p.n2 / 2);
+#define ROWI(NN)                                                                                       \
+    case NN: {                                                                                         \
+        constexpr int FPW = spec_fpw<NN>();                                                            \
+        hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW),          \
+                           dim3(FPW * NN / 4), 0, s, p.n1, sp, out_d, out_t, tw2);                     \
+        break;                                                                                         \
+    }
+    switch (p.n2) {
+        ROWI(8) ROWI(16) ROWI(32) ROWI(64) ROWI(128) ROWI(256) ROWI(512) ROWI(1024) ROWI(2048)
+        default: return hipErrorInvalidValue;
+    }
+#undef ROWI
+    return hipGetLastError();
+}
+
+template hipError_t launch_spec_row_fwd<float>(const SpecParams&, const float*, const float*, cpx<double>*,
+                                               const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_fwd<double>(const SpecParams&, const double*, const double*,
+                                                cpx<double>*, const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_inv<float>(const SpecParams&, int, const cpx<double>*, double*, float*,
+                                               const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_inv<double>(const SpecParams&, int, const cpx<double>*, double*,
+                                                double*, const cpx<double>*, hipStream_t);
+
+}  // namespace regnk

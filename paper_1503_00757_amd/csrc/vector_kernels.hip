@@ -1,0 +1,147 @@
+// FP64 inner products, norms and vector updates for PCG (Alg. 2) and the line search (Alg. 1).
+// Reductions are deterministic: block b always sums the same contiguous chunk in the same order
+// (fixed shuffle tree inside a wave, fixed order over waves), and one block sums the per-block
+// partials in a fixed order, so two runs give bitwise identical results.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace regnk {
+
+template <typename TI>
+struct DotPtrs {
+    const TI* a[4];
+    const TI* b[4];
+};
+
+template <typename TI>
+__global__ __launch_bounds__(RED_THREADS) void dots_kernel(int nk, DotPtrs<TI> p, long n, double* __restrict__ partial) {
+    __shared__ double sh[RED_THREADS / 64];
+    const long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
+    const long lo = (long)blockIdx.x * chunk;
+    const long hi = lo + chunk < n ? lo + chunk : n;
+    for (int k = 0; k < nk; ++k) {
+        double acc = 0.0;
+        const TI* __restrict__ a = p.a[k];
+        const TI* __restrict__ b = p.b[k];
+        for (long i = lo + threadIdx.x; i < hi; i += RED_THREADS) acc += (double)a[i] * (double)b[i];
+        const double s = block_sum<RED_THREADS>(acc, sh);
+        if (threadIdx.x == 0) partial[k * RED_BLOCKS + blockIdx.x] = s;
+    }
+}
+
+template <typename TI>
+__global__ __launch_bounds__(RED_THREADS) void sqdiff_kernel(const TI* __restrict__ x, const TI* __restrict__ y, long n,
+                                                             double* __restrict__ partial) {
+    __shared__ double sh[RED_THREADS / 64];
+    const long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
+    const long lo = (long)blockIdx.x * chunk;
+    const long hi = lo + chunk < n ? lo + chunk : n;
+    double acc = 0.0;
+    for (long i = lo + threadIdx.x; i < hi; i += RED_THREADS) {
+        const double d = (double)x[i] - (double)y[i];
+        acc += d * d;
+    }
+    const double s = block_sum<RED_THREADS>(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0.5 * s;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void finalize_kernel(const double* __restrict__ partial, double* __restrict__ out) {
+    __shared__ double sh[RED_THREADS / 64];
+    const int k = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partial[k * RED_BLOCKS + i];
+    const double s = block_sum<RED_THREADS>(acc, sh);
+    if (threadIdx.x == 0) out[k] = s;
+}
+
+__global__ void axpby_kernel(long n, double alpha, const double* __restrict__ x, double beta, double* __restrict__ y) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = alpha * x[i] + beta * y[i];
+}
+
+__global__ void add_scaled_kernel(long n, const double* x, double alpha, const double* __restrict__ y, double* z) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        z[i] = x[i] + alpha * y[i];
+}
+
+template <typename TO>
+__global__ void convert_kernel(long n, const double* __restrict__ in, TO* __restrict__ out) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = (TO)in[i];
+}
+
+template <typename TI>
+__global__ void widen_kernel(long n, const TI* __restrict__ in, double* __restrict__ out) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = (double)in[i];
+}
+
+__global__ void fill_kernel(long n, double v, double* __restrict__ y) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = v;
+}
+
+static inline int grid_for(long n) {
+    long b = (n + 255) / 256;
+    return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+template <typename TI>
+hipError_t launch_dots(int nk, const TI* const* a, const TI* const* b, long n, double* partial, double* out,
+                       hipStream_t s) {
+    if (nk < 1 || nk > 4) return hipErrorInvalidValue;
+    DotPtrs<TI> p{};
+    for (int k = 0; k < nk; ++k) {
+        p.a[k] = a[k];
+        p.b[k] = b[k];
+    }
+    hipLaunchKernelGGL((dots_kernel<TI>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, nk, p, n, partial);
+    hipLaunchKernelGGL(finalize_kernel, dim3(nk), dim3(RED_THREADS), 0, s, partial, out);
+    return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_sqdiff(const TI* x, const TI* y, long n, double* partial, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((sqdiff_kernel<TI>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, y, n, partial);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(long n, double alpha, const double* x, double beta, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, alpha, x, beta, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_scaled(long n, const double* x, double alpha, const double* y, double* z, hipStream_t s) {
+    hipLaunchKernelGGL(add_scaled_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, x, alpha, y, z);
+    return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_convert(long n, const double* in, TO* out, hipStream_t s) {
+    hipLaunchKernelGGL((convert_kernel<TO>), dim3(grid_for(n)), dim3(256), 0, s, n, in, out);
+    return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_widen(long n, const TI* in, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((widen_kernel<TI>), dim3(grid_for(n)), dim3(256), 0, s, n, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, v, y);
+    return hipGetLastError();
+}
+
+template hipError_t launch_dots<double>(int, const double* const*, const double* const*, long, double*, double*,
+                                        hipStream_t);
+template hipError_t launch_dots<float>(int, const float* const*, const float* const*, long, double*, double*,
+                                       hipStream_t);
+template hipError_t launch_sqdiff<double>(const double*, const double*, long, double*, double*, hipStream_t);
+template hipError_t launch_sqdiff<float>(const float*, const float*, long, double*, double*, hipStream_t);
+template hipError_t launch_convert<float>(long, const double*, float*, hipStream_t);
+template hipError_t launch_convert<double>(long, const double*, double*, hipStream_t);
+template hipError_t launch_widen<float>(long, const float*, double*, hipStream_t);
+template hipError_t launch_widen<double>(long, const double*, double*, hipStream_t);
+
+}  // namespace regnk

@@ -1,0 +1,162 @@
+"""ctypes declarations of the C ABI in ``include/regnk.h`` (argument marshalling only).
+
+Every ``reg_*`` function here has the name and argument order of the C function; device arrays are
+passed as integer addresses (``tensor.data_ptr()``), host outputs are returned.  A non-zero status
+raises ``RegError`` carrying the status code and ``reg_last_error()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+REG_OK, REG_EINVAL, REG_ENOMEM, REG_EDEVICE, REG_ENOTCONV, REG_ENONFINITE, REG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+REG_H1, REG_H2 = 1, 2
+REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE = 0, 1, 2
+REG_FP64, REG_FP32_TRANSPORT = 0, 1
+REG_ADJ_DISCRETE, REG_ADJ_PAPER = 0, 1
+
+STATUS_NAMES = {0: "REG_OK", -1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_ENOTCONV",
+                -5: "REG_ENONFINITE", -6: "REG_ESTATE"}
+
+
+class RegParams(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("nt", C.c_int32), ("norm", C.c_int32),
+                ("constraint", C.c_int32), ("precision", C.c_int32), ("adjoint", C.c_int32),
+                ("reserved", C.c_int32), ("beta_v", C.c_double), ("beta_w", C.c_double)]
+
+
+class RegSolveOpts(C.Structure):
+    _fields_ = [("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("fixed_pcg_iters", C.c_int32),
+                ("max_backtracks", C.c_int32), ("gtol_rel", C.c_double), ("armijo_c1", C.c_double),
+                ("armijo_rho", C.c_double), ("v0", C.c_void_p)]
+
+
+class RegSolveStats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("n_matvec", C.c_int32),
+                ("n_pde", C.c_int32), ("backtracks", C.c_int32), ("status", C.c_int32),
+                ("g0_norm", C.c_double), ("g_rel", C.c_double), ("J", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RegError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libregnk.so")
+
+
+def lib():
+    """Load the HIP library (no fallback: raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_1503_00757_amd.build`")
+        L = C.CDLL(path)
+        vp, dp, i32, d, sz = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_size_t
+        L.reg_workspace_bytes.argtypes = [C.POINTER(RegParams), C.POINTER(sz)]
+        L.reg_create.argtypes = [C.POINTER(RegParams), vp, vp, vp, sz, vp, C.POINTER(vp)]
+        L.reg_destroy.argtypes = [vp]
+        L.reg_set_stream.argtypes = [vp, vp]
+        L.reg_state_forward.argtypes = [vp, vp, vp]
+        L.reg_objective.argtypes = [vp, vp, dp, dp]
+        L.reg_gradient.argtypes = [vp, vp, vp, dp]
+        L.reg_hessian_matvec.argtypes = [vp, vp, vp]
+        L.reg_precond_apply.argtypes = [vp, vp, vp]
+        L.reg_pcg.argtypes = [vp, vp, d, i32, i32, vp, C.POINTER(i32), dp]
+        L.reg_solve.argtypes = [vp, C.POINTER(RegSolveOpts), vp, C.POINTER(RegSolveStats)]
+        L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp]
+        L.reg_last_error.argtypes = []
+        L.reg_last_error.restype = C.c_char_p
+        for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
+                     "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
+                     "reg_solve", "reg_time_pass"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def reg_last_error() -> str:
+    return lib().reg_last_error().decode()
+
+
+def _check(status: int):
+    if status != REG_OK:
+        raise RegError(status, reg_last_error())
+
+
+def reg_workspace_bytes(params: RegParams) -> int:
+    out = C.c_size_t(0)
+    _check(lib().reg_workspace_bytes(C.byref(params), C.byref(out)))
+    return out.value
+
+
+def reg_create(params: RegParams, m_T: int, m_R: int, workspace: int, workspace_bytes: int, stream: int):
+    h = C.c_void_p(0)
+    _check(lib().reg_create(C.byref(params), m_T, m_R, workspace, workspace_bytes, stream, C.byref(h)))
+    return h
+
+
+def reg_destroy(h):
+    _check(lib().reg_destroy(h))
+
+
+def reg_set_stream(h, stream: int):
+    _check(lib().reg_set_stream(h, stream))
+
+
+def reg_state_forward(h, v: int, m1: int):
+    _check(lib().reg_state_forward(h, v, m1))
+
+
+def reg_objective(h, v: int):
+    J = C.c_double(0)
+    terms = (C.c_double * 3)()
+    _check(lib().reg_objective(h, v, C.byref(J), terms))
+    return J.value, list(terms)
+
+
+def reg_gradient(h, v: int, g: int, want_J: bool = True):
+    J = C.c_double(0)
+    _check(lib().reg_gradient(h, v, g, C.byref(J) if want_J else None))
+    return J.value if want_J else None
+
+
+def reg_hessian_matvec(h, vtilde: int, Hvtilde: int):
+    _check(lib().reg_hessian_matvec(h, vtilde, Hvtilde))
+
+
+def reg_precond_apply(h, r: int, z: int):
+    _check(lib().reg_precond_apply(h, r, z))
+
+
+def reg_pcg(h, rhs: int, eta: float, max_iters: int, fixed_iters: int, x: int):
+    it = C.c_int32(0)
+    rr = C.c_double(0)
+    _check(lib().reg_pcg(h, rhs, eta, max_iters, fixed_iters, x, C.byref(it), C.byref(rr)))
+    return it.value, rr.value
+
+
+def reg_solve(h, opts: RegSolveOpts, v_out: int, raise_on_error: bool = True):
+    st = RegSolveStats()
+    status = lib().reg_solve(h, C.byref(opts), v_out, C.byref(st))
+    if raise_on_error:
+        _check(status)
+    return status, st
+
+
+def reg_time_pass(h, which: int, reps: int):
+    ms = C.c_double(0)
+    by = C.c_double(0)
+    _check(lib().reg_time_pass(h, which, reps, C.byref(ms), C.byref(by)))
+    return ms.value, by.value

@@ -1,0 +1,107 @@
+"""Convenience wrapper: one registration problem whose workspace and vectors live in torch tensors.
+
+All arithmetic happens in the HIP library; this class allocates device memory through torch, passes
+pointers and the current stream, and returns tensors.
+"""
+from __future__ import annotations
+
+from . import ffi
+
+_NORMS = {"H1": ffi.REG_H1, "H2": ffi.REG_H2}
+_CONS = {"none": ffi.REG_UNCONSTRAINED, "divfree": ffi.REG_DIVFREE, "mass_source": ffi.REG_MASS_SOURCE}
+_PREC = {"fp64": ffi.REG_FP64, "fp32": ffi.REG_FP32_TRANSPORT}
+_ADJ = {"dto": ffi.REG_ADJ_DISCRETE, "paper": ffi.REG_ADJ_PAPER}
+
+
+def make_params(n1, n2, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0, precision="fp32",
+                adjoint="dto") -> ffi.RegParams:
+    return ffi.RegParams(n1, n2, nt, _NORMS[norm], _CONS[constraint], _PREC[precision], _ADJ[adjoint], 0,
+                         float(beta_v), float(beta_w))
+
+
+class Problem:
+    def __init__(self, mT, mR, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0,
+                 precision="fp32", adjoint="dto", stream=None):
+        import torch
+        self.torch = torch
+        if mT.dtype != torch.float64 or mR.dtype != torch.float64 or not mT.is_cuda or not mR.is_cuda:
+            raise ValueError("m_T and m_R must be float64 device tensors")
+        n1, n2 = mT.shape
+        self.n1, self.n2, self.nt = n1, n2, nt
+        self.device = mT.device
+        self.params = make_params(n1, n2, nt, norm, constraint, beta_v, beta_w, precision, adjoint)
+        self.ws_bytes = ffi.reg_workspace_bytes(self.params)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.mT = mT.contiguous()
+        self.mR = mR.contiguous()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = ffi.reg_create(self.params, self.mT.data_ptr(), self.mR.data_ptr(), self.ws_ptr,
+                                self.ws_bytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ffi.reg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vec(self):
+        return self.torch.empty((2, self.n1, self.n2), dtype=self.torch.float64, device=self.device)
+
+    @staticmethod
+    def _c(x):
+        return x.contiguous()
+
+    def state_forward(self, v):
+        v = self._c(v)
+        m1 = self.torch.empty((self.n1, self.n2), dtype=self.torch.float64, device=self.device)
+        ffi.reg_state_forward(self.h, v.data_ptr(), m1.data_ptr())
+        return m1
+
+    def objective(self, v):
+        v = self._c(v)
+        return ffi.reg_objective(self.h, v.data_ptr())
+
+    def gradient(self, v, want_J=True):
+        v = self._c(v)
+        g = self.vec()
+        J = ffi.reg_gradient(self.h, v.data_ptr(), g.data_ptr(), want_J)
+        return g, J
+
+    def hessian_matvec(self, vt, out=None):
+        vt = self._c(vt)
+        out = self.vec() if out is None else out
+        ffi.reg_hessian_matvec(self.h, vt.data_ptr(), out.data_ptr())
+        return out
+
+    def precond(self, r):
+        r = self._c(r)
+        z = self.vec()
+        ffi.reg_precond_apply(self.h, r.data_ptr(), z.data_ptr())
+        return z
+
+    def pcg(self, rhs, eta=1e-3, max_iters=100, fixed_iters=0):
+        rhs = self._c(rhs)
+        x = self.vec()
+        it, rr = ffi.reg_pcg(self.h, rhs.data_ptr(), eta, max_iters, fixed_iters, x.data_ptr())
+        return x, it, rr
+
+    def solve(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
+              armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True):
+        v0c = self._c(v0) if v0 is not None else None
+        opts = ffi.RegSolveOpts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
+                                armijo_rho, v0c.data_ptr() if v0c is not None else None)
+        v = self.vec()
+        status, st = ffi.reg_solve(self.h, opts, v.data_ptr(), raise_on_error)
+        d = st.as_dict()
+        d["return_status"] = status
+        return v, d
+
+    def time_pass(self, which, reps=100):
+        return ffi.reg_time_pass(self.h, which, reps)

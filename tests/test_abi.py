@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every symbol declared in include/regnk.h; host-side argument
+checking (no device work).  CPU only."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1503_00757_amd as R
+from paper_1503_00757_amd.problem import make_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:reg_status|const char\*)\s+(reg_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("reg_create", "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_solve",
+                 "reg_precond_apply", "reg_pcg", "reg_workspace_bytes", "reg_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = R.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", R.library_path()], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (reg_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(R.RegParams) == 8 * 4 + 2 * 8
+    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 8
+    assert ctypes.sizeof(R.RegSolveStats) == 6 * 4 + 3 * 8
+
+
+def test_workspace_bytes_scales_with_grid_and_steps():
+    a = R.reg_workspace_bytes(make_params(64, 64, 4))
+    b = R.reg_workspace_bytes(make_params(64, 64, 8))
+    c = R.reg_workspace_bytes(make_params(128, 64, 4))
+    d = R.reg_workspace_bytes(make_params(64, 64, 4, precision="fp64"))
+    assert b > a and c > a and d > a
+    # the stored trajectory (2 nt + 1 vector fields in transport precision) dominates the growth in nt
+    assert b - a >= 8 * 2 * 64 * 64 * 4
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n1=60), dict(n2=4), dict(n1=4096), dict(nt=0), dict(beta_v=0.0), dict(beta_v=-1.0),
+    dict(constraint="mass_source", beta_w=0.0), dict(constraint="divfree", beta_w=1e-3),
+])
+def test_invalid_parameters_are_rejected(kw):
+    args = dict(n1=64, n2=64, nt=4, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0)
+    args.update(kw)
+    p = make_params(args["n1"], args["n2"], args["nt"], args["norm"], args["constraint"], args["beta_v"],
+                    args["beta_w"])
+    with pytest.raises(R.RegError) as e:
+        R.reg_workspace_bytes(p)
+    assert e.value.status == -1
+    assert len(R.reg_last_error()) > 0
+
+
+def test_bad_enum_and_reserved_rejected():
+    p = make_params(64, 64, 4)
+    p.norm = 3
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(p)
+    p = make_params(64, 64, 4)
+    p.reserved = 1
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(p)
+
+
+def test_create_rejects_null_and_small_workspace_without_device_work():
+    p = make_params(64, 64, 4)
+    need = R.reg_workspace_bytes(p)
+    with pytest.raises(R.RegError) as e:
+        R.reg_create(p, 0, 0, 0, need, 0)
+    assert e.value.status == -1
+    with pytest.raises(R.RegError) as e:
+        R.reg_create(p, 256, 256, 256, need - 1, 0)   # never dereferenced: size is checked first
+    assert e.value.status == -2
