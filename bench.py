@@ -130,14 +130,29 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the solve and 1024^2 measurements")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: 256^2 headline workload (default); c3: 1024^2, n_t=32 (profiling)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the single-pair path "
               "does not shard across GPUs; see the design notes for how it would)", file=sys.stderr)
         sys.exit(2)
     import torch
-    print(f"[bench] 256^2 nt=16 setup", file=sys.stderr, flush=True)
-    w, P, vlin, vt = setup(2)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: 3 copies of {args.copy_probe_mib} MiB (read + write each)", file=sys.stderr,
+              flush=True)
+        del a, b
+    cfg = 2 if args.workload == "c2" else 3
+    print(f"[bench] workload {args.workload} setup", file=sys.stderr, flush=True)
+    w, P, vlin, vt = setup(cfg)
     dt = bench_pcg(P, vlin, args.steps, args.warmup)
     print(f"[bench] pcg {args.steps} steps {dt:.3f}s", file=sys.stderr, flush=True)
     rl = roofline(P)
@@ -147,7 +162,7 @@ def main():
         print("[bench] solve", file=sys.stderr, flush=True)
         extras["solve_to_grel_1e-2_plain"] = bench_solve(P)
     P.close()
-    if not args.no_extras:
+    if not args.no_extras and cfg == 2:
         print("[bench] 1024^2 nt=32", file=sys.stderr, flush=True)
         w3, P3, vlin3, vt3 = setup(3)
         P3.gradient(vlin3, want_J=False)
@@ -164,15 +179,19 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
+    if cfg == 3:
+        wl = ("c3: one pair, 1024x1024 periodic grid, n_t=32, H1 + divergence-free, beta_v=1e-4; FP32 "
+              "transport/FFT, FP64 assembly and PCG; step = one PCG iteration")
+    else:
+        wl = ("c2: one pair, 256x256 periodic grid, n_t=16, H2 + mass source, beta_v=1e-3, "
+              "beta_w=1e-4; FP32 transport/FFT, FP64 assembly and PCG; step = one PCG "
+              "iteration (1 GN matvec + preconditioner + FP64 PCG updates)")
     out = {
-        "metric": "GN Hessian matvecs/s at 256^2", "value": round(args.steps / dt, 2), "unit": "matvecs/s",
+        "metric": f"GN Hessian matvecs/s at {w.n1}^2", "value": round(args.steps / dt, 2), "unit": "matvecs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "c2: one pair, 256x256 periodic grid, n_t=16, H2 + mass source, beta_v=1e-3, "
-                               "beta_w=1e-4; FP32 transport/FFT, FP64 assembly and PCG; step = one PCG "
-                               "iteration (1 GN matvec + preconditioner + FP64 PCG updates)",
-                   "n1": 256, "n2": 256, "nt": 16},
+        "config": {"workload": wl, "n1": w.n1, "n2": w.n2, "nt": w.nt},
         "roofline": rl,
         "cpu_baseline": cpu,
     }

@@ -30,6 +30,8 @@ struct PassArgs {
     T* OUT;                  // output field
     T* OUT2;                 // second output field (lam(1) = m_R - m_1)
     T* GOUT;                 // gradient output (vector field) of the state passes
+    float* GOUTF;            // same, rounded to FP32 (FP64 state solve feeding an FP32 trajectory)
+    float* OUT2F;            // lam(1) rounded to FP32
     T* B;                    // body-force accumulator (vector field)
     const cpx<T>* tw;        // twiddles of the pass axis length
 };

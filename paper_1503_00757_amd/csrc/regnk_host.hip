@@ -65,6 +65,7 @@ struct Layout {
 
 struct Offsets {
     size_t mT, mR, vT, vw, vtT, traj, fld[NFIELD], B, Bt;
+    size_t mT64, mR64, sfld[5];   // FP64 state-solve buffers (FP32 transport mode only)
     size_t tw1f, tw2f, tw1d, tw2d;
     size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal;
     size_t total;
@@ -107,6 +108,10 @@ Offsets layout(const reg_params* p) {
     for (int i = 0; i < NFIELD; ++i) o.fld[i] = L.take(nn * ts);
     o.B = L.take(2 * nn * ts);
     o.Bt = L.take(2 * nn * ts);
+    const size_t s64 = p->precision == REG_FP64 ? 0 : nn * 8;
+    o.mT64 = L.take(s64);
+    o.mR64 = L.take(s64);
+    for (int i = 0; i < 5; ++i) o.sfld[i] = L.take(s64);
     o.tw1f = L.take(p->n1 * 8);
     o.tw2f = L.take(p->n2 * 8);
     o.tw1d = L.take(p->n1 * 16);
@@ -150,6 +155,10 @@ struct reg_problem {
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
     double* pcg(int i) const { return at<double>(o.pcg[i]); }
+    // FP64 state solve: template, reference and scratch fields (the transport buffers in FP64 mode)
+    double* sT() const { return at<double>(f64 ? o.mT : o.mT64); }
+    double* sR() const { return at<double>(f64 ? o.mR : o.mR64); }
+    double* sF(int i) const { return at<double>(f64 ? o.fld[i] : o.sfld[i]); }
     double* scal() const { return at<double>(o.scal); }
     double* partial() const { return at<double>(o.partial); }
     cpx<double>* spec() const { return at<cpx<double>>(o.spec); }
@@ -205,41 +214,53 @@ reg_status pass(const reg_problem* P, int op, int axis, const PassArgs<T>& a) {
 }
 
 // ---- state solve forward (eq. (state-eq-elim)) ----------------------------------------------------
-// v: transport-precision velocity (2 nn).  store: write G_j, G*_j (and G_nt in paper mode) to the
-// trajectory.  m1: output field.  lam1 (nullable): lam(1) = m_R - m_1.
+// Always in FP64: the stored gradients feed every later matvec, and FP32 round-off in the state is
+// amplified by the spectral derivative (and by Heun's growth at high wavenumbers) into G = grad m.
+// v: FP64 velocity (2 nn).  store: write G_j, G*_j (and G_nt in paper mode) to the trajectory in the
+// transport precision T.  m1: FP64 output field.  lam1 (nullable): lam(1) = m_R - m_1 in precision T.
 template <typename T>
-reg_status state_forward(reg_problem* P, const T* v, bool store, T* m1, T* lam1) {
+void set_gout(PassArgs<double>& a, T* g) {
+    if constexpr (sizeof(T) == 8) a.GOUT = reinterpret_cast<double*>(g);
+    else a.GOUTF = reinterpret_cast<float*>(g);
+}
+
+template <typename T>
+reg_status state_forward(reg_problem* P, const double* v, bool store, double* m1, T* lam1) {
     TV<T> tv{P};
     const long nn = P->nn;
-    const T* cur = tv.mT();
-    T* Fa = tv.F(0);
-    T* Fb = tv.F(3);
-    T* Fp = tv.F(1);
-    T* Fs = tv.F(2);
+    const double* cur = P->sT();
+    double* Fa = P->sF(0);
+    double* Fb = P->sF(3);
+    double* Fp = P->sF(1);
+    double* Fs = P->sF(2);
     for (int j = 0; j < P->nt; ++j) {
         const bool last = j == P->nt - 1;
-        T* nxt = last ? m1 : (cur == Fa ? Fb : Fa);
+        double* nxt = last ? m1 : (cur == Fa ? Fb : Fa);
         T* G = store ? tv.G(slot_G(P, j)) : nullptr;
         T* Gs = store ? tv.G(slot_Gs(P, j)) : nullptr;
-        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
-        r.U = cur; r.V = v + nn; r.OUT = Fp; r.GOUT = G;
-        CKS(pass<T>(P, OP_S1, 2, r));
-        c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs; c.GOUT = G;
-        CKS(pass<T>(P, OP_S1, 1, c));
-        r = base_args<T>(P, 2); c = base_args<T>(P, 1);
-        r.U = Fs; r.X = cur; r.V = v + nn; r.OUT = Fp; r.GOUT = Gs;
-        CKS(pass<T>(P, OP_S2, 2, r));
-        c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt; c.GOUT = Gs;
-        if (last) { c.OUT2 = lam1; c.MR = tv.mR(); }
-        CKS(pass<T>(P, OP_S2, 1, c));
+        PassArgs<double> r = base_args<double>(P, 2), c = base_args<double>(P, 1);
+        r.U = cur; r.V = v + nn; r.OUT = Fp; set_gout<T>(r, G);
+        CKS(pass<double>(P, OP_S1, 2, r));
+        c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs; set_gout<T>(c, G);
+        CKS(pass<double>(P, OP_S1, 1, c));
+        r = base_args<double>(P, 2); c = base_args<double>(P, 1);
+        r.U = Fs; r.X = cur; r.V = v + nn; r.OUT = Fp; set_gout<T>(r, Gs);
+        CKS(pass<double>(P, OP_S2, 2, r));
+        c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt; set_gout<T>(c, Gs);
+        if (last && lam1) {
+            c.MR = P->sR();
+            if constexpr (sizeof(T) == 8) c.OUT2 = reinterpret_cast<double*>(lam1);
+            else c.OUT2F = reinterpret_cast<float*>(lam1);
+        }
+        CKS(pass<double>(P, OP_S2, 1, c));
         cur = nxt;
     }
     if (store && P->p.adjoint == REG_ADJ_PAPER) {   // G_{n_t} for the trapezoid end point
-        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
-        r.U = m1; r.GOUT = tv.G(slot_G(P, P->nt));
-        CKS(pass<T>(P, OP_GRAD, 2, r));
-        c.U = m1; c.GOUT = tv.G(slot_G(P, P->nt));
-        CKS(pass<T>(P, OP_GRAD, 1, c));
+        PassArgs<double> r = base_args<double>(P, 2), c = base_args<double>(P, 1);
+        r.U = m1; set_gout<T>(r, tv.G(slot_G(P, P->nt)));
+        CKS(pass<double>(P, OP_GRAD, 2, r));
+        c.U = m1; set_gout<T>(c, tv.G(slot_G(P, P->nt)));
+        CKS(pass<double>(P, OP_GRAD, 1, c));
     }
     return REG_OK;
 }
@@ -383,10 +404,8 @@ reg_status reg_terms(reg_problem* P, const double* v64, double* rv, double* rw) 
     return REG_OK;
 }
 
-template <typename T>
-reg_status data_term(reg_problem* P, const T* m1, double* out) {
-    TV<T> tv{P};
-    CK(launch_sqdiff<T>(tv.mR(), m1, P->nn, P->partial(), P->scal(), P->stream));
+reg_status data_term(reg_problem* P, const double* m1, double* out) {
+    CK(launch_sqdiff<double>(P->sR(), m1, P->nn, P->partial(), P->scal(), P->stream));
     double s = 0;
     CKS(fetch(P, 1, &s));
     *out = P->h1h2 * s;
@@ -398,10 +417,10 @@ template <typename T>
 reg_status objective_t(reg_problem* P, const double* v, double* J, double* terms) {
     TV<T> tv{P};
     double* vp = P->at<double>(P->o.vtrial);
-    CKS(project<T>(P, v, vp, tv.vw()));
-    CKS(state_forward<T>(P, tv.vw(), false, tv.F(4), nullptr));
+    CKS(project<T>(P, v, vp, (T*)nullptr));
+    CKS(state_forward<T>(P, vp, false, P->sF(4), (T*)nullptr));
     double d = 0, rv = 0, rw = 0;
-    CKS(data_term<T>(P, tv.F(4), &d));
+    CKS(data_term(P, P->sF(4), &d));
     CKS(reg_terms(P, vp, &rv, &rw));
     *J = d + rv + rw;
     if (terms) { terms[0] = d; terms[1] = rv; terms[2] = rw; }
@@ -418,10 +437,10 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
     P->linearized = false;
     P->matvec_done = false;
     CKS(project<T>(P, v, v64, tv.vT()));
-    CKS(state_forward<T>(P, tv.vT(), true, tv.F(4), tv.F(5)));
+    CKS(state_forward<T>(P, v64, true, P->sF(4), tv.F(5)));
     double d = 0, rv = 0, rw = 0;
     if (Jout) {
-        CKS(data_term<T>(P, tv.F(4), &d));
+        CKS(data_term(P, P->sF(4), &d));
         CKS(reg_terms(P, v64, &rv, &rw));
     }
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(5), tv.B()));
@@ -746,6 +765,8 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
     } else {
         CKC(launch_convert<float>(P->nn, m_T, P->at<float>(o.mT), P->stream));
         CKC(launch_convert<float>(P->nn, m_R, P->at<float>(o.mR), P->stream));
+        CKC(launch_convert<double>(P->nn, m_T, P->at<double>(o.mT64), P->stream));
+        CKC(launch_convert<double>(P->nn, m_R, P->at<double>(o.mR64), P->stream));
     }
     // inputs must be finite
     {
@@ -775,17 +796,15 @@ reg_status reg_set_stream(reg_problem* h, void* hip_stream) {
 
 reg_status reg_state_forward(reg_problem* h, const double* v, double* m1) {
     if (!h || !v || !m1) return fail(REG_EINVAL, "NULL argument");
+    double* vp = h->at<double>(h->o.vtrial);
     if (h->f64) {
-        TV<double> tv{h};
-        CKS(project<double>(h, v, h->at<double>(h->o.vtrial), tv.vw()));
-        CKS(state_forward<double>(h, tv.vw(), false, tv.F(4), nullptr));
-        CK(hipMemcpyAsync(m1, tv.F(4), h->nn * 8, hipMemcpyDeviceToDevice, h->stream));
+        CKS(project<double>(h, v, vp, (double*)nullptr));
+        CKS(state_forward<double>(h, vp, false, h->sF(4), (double*)nullptr));
     } else {
-        TV<float> tv{h};
-        CKS(project<float>(h, v, h->at<double>(h->o.vtrial), tv.vw()));
-        CKS(state_forward<float>(h, tv.vw(), false, tv.F(4), nullptr));
-        CK(launch_widen<float>(h->nn, tv.F(4), m1, h->stream));
+        CKS(project<float>(h, v, vp, (float*)nullptr));
+        CKS(state_forward<float>(h, vp, false, h->sF(4), (float*)nullptr));
     }
+    CK(hipMemcpyAsync(m1, h->sF(4), h->nn * 8, hipMemcpyDeviceToDevice, h->stream));
     return REG_OK;
 }
 

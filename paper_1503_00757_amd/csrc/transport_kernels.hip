@@ -54,11 +54,13 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs<T>& a, long idx, T 
     const int gcomp = (AXIS == 2) ? 1 : 0;   // which gradient component this axis produces
     if constexpr (OP == OP_S1) {
         if (a.GOUT) a.GOUT[gcomp * nn + idx] = d;
+        if (a.GOUTF) a.GOUTF[gcomp * nn + idx] = (float)d;
         const T v = a.V[idx];
         if constexpr (AXIS == 2) a.OUT[idx] = uu - h * v * d;          // P = m_j - h v2 d2 m_j
         else a.OUT[idx] = a.X[idx] - h * v * d;                        // m* = P - h v1 d1 m_j
     } else if constexpr (OP == OP_S2) {
         if (a.GOUT) a.GOUT[gcomp * nn + idx] = d;
+        if (a.GOUTF) a.GOUTF[gcomp * nn + idx] = (float)d;
         const T v = a.V[idx];
         if constexpr (AXIS == 2) {
             a.OUT[idx] = T(0.5) * (a.X[idx] + uu) - hh * v * d;      // Q
@@ -66,6 +68,7 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs<T>& a, long idx, T 
             const T o = a.X[idx] - hh * v * d;                         // m_{j+1}
             a.OUT[idx] = o;
             if (a.OUT2) a.OUT2[idx] = a.MR[idx] - o;                   // lam(1) = m_R - m_1
+            if (a.OUT2F) a.OUT2F[idx] = (float)(a.MR[idx] - o);
         }
     } else if constexpr (OP == OP_A1) {
         if constexpr (AXIS == 2) {
@@ -120,7 +123,8 @@ __device__ __forceinline__ void pass_epilogue(const PassArgs<T>& a, long idx, T 
             a.OUT[idx] = (a.flags & F_NEG) ? -o : o;                   // lam~(1) = -m~(1)
         }
     } else if constexpr (OP == OP_GRAD) {
-        a.GOUT[gcomp * nn + idx] = d;
+        if (a.GOUT) a.GOUT[gcomp * nn + idx] = d;
+        if (a.GOUTF) a.GOUTF[gcomp * nn + idx] = (float)d;
     }
 }
 
