@@ -149,14 +149,29 @@ typedef struct {
 reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
                      reg_solve_stats* stats_host);
 
-/* Measurement hook: launch one of the library's passes `reps` times back to back on the problem's
- * stream at the current linearisation point and report the mean device time per launch (hipEvents
- * around the launches) and the compulsory HBM bytes that pass moves per launch.
- * which: 0 incremental-adjoint stage-2 row pass (the busiest pass), 1 incremental-state stage-2 row
- * pass, 2 incremental-adjoint stage-2 column pass, 3 incremental-state stage-2 column pass.
- * Synchronises the stream. */
+/* Measurement hook: launch one of the eight passes of a Hessian-matvec time step `reps` times back
+ * to back on the problem's stream at the current linearisation point and report the mean device
+ * time per launch (hipEvents around the launches) and the compulsory HBM bytes of one launch (each
+ * operand field read once, each result written once).  which: 0 incremental-adjoint stage-2 row
+ * pass (the busiest pass), 1 incremental-state stage-2 row pass, 2 incremental-adjoint stage-2
+ * column pass, 3 incremental-state stage-2 column pass, 4..7 the stage-1 passes in the same order.
+ * REG_ESTATE before the first reg_hessian_matvec.  Synchronises the stream. */
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms_per_launch_host,
                          double* bytes_per_launch_host);
+
+/* Launch-shape autotuner for the FP32 transport passes (elements per thread of the register FFT and
+ * transforms per workgroup): times every available shape of the eight matvec passes `reps` times
+ * at the current linearisation point, keeps the fastest per pass in the handle, and writes a JSON
+ * report of the timings (microseconds per launch) and the choice to `report` (nullable, truncated to
+ * report_bytes).  Results are identical for every shape; only speed differs.  REG_ESTATE before the
+ * first reg_hessian_matvec.  FP64 problems use fixed shapes (no-op).  Synchronises the stream. */
+reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes);
+
+/* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): variants[0..6] are
+ * the row-pass shapes and variants[7..13] the column-pass shapes of the pass ops
+ * {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental state 2, gradient}.
+ * count must be 14. */
+reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count);
 
 /* Thread-local description of the last error (never NULL). */
 const char* reg_last_error(void);

@@ -108,6 +108,143 @@ __device__ __forceinline__ void fft4(cpx<T> (&x)[4], cpx<T>* __restrict__ lds0,
     }
 }
 
+// ---- mixed-radix FFT with E elements per thread ------------------------------------------------
+// T = N/E threads per transform; thread t holds elements t + T m (m = 0..E-1) on entry and on exit.
+// Stages have radix E while the remaining factor allows, then one stage of the remaining radix
+// (2, 4 or 8).  In a stage of radix R each thread runs B = E/R butterflies j = t + T b; input r of
+// butterfly j is element j + r N/R, i.e. register b + B r, so every stage reads the thread's own
+// register set and only the exchanges between stages go through LDS (one barrier each).
+template <int M>
+struct RootTab;   // exp(-2 pi i m / M), m < M, for the internal twiddles of the radix-8/16 kernels
+template <>
+struct RootTab<8> {
+    static constexpr double c[8] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
+                                    -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440};
+    static constexpr double s[8] = {0.0, -0.70710678118654752440, -1.0, -0.70710678118654752440,
+                                    0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440};
+};
+template <>
+struct RootTab<16> {
+    static constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                     0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                     -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                                     0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+    static constexpr double s[16] = {0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                     -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                                     0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                     1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+};
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4v(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+    const cpx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    const cpx<T> s13 = cadd(a1, a3), d13 = cmi<T, INV>(csub(a1, a3));
+    a0 = cadd(s02, s13);
+    a2 = csub(s02, s13);
+    a1 = cadd(d02, d13);
+    a3 = csub(d02, d13);
+}
+
+// In-place DFT of R points (forward: exp(-2 pi i n k / R); inverse: conjugate).
+// R = 8 and 16 are split as R = 4 * (R/4): n = (R/4) n1 + n2, k = k1 + 4 k2,
+// X[k1 + 4 k2] = sum_{n2} W_{R/4}^{n2 k2} W_R^{n2 k1} sum_{n1} W_4^{n1 k1} x[(R/4) n1 + n2].
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cpx<T> (&a)[R]) {
+    if constexpr (R == 2) {
+        const cpx<T> t0 = a[0];
+        a[0] = cadd(t0, a[1]);
+        a[1] = csub(t0, a[1]);
+    } else if constexpr (R == 4) {
+        dft4v<T, INV>(a[0], a[1], a[2], a[3]);
+    } else {
+        constexpr int Q2 = R / 4;
+        cpx<T> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < Q2; ++n2) {
+            cpx<T> b0 = a[n2], b1 = a[Q2 + n2], b2 = a[2 * Q2 + n2], b3 = a[3 * Q2 + n2];
+            dft4v<T, INV>(b0, b1, b2, b3);
+            const cpx<T> bb[4] = {b0, b1, b2, b3};
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) {
+                const int m = (n2 * k1) % R;
+                const cpx<T> w = {T(RootTab<R>::c[m]), T(RootTab<R>::s[m])};
+                y[n2 * 4 + k1] = (m == 0) ? bb[k1] : ctw<T, INV>(bb[k1], w);
+            }
+        }
+        // DFT of length Q2 over n2 for each k1; result index k1 + 4 k2
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            if constexpr (Q2 == 2) {
+                const cpx<T> u0 = y[0 * 4 + k1], u1 = y[1 * 4 + k1];
+                a[k1] = cadd(u0, u1);
+                a[k1 + 4] = csub(u0, u1);
+            } else {
+                cpx<T> u0 = y[0 * 4 + k1], u1 = y[1 * 4 + k1], u2 = y[2 * 4 + k1], u3 = y[3 * 4 + k1];
+                dft4v<T, INV>(u0, u1, u2, u3);
+                a[k1] = u0;
+                a[k1 + 4] = u1;
+                a[k1 + 8] = u2;
+                a[k1 + 12] = u3;
+            }
+        }
+    }
+}
+
+template <typename T, int N, int E, int R, int NS, bool LAST, bool INV>
+__device__ __forceinline__ void fft_stage(cpx<T> (&x)[E], cpx<T>* __restrict__ o, int t,
+                                          const cpx<T>* __restrict__ tw) {
+    constexpr int TT = N / E, B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + TT * b;
+        const int k = j & (NS - 1);
+        cpx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = x[b + B * r];
+        if constexpr (NS > 1) {
+            constexpr int step = N / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[r] = ctw<T, INV>(a[r], tw[(r * k * step) & (N - 1)]);
+        }
+        dftR<T, R, INV>(a);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[b + B * r] = a[r];
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) o[lpad(base + r * NS)] = a[r];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = o[lpad(t + TT * m)];
+    }
+}
+
+template <typename T, int N, int E, int NS, bool INV>
+__device__ __forceinline__ void fft_stages(cpx<T> (&x)[E], cpx<T>* __restrict__ lds0, cpx<T>* __restrict__ lds1,
+                                           int t, const cpx<T>* __restrict__ tw, int& buf) {
+    constexpr int REM = N / NS;
+    constexpr int R = REM >= E ? E : REM;
+    constexpr bool LAST = (NS * R == N);
+    fft_stage<T, N, E, R, NS, LAST, INV>(x, buf ? lds1 : lds0, t, tw);
+    if constexpr (!LAST) {
+        buf ^= 1;
+        fft_stages<T, N, E, NS * R, INV>(x, lds0, lds1, t, tw, buf);
+    }
+}
+
+// Length-N FFT, E elements per thread (E in {4, 8, 16}, E <= N/2); see fft4 for `buf`.
+template <typename T, int N, int E, bool INV>
+__device__ __forceinline__ void fftE(cpx<T> (&x)[E], cpx<T>* __restrict__ lds0, cpx<T>* __restrict__ lds1, int t,
+                                     const cpx<T>* __restrict__ tw, int& buf) {
+    static_assert(E == 4 || E == 8 || E == 16, "E");
+    static_assert(N >= 2 * E, "N >= 2E");
+    fft_stages<T, N, E, 1, INV>(x, lds0, lds1, t, tw, buf);
+}
+
 // Signed integer wavenumber of DFT index e on a length-N axis, with the Nyquist index mapped to 0.
 template <int N>
 __device__ __forceinline__ int kwave(int e) {

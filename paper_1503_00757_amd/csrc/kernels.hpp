@@ -36,8 +36,11 @@ struct PassArgs {
     const cpx<T>* tw;        // twiddles of the pass axis length
 };
 
+constexpr int NUM_ROW_VARIANTS = 4;
+constexpr int NUM_COL_VARIANTS = 7;
+// var: launch-shape variant of the pass (0 = default; see transport_kernels.hpp)
 template <typename T>
-hipError_t launch_pass(int op, int axis, const PassArgs<T>& a, hipStream_t s);
+hipError_t launch_pass(int op, int axis, int var, const PassArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_body_end(long nn, T w, const T* lam, const T* G, T* B, hipStream_t s);
 

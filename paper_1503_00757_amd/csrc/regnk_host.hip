@@ -151,6 +151,7 @@ struct reg_problem {
     bool matvec_done = false;
     SpecParams sp;
     double h1h2;
+    int var[2][7] = {};   // launch-shape variant per [axis: 0 column, 1 row][pass op] (FP32 passes)
 
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
@@ -209,7 +210,7 @@ PassArgs<T> base_args(const reg_problem* P, int axis) {
 
 template <typename T>
 reg_status pass(const reg_problem* P, int op, int axis, const PassArgs<T>& a) {
-    CK(launch_pass<T>(op, axis, a, P->stream));
+    CK(launch_pass<T>(op, axis, P->var[axis == 2 ? 1 : 0][op], a, P->stream));
     return REG_OK;
 }
 
@@ -639,50 +640,73 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
     return REG_OK;
 }
 
-// ---- measurement hook ---------------------------------------------------------------------------
+// ---- measurement hook and autotuner ------------------------------------------------------------
+// The eight passes of one matvec time step (DTO quadrature unless the problem uses the paper's),
+// set up on live buffers at a middle time step: which = 0 A2 row, 1 I2 row, 2 A2 column,
+// 3 I2 column, 4 A1 row, 5 I1 row, 6 A1 column, 7 I1 column.  Outputs go to a scratch field (the
+// body-force accumulator of the A2 row pass is updated in place; every matvec rewrites it).
+struct PassSpec {
+    int op, axis;
+    double fields;   // scalar fields of compulsory HBM traffic per launch (reads + writes)
+};
+
 template <typename T>
-reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes) {
+reg_status pass_spec(reg_problem* P, int which, PassArgs<T>& a, PassSpec& ps) {
     TV<T> tv{P};
-    if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
     const long nn = P->nn;
     const int j = P->nt > 1 ? P->nt / 2 : 0;
     const bool paper = P->p.adjoint == REG_ADJ_PAPER;
-    PassArgs<T> a;
-    int op, axis;
-    double fields;
-    switch (which) {
-        case 0:   // incremental adjoint, stage 2, row pass (body-force accumulation)
-            a = base_args<T>(P, 2);
-            a.U = tv.F(2); a.X = tv.F(0); a.V = tv.vT() + nn; a.OUT = tv.F(1);
-            if (!paper) { a.B = tv.Bt(); a.G = tv.G(slot_G(P, j)); a.G2 = tv.G(slot_Gs(P, j)); a.bw = T(0.5 / P->nt); }
-            op = OP_A2; axis = 2; fields = paper ? 4 : 12;
-            break;
-        case 1:   // incremental state, stage 2, row pass
-            a = base_args<T>(P, 2);
-            a.U = tv.F(2); a.X = tv.F(0); a.V = tv.vT() + nn; a.VT = tv.vtT();
-            a.G = paper ? tv.G(slot_G(P, j + 1)) : tv.G(slot_Gs(P, j)); a.OUT = tv.F(1);
-            op = OP_I2; axis = 2; fields = 8;
-            break;
-        case 2:   // incremental adjoint, stage 2, column pass
-            a = base_args<T>(P, 1);
-            a.U = tv.F(2); a.V = tv.vT(); a.X = tv.F(1); a.OUT = tv.F(6);
-            op = OP_A2; axis = 1; fields = 4;
-            break;
-        case 3:   // incremental state, stage 2, column pass
-            a = base_args<T>(P, 1);
-            a.U = tv.F(2); a.V = tv.vT(); a.X = tv.F(1); a.OUT = tv.F(6);
-            op = OP_I2; axis = 1; fields = 4;
-            break;
-        default:
-            return fail(REG_EINVAL, "unknown pass %d", which);
+    static const int ops[8] = {OP_A2, OP_I2, OP_A2, OP_I2, OP_A1, OP_I1, OP_A1, OP_I1};
+    if (which < 0 || which > 7) return fail(REG_EINVAL, "unknown pass %d", which);
+    ps.op = ops[which];
+    ps.axis = (which == 2 || which == 3 || which == 6 || which == 7) ? 1 : 2;
+    a = base_args<T>(P, ps.axis);
+    a.OUT = tv.F(6);
+    const T* vax = ps.axis == 2 ? tv.vT() + nn : tv.vT();
+    a.V = vax;
+    if (ps.axis == 1) {   // every column pass: U, V, X -> OUT
+        a.U = (ps.op == OP_A2 || ps.op == OP_I2) ? tv.F(2) : tv.F(0);
+        a.X = tv.F(1);
+        ps.fields = 4;
+        return REG_OK;
     }
-    if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
+    switch (ps.op) {
+        case OP_A2:
+            a.U = tv.F(2); a.X = tv.F(0);
+            if (!paper) { a.B = tv.Bt(); a.G = tv.G(slot_G(P, j)); a.G2 = tv.G(slot_Gs(P, j)); a.bw = T(0.5 / P->nt); }
+            ps.fields = paper ? 4 : 12;
+            break;
+        case OP_I2:
+            a.U = tv.F(2); a.X = tv.F(0); a.VT = tv.vtT();
+            a.G = paper ? tv.G(slot_G(P, j + 1)) : tv.G(slot_Gs(P, j));
+            ps.fields = 8;
+            break;
+        case OP_A1:
+            a.U = tv.F(0);
+            if (paper) { a.B = tv.Bt(); a.G = tv.G(slot_G(P, j + 1)); a.bw = T(1.0 / P->nt); }
+            ps.fields = paper ? 9 : 3;
+            break;
+        default:   // OP_I1
+            a.U = tv.F(0); a.VT = tv.vtT(); a.G = tv.G(slot_G(P, j));
+            ps.fields = 7;
+            break;
+    }
+    return REG_OK;
+}
+
+template <typename T>
+reg_status time_launches(reg_problem* P, int op, int axis, int var, const PassArgs<T>& a, int reps, double* ms) {
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    CKS(pass<T>(P, op, axis, a));   // warm-up
+    hipError_t err = launch_pass<T>(op, axis, var, a, P->stream);   // warm-up (and validity check)
+    if (err != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(REG_EINVAL, "variant %d not available: %s", var, hipGetErrorString(err));
+    }
     CK(hipEventRecord(e0, P->stream));
-    for (int i = 0; i < reps; ++i) CKS(pass<T>(P, op, axis, a));
+    for (int i = 0; i < reps; ++i) CK(launch_pass<T>(op, axis, var, a, P->stream));
     CK(hipEventRecord(e1, P->stream));
     CK(hipEventSynchronize(e1));
     float t = 0;
@@ -690,7 +714,63 @@ reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* 
     CK(hipEventDestroy(e0));
     CK(hipEventDestroy(e1));
     *ms = (double)t / reps;
-    *bytes = fields * (double)nn * sizeof(T);
+    return REG_OK;
+}
+
+template <typename T>
+reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes) {
+    if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
+    if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
+    PassArgs<T> a;
+    PassSpec ps;
+    CKS(pass_spec<T>(P, which, a, ps));
+    CKS(time_launches<T>(P, ps.op, ps.axis, P->var[ps.axis == 2 ? 1 : 0][ps.op], a, reps, ms));
+    *bytes = ps.fields * (double)P->nn * sizeof(T);
+    return REG_OK;
+}
+
+const char* op_name(int op) {
+    static const char* n[7] = {"S1", "S2", "A1", "A2", "I1", "I2", "GRAD"};
+    return n[op];
+}
+
+reg_status autotune_f32(reg_problem* P, int reps, char* report, size_t cap) {
+    if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before tuning");
+    if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
+    std::string js = "{";
+    for (int which = 0; which < 8; ++which) {
+        PassArgs<float> a;
+        PassSpec ps;
+        CKS(pass_spec<float>(P, which, a, ps));
+        const int ai = ps.axis == 2 ? 1 : 0;
+        const int nv = ps.axis == 2 ? NUM_ROW_VARIANTS : NUM_COL_VARIANTS;
+        int best = P->var[ai][ps.op];
+        double best_ms = 1e30;
+        char buf[96];
+        snprintf(buf, sizeof buf, "%s\"%s_%s\": [", which ? ", " : "", op_name(ps.op), ps.axis == 2 ? "row" : "col");
+        js += buf;
+        bool firstv = true;
+        for (int v = 0; v < nv; ++v) {
+            double ms = 0;
+            if (time_launches<float>(P, ps.op, ps.axis, v, a, reps, &ms) != REG_OK) continue;
+            snprintf(buf, sizeof buf, "%s[%d, %.3f]", firstv ? "" : ", ", v, ms * 1e3);
+            js += buf;
+            firstv = false;
+            if (ms < best_ms) { best_ms = ms; best = v; }
+        }
+        js += "]";
+        P->var[ai][ps.op] = best;
+    }
+    js += ", \"chosen\": {\"row\": [";
+    for (int op = 0; op < 7; ++op) js += std::to_string(P->var[1][op]) + (op < 6 ? ", " : "");
+    js += "], \"col\": [";
+    for (int op = 0; op < 7; ++op) js += std::to_string(P->var[0][op]) + (op < 6 ? ", " : "");
+    js += "]}}";
+    g_err = "no error";
+    if (report && cap > 0) {
+        strncpy(report, js.c_str(), cap - 1);
+        report[cap - 1] = 0;
+    }
     return REG_OK;
 }
 
@@ -866,6 +946,33 @@ reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out, 
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes) {
     if (!h || !ms || !bytes) return fail(REG_EINVAL, "NULL argument");
     return DISPATCH(h, time_pass_t<float>(h, which, reps, ms, bytes), time_pass_t<double>(h, which, reps, ms, bytes));
+}
+
+reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes) {
+    if (!h) return fail(REG_EINVAL, "NULL handle");
+    if (h->f64) {   // FP64 passes use one fixed shape
+        if (report && report_bytes > 0) {
+            strncpy(report, "{\"fp64\": \"fixed shapes\"}", report_bytes - 1);
+            report[report_bytes - 1] = 0;
+        }
+        return REG_OK;
+    }
+    return autotune_f32(h, reps, report, report_bytes);
+}
+
+reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count) {
+    if (!h || !variants) return fail(REG_EINVAL, "NULL argument");
+    if (count != 14) return fail(REG_EINVAL, "count must be 14 (7 row variants, then 7 column variants)");
+    for (int op = 0; op < 7; ++op) {
+        if (variants[op] < 0 || variants[op] >= NUM_ROW_VARIANTS || variants[7 + op] < 0 ||
+            variants[7 + op] >= NUM_COL_VARIANTS)
+            return fail(REG_EINVAL, "variant index out of range");
+    }
+    for (int op = 0; op < 7; ++op) {
+        h->var[1][op] = variants[op];
+        h->var[0][op] = variants[7 + op];
+    }
+    return REG_OK;
 }
 
 }  // extern "C"

@@ -76,11 +76,13 @@ def lib():
         L.reg_pcg.argtypes = [vp, vp, d, i32, i32, vp, C.POINTER(i32), dp]
         L.reg_solve.argtypes = [vp, C.POINTER(RegSolveOpts), vp, C.POINTER(RegSolveStats)]
         L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp]
+        L.reg_autotune.argtypes = [vp, i32, C.c_char_p, sz]
+        L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
         L.reg_last_error.argtypes = []
         L.reg_last_error.restype = C.c_char_p
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
-                     "reg_solve", "reg_time_pass"):
+                     "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -160,3 +162,14 @@ def reg_time_pass(h, which: int, reps: int):
     by = C.c_double(0)
     _check(lib().reg_time_pass(h, which, reps, C.byref(ms), C.byref(by)))
     return ms.value, by.value
+
+
+def reg_autotune(h, reps: int = 50) -> str:
+    buf = C.create_string_buffer(8192)
+    _check(lib().reg_autotune(h, reps, buf, len(buf)))
+    return buf.value.decode()
+
+
+def reg_set_pass_variants(h, variants):
+    arr = (C.c_int32 * len(variants))(*variants)
+    _check(lib().reg_set_pass_variants(h, arr, len(variants)))

@@ -105,3 +105,11 @@ class Problem:
 
     def time_pass(self, which, reps=100):
         return ffi.reg_time_pass(self.h, which, reps)
+
+    def autotune(self, reps=50):
+        """Pick the fastest launch shape of each FP32 transport pass; returns the JSON timing report."""
+        import json
+        return json.loads(ffi.reg_autotune(self.h, reps))
+
+    def set_pass_variants(self, variants):
+        ffi.reg_set_pass_variants(self.h, list(variants))

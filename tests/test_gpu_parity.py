@@ -146,3 +146,29 @@ def test_constant_template_hessian_is_regulariser(problems):
         assert rel(H, expect) < 1e-9   # b~ is FP32 round-off of the derivative of a constant
     finally:
         P.close()
+
+
+@pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "128x32_nt3_H1_none_fp32", "2048x16_nt128_H1_none_fp32"])
+def test_every_launch_shape_matches_oracle(problems, name):
+    """The autotuner may pick any launch shape (elements per thread, transforms per block): every one
+    must give an oracle-parity matvec; the tuned choice must too."""
+    import paper_1503_00757_amd as R
+    case = CASES[name]
+    P = get(problems, name)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    ref = oracle_results(case)
+    P.gradient(dev(vlin), want_J=False)
+    tol = max(case.tol, 10 * ref["sens_H"])
+    for vr in range(4):
+        for vc in range(7):
+            P.set_pass_variants([vr] * 7 + [vc] * 7)
+            H = P.hessian_matvec(dev(vt))
+            assert rel(host(H), ref["H"]) < tol, (vr, vc)
+    P.set_pass_variants([0] * 14)
+    rep = P.autotune(reps=5)
+    assert "chosen" in rep
+    H = P.hessian_matvec(dev(vt))
+    assert rel(host(H), ref["H"]) < tol
+    P.set_pass_variants([0] * 14)
+    with pytest.raises(R.RegError):
+        P.set_pass_variants([9] * 14)
