@@ -77,10 +77,12 @@ def bench_matvec(P, vt, reps):
 
 
 def roofline(P, reps=200):
-    """Dominant kernel: the incremental-adjoint stage-2 row pass (reads 9 and writes 3 fields)."""
+    """Dominant kernel: the fused GN incremental-adjoint stage-2 launch (stage_fused_kernel<..., OP_A2>):
+    row blocks read 10 and write 3 fields (incl. the body-force accumulation), column blocks read 3
+    and write 1."""
     ms, by = P.time_pass(0, reps)
     achieved = by / (ms * 1e-3) / 1e9
-    return {"kernel": "row_pass_kernel<float,N,1,OP_A2> (incremental adjoint stage 2, row pass)",
+    return {"kernel": "stage_fused_kernel<float, N, ..., OP_A2> (GN incremental adjoint, RK2 stage 2)",
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": by, "us_per_launch": round(ms * 1e3, 3)}

@@ -149,28 +149,28 @@ typedef struct {
 reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
                      reg_solve_stats* stats_host);
 
-/* Measurement hook: launch one of the eight passes of a Hessian-matvec time step `reps` times back
- * to back on the problem's stream at the current linearisation point and report the mean device
- * time per launch (hipEvents around the launches) and the compulsory HBM bytes of one launch (each
- * operand field read once, each result written once).  which: 0 incremental-adjoint stage-2 row
- * pass (the busiest pass), 1 incremental-state stage-2 row pass, 2 incremental-adjoint stage-2
- * column pass, 3 incremental-state stage-2 column pass, 4..7 the stage-1 passes in the same order.
+/* Measurement hook: launch one of the four RK2-stage launches of a Hessian-matvec time step `reps`
+ * times back to back on the problem's stream at the current linearisation point and report the
+ * mean device time per launch (hipEvents around the launches, best of three batches) and the
+ * compulsory HBM bytes of one launch (each operand field read once, each result written once).
+ * which: 0 GN incremental-adjoint stage 2 (the busiest launch: it also accumulates the body force),
+ * 1 incremental-state stage 2, 2 GN incremental-adjoint stage 1, 3 incremental-state stage 1.
  * REG_ESTATE before the first reg_hessian_matvec.  Synchronises the stream. */
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms_per_launch_host,
                          double* bytes_per_launch_host);
 
-/* Launch-shape autotuner for the FP32 transport passes (elements per thread of the register FFT and
- * transforms per workgroup): times every available shape of the eight matvec passes `reps` times
- * at the current linearisation point, keeps the fastest per pass in the handle, and writes a JSON
- * report of the timings (microseconds per launch) and the choice to `report` (nullable, truncated to
- * report_bytes).  Results are identical for every shape; only speed differs.  REG_ESTATE before the
- * first reg_hessian_matvec.  FP64 problems use fixed shapes (no-op).  Synchronises the stream. */
+/* Launch-shape autotuner for the FP32 transport stages on square grids of 64+ points (elements per
+ * thread of the row and column register FFTs, threads per block): times every available shape of
+ * the four matvec stage launches `reps` times at the current linearisation point, keeps the fastest
+ * per stage in the handle, and writes a JSON report of the timings (microseconds per launch) and
+ * the choice to `report` (nullable, truncated to report_bytes).  Results are identical for every
+ * shape up to rounding; only speed differs.  REG_ESTATE before the first reg_hessian_matvec.  FP64
+ * problems use fixed shapes (no-op).  Synchronises the stream. */
 reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes);
 
-/* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): variants[0..6] are
- * the row-pass shapes and variants[7..13] the column-pass shapes of the pass ops
- * {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental state 2, gradient}.
- * count must be 14. */
+/* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): one shape index in
+ * [0, 8) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
+ * state 2, gradient}; count must be 7. */
 reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count);
 
 /* Thread-local description of the last error (never NULL). */

@@ -190,9 +190,45 @@ __device__ __forceinline__ void dftR(cpx<T> (&a)[R]) {
     }
 }
 
-template <typename T, int N, int E, int R, int NS, bool LAST, bool INV>
-__device__ __forceinline__ void fft_stage(cpx<T> (&x)[E], cpx<T>* __restrict__ o, int t,
-                                          const cpx<T>* __restrict__ tw) {
+// Twiddles of all stages are loaded into registers once (they serve the forward and the inverse
+// transform): stage (R, NS) needs W_{NS R}^{r k} for r = 1..R-1 and each of the thread's B
+// butterflies, k = (t + T b) mod NS; the first stage (NS = 1) needs none.
+template <int N, int E, int NS>
+constexpr int tw_count() {
+    constexpr int REM = N / NS;
+    constexpr int R = REM >= E ? E : REM;
+    constexpr int here = NS > 1 ? (R - 1) * (E / R) : 0;
+    if constexpr (NS * R == N) {
+        return here;
+    } else {
+        return here + tw_count<N, E, NS * R>();
+    }
+}
+template <int N, int E>
+constexpr int tw_regs() { return tw_count<N, E, 1>() > 0 ? tw_count<N, E, 1>() : 1; }
+
+template <typename T, int N, int E, int NS, int OFF, int NW>
+__device__ __forceinline__ void load_tw(cpx<T> (&W)[NW], int t, const cpx<T>* __restrict__ tw) {
+    constexpr int TT = N / E;
+    constexpr int REM = N / NS;
+    constexpr int R = REM >= E ? E : REM;
+    constexpr int B = E / R;
+    if constexpr (NS > 1) {
+        constexpr int step = N / (NS * R);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int k = (t + TT * b) & (NS - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) W[OFF + b * (R - 1) + (r - 1)] = tw[(r * k * step) & (N - 1)];
+        }
+    }
+    if constexpr (NS * R < N) {
+        load_tw<T, N, E, NS * R, OFF + (NS > 1 ? (R - 1) * B : 0), NW>(W, t, tw);
+    }
+}
+
+template <typename T, int N, int E, int R, int NS, bool LAST, bool INV, int OFF, int NW>
+__device__ __forceinline__ void fft_stage(cpx<T> (&x)[E], cpx<T>* __restrict__ o, int t, const cpx<T> (&W)[NW]) {
     constexpr int TT = N / E, B = E / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -202,9 +238,8 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&x)[E], cpx<T>* __restrict__ o
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r] = x[b + B * r];
         if constexpr (NS > 1) {
-            constexpr int step = N / (NS * R);
 #pragma unroll
-            for (int r = 1; r < R; ++r) a[r] = ctw<T, INV>(a[r], tw[(r * k * step) & (N - 1)]);
+            for (int r = 1; r < R; ++r) a[r] = ctw<T, INV>(a[r], W[OFF + b * (R - 1) + (r - 1)]);
         }
         dftR<T, R, INV>(a);
         if constexpr (LAST) {
@@ -223,26 +258,27 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&x)[E], cpx<T>* __restrict__ o
     }
 }
 
-template <typename T, int N, int E, int NS, bool INV>
+template <typename T, int N, int E, int NS, bool INV, int OFF, int NW>
 __device__ __forceinline__ void fft_stages(cpx<T> (&x)[E], cpx<T>* __restrict__ lds0, cpx<T>* __restrict__ lds1,
-                                           int t, const cpx<T>* __restrict__ tw, int& buf) {
+                                           int t, const cpx<T> (&W)[NW], int& buf) {
     constexpr int REM = N / NS;
     constexpr int R = REM >= E ? E : REM;
     constexpr bool LAST = (NS * R == N);
-    fft_stage<T, N, E, R, NS, LAST, INV>(x, buf ? lds1 : lds0, t, tw);
+    fft_stage<T, N, E, R, NS, LAST, INV, OFF, NW>(x, buf ? lds1 : lds0, t, W);
     if constexpr (!LAST) {
         buf ^= 1;
-        fft_stages<T, N, E, NS * R, INV>(x, lds0, lds1, t, tw, buf);
+        fft_stages<T, N, E, NS * R, INV, OFF + (NS > 1 ? (R - 1) * (E / R) : 0), NW>(x, lds0, lds1, t, W, buf);
     }
 }
 
-// Length-N FFT, E elements per thread (E in {4, 8, 16}, E <= N/2); see fft4 for `buf`.
-template <typename T, int N, int E, bool INV>
+// Length-N FFT, E elements per thread (E in {4, 8, 16}, E <= N/2); W from load_tw<T, N, E, 1, 0>;
+// see fft4 for `buf`.
+template <typename T, int N, int E, bool INV, int NW>
 __device__ __forceinline__ void fftE(cpx<T> (&x)[E], cpx<T>* __restrict__ lds0, cpx<T>* __restrict__ lds1, int t,
-                                     const cpx<T>* __restrict__ tw, int& buf) {
+                                     const cpx<T> (&W)[NW], int& buf) {
     static_assert(E == 4 || E == 8 || E == 16, "E");
     static_assert(N >= 2 * E, "N >= 2E");
-    fft_stages<T, N, E, 1, INV>(x, lds0, lds1, t, tw, buf);
+    fft_stages<T, N, E, 1, INV, 0, NW>(x, lds0, lds1, t, W, buf);
 }
 
 // Signed integer wavenumber of DFT index e on a length-N axis, with the Nyquist index mapped to 0.

@@ -9,40 +9,50 @@ namespace regnk {
 template <typename T>
 struct cpx;
 
-// Transport pass operations (see transport_kernels.hip for the formulas).
+// Transport stage operations (see transport_kernels.hpp for the formulas).
 enum PassOp { OP_S1 = 0, OP_S2, OP_A1, OP_A2, OP_I1, OP_I2, OP_GRAD };
 enum PassFlags { F_ZERO = 1, F_FIRST = 2, F_NEG = 4 };
 
+// One RK2 stage: input u = A + Bf (Bf nullable; negated with F_NEG; with F_ZERO u = -h v~ . G2).
+// Row blocks write ROUT (and UOUT = u, gradient component 1, body force); column blocks write COUT
+// (and gradient component 0).  The stage result is ROUT + COUT.
 template <typename T>
-struct PassArgs {
+struct StageArgs {
     int n1, n2;
     long nn;                 // n1 * n2
     T h;                     // time step 1/n_t
     T bw;                    // body-force quadrature weight
     int flags;
-    const T* U;              // field whose derivative the pass takes (times V for the adjoint ops)
-    const T* V;              // velocity component of the pass axis (v2 rows, v1 columns)
-    const T* X;              // second field (m_j, l_{j+1}, or the row-pass partial result)
+    const T* A;
+    const T* Bf;
+    const T* V1;             // velocity component 1 (column transforms)
+    const T* V2;             // velocity component 2 (row transforms)
+    const T* X;              // previous-stage field for the RK2 combination (m_j, l_{j+1}, m~_j)
     const T* VT;             // v~ (vector field)
     const T* G;              // stored gradient (vector field)
     const T* G2;             // second stored gradient (vector field)
-    const T* MR;             // reference image
-    T* OUT;                  // output field
-    T* OUT2;                 // second output field (lam(1) = m_R - m_1)
-    T* GOUT;                 // gradient output (vector field) of the state passes
+    T* ROUT;
+    T* UOUT;
+    T* COUT;
+    T* GOUT;                 // grad m output of the state stages (vector field)
     float* GOUTF;            // same, rounded to FP32 (FP64 state solve feeding an FP32 trajectory)
-    float* OUT2F;            // lam(1) rounded to FP32
     T* B;                    // body-force accumulator (vector field)
-    const cpx<T>* tw;        // twiddles of the pass axis length
+    const cpx<T>* tw1;       // twiddles of length n1 (column transforms)
+    const cpx<T>* tw2;       // twiddles of length n2 (row transforms)
 };
 
-constexpr int NUM_ROW_VARIANTS = 4;
-constexpr int NUM_COL_VARIANTS = 7;
-// var: launch-shape variant of the pass (0 = default; see transport_kernels.hpp)
+constexpr int NUM_STAGE_VARIANTS = 8;
+// var: launch-shape variant (0 = default; see transport_kernels.hpp).  FP32 stages exist for the
+// matvec ops (OP_A1, OP_A2, OP_I1, OP_I2); the state ops run in FP64.
 template <typename T>
-hipError_t launch_pass(int op, int axis, int var, const PassArgs<T>& a, hipStream_t s);
+hipError_t launch_stage(int op, int var, const StageArgs<T>& a, hipStream_t s);
+// m1 = Q + C (FP64); lam (nullable) = m_R - m1 in precision T
 template <typename T>
-hipError_t launch_body_end(long nn, T w, const T* lam, const T* G, T* B, hipStream_t s);
+hipError_t launch_finalize_state(long nn, const double* Q, const double* C, const double* mR, double* m1, T* lam,
+                                 hipStream_t s);
+// B += w (Q + C) G (vector fields B, G)
+template <typename T>
+hipError_t launch_body_end(long nn, T w, const T* Q, const T* C, const T* G, T* B, hipStream_t s);
 
 // ---- 2D spectral operators (FP64) -----------------------------------------------------------
 enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG };
@@ -91,5 +101,28 @@ hipError_t launch_convert(long n, const double* in, TO* out, hipStream_t s);
 template <typename TI>
 hipError_t launch_widen(long n, const TI* in, double* out, hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
+
+// ---- PCG with device-side scalars (Alg. 2) ----------------------------------------------------
+// Slots of the FP64 scalar array shared by the PCG kernels.
+enum PcgSlot {
+    S_RZ = 0,    // <r, z>_W of the current iterate
+    S_RR0,       // ||r_0||^2 (written next to S_RZ by the start-up dots)
+    S_SHS,       // <s, H s>_W
+    S_RR,        // ||r||^2 after the update
+    S_RZN,       // <r, z>_W after the update (written next to S_RR)
+    S_KAPPA,
+    S_MU,
+    S_ACTIVE,    // 1 while iterating, 0 after a breakdown (<s, H s> <= 0 or not finite)
+    S_BREAK,     // iteration at which the breakdown happened (0: none)
+    S_ITER,      // iterations executed
+    NUM_PCG_SLOTS
+};
+enum PcgScalarMode { PCG_INIT = 0, PCG_KAPPA, PCG_MU };
+hipError_t launch_pcg_scalar(int mode, double* scal, hipStream_t s);
+// x += kappa s, r -= kappa s~ (kappa from scal)
+hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
+                             hipStream_t stream);
+// s = z + mu s (mu from scal)
+hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal, hipStream_t stream);
 
 }  // namespace regnk

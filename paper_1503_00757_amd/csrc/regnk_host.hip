@@ -50,9 +50,10 @@ static reg_status fail(reg_status s, const char* fmt, ...) {
 // ---------------------------------------------------------------------------------------------
 namespace {
 
-constexpr int NFIELD = 7;    // scalar scratch fields in transport precision
+constexpr int NFIELD = 9;    // scalar scratch fields in transport precision
+constexpr int NSFIELD = 8;   // FP64 state-solve scratch fields
 constexpr int NPCG = 7;      // x, r, z, kr, s, st, kst
-constexpr int NSCAL = 16;
+constexpr int NSCAL = 32;
 
 struct Layout {
     size_t total = 0;
@@ -65,7 +66,7 @@ struct Layout {
 
 struct Offsets {
     size_t mT, mR, vT, vw, vtT, traj, fld[NFIELD], B, Bt;
-    size_t mT64, mR64, sfld[5];   // FP64 state-solve buffers (FP32 transport mode only)
+    size_t mT64, mR64, sfld[NSFIELD];   // FP64 state-solve buffers (FP32 transport mode only)
     size_t tw1f, tw2f, tw1d, tw2d;
     size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal;
     size_t total;
@@ -111,7 +112,7 @@ Offsets layout(const reg_params* p) {
     const size_t s64 = p->precision == REG_FP64 ? 0 : nn * 8;
     o.mT64 = L.take(s64);
     o.mR64 = L.take(s64);
-    for (int i = 0; i < 5; ++i) o.sfld[i] = L.take(s64);
+    for (int i = 0; i < NSFIELD; ++i) o.sfld[i] = L.take(s64);
     o.tw1f = L.take(p->n1 * 8);
     o.tw2f = L.take(p->n2 * 8);
     o.tw1d = L.take(p->n1 * 16);
@@ -151,7 +152,20 @@ struct reg_problem {
     bool matvec_done = false;
     SpecParams sp;
     double h1h2;
-    int var[2][7] = {};   // launch-shape variant per [axis: 0 column, 1 row][pass op] (FP32 passes)
+    int var[7] = {};   // launch-shape variant per stage op (FP32 square grids)
+    // Captured Hessian-matvec launch sequences, one per (input, output, K^-1 output) pointer set.
+    struct MvGraph {
+        const double* in = nullptr;
+        double* out = nullptr;
+        double* kout = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    static constexpr int NGRAPH = 4;
+    MvGraph graph[NGRAPH];
+    int graph_next = 0;
+    bool use_graphs = true;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t pcg_iter_graph = nullptr;   // one PCG iteration (matvec + scalar updates)
 
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
@@ -197,30 +211,38 @@ inline int slot_G(const reg_problem* P, int j) { (void)P; return j; }
 inline int slot_Gs(const reg_problem* P, int j) { return P->nt + 1 + j; }
 
 template <typename T>
-PassArgs<T> base_args(const reg_problem* P, int axis) {
+StageArgs<T> base_args(const reg_problem* P) {
     TV<T> tv{P};
-    PassArgs<T> a{};
+    StageArgs<T> a{};
     a.n1 = P->n1;
     a.n2 = P->n2;
     a.nn = P->nn;
     a.h = T(1.0 / P->nt);
-    a.tw = axis == 2 ? tv.tw2() : tv.tw1();
+    a.tw1 = tv.tw1();
+    a.tw2 = tv.tw2();
     return a;
 }
 
 template <typename T>
-reg_status pass(const reg_problem* P, int op, int axis, const PassArgs<T>& a) {
-    CK(launch_pass<T>(op, axis, P->var[axis == 2 ? 1 : 0][op], a, P->stream));
+reg_status stage(const reg_problem* P, int op, const StageArgs<T>& a) {
+    CK(launch_stage<T>(op, P->var[op], a, P->stream));
     return REG_OK;
 }
+
+// Every stage result is kept as the pair (R, C) of its row and column parts; the next stage
+// rebuilds u = R + C pointwise.  Scratch roles: (Ra, Ca) current pair, P/E stage-1 pair, U the
+// materialised stage input, (Rb, Cb) next pair.
+struct Pair {
+    int r, c;
+};
 
 // ---- state solve forward (eq. (state-eq-elim)) ----------------------------------------------------
 // Always in FP64: the stored gradients feed every later matvec, and FP32 round-off in the state is
 // amplified by the spectral derivative (and by Heun's growth at high wavenumbers) into G = grad m.
 // v: FP64 velocity (2 nn).  store: write G_j, G*_j (and G_nt in paper mode) to the trajectory in the
-// transport precision T.  m1: FP64 output field.  lam1 (nullable): lam(1) = m_R - m_1 in precision T.
+// transport precision T.  m1: FP64 output field (sF(7)).  lam1 (nullable): lam(1) = m_R - m_1 in T.
 template <typename T>
-void set_gout(PassArgs<double>& a, T* g) {
+void set_gout(StageArgs<double>& a, T* g) {
     if constexpr (sizeof(T) == 8) a.GOUT = reinterpret_cast<double*>(g);
     else a.GOUTF = reinterpret_cast<float*>(g);
 }
@@ -229,122 +251,106 @@ template <typename T>
 reg_status state_forward(reg_problem* P, const double* v, bool store, double* m1, T* lam1) {
     TV<T> tv{P};
     const long nn = P->nn;
-    const double* cur = P->sT();
-    double* Fa = P->sF(0);
-    double* Fb = P->sF(3);
-    double* Fp = P->sF(1);
-    double* Fs = P->sF(2);
+    Pair cur{0, 1}, nxt{5, 6};
     for (int j = 0; j < P->nt; ++j) {
-        const bool last = j == P->nt - 1;
-        double* nxt = last ? m1 : (cur == Fa ? Fb : Fa);
         T* G = store ? tv.G(slot_G(P, j)) : nullptr;
         T* Gs = store ? tv.G(slot_Gs(P, j)) : nullptr;
-        PassArgs<double> r = base_args<double>(P, 2), c = base_args<double>(P, 1);
-        r.U = cur; r.V = v + nn; r.OUT = Fp; set_gout<T>(r, G);
-        CKS(pass<double>(P, OP_S1, 2, r));
-        c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs; set_gout<T>(c, G);
-        CKS(pass<double>(P, OP_S1, 1, c));
-        r = base_args<double>(P, 2); c = base_args<double>(P, 1);
-        r.U = Fs; r.X = cur; r.V = v + nn; r.OUT = Fp; set_gout<T>(r, Gs);
-        CKS(pass<double>(P, OP_S2, 2, r));
-        c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt; set_gout<T>(c, Gs);
-        if (last && lam1) {
-            c.MR = P->sR();
-            if constexpr (sizeof(T) == 8) c.OUT2 = reinterpret_cast<double*>(lam1);
-            else c.OUT2F = reinterpret_cast<float*>(lam1);
-        }
-        CKS(pass<double>(P, OP_S2, 1, c));
-        cur = nxt;
+        StageArgs<double> s1 = base_args<double>(P);
+        s1.A = j == 0 ? P->sT() : P->sF(cur.r);
+        s1.Bf = j == 0 ? nullptr : P->sF(cur.c);
+        s1.V1 = v; s1.V2 = v + nn;
+        s1.ROUT = P->sF(2); s1.UOUT = P->sF(4); s1.COUT = P->sF(3);
+        set_gout<T>(s1, G);
+        CKS(stage<double>(P, OP_S1, s1));
+        StageArgs<double> s2 = base_args<double>(P);
+        s2.A = P->sF(2); s2.Bf = P->sF(3); s2.X = P->sF(4);
+        s2.V1 = v; s2.V2 = v + nn;
+        s2.ROUT = P->sF(nxt.r); s2.COUT = P->sF(nxt.c);
+        set_gout<T>(s2, Gs);
+        CKS(stage<double>(P, OP_S2, s2));
+        std::swap(cur, nxt);
     }
+    CK(launch_finalize_state<T>(nn, P->sF(cur.r), P->sF(cur.c), P->sR(), m1, lam1, P->stream));
     if (store && P->p.adjoint == REG_ADJ_PAPER) {   // G_{n_t} for the trapezoid end point
-        PassArgs<double> r = base_args<double>(P, 2), c = base_args<double>(P, 1);
-        r.U = m1; set_gout<T>(r, tv.G(slot_G(P, P->nt)));
-        CKS(pass<double>(P, OP_GRAD, 2, r));
-        c.U = m1; set_gout<T>(c, tv.G(slot_G(P, P->nt)));
-        CKS(pass<double>(P, OP_GRAD, 1, c));
+        StageArgs<double> g = base_args<double>(P);
+        g.A = m1;
+        set_gout<T>(g, tv.G(slot_G(P, P->nt)));
+        CKS(stage<double>(P, OP_GRAD, g));
     }
     return REG_OK;
 }
 
 // ---- adjoint solve backward (eq. (adj-eq-elim)); also the GN incremental adjoint ------------------
-// lamT: terminal value (field, read only).  B: body force (vector, overwritten) in the selected
-// quadrature, using the stored trajectory.
+// Terminal value lam(1) = sign (TA + TB) (TB nullable).  B: body force (vector, overwritten) in the
+// selected quadrature, using the stored trajectory.
 template <typename T>
-reg_status adjoint_backward(reg_problem* P, const T* v, const T* lamT, T* B) {
+reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB, bool negate, T* B) {
     TV<T> tv{P};
     const long nn = P->nn;
     const T h = T(1.0 / P->nt);
     const bool paper = P->p.adjoint == REG_ADJ_PAPER;
-    const T* cur = lamT;
-    T* La = tv.F(0);
-    T* Lb = tv.F(3);
-    T* Fp = tv.F(1);
-    T* Fs = tv.F(2);
+    // the terminal pair may live in scratch fields 0/1 or 5/6: write the first result elsewhere
+    Pair nxt = (TA == tv.F(5) || TA == tv.F(6)) ? Pair{0, 1} : Pair{5, 6};
+    const T* A = TA;
+    const T* Bf = TB;
     for (int j = P->nt - 1; j >= 0; --j) {
         const bool first = j == P->nt - 1;
-        T* nxt = (cur == La) ? Lb : La;
-        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
-        r.U = cur; r.V = v + nn; r.OUT = Fp;
+        StageArgs<T> s1 = base_args<T>(P);
+        s1.A = A; s1.Bf = Bf; s1.flags = (first && negate) ? F_NEG : 0;
+        s1.V1 = v; s1.V2 = v + nn;
+        s1.ROUT = tv.F(2); s1.UOUT = tv.F(4); s1.COUT = tv.F(3);
         if (paper) {
-            r.B = B; r.G = tv.G(slot_G(P, j + 1));
-            r.bw = (j + 1 == P->nt) ? T(0.5) * h : h;
-            r.flags = first ? F_FIRST : 0;
+            s1.B = B; s1.G = tv.G(slot_G(P, j + 1));
+            s1.bw = (j + 1 == P->nt) ? T(0.5) * h : h;
+            s1.flags |= first ? F_FIRST : 0;
         }
-        CKS(pass<T>(P, OP_A1, 2, r));
-        c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs;
-        CKS(pass<T>(P, OP_A1, 1, c));
-        r = base_args<T>(P, 2); c = base_args<T>(P, 1);
-        r.U = Fs; r.X = cur; r.V = v + nn; r.OUT = Fp;
+        CKS(stage<T>(P, OP_A1, s1));
+        StageArgs<T> s2 = base_args<T>(P);
+        s2.A = tv.F(2); s2.Bf = tv.F(3); s2.X = tv.F(4);
+        s2.V1 = v; s2.V2 = v + nn;
+        s2.ROUT = tv.F(nxt.r); s2.COUT = tv.F(nxt.c);
         if (!paper) {
-            r.B = B; r.G = tv.G(slot_G(P, j)); r.G2 = tv.G(slot_Gs(P, j));
-            r.bw = T(0.5) * h;
-            r.flags = first ? F_FIRST : 0;
+            s2.B = B; s2.G = tv.G(slot_G(P, j)); s2.G2 = tv.G(slot_Gs(P, j));
+            s2.bw = T(0.5) * h;
+            s2.flags = first ? F_FIRST : 0;
         }
-        CKS(pass<T>(P, OP_A2, 2, r));
-        c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt;
-        CKS(pass<T>(P, OP_A2, 1, c));
-        cur = nxt;
+        CKS(stage<T>(P, OP_A2, s2));
+        A = tv.F(nxt.r);
+        Bf = tv.F(nxt.c);
+        nxt = (nxt.r == 0) ? Pair{5, 6} : Pair{0, 1};
     }
-    if (paper) CK(launch_body_end<T>(nn, T(0.5) * h, cur, tv.G(slot_G(P, 0)), B, P->stream));
+    if (paper) CK(launch_body_end<T>(nn, T(0.5) * h, A, Bf, tv.G(slot_G(P, 0)), B, P->stream));
     return REG_OK;
 }
 
-// ---- incremental state forward (eq. (inc-state-eq-elim)); writes lam~(1) = -m~(1) -----------------
+// ---- incremental state forward (eq. (inc-state-eq-elim)) ---------------------------------------
+// Leaves m~(1) = R + C; returns the scratch indices of the pair.
 template <typename T>
-reg_status inc_state_forward(reg_problem* P, const T* v, const T* vt, T* lamt1) {
+reg_status inc_state_forward(reg_problem* P, const T* v, const T* vt, Pair* out) {
     TV<T> tv{P};
     const long nn = P->nn;
     const bool paper = P->p.adjoint == REG_ADJ_PAPER;
-    T* Ma = tv.F(0);
-    T* Mb = tv.F(3);
-    T* Fp = tv.F(1);
-    T* Fs = tv.F(2);
-    const T* cur = nullptr;   // m~_0 = 0
+    Pair cur{0, 1}, nxt{5, 6};
     for (int j = 0; j < P->nt; ++j) {
-        const bool last = j == P->nt - 1;
-        T* nxt = last ? lamt1 : (cur == Ma ? Mb : Ma);
         const T* Gsrc2 = paper ? tv.G(slot_G(P, j + 1)) : tv.G(slot_Gs(P, j));
-        PassArgs<T> r = base_args<T>(P, 2), c = base_args<T>(P, 1);
+        StageArgs<T> s2 = base_args<T>(P);
         if (j == 0) {
-            // m~*_0 = -h v~ . G_0 is formed on the fly by both passes
-            r.flags = F_ZERO; r.VT = vt; r.G2 = tv.G(slot_G(P, 0)); r.G = Gsrc2; r.V = v + nn; r.OUT = Fp;
-            CKS(pass<T>(P, OP_I2, 2, r));
-            c.flags = F_ZERO | (last ? F_NEG : 0); c.VT = vt; c.G2 = tv.G(slot_G(P, 0)); c.V = v; c.X = Fp;
-            c.OUT = nxt;
-            CKS(pass<T>(P, OP_I2, 1, c));
+            // m~_0 = 0: stage 1 is m~*_0 = -h v~ . G_0, formed on the fly by both parts of stage 2
+            s2.flags = F_ZERO; s2.G2 = tv.G(slot_G(P, 0));
         } else {
-            r.U = cur; r.V = v + nn; r.VT = vt; r.G = tv.G(slot_G(P, j)); r.OUT = Fp;
-            CKS(pass<T>(P, OP_I1, 2, r));
-            c.U = cur; c.V = v; c.X = Fp; c.OUT = Fs;
-            CKS(pass<T>(P, OP_I1, 1, c));
-            r = base_args<T>(P, 2); c = base_args<T>(P, 1);
-            r.U = Fs; r.X = cur; r.V = v + nn; r.VT = vt; r.G = Gsrc2; r.OUT = Fp;
-            CKS(pass<T>(P, OP_I2, 2, r));
-            c.U = Fs; c.V = v; c.X = Fp; c.OUT = nxt; c.flags = last ? F_NEG : 0;
-            CKS(pass<T>(P, OP_I2, 1, c));
+            StageArgs<T> s1 = base_args<T>(P);
+            s1.A = tv.F(cur.r); s1.Bf = tv.F(cur.c);
+            s1.V1 = v; s1.V2 = v + nn; s1.VT = vt; s1.G = tv.G(slot_G(P, j));
+            s1.ROUT = tv.F(2); s1.UOUT = tv.F(4); s1.COUT = tv.F(3);
+            CKS(stage<T>(P, OP_I1, s1));
+            s2.A = tv.F(2); s2.Bf = tv.F(3); s2.X = tv.F(4);
         }
-        cur = nxt;
+        s2.V1 = v; s2.V2 = v + nn; s2.VT = vt; s2.G = Gsrc2;
+        s2.ROUT = tv.F(nxt.r); s2.COUT = tv.F(nxt.c);
+        CKS(stage<T>(P, OP_I2, s2));
+        std::swap(cur, nxt);
     }
+    *out = cur;
     return REG_OK;
 }
 
@@ -419,9 +425,9 @@ reg_status objective_t(reg_problem* P, const double* v, double* J, double* terms
     TV<T> tv{P};
     double* vp = P->at<double>(P->o.vtrial);
     CKS(project<T>(P, v, vp, (T*)nullptr));
-    CKS(state_forward<T>(P, vp, false, P->sF(4), (T*)nullptr));
+    CKS(state_forward<T>(P, vp, false, P->sF(7), (T*)nullptr));
     double d = 0, rv = 0, rw = 0;
-    CKS(data_term(P, P->sF(4), &d));
+    CKS(data_term(P, P->sF(7), &d));
     CKS(reg_terms(P, vp, &rv, &rw));
     *J = d + rv + rw;
     if (terms) { terms[0] = d; terms[1] = rv; terms[2] = rw; }
@@ -438,13 +444,13 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
     P->linearized = false;
     P->matvec_done = false;
     CKS(project<T>(P, v, v64, tv.vT()));
-    CKS(state_forward<T>(P, v64, true, P->sF(4), tv.F(5)));
+    CKS(state_forward<T>(P, v64, true, P->sF(7), tv.F(8)));
     double d = 0, rv = 0, rw = 0;
     if (Jout) {
-        CKS(data_term(P, P->sF(4), &d));
+        CKS(data_term(P, P->sF(7), &d));
         CKS(reg_terms(P, v64, &rv, &rw));
     }
-    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(5), tv.B()));
+    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(8), (const T*)nullptr, false, tv.B()));
     CKS(spec_fwd<double>(P, 0, v64));
     CKS(spec_fwd<T>(P, 1, tv.B()));
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
@@ -465,8 +471,10 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     TV<T> tv{P};
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
     CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
-    CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), tv.F(5)));
-    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(5), tv.Bt()));
+    Pair mt;
+    CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), &mt));
+    // lam~(1) = -m~(1)
+    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(mt.r), tv.F(mt.c), true, tv.Bt()));
     CKS(spec_fwd<double>(P, 0, vt64));
     CKS(spec_fwd<T>(P, 1, tv.Bt()));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
@@ -474,6 +482,72 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     if (kout) CKS(spec_inv<double>(P, 1, kout, (double*)nullptr));
     P->matvec_done = true;
     return REG_OK;
+}
+
+void drop_graphs(reg_problem* P) {
+    for (auto& g : P->graph) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = reg_problem::MvGraph{};
+    }
+    P->graph_next = 0;
+    if (P->pcg_iter_graph) (void)hipGraphExecDestroy(P->pcg_iter_graph);
+    P->pcg_iter_graph = nullptr;
+}
+
+// Capture the work `enqueue` puts on the problem's stream into an executable graph (on the private
+// capture stream).  Returns nullptr if capture is unavailable.
+template <typename F>
+hipGraphExec_t capture_graph(reg_problem* P, F enqueue) {
+    if (!P->capture_stream && hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    hipStream_t saved = P->stream;
+    P->stream = P->capture_stream;
+    bool ok = hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    reg_status s = ok ? enqueue() : REG_EDEVICE;
+    hipError_t e = ok ? hipStreamEndCapture(P->capture_stream, &graph) : hipErrorUnknown;
+    P->stream = saved;
+    ok = ok && s == REG_OK && e == hipSuccess && graph;
+    hipGraphExec_t exec = nullptr;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return ok ? exec : nullptr;
+}
+
+// The matvec is a fixed chain of ~12 n_t + 10 kernels whose arguments depend only on workspace
+// pointers, so it is captured once into a HIP graph (on a private stream) and replayed on the
+// problem's stream; this removes the host launch cost per pass.  Falls back to direct launches if
+// capture is unavailable.
+template <typename T>
+reg_status matvec_run(reg_problem* P, const double* vt64, double* out, double* kout) {
+    if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
+    if (P->use_graphs) {
+        reg_problem::MvGraph* hit = nullptr;
+        for (auto& g : P->graph)
+            if (g.exec && g.in == vt64 && g.out == out && g.kout == kout) hit = &g;
+        if (!hit) {
+            hipGraphExec_t exec = capture_graph(P, [&]() { return matvec_t<T>(P, vt64, out, kout); });
+            if (exec) {
+                reg_problem::MvGraph& slot = P->graph[P->graph_next];
+                if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+                slot = reg_problem::MvGraph{vt64, out, kout, exec};
+                P->graph_next = (P->graph_next + 1) % reg_problem::NGRAPH;
+                hit = &slot;
+            } else {
+                P->use_graphs = false;
+                drop_graphs(P);
+            }
+        }
+        if (hit) {
+            CK(hipGraphLaunch(hit->exec, P->stream));
+            P->matvec_done = true;
+            return REG_OK;
+        }
+    }
+    return matvec_t<T>(P, vt64, out, kout);
 }
 
 reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
@@ -487,64 +561,92 @@ reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
 // ---- PCG (Alg. 2) -----------------------------------------------------------------------------
 enum { PX = 0, PR, PZ, PKR, PS, PST, PKST };
 
+// One PCG iteration with device-side scalars: s~ = H s, kappa, x and r updates, z = P^{-1} r,
+// the new <r, z>_W and ||r||^2, mu, s = z + mu s.  No host synchronisation inside.
+template <typename T>
+reg_status pcg_iter_enqueue(reg_problem* P) {
+    const long n = 2 * P->nn;
+    const bool W = P->p.constraint == REG_MASS_SOURCE;
+    double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
+    double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
+    double* sc = P->scal();
+    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr));
+    {
+        const double* a[1] = {s};
+        const double* b[1] = {W ? kst : st};
+        CK(launch_dots<double>(1, a, b, n, P->partial(), sc + S_SHS, P->stream));
+    }
+    CK(launch_pcg_scalar(PCG_KAPPA, sc, P->stream));
+    CK(launch_pcg_update(n, x, r, s, st, sc, P->stream));
+    CKS(precond_t(P, r, z, W ? kr : nullptr));
+    {
+        const double* a[2] = {r, W ? kr : r};
+        const double* b[2] = {r, z};
+        CK(launch_dots<double>(2, a, b, n, P->partial(), sc + S_RR, P->stream));
+    }
+    CK(launch_pcg_scalar(PCG_MU, sc, P->stream));
+    CK(launch_pcg_dir(n, s, z, sc, P->stream));
+    return REG_OK;
+}
+
+template <typename T>
+reg_status pcg_iter_run(reg_problem* P) {
+    if (P->use_graphs && !P->pcg_iter_graph) {
+        P->pcg_iter_graph = capture_graph(P, [&]() { return pcg_iter_enqueue<T>(P); });
+        if (!P->pcg_iter_graph) P->use_graphs = false;
+    }
+    if (P->pcg_iter_graph) {
+        CK(hipGraphLaunch(P->pcg_iter_graph, P->stream));
+        P->matvec_done = true;
+        return REG_OK;
+    }
+    return pcg_iter_enqueue<T>(P);
+}
+
 template <typename T>
 reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, int fixed_iters, double* xout,
                  int* iters, double* relres, int* nmv) {
     const long n = 2 * P->nn;
     const bool W = P->p.constraint == REG_MASS_SOURCE;
+    if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
     double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
-    double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
+    double* s = P->pcg(PS);
+    double* sc = P->scal();
     CK(hipMemcpyAsync(r, rhs, n * 8, hipMemcpyDeviceToDevice, P->stream));
     CK(launch_fill(n, 0.0, x, P->stream));
     CKS(precond_t(P, r, z, W ? kr : nullptr));
     CK(hipMemcpyAsync(s, z, n * 8, hipMemcpyDeviceToDevice, P->stream));
-    double v2[2];
     {
         const double* a[2] = {W ? kr : r, r};
         const double* b[2] = {z, r};
-        CKS(dots(P, 2, a, b, v2));
+        CK(launch_dots<double>(2, a, b, n, P->partial(), sc + S_RZ, P->stream));   // S_RZ, S_RR0
     }
-    double rz = v2[0];
-    const double r0 = std::sqrt(v2[1]);
-    double rn = r0;
+    CK(launch_pcg_scalar(PCG_INIT, sc, P->stream));
+    double h[NUM_PCG_SLOTS];
+    CK(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    const double r0 = std::sqrt(h[S_RR0]);
+    if (!std::isfinite(r0)) return fail(REG_ENONFINITE, "PCG: right-hand side is not finite");
     const int nit = fixed_iters > 0 ? fixed_iters : max_iters;
     int l = 0;
     while (l < nit) {
-        CKS(matvec_t<T>(P, s, st, W ? kst : nullptr));
-        if (nmv) ++*nmv;
-        double sHs = 0;
-        {
-            const double* a[1] = {s};
-            const double* b[1] = {W ? kst : st};
-            CKS(dots(P, 1, a, b, &sHs));
-        }
+        CKS(pcg_iter_run<T>(P));
         ++l;
-        if (!std::isfinite(sHs)) return fail(REG_ENONFINITE, "PCG: <s, H s> is not finite");
-        if (!(sHs > 0.0)) {
-            if (l == 1) CK(hipMemcpyAsync(x, s, n * 8, hipMemcpyDeviceToDevice, P->stream));
-            break;
-        }
-        const double kappa = rz / sHs;
-        CK(launch_add_scaled(n, x, kappa, s, x, P->stream));
-        CK(launch_add_scaled(n, r, -kappa, st, r, P->stream));
-        // preconditioned residual first, so that one synchronisation returns ||r||^2 and <r, z>_W
-        CKS(precond_t(P, r, z, W ? kr : nullptr));
-        {
-            const double* a[2] = {r, W ? kr : r};
-            const double* b[2] = {r, z};
-            CKS(dots(P, 2, a, b, v2));
-        }
-        rn = std::sqrt(v2[0]);
-        if (!std::isfinite(rn)) return fail(REG_ENONFINITE, "PCG: residual is not finite");
-        if (fixed_iters == 0 && rn <= eta * r0) break;
-        if (l >= nit) break;
-        const double mu = v2[1] / rz;
-        rz = v2[1];
-        CK(launch_axpby(n, 1.0, z, mu, s, P->stream));   // s = z + mu s
+        if (fixed_iters > 0) continue;   // fixed schedule: no stop test, no host round trip
+        CK(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, P->stream));
+        CK(hipStreamSynchronize(P->stream));
+        if (h[S_ACTIVE] == 0.0) break;
+        if (!std::isfinite(h[S_RR])) return fail(REG_ENONFINITE, "PCG: residual is not finite");
+        if (std::sqrt(h[S_RR]) <= eta * r0) break;
     }
+    CK(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    if (!std::isfinite(h[S_RR]) || !std::isfinite(h[S_RZ])) return fail(REG_ENONFINITE, "PCG: not finite");
+    const int done = (int)h[S_ITER];
+    if (nmv) *nmv += done;
     if (xout != x) CK(hipMemcpyAsync(xout, x, n * 8, hipMemcpyDeviceToDevice, P->stream));
-    if (iters) *iters = l;
-    if (relres) *relres = r0 > 0 ? rn / r0 : 0.0;
+    if (iters) *iters = done;
+    if (relres) *relres = r0 > 0 ? std::sqrt(h[S_RR]) / r0 : 0.0;
     return REG_OK;
 }
 
@@ -641,79 +743,72 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
 }
 
 // ---- measurement hook and autotuner ------------------------------------------------------------
-// The eight passes of one matvec time step (DTO quadrature unless the problem uses the paper's),
-// set up on live buffers at a middle time step: which = 0 A2 row, 1 I2 row, 2 A2 column,
-// 3 I2 column, 4 A1 row, 5 I1 row, 6 A1 column, 7 I1 column.  Outputs go to a scratch field (the
-// body-force accumulator of the A2 row pass is updated in place; every matvec rewrites it).
-struct PassSpec {
-    int op, axis;
-    double fields;   // scalar fields of compulsory HBM traffic per launch (reads + writes)
-};
-
+// The four stage launches of one matvec time step, set up on live buffers at a middle time step:
+// which = 0 GN adjoint stage 2, 1 incremental state stage 2, 2 GN adjoint stage 1, 3 incremental
+// state stage 1.  Outputs go to scratch fields (the body-force accumulator of adjoint stage 2 is
+// updated in place; every matvec rewrites it).  `fields` = scalar fields of compulsory HBM traffic
+// per launch (each operand read once, each result written once).
 template <typename T>
-reg_status pass_spec(reg_problem* P, int which, PassArgs<T>& a, PassSpec& ps) {
+reg_status stage_spec(reg_problem* P, int which, StageArgs<T>& a, int& op, double& fields) {
     TV<T> tv{P};
     const long nn = P->nn;
     const int j = P->nt > 1 ? P->nt / 2 : 0;
     const bool paper = P->p.adjoint == REG_ADJ_PAPER;
-    static const int ops[8] = {OP_A2, OP_I2, OP_A2, OP_I2, OP_A1, OP_I1, OP_A1, OP_I1};
-    if (which < 0 || which > 7) return fail(REG_EINVAL, "unknown pass %d", which);
-    ps.op = ops[which];
-    ps.axis = (which == 2 || which == 3 || which == 6 || which == 7) ? 1 : 2;
-    a = base_args<T>(P, ps.axis);
-    a.OUT = tv.F(6);
-    const T* vax = ps.axis == 2 ? tv.vT() + nn : tv.vT();
-    a.V = vax;
-    if (ps.axis == 1) {   // every column pass: U, V, X -> OUT
-        a.U = (ps.op == OP_A2 || ps.op == OP_I2) ? tv.F(2) : tv.F(0);
-        a.X = tv.F(1);
-        ps.fields = 4;
-        return REG_OK;
-    }
-    switch (ps.op) {
-        case OP_A2:
-            a.U = tv.F(2); a.X = tv.F(0);
+    if (which < 0 || which > 3) return fail(REG_EINVAL, "unknown stage %d", which);
+    a = base_args<T>(P);
+    a.V1 = tv.vT();
+    a.V2 = tv.vT() + nn;
+    switch (which) {
+        case 0:   // rows: A, B, X, v2, (G, G*, b: 6) -> R, (b: 2); columns: A, B, v1 -> C
+            op = OP_A2;
+            a.A = tv.F(2); a.Bf = tv.F(3); a.X = tv.F(4); a.ROUT = tv.F(5); a.COUT = tv.F(6);
             if (!paper) { a.B = tv.Bt(); a.G = tv.G(slot_G(P, j)); a.G2 = tv.G(slot_Gs(P, j)); a.bw = T(0.5 / P->nt); }
-            ps.fields = paper ? 4 : 12;
+            fields = (paper ? 5 : 13) + 4;
             break;
-        case OP_I2:
-            a.U = tv.F(2); a.X = tv.F(0); a.VT = tv.vtT();
+        case 1:   // rows: A, B, X, v2, v~(2), G(2) -> R; columns: A, B, v1 -> C
+            op = OP_I2;
+            a.A = tv.F(2); a.Bf = tv.F(3); a.X = tv.F(4); a.VT = tv.vtT();
             a.G = paper ? tv.G(slot_G(P, j + 1)) : tv.G(slot_Gs(P, j));
-            ps.fields = 8;
+            a.ROUT = tv.F(5); a.COUT = tv.F(6);
+            fields = 9 + 4;
             break;
-        case OP_A1:
-            a.U = tv.F(0);
+        case 2:   // rows: A, B, v2 -> R, U; columns: A, B, v1 -> C
+            op = OP_A1;
+            a.A = tv.F(0); a.Bf = tv.F(1); a.ROUT = tv.F(2); a.UOUT = tv.F(4); a.COUT = tv.F(3);
             if (paper) { a.B = tv.Bt(); a.G = tv.G(slot_G(P, j + 1)); a.bw = T(1.0 / P->nt); }
-            ps.fields = paper ? 9 : 3;
+            fields = (paper ? 11 : 5) + 4;
             break;
-        default:   // OP_I1
-            a.U = tv.F(0); a.VT = tv.vtT(); a.G = tv.G(slot_G(P, j));
-            ps.fields = 7;
+        default:  // rows: A, B, v2, v~(2), G(2) -> R, U; columns: A, B, v1 -> C
+            op = OP_I1;
+            a.A = tv.F(0); a.Bf = tv.F(1); a.VT = tv.vtT(); a.G = tv.G(slot_G(P, j));
+            a.ROUT = tv.F(2); a.UOUT = tv.F(4); a.COUT = tv.F(3);
+            fields = 9 + 4;
             break;
     }
     return REG_OK;
 }
 
 template <typename T>
-reg_status time_launches(reg_problem* P, int op, int axis, int var, const PassArgs<T>& a, int reps, double* ms) {
-    hipEvent_t e0, e1;
-    CK(hipEventCreate(&e0));
-    CK(hipEventCreate(&e1));
-    hipError_t err = launch_pass<T>(op, axis, var, a, P->stream);   // warm-up (and validity check)
-    if (err != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return fail(REG_EINVAL, "variant %d not available: %s", var, hipGetErrorString(err));
+reg_status time_launches(reg_problem* P, int op, int var, const StageArgs<T>& a, int reps, double* ms) {
+    hipError_t err = launch_stage<T>(op, var, a, P->stream);   // warm-up (and validity check)
+    if (err != hipSuccess) return fail(REG_EINVAL, "variant %d not available: %s", var, hipGetErrorString(err));
+    // best of three timed batches (clock and power-state noise)
+    double best = 1e30;
+    for (int rep3 = 0; rep3 < 3; ++rep3) {
+        hipEvent_t e0, e1;
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        CK(hipEventRecord(e0, P->stream));
+        for (int i = 0; i < reps; ++i) CK(launch_stage<T>(op, var, a, P->stream));
+        CK(hipEventRecord(e1, P->stream));
+        CK(hipEventSynchronize(e1));
+        float t = 0;
+        CK(hipEventElapsedTime(&t, e0, e1));
+        CK(hipEventDestroy(e0));
+        CK(hipEventDestroy(e1));
+        if ((double)t / reps < best) best = (double)t / reps;
     }
-    CK(hipEventRecord(e0, P->stream));
-    for (int i = 0; i < reps; ++i) CK(launch_pass<T>(op, axis, var, a, P->stream));
-    CK(hipEventRecord(e1, P->stream));
-    CK(hipEventSynchronize(e1));
-    float t = 0;
-    CK(hipEventElapsedTime(&t, e0, e1));
-    CK(hipEventDestroy(e0));
-    CK(hipEventDestroy(e1));
-    *ms = (double)t / reps;
+    *ms = best;
     return REG_OK;
 }
 
@@ -721,11 +816,12 @@ template <typename T>
 reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes) {
     if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
     if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
-    PassArgs<T> a;
-    PassSpec ps;
-    CKS(pass_spec<T>(P, which, a, ps));
-    CKS(time_launches<T>(P, ps.op, ps.axis, P->var[ps.axis == 2 ? 1 : 0][ps.op], a, reps, ms));
-    *bytes = ps.fields * (double)P->nn * sizeof(T);
+    StageArgs<T> a;
+    int op;
+    double fields;
+    CKS(stage_spec<T>(P, which, a, op, fields));
+    CKS(time_launches<T>(P, op, P->var[op], a, reps, ms));
+    *bytes = fields * (double)P->nn * sizeof(T);
     return REG_OK;
 }
 
@@ -738,34 +834,31 @@ reg_status autotune_f32(reg_problem* P, int reps, char* report, size_t cap) {
     if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before tuning");
     if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
     std::string js = "{";
-    for (int which = 0; which < 8; ++which) {
-        PassArgs<float> a;
-        PassSpec ps;
-        CKS(pass_spec<float>(P, which, a, ps));
-        const int ai = ps.axis == 2 ? 1 : 0;
-        const int nv = ps.axis == 2 ? NUM_ROW_VARIANTS : NUM_COL_VARIANTS;
-        int best = P->var[ai][ps.op];
+    for (int which = 0; which < 4; ++which) {
+        StageArgs<float> a;
+        int op;
+        double fields;
+        CKS(stage_spec<float>(P, which, a, op, fields));
+        int best = P->var[op];
         double best_ms = 1e30;
         char buf[96];
-        snprintf(buf, sizeof buf, "%s\"%s_%s\": [", which ? ", " : "", op_name(ps.op), ps.axis == 2 ? "row" : "col");
+        snprintf(buf, sizeof buf, "%s\"%s\": [", which ? ", " : "", op_name(op));
         js += buf;
         bool firstv = true;
-        for (int v = 0; v < nv; ++v) {
+        for (int v = 0; v < NUM_STAGE_VARIANTS; ++v) {
             double ms = 0;
-            if (time_launches<float>(P, ps.op, ps.axis, v, a, reps, &ms) != REG_OK) continue;
+            if (time_launches<float>(P, op, v, a, reps, &ms) != REG_OK) continue;
             snprintf(buf, sizeof buf, "%s[%d, %.3f]", firstv ? "" : ", ", v, ms * 1e3);
             js += buf;
             firstv = false;
             if (ms < best_ms) { best_ms = ms; best = v; }
         }
         js += "]";
-        P->var[ai][ps.op] = best;
+        P->var[op] = best;
     }
-    js += ", \"chosen\": {\"row\": [";
-    for (int op = 0; op < 7; ++op) js += std::to_string(P->var[1][op]) + (op < 6 ? ", " : "");
-    js += "], \"col\": [";
-    for (int op = 0; op < 7; ++op) js += std::to_string(P->var[0][op]) + (op < 6 ? ", " : "");
-    js += "]}}";
+    js += ", \"chosen\": [";
+    for (int op = 0; op < 7; ++op) js += std::to_string(P->var[op]) + (op < 6 ? ", " : "");
+    js += "]}";
     g_err = "no error";
     if (report && cap > 0) {
         strncpy(report, js.c_str(), cap - 1);
@@ -864,6 +957,9 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
 }
 
 reg_status reg_destroy(reg_problem* h) {
+    if (!h) return REG_OK;
+    drop_graphs(h);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     delete h;
     return REG_OK;
 }
@@ -879,12 +975,12 @@ reg_status reg_state_forward(reg_problem* h, const double* v, double* m1) {
     double* vp = h->at<double>(h->o.vtrial);
     if (h->f64) {
         CKS(project<double>(h, v, vp, (double*)nullptr));
-        CKS(state_forward<double>(h, vp, false, h->sF(4), (double*)nullptr));
+        CKS(state_forward<double>(h, vp, false, h->sF(7), (double*)nullptr));
     } else {
         CKS(project<float>(h, v, vp, (float*)nullptr));
-        CKS(state_forward<float>(h, vp, false, h->sF(4), (float*)nullptr));
+        CKS(state_forward<float>(h, vp, false, h->sF(7), (float*)nullptr));
     }
-    CK(hipMemcpyAsync(m1, h->sF(4), h->nn * 8, hipMemcpyDeviceToDevice, h->stream));
+    CK(hipMemcpyAsync(m1, h->sF(7), h->nn * 8, hipMemcpyDeviceToDevice, h->stream));
     return REG_OK;
 }
 
@@ -905,10 +1001,10 @@ reg_status reg_hessian_matvec(reg_problem* h, const double* vtilde, double* Hv) 
     double* vt64 = h->at<double>(h->o.vt64);
     if (h->f64) {
         CKS(project<double>(h, vtilde, vt64, (double*)nullptr));
-        return matvec_t<double>(h, vt64, Hv, nullptr);
+        return matvec_run<double>(h, vt64, Hv, nullptr);
     }
     CKS(project<float>(h, vtilde, vt64, (float*)nullptr));
-    return matvec_t<float>(h, vt64, Hv, nullptr);
+    return matvec_run<float>(h, vt64, Hv, nullptr);
 }
 
 reg_status reg_precond_apply(reg_problem* h, const double* r, double* z) {
@@ -957,21 +1053,17 @@ reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t repor
         }
         return REG_OK;
     }
+    drop_graphs(h);
     return autotune_f32(h, reps, report, report_bytes);
 }
 
 reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count) {
     if (!h || !variants) return fail(REG_EINVAL, "NULL argument");
-    if (count != 14) return fail(REG_EINVAL, "count must be 14 (7 row variants, then 7 column variants)");
-    for (int op = 0; op < 7; ++op) {
-        if (variants[op] < 0 || variants[op] >= NUM_ROW_VARIANTS || variants[7 + op] < 0 ||
-            variants[7 + op] >= NUM_COL_VARIANTS)
-            return fail(REG_EINVAL, "variant index out of range");
-    }
-    for (int op = 0; op < 7; ++op) {
-        h->var[1][op] = variants[op];
-        h->var[0][op] = variants[7 + op];
-    }
+    if (count != 7) return fail(REG_EINVAL, "count must be 7 (one launch shape per stage op)");
+    for (int op = 0; op < 7; ++op)
+        if (variants[op] < 0 || variants[op] >= NUM_STAGE_VARIANTS) return fail(REG_EINVAL, "variant index out of range");
+    for (int op = 0; op < 7; ++op) h->var[op] = variants[op];
+    drop_graphs(h);
     return REG_OK;
 }
 

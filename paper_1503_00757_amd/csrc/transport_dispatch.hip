@@ -1,46 +1,70 @@
-// Dispatch of the transport passes (kernels in transport_kernels.hpp, instantiated per op in
-// transport_op_*.hip).
+// Dispatch of the transport stages (kernels in transport_kernels.hpp, instantiated per op in
+// transport_op_*.hip) and the pointwise helpers of the state solve.
 #include "transport_kernels.hpp"
 
 namespace regnk {
 
-#define REGNK_EXTERN_OP(OPN)                                                                              \
-    extern template hipError_t launch_pass_op<float, OPN>(int, int, const PassArgs<float>&, hipStream_t); \
-    extern template hipError_t launch_pass_op<double, OPN>(int, int, const PassArgs<double>&, hipStream_t);
-REGNK_EXTERN_OP(OP_S1)
-REGNK_EXTERN_OP(OP_S2)
-REGNK_EXTERN_OP(OP_A1)
-REGNK_EXTERN_OP(OP_A2)
-REGNK_EXTERN_OP(OP_I1)
-REGNK_EXTERN_OP(OP_I2)
-REGNK_EXTERN_OP(OP_GRAD)
-#undef REGNK_EXTERN_OP
+extern template hipError_t launch_stage_op<float, OP_A1>(int, const StageArgs<float>&, hipStream_t);
+extern template hipError_t launch_stage_op<float, OP_A2>(int, const StageArgs<float>&, hipStream_t);
+extern template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t);
+extern template hipError_t launch_stage_op<float, OP_I2>(int, const StageArgs<float>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_S2>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_A1>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_A2>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_I1>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_I2>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<double, OP_GRAD>(int, const StageArgs<double>&, hipStream_t);
 
-template <typename T>
-hipError_t launch_pass(int op, int axis, int var, const PassArgs<T>& a, hipStream_t s) {
+template <>
+hipError_t launch_stage<float>(int op, int var, const StageArgs<float>& a, hipStream_t s) {
     switch (op) {
-        case OP_S1: return launch_pass_op<T, OP_S1>(axis, var, a, s);
-        case OP_S2: return launch_pass_op<T, OP_S2>(axis, var, a, s);
-        case OP_A1: return launch_pass_op<T, OP_A1>(axis, var, a, s);
-        case OP_A2: return launch_pass_op<T, OP_A2>(axis, var, a, s);
-        case OP_I1: return launch_pass_op<T, OP_I1>(axis, var, a, s);
-        case OP_I2: return launch_pass_op<T, OP_I2>(axis, var, a, s);
-        case OP_GRAD: return launch_pass_op<T, OP_GRAD>(axis, var, a, s);
+        case OP_A1: return launch_stage_op<float, OP_A1>(var, a, s);
+        case OP_A2: return launch_stage_op<float, OP_A2>(var, a, s);
+        case OP_I1: return launch_stage_op<float, OP_I1>(var, a, s);
+        case OP_I2: return launch_stage_op<float, OP_I2>(var, a, s);
     }
     return hipErrorInvalidValue;
 }
 
+template <>
+hipError_t launch_stage<double>(int op, int var, const StageArgs<double>& a, hipStream_t s) {
+    switch (op) {
+        case OP_S1: return launch_stage_op<double, OP_S1>(var, a, s);
+        case OP_S2: return launch_stage_op<double, OP_S2>(var, a, s);
+        case OP_A1: return launch_stage_op<double, OP_A1>(var, a, s);
+        case OP_A2: return launch_stage_op<double, OP_A2>(var, a, s);
+        case OP_I1: return launch_stage_op<double, OP_I1>(var, a, s);
+        case OP_I2: return launch_stage_op<double, OP_I2>(var, a, s);
+        case OP_GRAD: return launch_stage_op<double, OP_GRAD>(var, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static inline int pointwise_blocks(long nn) {
+    long b = (nn + 255) / 256;
+    return (int)(b > 4096 ? 4096 : (b < 1 ? 1 : b));
+}
+
 template <typename T>
-hipError_t launch_body_end(long nn, T w, const T* lam, const T* G, T* B, hipStream_t s) {
-    int blocks = (int)((nn + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL((body_end_kernel<T>), dim3(blocks), dim3(256), 0, s, nn, w, lam, G, B);
+hipError_t launch_finalize_state(long nn, const double* Q, const double* C, const double* mR, double* m1, T* lam,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL((finalize_state_kernel<T>), dim3(pointwise_blocks(nn)), dim3(256), 0, s, nn, Q, C, mR, m1, lam);
     return hipGetLastError();
 }
 
-template hipError_t launch_pass<float>(int, int, int, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_pass<double>(int, int, int, const PassArgs<double>&, hipStream_t);
-template hipError_t launch_body_end<float>(long, float, const float*, const float*, float*, hipStream_t);
-template hipError_t launch_body_end<double>(long, double, const double*, const double*, double*, hipStream_t);
+template <typename T>
+hipError_t launch_body_end(long nn, T w, const T* Q, const T* C, const T* G, T* B, hipStream_t s) {
+    hipLaunchKernelGGL((body_end_kernel<T>), dim3(pointwise_blocks(nn)), dim3(256), 0, s, nn, w, Q, C, G, B);
+    return hipGetLastError();
+}
+
+template hipError_t launch_finalize_state<float>(long, const double*, const double*, const double*, double*, float*,
+                                                 hipStream_t);
+template hipError_t launch_finalize_state<double>(long, const double*, const double*, const double*, double*, double*,
+                                                  hipStream_t);
+template hipError_t launch_body_end<float>(long, float, const float*, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_body_end<double>(long, double, const double*, const double*, const double*, double*,
+                                            hipStream_t);
 
 }  // namespace regnk

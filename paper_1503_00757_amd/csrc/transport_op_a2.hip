@@ -1,8 +1,8 @@
-// Instantiation of the A2 transport pass for both precisions (one translation unit per pass op
-// so that the many kernel shapes compile in parallel).
+// Instantiation of the A2 transport stage (both precisions); one
+// translation unit per stage op so that the many kernel shapes compile in parallel.
 #include "transport_kernels.hpp"
 
 namespace regnk {
-template hipError_t launch_pass_op<float, OP_A2>(int, int, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_pass_op<double, OP_A2>(int, int, const PassArgs<double>&, hipStream_t);
+template hipError_t launch_stage_op<float, OP_A2>(int, const StageArgs<float>&, hipStream_t);
+template hipError_t launch_stage_op<double, OP_A2>(int, const StageArgs<double>&, hipStream_t);
 }  // namespace regnk

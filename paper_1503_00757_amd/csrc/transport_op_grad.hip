@@ -1,8 +1,7 @@
-// Instantiation of the GRAD transport pass for both precisions (one translation unit per pass op
-// so that the many kernel shapes compile in parallel).
+// Instantiation of the GRAD transport stage (FP64; the state solve always runs in FP64); one
+// translation unit per stage op so that the many kernel shapes compile in parallel.
 #include "transport_kernels.hpp"
 
 namespace regnk {
-template hipError_t launch_pass_op<float, OP_GRAD>(int, int, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_pass_op<double, OP_GRAD>(int, int, const PassArgs<double>&, hipStream_t);
+template hipError_t launch_stage_op<double, OP_GRAD>(int, const StageArgs<double>&, hipStream_t);
 }  // namespace regnk

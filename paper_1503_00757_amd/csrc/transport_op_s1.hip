@@ -1,8 +1,7 @@
-// Instantiation of the S1 transport pass for both precisions (one translation unit per pass op
-// so that the many kernel shapes compile in parallel).
+// Instantiation of the S1 transport stage (FP64; the state solve always runs in FP64); one
+// translation unit per stage op so that the many kernel shapes compile in parallel.
 #include "transport_kernels.hpp"
 
 namespace regnk {
-template hipError_t launch_pass_op<float, OP_S1>(int, int, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_pass_op<double, OP_S1>(int, int, const PassArgs<double>&, hipStream_t);
+template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t);
 }  // namespace regnk

@@ -133,6 +133,71 @@ hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One thread: the scalar recurrences of PCG.
+__global__ void pcg_scalar_kernel(int mode, double* __restrict__ sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (mode == PCG_INIT) {
+        sc[S_ACTIVE] = 1.0;
+        sc[S_BREAK] = 0.0;
+        sc[S_ITER] = 0.0;
+        sc[S_RR] = sc[S_RR0];
+        sc[S_KAPPA] = 0.0;
+        sc[S_MU] = 0.0;
+    } else if (mode == PCG_KAPPA) {
+        const double shs = sc[S_SHS];
+        double kappa = 0.0;
+        if (sc[S_ACTIVE] != 0.0) {
+            sc[S_ITER] += 1.0;
+            if (shs > 0.0 && shs < 1.0e300) {
+                kappa = sc[S_RZ] / shs;
+            } else {                       // non-positive curvature: stop; on the first iteration
+                sc[S_ACTIVE] = 0.0;        // the step is the preconditioned steepest descent s_0
+                sc[S_BREAK] = sc[S_ITER];
+                kappa = sc[S_ITER] == 1.0 ? 1.0 : 0.0;
+            }
+        }
+        sc[S_KAPPA] = kappa;
+    } else {   // PCG_MU
+        if (sc[S_ACTIVE] != 0.0) {
+            const double rzn = sc[S_RZN];
+            sc[S_MU] = rzn / sc[S_RZ];
+            sc[S_RZ] = rzn;
+        } else {
+            sc[S_MU] = 0.0;
+        }
+    }
+}
+
+__global__ void pcg_update_kernel(long n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ s,
+                                  const double* __restrict__ st, const double* __restrict__ sc) {
+    const double kappa = sc[S_KAPPA];
+    const bool upd_r = sc[S_ACTIVE] != 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        x[i] += kappa * s[i];
+        if (upd_r) r[i] -= kappa * st[i];
+    }
+}
+
+__global__ void pcg_dir_kernel(long n, double* __restrict__ s, const double* __restrict__ z, const double* __restrict__ sc) {
+    const double mu = sc[S_MU];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        s[i] = z[i] + mu * s[i];
+}
+
+hipError_t launch_pcg_scalar(int mode, double* scal, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(64), 0, s, mode, scal);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, x, r, s, st, scal);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal, hipStream_t stream) {
+    hipLaunchKernelGGL(pcg_dir_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, s, z, scal);
+    return hipGetLastError();
+}
+
 template hipError_t launch_dots<double>(int, const double* const*, const double* const*, long, double*, double*,
                                         hipStream_t);
 template hipError_t launch_dots<float>(int, const float* const*, const float* const*, long, double*, double*,

