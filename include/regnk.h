@@ -149,10 +149,19 @@ typedef struct {
 reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
                      reg_solve_stats* stats_host);
 
-/* Measurement hook: launch one of the four RK2-stage launches of a Hessian-matvec time step `reps`
- * times back to back on the problem's stream at the current linearisation point and report the
- * mean device time per launch (hipEvents around the launches, best of three batches) and the
- * compulsory HBM bytes of one launch (each operand field read once, each result written once).
+/* Batched Alg. 1: solve `count` independent problems (any mix of sizes, steps and weights), pair i
+ * with opts[i] into v_out[i] (device vector field of that problem's size), stats into
+ * stats_host[i] (nullable).  Pairs run concurrently on up to eight internal streams, largest
+ * first; each problem's own stream is synchronised before its solve starts, and every solve has
+ * finished when the call returns.  A problem may appear only once.  Returns the first failure
+ * (REG_ENOTCONV after all others); stats carry each pair's own status. */
+reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const reg_solve_opts* opts,
+                           double* const* v_out, reg_solve_stats* stats_host);
+
+/* Measurement hook: run `reps` (1..1000) Hessian matvecs at the current linearisation point with
+ * hipEvents recorded on the problem's stream right before and after every launch of one of the four
+ * RK2-stage launches of a time step, and report that launch's mean device time and its compulsory
+ * HBM bytes (each operand field read once, each result written once).  Overwrites PCG scratch.
  * which: 0 GN incremental-adjoint stage 2 (the busiest launch: it also accumulates the body force),
  * 1 incremental-state stage 2, 2 GN incremental-adjoint stage 1, 3 incremental-state stage 1.
  * REG_ESTATE before the first reg_hessian_matvec.  Synchronises the stream. */

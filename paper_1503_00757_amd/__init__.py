@@ -11,7 +11,7 @@ from .ffi import (  # noqa: F401
     REG_ADJ_DISCRETE, REG_ADJ_PAPER,
     reg_workspace_bytes, reg_create, reg_destroy, reg_set_stream, reg_state_forward, reg_objective,
     reg_gradient, reg_hessian_matvec, reg_precond_apply, reg_pcg, reg_solve, reg_time_pass,
-    reg_autotune, reg_set_pass_variants,
+    reg_autotune, reg_set_pass_variants, reg_batch_solve,
     reg_last_error,
 )
-from .problem import Problem  # noqa: F401
+from .problem import Problem, batch_solve  # noqa: F401

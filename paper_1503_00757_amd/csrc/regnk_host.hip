@@ -3,8 +3,11 @@
 // the objective, PCG (Alg. 2) and the Newton loop (Alg. 1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -166,6 +169,10 @@ struct reg_problem {
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t pcg_iter_graph = nullptr;   // one PCG iteration (matvec + scalar updates)
+    // measurement hook: hipEvents around every launch of one stage op during real matvecs
+    int timing_op = -1;
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
 
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
@@ -224,8 +231,11 @@ StageArgs<T> base_args(const reg_problem* P) {
 }
 
 template <typename T>
-reg_status stage(const reg_problem* P, int op, const StageArgs<T>& a) {
+reg_status stage(reg_problem* P, int op, const StageArgs<T>& a) {
+    const bool timed = op == P->timing_op && P->tev_used + 2 <= P->tev.size();
+    if (timed) CK(hipEventRecord(P->tev[P->tev_used++], P->stream));
     CK(launch_stage<T>(op, P->var[op], a, P->stream));
+    if (timed) CK(hipEventRecord(P->tev[P->tev_used++], P->stream));
     return REG_OK;
 }
 
@@ -812,15 +822,39 @@ reg_status time_launches(reg_problem* P, int op, int var, const StageArgs<T>& a,
     return REG_OK;
 }
 
+// Mean device time of the selected stage's launches inside `reps` real matvecs (direct launches,
+// hipEvents recorded on the problem's stream right before and after each launch of that stage).
 template <typename T>
 reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes) {
     if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
-    if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
+    if (reps < 1 || reps > 1000) return fail(REG_EINVAL, "reps must be in [1, 1000]");
     StageArgs<T> a;
     int op;
     double fields;
     CKS(stage_spec<T>(P, which, a, op, fields));
-    CKS(time_launches<T>(P, op, P->var[op], a, reps, ms));
+    const size_t need = 2 * (size_t)P->nt * reps;
+    while (P->tev.size() < need) {
+        hipEvent_t e;
+        CK(hipEventCreate(&e));
+        P->tev.push_back(e);
+    }
+    P->timing_op = op;
+    P->tev_used = 0;
+    reg_status st = REG_OK;
+    for (int r = 0; r < reps && st == REG_OK; ++r)
+        st = matvec_t<T>(P, P->at<double>(P->o.vt64), P->pcg(PST), nullptr);
+    P->timing_op = -1;
+    CKS(st);
+    CK(hipStreamSynchronize(P->stream));
+    double total = 0;
+    const size_t pairs = P->tev_used / 2;
+    for (size_t i = 0; i < pairs; ++i) {
+        float t = 0;
+        CK(hipEventElapsedTime(&t, P->tev[2 * i], P->tev[2 * i + 1]));
+        total += t;
+    }
+    if (pairs == 0) return fail(REG_EINVAL, "no launches of the selected stage");
+    *ms = total / (double)pairs;
     *bytes = fields * (double)P->nn * sizeof(T);
     return REG_OK;
 }
@@ -959,6 +993,7 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
 reg_status reg_destroy(reg_problem* h) {
     if (!h) return REG_OK;
     drop_graphs(h);
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     delete h;
     return REG_OK;
@@ -1037,6 +1072,66 @@ reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out, 
         !(opts->armijo_rho > 0 && opts->armijo_rho < 1) || !(opts->armijo_c1 > 0 && opts->armijo_c1 < 1))
         return fail(REG_EINVAL, "bad solve options");
     return DISPATCH(h, solve_t<float>(h, opts, v_out, stats_host), solve_t<double>(h, opts, v_out, stats_host));
+}
+
+reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const reg_solve_opts* opts,
+                           double* const* v_out, reg_solve_stats* stats_host) {
+    if (count < 0 || (count > 0 && (!problems || !opts || !v_out)))
+        return fail(REG_EINVAL, "NULL argument or negative count");
+    for (int i = 0; i < count; ++i)
+        if (!problems[i] || !v_out[i]) return fail(REG_EINVAL, "problem %d or its output is NULL", i);
+    for (int i = 0; i < count; ++i)
+        for (int k = 0; k < i; ++k)
+            if (problems[i] == problems[k]) return fail(REG_EINVAL, "problem %d appears twice", i);
+    // largest problems first (most work per pair), then a shared work counter
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double wa = (double)problems[a]->nn * problems[a]->nt, wb = (double)problems[b]->nn * problems[b]->nt;
+        return wa > wb;
+    });
+    const int nworkers = std::min(count, 8);
+    std::atomic<int> next{0};
+    std::vector<reg_status> status(count, REG_OK);
+    std::vector<std::string> errs(count);
+    std::vector<reg_solve_stats> stats(count);
+    std::vector<hipError_t> stream_err(nworkers, hipSuccess);
+    auto worker = [&](int w) {
+        hipStream_t st = nullptr;
+        stream_err[w] = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (stream_err[w] != hipSuccess) return;
+        for (int k = next.fetch_add(1); k < count; k = next.fetch_add(1)) {
+            const int i = order[k];
+            reg_problem* P = problems[i];
+            hipStream_t saved = P->stream;
+            // the caller's stream may still hold work for this problem (its create, earlier calls)
+            if (hipStreamSynchronize(saved) != hipSuccess) {
+                status[i] = REG_EDEVICE;
+                errs[i] = "stream synchronisation failed";
+                continue;
+            }
+            P->stream = st;
+            status[i] = P->f64 ? solve_t<double>(P, &opts[i], v_out[i], &stats[i])
+                               : solve_t<float>(P, &opts[i], v_out[i], &stats[i]);
+            if (status[i] != REG_OK) errs[i] = g_err;
+            P->stream = saved;
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nworkers; ++w) pool.emplace_back(worker, w);
+    for (auto& t : pool) t.join();
+    for (int w = 0; w < nworkers; ++w)
+        if (stream_err[w] != hipSuccess) return fail(REG_EDEVICE, "stream creation failed: %s", hipGetErrorString(stream_err[w]));
+    if (stats_host)
+        for (int i = 0; i < count; ++i) stats_host[i] = stats[i];
+    for (int i = 0; i < count; ++i)
+        if (status[i] != REG_OK && status[i] != REG_ENOTCONV)
+            return fail(status[i], "pair %d: %s", i, errs[i].c_str());
+    for (int i = 0; i < count; ++i)
+        if (status[i] == REG_ENOTCONV) return fail(REG_ENOTCONV, "pair %d: %s", i, errs[i].c_str());
+    return REG_OK;
 }
 
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes) {

@@ -77,12 +77,14 @@ def lib():
         L.reg_solve.argtypes = [vp, C.POINTER(RegSolveOpts), vp, C.POINTER(RegSolveStats)]
         L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp]
         L.reg_autotune.argtypes = [vp, i32, C.c_char_p, sz]
+        L.reg_batch_solve.argtypes = [i32, C.POINTER(vp), C.POINTER(RegSolveOpts), C.POINTER(vp),
+                                      C.POINTER(RegSolveStats)]
         L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
         L.reg_last_error.argtypes = []
         L.reg_last_error.restype = C.c_char_p
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
-                     "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants"):
+                     "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -173,3 +175,15 @@ def reg_autotune(h, reps: int = 50) -> str:
 def reg_set_pass_variants(h, variants):
     arr = (C.c_int32 * len(variants))(*variants)
     _check(lib().reg_set_pass_variants(h, arr, len(variants)))
+
+
+def reg_batch_solve(handles, opts, v_outs, raise_on_error: bool = True):
+    n = len(handles)
+    H = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    O = (RegSolveOpts * n)(*opts)
+    V = (C.c_void_p * n)(*v_outs)
+    S = (RegSolveStats * n)()
+    status = lib().reg_batch_solve(n, H, O, V, S)
+    if raise_on_error:
+        _check(status)
+    return status, [S[i] for i in range(n)]

@@ -92,6 +92,11 @@ class Problem:
         it, rr = ffi.reg_pcg(self.h, rhs.data_ptr(), eta, max_iters, fixed_iters, x.data_ptr())
         return x, it, rr
 
+    def solve_opts(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
+                   armijo_c1=1e-4, armijo_rho=0.5, v0=None):
+        return ffi.RegSolveOpts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
+                                armijo_rho, v0.data_ptr() if v0 is not None else None)
+
     def solve(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
               armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True):
         v0c = self._c(v0) if v0 is not None else None
@@ -113,3 +118,12 @@ class Problem:
 
     def set_pass_variants(self, variants):
         ffi.reg_set_pass_variants(self.h, list(variants))
+
+
+def batch_solve(problems, raise_on_error=True, v0s=None, **opts):
+    """Solve many problems concurrently (reg_batch_solve); returns ([v], [stats dict])."""
+    outs = [p.vec() for p in problems]
+    v0s = v0s or [None] * len(problems)
+    o = [p.solve_opts(v0=(v0.contiguous() if v0 is not None else None), **opts) for p, v0 in zip(problems, v0s)]
+    status, st = ffi.reg_batch_solve([p.h for p in problems], o, [v.data_ptr() for v in outs], raise_on_error)
+    return outs, [s.as_dict() for s in st]

@@ -1,0 +1,57 @@
+"""reg_batch_solve: many pairs of mixed sizes, step counts and weights solved concurrently must give
+exactly what one-at-a-time solves give (same kernels, deterministic reductions), and a pair matches
+the oracle's Newton-Krylov solve."""
+import numpy as np
+import pytest
+
+import synthdata as sd
+from gpu_cases import dev, host, rel
+from oracle import Grid, Params, solver, transport
+
+pytestmark = pytest.mark.gpu
+
+
+def make_pair(n, nt, beta, seed, precision="fp32"):
+    import torch
+    from paper_1503_00757_amd import Problem
+    rng = np.random.Generator(np.random.PCG64(sd.BASE_SEED + 4000 + seed))
+    mT = sd.template_image(n, n, 8, min(8, n // 4), rng)
+    vs = sd.scale_to_cfl(sd.random_velocity(n, n, 4, rng, divfree=True), nt, 0.8)
+    p = Params(n, n, nt, "H1", "divfree", beta, 0.0)
+    mR = transport.state_forward(Grid(n, n), p, mT, vs).m[-1]
+    P = Problem(torch.tensor(mT, device="cuda:0"), torch.tensor(mR, device="cuda:0"), nt, "H1", "divfree",
+                beta, 0.0, precision)
+    return P, p, mT, mR
+
+
+def test_batch_equals_individual_solves_and_oracle():
+    from paper_1503_00757_amd import batch_solve
+    specs = [(64, 8, 1e-2), (128, 4, 3e-3), (32, 16, 1e-3), (64, 4, 5e-3), (128, 8, 1e-2), (32, 8, 2e-3)]
+    pairs = [make_pair(n, nt, b, i) for i, (n, nt, b) in enumerate(specs)]
+    try:
+        vs, stats = batch_solve([P for P, *_ in pairs], max_newton=10, gtol_rel=1e-2)
+        for (P, p, mT, mR), v, st in zip(pairs, vs, stats):
+            assert st["status"] == 0 and st["g_rel"] <= 1e-2
+            v1, st1 = P.solve(max_newton=10, gtol_rel=1e-2)
+            assert np.array_equal(host(v), host(v1))
+            assert st1["pcg_iters"] == st["pcg_iters"] and st1["newton_iters"] == st["newton_iters"]
+        P, p, mT, mR = pairs[0]
+        v_ref, st_ref = solver.solve(Grid(p.n1, p.n2), p, mT, mR, solver.SolveOpts(max_newton=10, gtol_rel=1e-2))
+        assert stats[0]["newton_iters"] == st_ref.newton_iters
+        assert rel(host(vs[0]), v_ref) < 1e-3
+    finally:
+        for P, *_ in pairs:
+            P.close()
+
+
+def test_batch_rejects_duplicates_and_reports_failures():
+    import paper_1503_00757_amd as R
+    P, *_ = make_pair(32, 4, 1e-2, 99)
+    try:
+        with pytest.raises(R.RegError) as e:
+            R.batch_solve([P, P])
+        assert e.value.status == R.ffi.REG_EINVAL
+        vs, st = R.batch_solve([P], raise_on_error=False, max_backtracks=0, armijo_c1=0.999999, gtol_rel=1e-8)
+        assert st[0]["status"] == R.ffi.REG_ENOTCONV
+    finally:
+        P.close()
