@@ -14,10 +14,13 @@ Modules
              with the body-force time integrals (Sec. 3.1-3.3, Sec. 4)
   reduced    objective, reduced gradient, GN Hessian matvec, preconditioner (Sec. 3.3, Sec. 4)
   solver     PCG (Alg. 2), Armijo backtracking and the outer Newton loop (Alg. 1)
+  fno        the learned warm-start network (a Fourier neural operator; not part of the paper):
+             forward, hand-written reverse mode, loss and Adam, in FP64 with optional bfloat16
+             multiplicands
 
 Every function is pinned by tests under ``tests/`` that check it against closed forms, invariants,
 brute force on tiny grids and an independent dense-matrix construction; see the headers of the
 individual modules for the readings taken where the paper is silent.
 """
 from .spectral import Grid, Params  # noqa: F401
-from . import spectral, transport, reduced, solver  # noqa: F401
+from . import spectral, transport, reduced, solver, fno  # noqa: F401

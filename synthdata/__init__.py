@@ -200,7 +200,8 @@ def make_workload(config: int, pair: int = 0, n: int | None = None, nt: int | No
        beta_v=1e-4.
     4: batch pair ``pair`` of 96: n in {128,256,512} (32 each), nt in {8,16,32}, beta_v
        log-uniform in [1e-4,1e-2]; H1, div-free; texture |k|<=16; v* div-free |k|<=8, CFL 0.8.
-    5: config 2's generator and settings at n (128 for training pairs, 256 for test pairs).
+    5: config 2's generator and settings at n (128 for training pairs, 256 for test pairs), with
+       the velocity amplitude of config 2 at 256^2 whatever n is.
     ``n``/``nt``/``beta_v`` override the grid size, step count and weight (for small test cases).
     """
     seed = BASE_SEED + config + 1000 * pair
@@ -216,7 +217,11 @@ def make_workload(config: int, pair: int = 0, n: int | None = None, nt: int | No
         n_ = n or (256 if config == 2 else 128)
         nt_ = nt or 16
         mT = template_image(n_, n_, 32, min(16, n_ // 2 - 1), rng)
-        vs = scale_to_cfl(random_velocity(n_, n_, 8, rng, divfree=True, compressible=True), nt_, 0.8)
+        # config 5 keeps the physical velocity amplitude of config 2 (CFL 0.8 on the 256^2 grid)
+        # at every grid size, so training pairs at 128^2 and test pairs at 256^2 share one
+        # distribution of continuous velocity fields
+        cfl = 0.8 if config == 2 else 0.8 * n_ / 256.0
+        vs = scale_to_cfl(random_velocity(n_, n_, 8, rng, divfree=True, compressible=True), nt_, cfl)
         vt = _direction(n_, n_, rng, "mass_source")
         return Workload(f"c{config}", n_, n_, nt_, "H2", "mass_source", beta_v or 1e-3, 1e-4,
                         mT, vs, vt, seed)
@@ -250,3 +255,37 @@ def random_vec(n1: int, n2: int, kmax: int, seed: int, divfree: bool = False) ->
     """A seeded band-limited vector field with unit L2 norm (for operator tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return unit_l2(random_velocity(n1, n2, kmax, rng, divfree=True, compressible=not divfree))
+
+
+# --------------------------------------------------------------------------------------------
+# Learned warm start: seeded draws of initial network weights and of training / test pairs
+# --------------------------------------------------------------------------------------------
+
+def network_init(seed: int = BASE_SEED + 55) -> np.ndarray:
+    """Initial weights of the warm-start network as one flat float32 vector, in the parameter order
+    of the network's interface (lifting 4->32; four Fourier layers of width 32 with 32x16 retained
+    modes; projection 32->64->2).
+
+    Draws only: pointwise weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)); spectral weights
+    (real and imaginary parts) ~ U(0, 1) / (32 * 32), the usual initialisation of Fourier layers.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    C, M, H = 32, 16, 64
+
+    def uni(shape, fan_in):
+        b = 1.0 / math.sqrt(fan_in)
+        return rng.uniform(-b, b, size=shape)
+
+    blocks = [uni((C, 4), 4), uni((C,), 4)]
+    for _ in range(4):
+        blocks += [rng.uniform(0.0, 1.0, size=(2 * M, M, C, C)) / (C * C),
+                   rng.uniform(0.0, 1.0, size=(2 * M, M, C, C)) / (C * C),
+                   uni((C, C), C), uni((C,), C)]
+    blocks += [uni((H, C), C), uni((H,), C), uni((2, H), H), uni((2,), H)]
+    return np.concatenate([b.ravel() for b in blocks]).astype(np.float32)
+
+
+def warmstart_pair(pair: int, n: int) -> Workload:
+    """Pair ``pair`` of the warm-start data set (config 5) at grid size n.  Training pairs use
+    indices 0..4095 at n = 128; test pairs use indices from 100000 on (unseen seeds) at n = 256."""
+    return make_workload(5, pair=pair, n=n)
