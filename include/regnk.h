@@ -86,6 +86,11 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
 /* Release the handle (the workspace stays the caller's). */
 reg_status reg_destroy(reg_problem* h);
 
+/* Replace the image pair of an existing problem (same grid and parameters): m_T, m_R are copied
+ * and checked as in reg_create; the linearisation point is dropped.  Captured launch graphs and
+ * tuned launch shapes stay valid, so one handle can serve a stream of pairs.  Synchronises. */
+reg_status reg_set_images(reg_problem* h, const double* m_T, const double* m_R);
+
 /* Change the stream subsequent calls enqueue on. */
 reg_status reg_set_stream(reg_problem* h, void* hip_stream);
 
@@ -132,11 +137,13 @@ typedef struct {
     double gtol_rel;          /* stop when ||g(v_k)|| / ||g(0)|| <= gtol_rel */
     double armijo_c1;         /* sufficient-decrease constant (1e-4) */
     double armijo_rho;        /* backtracking factor (0.5) */
-    const double* v0;         /* nullable device vector field: warm start */
+    const double* v0;         /* nullable device vector field: warm start (kept if J(v0) < J(0),
+                                 otherwise the solve starts from v = 0: stats.fallback_used) */
 } reg_solve_opts;
 
 typedef struct {
     int32_t newton_iters, pcg_iters, n_matvec, n_pde, backtracks, status;
+    int32_t fallback_used;    /* 1: the warm start v0 did not lower J below J(0); solved from v = 0 */
     double g0_norm;           /* ||g(0)|| at v = 0 (also for a warm start) */
     double g_rel;             /* final ||g|| / ||g(0)|| */
     double J;                 /* final objective */

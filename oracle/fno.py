@@ -11,15 +11,23 @@ module.  It shares nothing with the HIP library: the flat parameter layout and t
 network below are an interface that both sides implement on their own.
 
 Network (arrays shaped (batch, channel, n1, n2); x = 2 pi i / n):
-  a     = [m_T, m_R, (m_R - m_T) D1 m_T, (m_R - m_T) D2 m_T]     4 input features, D = periodic
-          central difference (u(i+1) - u(i-1)) / (2 h), h = 2 pi / n
-  h0    = Wl a + bl                                              lifting 4 -> 32
+  a     = [m_T, D1 m_T, D2 m_T, (D1 m_T)^2, D1 m_T D2 m_T, (D2 m_T)^2, r, r D1 m_T, r D2 m_T]
+          9 input features: D = periodic central difference (u(i+1) - u(i-1)) / (2 h), h = 2 pi / n;
+          r = (m_R - m_T) / s with s = sqrt(mean((m_R - m_T)^2)) (r = 0 if s = 0).  To first order
+          the velocity is linear in the misfit, so the network predicts v / s: the warm start is
+          v0 = s y.  Normalising by s keeps the misfit channels at unit scale (in bfloat16 the
+          difference of two nearly equal images would lose most of its digits)
+  h0    = Wl a + bl                                              lifting 9 -> 32
   z_l   = W_l h_l + b_l + S_l h_l,  h_{l+1} = gelu(z_l) (l < 3), h_4 = z_3
   S_l h = real( sum over retained k of w(k2) O(k) e^{i k.x} ),  O(k)[o] = sum_c H(k)[c] R_l(k)[c, o]
           H(k) = n^-2 sum_x h(x) e^{-i k.x} (Fourier coefficient); retained k1 in {0..15, -16..-1},
           k2 in {0..15}; w(0) = 1 and only the real part of the k2 = 0 column is kept (the
           inverse real FFT convention); w(k2 > 0) = 2 (Hermitian completion)
-  y     = Q2 gelu(Q1 h4 + q1) + q2                              projection 32 -> 64 -> 2
+  y     = B (Q2 gelu(Q1 h4 + q1) + q2)                          projection 32 -> 64 -> 2, then the
+          band limit B u = real( sum over retained k with |k| <= 12 of w(k2) U(k) e^{i k.x} ) (S with
+          identity weights on the disc |k| <= 12 and zero weights on the corners of the retained
+          square): the predicted velocity has no energy where the solutions have none, which the
+          H2 regulariser would weight by |k|^4
   gelu(x) = x Phi(x) (exact, with the normal CDF Phi)
 Loss over a batch: L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2 (Euclidean sums).
 
@@ -35,6 +43,7 @@ Two formulations of the same network:
     matrix product takes operands first stored in float32 and then rounded to bfloat16 (round to
     nearest even), and accumulates exactly (FP64 here); all other arithmetic stays FP64.  This is
     the plain definition of the network evaluated with bfloat16 multiplicands and wide accumulation.
+    The output band limit B is a fixed filter on the velocity itself and always takes exact products.
 The backward pass (reverse mode, by hand) follows the gemm formulation, rounding the operands of
 its products the same way when bf16=True; with bf16=False it is the exact gradient.
 """
@@ -48,9 +57,10 @@ from scipy.special import erf
 WIDTH = 32
 MODES = 16
 LAYERS = 4
-IN_CH = 4
+IN_CH = 9
 OUT_CH = 2
 HIDDEN = 64
+OUT_RADIUS = 12
 
 
 # ----------------------------------------------------------------------------------------------
@@ -100,15 +110,29 @@ def pack(d):
 # ----------------------------------------------------------------------------------------------
 # pieces
 # ----------------------------------------------------------------------------------------------
+def misfit_scale(mT, mR):
+    """s = sqrt(mean((m_R - m_T)^2))."""
+    d = np.asarray(mR, dtype=np.float64) - np.asarray(mT, dtype=np.float64)
+    return float(np.sqrt(np.mean(d * d)))
+
+
 def features(mT, mR):
-    """The 4 input channels of one pair (n1, n2) -> (4, n1, n2)."""
+    """The 9 input channels of one pair (n1, n2) -> ((9, n1, n2), s)."""
     mT = np.asarray(mT, dtype=np.float64)
     mR = np.asarray(mR, dtype=np.float64)
     n1, n2 = mT.shape
     d1 = (np.roll(mT, -1, axis=0) - np.roll(mT, 1, axis=0)) / (2.0 * (2.0 * np.pi / n1))
     d2 = (np.roll(mT, -1, axis=1) - np.roll(mT, 1, axis=1)) / (2.0 * (2.0 * np.pi / n2))
-    mis = mR - mT
-    return np.stack([mT, mR, mis * d1, mis * d2])
+    s = misfit_scale(mT, mR)
+    r = (mR - mT) / s if s > 0.0 else np.zeros_like(mT)
+    return np.stack([mT, d1, d2, d1 * d1, d1 * d2, d2 * d2, r, r * d1, r * d2]), s
+
+
+def predict(theta, mT, mR, bf16=False, spectral="gemm"):
+    """Warm start v0 = s y(features) for one pair."""
+    a, s = features(mT, mR)
+    y, _ = forward(theta, a[None], bf16=bf16, spectral=spectral)
+    return s * y[0]
 
 
 def gelu(x):
@@ -167,6 +191,20 @@ def spectral_conv_fft(h, Rr, Ri):
     return np.fft.irfft2(full * (n1 * n2), s=(n1, n2))
 
 
+def out_mask():
+    """1 on the retained modes with |k| <= OUT_RADIUS, 0 on the rest, shaped (2M rows j, M columns k2)."""
+    k1 = np.array(kept_k1(0))[:, None]
+    k2 = np.arange(MODES)[None, :]
+    return (k1 * k1 + k2 * k2 <= OUT_RADIUS * OUT_RADIUS).astype(np.float64)
+
+
+def band_limit_fft(u):
+    """B u through numpy's real FFTs: S with the identity as mode weights on the disc, per channel."""
+    C = u.shape[1]
+    eye = out_mask()[:, :, None, None] * np.eye(C)[None, None]
+    return spectral_conv_fft(u, eye, np.zeros_like(eye))
+
+
 class _Mul:
     """Products of the gemm formulation, with or without bfloat16 multiplicands."""
 
@@ -196,6 +234,30 @@ def _spectral_gemm(mul, bases, h, Rr, Ri):
     Yp = mul.mm(bases["IC"], Ob)                     # (B,C,n,32): [Re | Im] after the axis-1 inverse
     hp = mul.mm(Yp, bases["G2"])                     # (B,C,n,n)
     return hp, (Zr, Zi)
+
+
+def _band_limit_gemm(mul, bases, u):
+    """B u through the truncated DFT matrices (no mode product: the weights are the identity).
+    This fixed filter acts on the velocity itself and takes exact products also when the network
+    uses bfloat16 multiplicands (the GPU runs it in FP32)."""
+    mul = _Mul(False)
+    M = MODES
+    T = mul.mm(bases["CS"], mul.mm(u, bases["F2"]))
+    Zr = (T[:, :, :2 * M, :M] + T[:, :, 2 * M:, M:]) * out_mask()
+    Zi = (T[:, :, :2 * M, M:] - T[:, :, 2 * M:, :M]) * out_mask()
+    Ob = np.concatenate([np.concatenate([Zr, Zi], axis=3), np.concatenate([-Zi, Zr], axis=3)], axis=2)
+    return mul.mm(mul.mm(bases["IC"], Ob), bases["G2"])
+
+
+def _band_limit_gemm_T(mul, bases, dv):
+    """Transpose of _band_limit_gemm (the products in reverse order, transposed), exact products."""
+    mul = _Mul(False)
+    M = MODES
+    dOb = mul.mm(bases["IC"].T, mul.mm(dv, bases["G2"].T))
+    dZr = (dOb[:, :, :2 * M, :M] + dOb[:, :, 2 * M:, M:]) * out_mask()
+    dZi = (dOb[:, :, :2 * M, M:] - dOb[:, :, 2 * M:, :M]) * out_mask()
+    dT = np.concatenate([np.concatenate([dZr, dZi], axis=3), np.concatenate([-dZi, dZr], axis=3)], axis=2)
+    return mul.mm(mul.mm(bases["CS"].T, dT), bases["F2"].T)
 
 
 def _pointwise(mul, W, x):
@@ -231,7 +293,8 @@ def forward(theta, a, bf16=False, spectral="gemm"):
         cache["h"].append(h)
     zq = _pointwise(mul, P["Q1"], h) + P["q1"][None, :, None, None]
     s = gelu(zq)
-    y = _pointwise(mul, P["Q2"], s) + P["q2"][None, :, None, None]
+    u = _pointwise(mul, P["Q2"], s) + P["q2"][None, :, None, None]
+    y = band_limit_fft(u) if spectral == "fft" else _band_limit_gemm(mul, bases, u)
     cache["zq"], cache["s"] = zq, s
     return y, cache
 
@@ -260,6 +323,7 @@ def backward(cache, dy):
     sum_p = lambda x: x.sum(axis=(0, 2, 3))   # noqa: E731  (bias gradients)
     # projection
     s, zq, h4 = cache["s"], cache["zq"], cache["h"][LAYERS]
+    dy = _band_limit_gemm_T(mul, bases, dy)
     G["Q2"] = mul.ein("boxy,bcxy->oc", dy, s)
     G["q2"] = sum_p(dy)
     ds = mul.ein("oc,boxy->bcxy", P["Q2"], dy)

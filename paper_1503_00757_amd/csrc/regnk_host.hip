@@ -16,6 +16,7 @@
 #include "regnk.h"
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "host_common.hpp"
 
 using namespace regnk;
 
@@ -24,7 +25,7 @@ using namespace regnk;
 // ---------------------------------------------------------------------------------------------
 static thread_local std::string g_err = "no error";
 
-static reg_status fail(reg_status s, const char* fmt, ...) {
+reg_status regnk::fail(reg_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -33,20 +34,6 @@ static reg_status fail(reg_status s, const char* fmt, ...) {
     g_err = buf;
     return s;
 }
-
-#define CK(call)                                                                               \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail(REG_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
-                        __FILE__, __LINE__);                                                   \
-    } while (0)
-
-#define CKS(call)                                                                              \
-    do {                                                                                       \
-        reg_status s_ = (call);                                                                \
-        if (s_ != REG_OK) return s_;                                                           \
-    } while (0)
 
 // ---------------------------------------------------------------------------------------------
 // Workspace layout
@@ -685,11 +672,25 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
     const double g0 = std::sqrt(gg);
     S.g0_norm = g0;
     if (o->v0) {
+        // The warm start is kept only if it lowers the objective below J(0) (the globalisation
+        // needs a descent sequence from the plain start); otherwise the solve restarts from v = 0.
+        const double J0 = J, gg0 = gg;
         CK(hipMemcpyAsync(v, o->v0, n * 8, hipMemcpyDeviceToDevice, P->stream));
-        CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
+        reg_status s0 = gradient_t<T>(P, v, g, W ? kg : nullptr, &J);
         S.n_pde += 2;
-        const double* a[1] = {g};
-        CKS(dots(P, 1, a, a, &gg));
+        if (s0 != REG_OK && s0 != REG_ENONFINITE) return s0;
+        if (s0 == REG_OK) {
+            const double* a[1] = {g};
+            CKS(dots(P, 1, a, a, &gg));
+        }
+        if (s0 != REG_OK || !std::isfinite(J) || !std::isfinite(gg) || !(J < J0)) {
+            S.fallback_used = 1;
+            CK(launch_fill(n, 0.0, v, P->stream));
+            CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
+            S.n_pde += 2;
+            J = J0;
+            gg = gg0;
+        }
     }
     CK(hipMemcpyAsync(v, P->at<double>(P->o.v64), n * 8, hipMemcpyDeviceToDevice, P->stream));
     int k = 0;
@@ -919,6 +920,29 @@ void twiddles(int n, std::vector<cpx<float>>& f, std::vector<cpx<double>>& d) {
 // =============================================================================================
 // C ABI
 // =============================================================================================
+// Copy (and convert) the two images into the workspace and check that they are finite.
+static reg_status load_images(reg_problem* P, const double* m_T, const double* m_R) {
+    const Offsets& o = P->o;
+    if (P->f64) {
+        CK(launch_convert<double>(P->nn, m_T, P->at<double>(o.mT), P->stream));
+        CK(launch_convert<double>(P->nn, m_R, P->at<double>(o.mR), P->stream));
+    } else {
+        CK(launch_convert<float>(P->nn, m_T, P->at<float>(o.mT), P->stream));
+        CK(launch_convert<float>(P->nn, m_R, P->at<float>(o.mR), P->stream));
+        CK(launch_convert<double>(P->nn, m_T, P->at<double>(o.mT64), P->stream));
+        CK(launch_convert<double>(P->nn, m_R, P->at<double>(o.mR64), P->stream));
+    }
+    const double* a[2] = {m_T, m_R};
+    CK(launch_dots<double>(2, a, a, P->nn, P->partial(), P->scal(), P->stream));
+    double r[2];
+    CK(hipMemcpyAsync(r, P->scal(), sizeof r, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    if (!std::isfinite(r[0]) || !std::isfinite(r[1])) return fail(REG_EINVAL, "m_T or m_R contains non-finite values");
+    P->linearized = false;
+    P->matvec_done = false;
+    return REG_OK;
+}
+
 extern "C" {
 
 const char* reg_last_error(void) { return g_err.c_str(); }
@@ -966,28 +990,18 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
     CKC(hipMemcpyAsync(P->ws + o.tw2f, f2.data(), f2.size() * sizeof(f2[0]), hipMemcpyHostToDevice, P->stream));
     CKC(hipMemcpyAsync(P->ws + o.tw1d, d1.data(), d1.size() * sizeof(d1[0]), hipMemcpyHostToDevice, P->stream));
     CKC(hipMemcpyAsync(P->ws + o.tw2d, d2.data(), d2.size() * sizeof(d2[0]), hipMemcpyHostToDevice, P->stream));
-    if (P->f64) {
-        CKC(launch_convert<double>(P->nn, m_T, P->at<double>(o.mT), P->stream));
-        CKC(launch_convert<double>(P->nn, m_R, P->at<double>(o.mR), P->stream));
-    } else {
-        CKC(launch_convert<float>(P->nn, m_T, P->at<float>(o.mT), P->stream));
-        CKC(launch_convert<float>(P->nn, m_R, P->at<float>(o.mR), P->stream));
-        CKC(launch_convert<double>(P->nn, m_T, P->at<double>(o.mT64), P->stream));
-        CKC(launch_convert<double>(P->nn, m_R, P->at<double>(o.mR64), P->stream));
-    }
-    // inputs must be finite
     {
-        const double* a[2] = {m_T, m_R};
-        CKC(launch_dots<double>(2, a, a, P->nn, P->partial(), P->scal(), P->stream));
-        double r[2];
-        CKC(hipMemcpyAsync(r, P->scal(), sizeof r, hipMemcpyDeviceToHost, P->stream));
-        CKC(hipStreamSynchronize(P->stream));
-        if (!std::isfinite(r[0]) || !std::isfinite(r[1]))
-            return cleanup(fail(REG_EINVAL, "m_T or m_R contains non-finite values"));
+        reg_status st = load_images(P, m_T, m_R);
+        if (st != REG_OK) return cleanup(st);
     }
 #undef CKC
     *out = P;
     return REG_OK;
+}
+
+reg_status reg_set_images(reg_problem* h, const double* m_T, const double* m_R) {
+    if (!h || !m_T || !m_R) return fail(REG_EINVAL, "NULL argument");
+    return load_images(h, m_T, m_R);
 }
 
 reg_status reg_destroy(reg_problem* h) {

@@ -36,6 +36,7 @@ class RegSolveOpts(C.Structure):
 class RegSolveStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("n_matvec", C.c_int32),
                 ("n_pde", C.c_int32), ("backtracks", C.c_int32), ("status", C.c_int32),
+                ("fallback_used", C.c_int32),
                 ("g0_norm", C.c_double), ("g_rel", C.c_double), ("J", C.c_double)]
 
     def as_dict(self):
@@ -67,6 +68,20 @@ def lib():
         L.reg_workspace_bytes.argtypes = [C.POINTER(RegParams), C.POINTER(sz)]
         L.reg_create.argtypes = [C.POINTER(RegParams), vp, vp, vp, sz, vp, C.POINTER(vp)]
         L.reg_destroy.argtypes = [vp]
+        L.reg_set_images.argtypes = [vp, vp, vp]
+        f32, i64 = C.c_float, C.c_int64
+        L.reg_fno_param_count.argtypes = [C.POINTER(i64)]
+        L.reg_fno_workspace_bytes.argtypes = [i32, i32, C.POINTER(sz)]
+        L.reg_fno_create.argtypes = [i32, i32, vp, sz, vp, C.POINTER(vp)]
+        L.reg_fno_destroy.argtypes = [vp]
+        L.reg_fno_features.argtypes = [vp, vp, vp, vp, vp]
+        L.reg_fno_target.argtypes = [vp, vp, vp, vp]
+        L.reg_fno_gather.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+        L.reg_fno_forward.argtypes = [vp, vp, vp, vp]
+        L.reg_fno_backward.argtypes = [vp, vp, vp, vp, vp]
+        L.reg_fno_adam.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32]
+        L.reg_fno_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, f32, vp]
+        L.reg_fno_predict.argtypes = [vp, vp, vp, vp, vp]
         L.reg_set_stream.argtypes = [vp, vp]
         L.reg_state_forward.argtypes = [vp, vp, vp]
         L.reg_objective.argtypes = [vp, vp, dp, dp]
@@ -187,3 +202,68 @@ def reg_batch_solve(handles, opts, v_outs, raise_on_error: bool = True):
     if raise_on_error:
         _check(status)
     return status, [S[i] for i in range(n)]
+
+
+def reg_set_images(h, m_T: int, m_R: int):
+    _check(lib().reg_set_images(h, m_T, m_R))
+
+
+# ---- learned warm start (include/regnet.h) -------------------------------------------------------
+REG_FNO_PARAMS = 4201090
+REG_FNO_SYMMETRIES = 8
+
+
+def reg_fno_param_count() -> int:
+    c = C.c_int64()
+    _check(lib().reg_fno_param_count(C.byref(c)))
+    return c.value
+
+
+def reg_fno_workspace_bytes(n: int, batch: int) -> int:
+    b = C.c_size_t()
+    _check(lib().reg_fno_workspace_bytes(n, batch, C.byref(b)))
+    return b.value
+
+
+def reg_fno_create(n: int, batch: int, workspace: int, workspace_bytes: int, stream: int):
+    h = C.c_void_p()
+    _check(lib().reg_fno_create(n, batch, workspace, workspace_bytes, stream, C.byref(h)))
+    return h
+
+
+def reg_fno_destroy(h):
+    _check(lib().reg_fno_destroy(h))
+
+
+def reg_fno_features(h, m_T: int, m_R: int, out: int, scale=None):
+    _check(lib().reg_fno_features(h, m_T, m_R, out, scale))
+
+
+def reg_fno_target(h, v: int, scale: int, out: int):
+    _check(lib().reg_fno_target(h, v, scale, out))
+
+
+def reg_fno_gather(h, data_set: int, nset: int, channels: int, idx: int, sym, out: int):
+    _check(lib().reg_fno_gather(h, data_set, nset, channels, idx, sym, out))
+
+
+def reg_fno_forward(h, params: int, inp: int, out):
+    _check(lib().reg_fno_forward(h, params, inp, out))
+
+
+def reg_fno_backward(h, params: int, target: int, grad: int, loss):
+    _check(lib().reg_fno_backward(h, params, target, grad, loss))
+
+
+def reg_fno_adam(h, params: int, grad: int, m: int, v: int, step: int, lr: float, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8):
+    _check(lib().reg_fno_adam(h, params, grad, m, v, step, lr, beta1, beta2, eps))
+
+
+def reg_fno_train_step(h, params: int, inp: int, target: int, grad: int, m: int, v: int, step: int, lr: float,
+                       loss):
+    _check(lib().reg_fno_train_step(h, params, inp, target, grad, m, v, step, lr, loss))
+
+
+def reg_fno_predict(h, params: int, m_T: int, m_R: int, v0: int):
+    _check(lib().reg_fno_predict(h, params, m_T, m_R, v0))

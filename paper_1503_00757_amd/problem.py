@@ -51,6 +51,15 @@ class Problem:
         except Exception:
             pass
 
+    def set_images(self, mT, mR):
+        """Load a new image pair (same grid and settings) into this handle (reg_set_images)."""
+        if mT.dtype != self.torch.float64 or mR.dtype != self.torch.float64 or tuple(mT.shape) != (self.n1, self.n2) \
+                or tuple(mR.shape) != (self.n1, self.n2):
+            raise ValueError("m_T and m_R must be float64 device tensors of the problem's grid size")
+        self.mT = mT.contiguous()
+        self.mR = mR.contiguous()
+        ffi.reg_set_images(self.h, self.mT.data_ptr(), self.mR.data_ptr())
+
     def vec(self):
         return self.torch.empty((2, self.n1, self.n2), dtype=self.torch.float64, device=self.device)
 

@@ -1,0 +1,305 @@
+"""Learned warm start (``include/regnet.h``): a Fourier neural operator predicts the initial velocity of
+the Gauss-Newton solve (Alg. 1) from (m_T, m_R).  It is trained on the GPU by the library's own
+forward, reverse-pass and Adam kernels on registrations that the plain solver produced, and the
+plain solver stays the judge: ``reg_solve`` drops a warm start that does not lower the objective.
+
+This module only holds device buffers (torch tensors), the training schedule (batch order, learning
+rate) and host timing; every arithmetic step runs in ``libregnk.so``.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import ffi
+from .problem import Problem, batch_solve
+
+N_PARAMS = ffi.REG_FNO_PARAMS
+
+
+class Network:
+    """One network handle for an n x n grid and a fixed batch size."""
+
+    def __init__(self, n: int, batch: int, device, stream=None):
+        import torch
+        self.torch = torch
+        self.n, self.batch, self.device = n, batch, device
+        self.ws_bytes = ffi.reg_fno_workspace_bytes(n, batch)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.h = ffi.reg_fno_create(n, batch, ptr, self.ws_bytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            ffi.reg_fno_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, *shape):
+        return self.torch.empty(shape, dtype=self.torch.float32, device=self.device)
+
+    def features(self, mT, mR, out=None, scale=None):
+        """[9][n][n] float32 input features of one pair (FP64 device fields); the misfit scale s goes
+        to `scale` (a device float64 tensor of one element) when given."""
+        out = self._f32(9, self.n, self.n) if out is None else out
+        ffi.reg_fno_features(self.h, mT.contiguous().data_ptr(), mR.contiguous().data_ptr(), out.data_ptr(),
+                             scale.data_ptr() if scale is not None else None)
+        return out
+
+    def target(self, v, scale, out=None):
+        """[2][n][n] float32 training target v / s of a solved velocity (FP64) and its pair's scale."""
+        out = self._f32(2, self.n, self.n) if out is None else out
+        ffi.reg_fno_target(self.h, v.contiguous().data_ptr(), scale.data_ptr(), out.data_ptr())
+        return out
+
+    def gather(self, data_set, idx, out=None, sym=None):
+        """out[c][b] = data_set[idx[b]][c] mapped by the grid symmetry sym[b] (nullable), for a
+        sample-major data set [N][C][n][n]."""
+        nset, ch = data_set.shape[0], data_set.shape[1]
+        for t in (idx,) if sym is None else (idx, sym):
+            if t.dtype != self.torch.int32 or t.numel() < self.batch or not t.is_cuda:
+                raise ValueError("idx / sym must be device int32 tensors with at least `batch` entries")
+        out = self._f32(ch, self.batch, self.n, self.n) if out is None else out
+        ffi.reg_fno_gather(self.h, data_set.data_ptr(), nset, ch, idx.data_ptr(),
+                           sym.data_ptr() if sym is not None else None, out.data_ptr())
+        return out
+
+    def forward(self, params, inp, out=None):
+        out = self._f32(2, self.batch, self.n, self.n) if out is None else out
+        ffi.reg_fno_forward(self.h, params.data_ptr(), inp.contiguous().data_ptr(), out.data_ptr())
+        return out
+
+    def backward(self, params, target, grad=None, loss=None):
+        grad = self._f32(N_PARAMS) if grad is None else grad
+        ffi.reg_fno_backward(self.h, params.data_ptr(), target.contiguous().data_ptr(), grad.data_ptr(),
+                             loss.data_ptr() if loss is not None else None)
+        return grad
+
+    def adam(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        ffi.reg_fno_adam(self.h, params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, beta1,
+                         beta2, eps)
+
+    def train_step(self, params, inp, target, grad, m, v, step, lr, loss=None):
+        ffi.reg_fno_train_step(self.h, params.data_ptr(), inp.data_ptr(), target.data_ptr(), grad.data_ptr(),
+                               m.data_ptr(), v.data_ptr(), step, lr, loss.data_ptr() if loss is not None else None)
+
+    def predict(self, params, mT, mR, out=None):
+        """FP64 [2][n][n] velocity for one pair (batch-1 handle)."""
+        out = self.torch.empty((2, self.n, self.n), dtype=self.torch.float64, device=self.device) if out is None else out
+        ffi.reg_fno_predict(self.h, params.data_ptr(), mT.contiguous().data_ptr(), mR.contiguous().data_ptr(),
+                            out.data_ptr())
+        return out
+
+
+class WarmStart:
+    """Network parameters (float32 master copy on the device), Adam state and the training loop."""
+
+    def __init__(self, params, device):
+        import torch
+        self.torch = torch
+        self.device = device
+        p = torch.as_tensor(params, dtype=torch.float32)
+        if p.numel() != N_PARAMS:
+            raise ValueError(f"expected {N_PARAMS} parameters, got {p.numel()}")
+        self.params = p.to(device).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step = 0
+        self._pred = {}
+
+    def train(self, feats, targets, epochs, batch=16, lr=1e-3, lr_final=5e-5, seed=0, log=None, augment=True):
+        """Adam on (1/B) sum ||y - t||^2 / ||t||^2 over shuffled batches; cosine learning-rate decay from
+        lr to lr_final.  feats: [N][9][n][n], targets: [N][2][n][n] normalised velocities v / s
+        (float32, device).  With augment, every sample of a batch is mapped by a random one of the 8
+        symmetries of the periodic square grid (exact for the discrete problem).  Returns the mean
+        training loss of every epoch."""
+        torch = self.torch
+        N, n = feats.shape[0], feats.shape[-1]
+        if N < batch:
+            raise ValueError("fewer samples than one batch")
+        net = Network(n, batch, self.device)
+        inp = net._f32(feats.shape[1], batch, n, n)
+        tgt = net._f32(2, batch, n, n)
+        steps_per_epoch = N // batch
+        total = epochs * steps_per_epoch
+        losses = torch.zeros(steps_per_epoch, dtype=torch.float64, device=self.device)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        history = []
+        done = 0
+        for ep in range(epochs):
+            order = torch.tensor(rng.permutation(N)[:steps_per_epoch * batch].astype(np.int32), device=self.device)
+            syms = torch.tensor(rng.integers(0, ffi.REG_FNO_SYMMETRIES, steps_per_epoch * batch).astype(np.int32),
+                                device=self.device) if augment else None
+            for i in range(steps_per_epoch):
+                idx = order[i * batch:(i + 1) * batch]
+                sym = syms[i * batch:(i + 1) * batch] if augment else None
+                net.gather(feats, idx, inp, sym)
+                net.gather(targets, idx, tgt, sym)
+                self.step += 1
+                frac = done / max(1, total - 1)
+                lr_i = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * frac))
+                ffi.reg_fno_train_step(net.h, self.params.data_ptr(), inp.data_ptr(), tgt.data_ptr(),
+                                       self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.step,
+                                       lr_i, losses.data_ptr() + 8 * i)
+                done += 1
+            history.append(float(losses.mean().item()))
+            if log:
+                log(f"epoch {ep + 1}/{epochs}: training loss {history[-1]:.4f}")
+        net.close()
+        return history
+
+    def evaluate(self, feats, targets, batch=16):
+        """Mean relative squared error over a data set (no parameter change)."""
+        torch = self.torch
+        N, n = feats.shape[0], feats.shape[-1]
+        b = min(batch, N)
+        net = Network(n, b, self.device)
+        inp, tgt = net._f32(feats.shape[1], b, n, n), net._f32(2, b, n, n)
+        grad = torch.empty_like(self.params)
+        nb = N // b
+        losses = torch.zeros(nb, dtype=torch.float64, device=self.device)
+        for i in range(nb):
+            idx = torch.arange(i * b, (i + 1) * b, dtype=torch.int32, device=self.device)
+            net.gather(feats, idx, inp)
+            net.gather(targets, idx, tgt)
+            net.forward(self.params, inp)
+            net.backward(self.params, tgt, grad, losses[i:i + 1])
+        out = float(losses.mean().item())
+        net.close()
+        return out
+
+    def predict(self, mT, mR, out=None):
+        n = mT.shape[-1]
+        if n not in self._pred:
+            self._pred[n] = Network(n, 1, self.device)
+        return self._pred[n].predict(self.params, mT, mR, out)
+
+
+# ---- data set and evaluation helpers ---------------------------------------------------------------
+SOLVER = dict(norm="H2", constraint="mass_source", beta_v=1e-3, beta_w=1e-4, precision="fp32")
+
+
+def transport_reference(mT, vstar, nt, device, **settings):
+    """m_R = m_T transported by v* (the library's FP64 state solve)."""
+    import torch
+    s = dict(SOLVER, **settings)
+    P = Problem(mT, mT, nt, **s)
+    m1 = P.state_forward(torch.as_tensor(vstar, dtype=torch.float64, device=device))
+    P.close()
+    return m1
+
+
+def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settings):
+    """Features and plain-solver labels for a list of (m_T, v*) numpy pairs of one grid size.
+
+    Returns (feats [N][9][n][n], labels [N][2][n][n], stats list); the labels are the velocities of the
+    plain solves (v0 = 0) to ||g|| / ||g(0)|| <= label_gtol divided by each pair's misfit scale,
+    solved `pool` at a time with reg_batch_solve on handles reused through reg_set_images."""
+    import torch
+    s = dict(SOLVER, **settings)
+    N = len(pairs)
+    n = pairs[0][0].shape[0]
+    feats = torch.empty((N, 9, n, n), dtype=torch.float32, device=device)
+    scale = torch.empty(1, dtype=torch.float64, device=device)
+    labels = torch.empty((N, 2, n, n), dtype=torch.float32, device=device)
+    net = Network(n, 1, device)
+    gen = None
+    probs = []
+    all_stats = []
+    t0 = time.perf_counter()
+    for c0 in range(0, N, pool):
+        chunk = pairs[c0:c0 + pool]
+        imgs = []
+        for mT_np, vs in chunk:
+            mT = torch.as_tensor(mT_np, dtype=torch.float64, device=device)
+            if gen is None:
+                gen = Problem(mT, mT, nt, **s)
+            gen.set_images(mT, mT)
+            mR = gen.state_forward(torch.as_tensor(vs, dtype=torch.float64, device=device))
+            imgs.append((mT, mR))
+        while len(probs) < len(chunk):
+            probs.append(Problem(imgs[len(probs)][0], imgs[len(probs)][1], nt, **s))
+        for p, (mT, mR) in zip(probs, imgs):
+            p.set_images(mT, mR)
+        vs_out, st = batch_solve(probs[:len(chunk)], raise_on_error=False, gtol_rel=label_gtol)
+        for i, (v, (mT, mR)) in enumerate(zip(vs_out, imgs)):
+            net.features(mT, mR, feats[c0 + i], scale)
+            net.target(v, scale, labels[c0 + i])
+        all_stats += st
+        if log and (c0 // pool) % 64 == 0:
+            log(f"labels {c0 + len(chunk)}/{N} ({time.perf_counter() - t0:.1f} s)")
+    for p in probs:
+        p.close()
+    if gen is not None:
+        gen.close()
+    net.close()
+    return feats, labels, all_stats
+
+
+def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup=1, log=None, **settings):
+    """Time to ||g|| / ||g(0)|| <= gtol for every (m_T, v*) pair: plain solve (v0 = 0) and learned solve
+    (network inference + solve from its v0, which includes g(0) and g(v0)) on one problem handle.
+    Returns per-pair records."""
+    import torch
+    s = dict(SOLVER, **settings)
+    recs = []
+    P = None
+    gen = None
+    for i, (mT_np, vs) in enumerate(pairs):
+        mT = torch.as_tensor(mT_np, dtype=torch.float64, device=device)
+        if gen is None:
+            gen = Problem(mT, mT, nt, **s)
+        gen.set_images(mT, mT)
+        mR = gen.state_forward(torch.as_tensor(vs, dtype=torch.float64, device=device))
+        if P is None:
+            P = Problem(mT, mR, nt, **s)
+            for _ in range(warmup):   # graph capture and first-touch costs, not timed
+                P.solve(gtol_rel=gtol, raise_on_error=False)
+                ws.predict(mT, mR)
+        P.set_images(mT, mR)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, sp = P.solve(gtol_rel=gtol, raise_on_error=False)
+        t1 = time.perf_counter()
+        v0 = ws.predict(mT, mR)
+        _, sl = P.solve(gtol_rel=gtol, v0=v0, raise_on_error=False)
+        t2 = time.perf_counter()
+        recs.append({"plain_s": t1 - t0, "learned_s": t2 - t1, "plain": sp, "learned": sl})
+        if log and i % 32 == 0:
+            log(f"pair {i}: plain {1e3 * (t1 - t0):.1f} ms ({sp['newton_iters']} GN, {sp['pcg_iters']} PCG), "
+                f"learned {1e3 * (t2 - t1):.1f} ms ({sl['newton_iters']} GN, {sl['pcg_iters']} PCG, "
+                f"fallback {sl['fallback_used']})")
+    if P is not None:
+        P.close()
+    if gen is not None:
+        gen.close()
+    return recs
+
+
+def summarize(recs):
+    import statistics as stt
+    f = lambda k, sub: [r[sub][k] for r in recs]   # noqa: E731
+    return {
+        "pairs": len(recs),
+        "plain_ms_mean": 1e3 * stt.mean(r["plain_s"] for r in recs),
+        "learned_ms_mean": 1e3 * stt.mean(r["learned_s"] for r in recs),
+        "plain_ms_median": 1e3 * stt.median(r["plain_s"] for r in recs),
+        "learned_ms_median": 1e3 * stt.median(r["learned_s"] for r in recs),
+        "plain_newton_mean": stt.mean(f("newton_iters", "plain")),
+        "learned_newton_mean": stt.mean(f("newton_iters", "learned")),
+        "plain_pcg_mean": stt.mean(f("pcg_iters", "plain")),
+        "learned_pcg_mean": stt.mean(f("pcg_iters", "learned")),
+        "plain_converged": sum(1 for r in recs if r["plain"]["g_rel"] <= 1e-2 and r["plain"]["status"] == 0),
+        "learned_converged": sum(1 for r in recs if r["learned"]["g_rel"] <= 1e-2 and r["learned"]["status"] == 0),
+        "fallback_rate": stt.mean(f("fallback_used", "learned")),
+        "faster_fraction": sum(1 for r in recs if r["learned_s"] < r["plain_s"]) / len(recs),
+    }

@@ -263,7 +263,7 @@ def random_vec(n1: int, n2: int, kmax: int, seed: int, divfree: bool = False) ->
 
 def network_init(seed: int = BASE_SEED + 55) -> np.ndarray:
     """Initial weights of the warm-start network as one flat float32 vector, in the parameter order
-    of the network's interface (lifting 4->32; four Fourier layers of width 32 with 32x16 retained
+    of the network's interface (lifting 9->32; four Fourier layers of width 32 with 32x16 retained
     modes; projection 32->64->2).
 
     Draws only: pointwise weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)); spectral weights
@@ -276,7 +276,7 @@ def network_init(seed: int = BASE_SEED + 55) -> np.ndarray:
         b = 1.0 / math.sqrt(fan_in)
         return rng.uniform(-b, b, size=shape)
 
-    blocks = [uni((C, 4), 4), uni((C,), 4)]
+    blocks = [uni((C, 9), 9), uni((C,), 9)]
     for _ in range(4):
         blocks += [rng.uniform(0.0, 1.0, size=(2 * M, M, C, C)) / (C * C),
                    rng.uniform(0.0, 1.0, size=(2 * M, M, C, C)) / (C * C),

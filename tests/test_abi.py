@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(R.RegParams) == 8 * 4 + 2 * 8
     assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 8
-    assert ctypes.sizeof(R.RegSolveStats) == 6 * 4 + 3 * 8
+    assert ctypes.sizeof(R.RegSolveStats) == 7 * 4 + 4 + 3 * 8   # 4 bytes of padding before the doubles
 
 
 def test_workspace_bytes_scales_with_grid_and_steps():

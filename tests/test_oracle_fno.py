@@ -33,7 +33,7 @@ def test_bf16_rounding_matches_torch():
 def test_param_count():
     C, M = 32, 16
     per_layer = 2 * (2 * M * M * C * C) + C * C + C
-    assert fno.param_count() == C * 4 + C + 4 * per_layer + 64 * C + 64 + 2 * 64 + 2 == 4200930
+    assert fno.param_count() == C * 9 + C + 4 * per_layer + 64 * C + 64 + 2 * 64 + 2 == 4201090
     th = _theta(0)
     np.testing.assert_array_equal(fno.pack(fno.unpack(th)), th)
 
@@ -42,7 +42,7 @@ def test_param_count():
 def test_gemm_formulation_equals_fft_formulation(n):
     rng = np.random.default_rng(2)
     th = _theta(3)
-    a = rng.standard_normal((2, 4, n, n))
+    a = rng.standard_normal((2, 9, n, n))
     y_fft, _ = fno.forward(th, a, spectral="fft")
     y_gemm, _ = fno.forward(th, a, spectral="gemm")
     assert np.abs(y_fft - y_gemm).max() <= 1e-12 * np.abs(y_fft).max()
@@ -82,6 +82,32 @@ def test_spectral_layer_on_single_modes(form):
         assert np.abs(S(np.cos(k1 * X1 + k2 * X2))).max() < 1e-13
 
 
+@pytest.mark.parametrize("form", ["fft", "gemm"])
+def test_band_limit_closed_forms(form):
+    """B keeps the retained modes with |k| <= 12 and removes all others; it is symmetric."""
+    n = 64
+    X1, X2 = _grid(n)
+
+    def Bop(u):
+        u = u[None, None]
+        if form == "fft":
+            return fno.band_limit_fft(u)[0, 0]
+        return fno._band_limit_gemm(fno._Mul(False), fno.dft_bases(n), u)[0, 0]
+
+    for k1, k2 in [(0, 0), (3, 0), (-7, 5), (12, 0), (-8, 8), (0, 12), (5, -10), (-10, -6)]:
+        for f in (np.cos, np.sin):
+            u = f(k1 * X1 + k2 * X2)
+            np.testing.assert_allclose(Bop(u), u, atol=1e-13)
+    for k1, k2 in [(16, 3), (20, 0), (2, 16), (-17, 1), (9, 9), (-13, 0), (12, 1), (5, -11), (15, 15), (-16, 0)]:
+        assert np.abs(Bop(np.cos(k1 * X1 + k2 * X2))).max() < 1e-13, (k1, k2)
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal((2, n, n))
+    assert abs((Bop(a) * b).sum() - (a * Bop(b)).sum()) < 1e-10 * np.abs(a).sum()
+    if form == "gemm":
+        mul, bases = fno._Mul(False), fno.dft_bases(n)
+        np.testing.assert_allclose(fno._band_limit_gemm_T(mul, bases, b[None, None])[0, 0], Bop(b), atol=1e-12)
+
+
 def test_dft_bases_closed_forms():
     n = 64
     b = fno.dft_bases(n)
@@ -117,12 +143,22 @@ def test_features_closed_form():
     X1, X2 = _grid(n)
     h = 2 * np.pi / n
     mT = np.sin(X1) + np.cos(2 * X2)
-    mR = mT + 0.5
-    a = fno.features(mT, mR)
-    np.testing.assert_allclose(a[0], mT)
-    np.testing.assert_allclose(a[1], mR)
-    np.testing.assert_allclose(a[2], 0.5 * np.cos(X1) * np.sin(h) / h, atol=1e-14)
-    np.testing.assert_allclose(a[3], 0.5 * -2 * np.sin(2 * X2) * np.sin(2 * h) / (2 * h), atol=1e-14)
+    mR = mT + 0.5 * np.cos(X2)                      # misfit cos(x2) / 2: rms 1 / (2 sqrt 2)
+    a, s = fno.features(mT, mR)
+    assert abs(s - 0.5 / np.sqrt(2.0)) < 1e-15
+    d1 = np.cos(X1) * np.sin(h) / h                   # central differences of sin, cos
+    d2 = -2 * np.sin(2 * X2) * np.sin(2 * h) / (2 * h)
+    r = np.sqrt(2.0) * np.cos(X2)
+    want = [mT, d1, d2, d1 * d1, d1 * d2, d2 * d2, r, r * d1, r * d2]
+    for c in range(9):
+        np.testing.assert_allclose(a[c], want[c], atol=1e-14)
+    a0, s0 = fno.features(mT, mT)                     # identical images: no misfit channels
+    assert s0 == 0.0 and not a0[6:].any()
+    th = _theta(2)
+    assert not fno.predict(th, mT, mT).any()
+    v1 = fno.predict(th, mT, mR)
+    v2 = fno.predict(th, mT, mT + 3.0 * (mR - mT))    # the warm start scales with the misfit
+    np.testing.assert_allclose(v2, 3.0 * v1, rtol=1e-12, atol=1e-15)
 
 
 def test_loss_closed_form():
@@ -143,7 +179,7 @@ def test_gradient_matches_finite_differences_per_block():
     n = 32
     rng = np.random.default_rng(6)
     th = _theta(7, 0.08)
-    a = rng.standard_normal((2, 4, n, n))
+    a = rng.standard_normal((2, 9, n, n))
     t = rng.standard_normal((2, 2, n, n))
     y, cache = fno.forward(th, a)
     _, dy = fno.loss(y, t)
@@ -155,7 +191,7 @@ def test_gradient_matches_finite_differences_per_block():
         k = int(np.prod(shp))
         d = np.zeros_like(th)
         d[off:off + k] = rng.standard_normal(k)
-        eps = 1e-5 * np.linalg.norm(th) / np.linalg.norm(d)
+        eps = 1e-5 * np.linalg.norm(th[off:off + k]) / np.linalg.norm(d)   # relative to the block
         fd = (f(th + eps * d) - f(th - eps * d)) / (2 * eps)
         an = float(g @ d)
         # truncation O(eps^2) plus the rounding of L in the difference quotient
@@ -168,7 +204,7 @@ def test_bf16_network_stays_close_to_exact():
     n = 32
     rng = np.random.default_rng(8)
     th = _theta(9)
-    a = rng.standard_normal((2, 4, n, n))
+    a = rng.standard_normal((2, 9, n, n))
     t = rng.standard_normal((2, 2, n, n))
     y, c = fno.forward(th, a)
     yb, cb = fno.forward(th, a, bf16=True)
