@@ -12,9 +12,11 @@ regularisation + projection assembly), one preconditioner application and the FP
 products and vector updates.  ``value`` = steps per second = matvecs per second.
 
 Also reported: the dominant kernel's achieved HBM bandwidth against the 8 TB/s peak (hipEvents around
-back-to-back launches of that kernel on the library's stream), the time to ||g||/||g(0)|| <= 1e-2 of
-the plain solver on the same workload, matvec throughput and roofline fraction at 1024^2 / n_t = 32,
-and the FP64 CPU oracle timed on the host cores on a bounded sample (rank 0 only).
+its launches inside real matvecs on the library's stream), the time to ||g||/||g(0)|| <= 1e-2 of the
+plain solver on the same workload, matvec throughput and roofline fraction at 1024^2 / n_t = 32, the
+learned warm start (config 5: a Fourier network trained on the GPU by the library's kernels on 4096
+plain-solver registrations at 128^2, then plain vs learned time to ||g||/||g(0)|| <= 1e-2 on 256
+unseen pairs at 256^2), and the FP64 CPU oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -190,6 +192,93 @@ def bench_batch(npairs=96):
             "speedup_vs_sequential": round(t_seq / t_batch, 2), "per_size": sizes, "data": "synthetic"}
 
 
+def _single_thread():
+    """Pool-worker initialiser: one BLAS / OpenMP thread per worker (set before numpy loads in the
+    worker, which is when its thread pools are sized)."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    import numpy  # noqa: F401
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _warmstart_pair(args):
+    import synthdata as sd
+    p, n = args
+    w = sd.warmstart_pair(p, n)
+    return w.mT, w.vstar
+
+
+def warmstart_pairs(ntrain, ntest, ntr=128, nte=256):
+    """Seeded pairs of the warm-start data set, drawn on the host cores before the GPU is touched:
+    training pairs 0..ntrain-1 at ntr^2, unseen test pairs from index 100000 on at nte^2."""
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 4))
+    with ProcessPoolExecutor(workers, initializer=_single_thread) as ex:
+        train = list(ex.map(_warmstart_pair, [(p, ntr) for p in range(ntrain)], chunksize=32))
+        test = list(ex.map(_warmstart_pair, [(100000 + p, nte) for p in range(ntest)], chunksize=4))
+    return train, test
+
+
+def bench_warmstart(train, test, epochs=60, label_gtol=1e-3):
+    """Config 5: label the training pairs with the plain solver, train the warm-start network with the
+    library's kernels (Adam, batch 16, grid-symmetry augmentation), then time the plain and the
+    learned solve (network inference + solve from its v0, which includes g(0) and g(v0)) to
+    ||g||/||g(0)|| <= 1e-2 on every unseen test pair, on one problem handle."""
+    import torch
+    import synthdata as sd
+    from paper_1503_00757_amd import warmstart as W
+    dev = torch.device("cuda:0")
+    log = lambda m: print(f"[bench] c5 {m}", file=sys.stderr, flush=True)   # noqa: E731
+    t0 = time.perf_counter()
+    feats, labels, st = W.build_dataset(train, 16, dev, label_gtol=label_gtol, pool=16, log=log)
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - t0
+    ws = W.WarmStart(sd.network_init(), dev)
+    nval = max(16, len(train) // 16)
+    t0 = time.perf_counter()
+    hist = ws.train(feats[:-nval], labels[:-nval], epochs, batch=16,
+                    log=lambda m: log(m) if m.startswith("epoch") and int(m.split()[1].split("/")[0]) % 10 == 0 else None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = epochs * ((len(train) - nval) // 16)
+    val = ws.evaluate(feats[-nval:], labels[-nval:])
+    del feats, labels
+    # inference latency at the test size (features + network + rescale), events on the current stream
+    mT = torch.tensor(test[0][0], device=dev)
+    ws.predict(mT, mT)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        ws.predict(mT, mT)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / 20
+    log(f"comparing plain vs learned on {len(test)} unseen pairs")
+    recs = W.compare_plain_vs_learned(test, 16, ws, dev, log=log)
+    s = W.summarize(recs)
+    return {
+        "protocol": f"train {len(train) - nval} pairs at {train[0][0].shape[0]}^2 (+{nval} held out), "
+                    f"{epochs} epochs; test {len(test)} unseen pairs at {test[0][0].shape[0]}^2; "
+                    "H2 + mass source, beta_v=1e-3, beta_w=1e-4, n_t=16, FP32 transport",
+        "time_to_grel_1e-2_ms": {"plain_mean": round(s["plain_ms_mean"], 3), "learned_mean": round(s["learned_ms_mean"], 3),
+                                 "plain_median": round(s["plain_ms_median"], 3),
+                                 "learned_median": round(s["learned_ms_median"], 3),
+                                 "speedup_mean": round(s["plain_ms_mean"] / s["learned_ms_mean"], 3)},
+        "newton_mean": {"plain": s["plain_newton_mean"], "learned": s["learned_newton_mean"]},
+        "pcg_mean": {"plain": s["plain_pcg_mean"], "learned": s["learned_pcg_mean"]},
+        "converged": {"plain": s["plain_converged"], "learned": s["learned_converged"]},
+        "fallback_rate": s["fallback_rate"], "faster_fraction": s["faster_fraction"],
+        "label_seconds": round(t_labels, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
+        "train_ms_per_step_batch16": round(t_train / steps * 1e3, 3),
+        "train_loss_last_epoch": round(hist[-1], 5), "heldout_rel_sq_error": round(val, 5),
+        "inference_ms": round(t_inf, 3),
+    }
+
+
 def cpu_baseline(budget_s=12.0):
     """The FP64 oracle's GN matvec on the host cores (bounded sample of the same workload)."""
     import numpy as np
@@ -223,9 +312,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the solve and 1024^2 measurements")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: 256^2 headline workload (default); c3: 1024^2, n_t=32 (profiling); "
-                         "c4: 96-pair batched solve")
+                         "c4: 96-pair batched solve; c5: learned warm start alone")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg (config 5)")
+    ap.add_argument("--warmstart-train", type=int, default=4096)
+    ap.add_argument("--warmstart-test", type=int, default=256)
+    ap.add_argument("--warmstart-epochs", type=int, default=60)
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file with launch shapes chosen by an earlier run (written if missing)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -235,6 +328,11 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the single-pair path "
               "does not shard across GPUs; see the design notes for how it would)", file=sys.stderr)
         sys.exit(2)
+    ws_pairs = None
+    if args.workload == "c5" or (args.workload == "c2" and not args.no_extras and not args.no_warmstart):
+        t0 = time.perf_counter()
+        ws_pairs = warmstart_pairs(args.warmstart_train, args.warmstart_test)
+        print(f"[bench] c5 pairs drawn in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     import torch
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -248,6 +346,14 @@ def main():
         del a, b
     if args.workload == "c4":
         print(json.dumps(bench_batch()))
+        return
+    if args.workload == "c5":
+        r = bench_warmstart(*ws_pairs, epochs=args.warmstart_epochs)
+        t = r["time_to_grel_1e-2_ms"]
+        print(json.dumps({"metric": "time to ||g||/||g(0)|| <= 1e-2 at 256^2, learned warm start (config 5)",
+                          "value": t["learned_mean"], "unit": "ms", "higher_is_better": False,
+                          "plain_value": t["plain_mean"], "n_gpus": 1, "dtype": "f32 transport, bf16 network",
+                          "data": "synthetic", **r}))
         return
     cfg = 2 if args.workload == "c2" else 3
     print(f"[bench] workload {args.workload} setup", file=sys.stderr, flush=True)
@@ -275,6 +381,9 @@ def main():
                                     "model_bytes_per_matvec": bmodel,
                                     "model_frac_of_8TBs": round(bmodel / t3 / 8e12, 4),
                                     "dominant_kernel": rl3}
+    if ws_pairs is not None:
+        print("[bench] c5 learned warm start", file=sys.stderr, flush=True)
+        extras["c5_warm_start"] = bench_warmstart(*ws_pairs, epochs=args.warmstart_epochs)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
