@@ -165,15 +165,19 @@ reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
 reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const reg_solve_opts* opts,
                            double* const* v_out, reg_solve_stats* stats_host);
 
-/* Measurement hook: run `reps` (1..1000) Hessian matvecs at the current linearisation point with
- * hipEvents recorded on the problem's stream right before and after every launch of one of the four
- * RK2-stage launches of a time step, and report that launch's mean device time and its compulsory
- * HBM bytes (each operand field read once, each result written once).  Overwrites PCG scratch.
+/* Measurement hook: run `reps` (1..1000, reps * nt <= 512) Hessian matvecs at the current
+ * linearisation point and time every launch of one of the four RK2-stage launches of a time step:
+ * ms_per_launch_host = mean dispatch interval, from start / end events that the dispatch itself
+ * stamps (what a profiler reports as the kernel's duration); exec_ms_host (nullable) = mean
+ * execution interval of its blocks on the device wall clock (latest block end, after its stores
+ * completed, minus earliest block start); the difference is the workgroup dispatch ramp and the
+ * end-of-kernel completion.  bytes_per_launch_host = the launch's compulsory HBM bytes (each
+ * operand field read once, each result written once).  Overwrites PCG scratch.
  * which: 0 GN incremental-adjoint stage 2 (the busiest launch: it also accumulates the body force),
  * 1 incremental-state stage 2, 2 GN incremental-adjoint stage 1, 3 incremental-state stage 1.
  * REG_ESTATE before the first reg_hessian_matvec.  Synchronises the stream. */
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms_per_launch_host,
-                         double* bytes_per_launch_host);
+                         double* bytes_per_launch_host, double* exec_ms_host);
 
 /* Launch-shape autotuner for the FP32 transport stages on square grids of 64+ points (elements per
  * thread of the row and column register FFTs, threads per block): times every available shape of
@@ -185,7 +189,7 @@ reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms
 reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes);
 
 /* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): one shape index in
- * [0, 8) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
+ * [0, 9) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
  * state 2, gradient}; count must be 7. */
 reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count);
 

@@ -39,13 +39,19 @@ struct StageArgs {
     T* B;                    // body-force accumulator (vector field)
     const cpx<T>* tw1;       // twiddles of length n1 (column transforms)
     const cpx<T>* tw2;       // twiddles of length n2 (row transforms)
+    unsigned long long* clk; // timing (nullable): block b stores its start / end (device wall clock)
+                             // to clk[2b], clk[2b+1]; a stage has at most (n1 + n2) / 2 blocks
 };
+// clk[2 i] = ~0, clk[2 i + 1] = 0 for i < pairs (before timed stages)
+hipError_t launch_clk_init(unsigned long long* clk, int pairs, hipStream_t s);
 
-constexpr int NUM_STAGE_VARIANTS = 8;
+constexpr int NUM_STAGE_VARIANTS = 9;
 // var: launch-shape variant (0 = default; see transport_kernels.hpp).  FP32 stages exist for the
 // matvec ops (OP_A1, OP_A2, OP_I1, OP_I2); the state ops run in FP64.
+// t0 / t1 (nullable): events stamped by the dispatch itself at the stage's start and end (timing).
 template <typename T>
-hipError_t launch_stage(int op, int var, const StageArgs<T>& a, hipStream_t s);
+hipError_t launch_stage(int op, int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
 // m1 = Q + C (FP64); lam (nullable) = m_R - m1 in precision T
 template <typename T>
 hipError_t launch_finalize_state(long nn, const double* Q, const double* C, const double* mR, double* m1, T* lam,

@@ -48,12 +48,12 @@ constexpr long OFF_q2 = OFF_Q2 + FNO_OUT * FNO_H;
 constexpr long N_PARAMS = OFF_q2 + FNO_OUT;
 static_assert(N_PARAMS == REG_FNO_PARAMS, "parameter layout");
 
-constexpr int KSPLIT_MAX = 256;
+constexpr int KSPLIT_MAX = 1024;   // weight gradients: K = P split into chunks of >= 512
 constexpr long PART_FLOATS = (long)KSPLIT_MAX * FNO_H * FNO_C;
 
 struct NetLayout {
     size_t F2, CS, IC, G2, in, y, u, du, h[FNO_L + 1], z[FNO_L - 1], zq, s, hp, Y, Yp, T, Zs[FNO_L], O, dZ, Wexp, dWexp, dy,
-        dzq, dA, dB, part, sums, loss, red, sq, scale, total;
+        dzq, dA, dB, part, rsum, sums, loss, red, sq, scale, total;
 };
 
 NetLayout net_layout(int n, int B) {
@@ -91,6 +91,7 @@ NetLayout net_layout(int n, int B) {
     L.dA = take(FNO_C * P * f);
     L.dB = take(FNO_C * P * f);
     L.part = take(PART_FLOATS * f);
+    L.rsum = take((size_t)FNO_H * RS_CHUNKS * sizeof(double));
     L.sums = take(2 * (size_t)B * sizeof(double));
     L.loss = take(sizeof(double));
     L.red = take(RED_BLOCKS * sizeof(double));
@@ -142,7 +143,7 @@ reg_status wgrad(reg_fno* F, int M, int N, const float* A, const float* X, float
     g.M = M; g.N = N; g.K = (int)F->P;
     g.A = A; g.am = F->P; g.ak = 1;
     g.B = X; g.bk = 1; g.bn = F->P;
-    g.ksplit = (int)std::min<long>(KSPLIT_MAX, std::max<long>(1, F->P / 2048));
+    g.ksplit = (int)std::min<long>(KSPLIT_MAX, std::max<long>(1, F->P / 512));
     g.part = F->f(F->L.part);
     CK(launch_gemm(g, F->stream));
     CK(launch_splitk_reduce(g.ksplit, M, N, g.part, 1.0f, 0.0f, out, cm, 1, F->stream));
@@ -354,7 +355,7 @@ reg_status backward_impl(reg_fno* F, const float* th, const float* target, float
     dy = F->f(L.du);   // from here on: the gradient with respect to u
     // projection
     CKS(wgrad(F, FNO_OUT, FNO_H, dy, F->f(L.s), grad + OFF_Q2, FNO_H));
-    CK(launch_rowsum(FNO_OUT, P, dy, grad + OFF_q2, F->stream));
+    CK(launch_rowsum(FNO_OUT, P, dy, F->at<double>(L.rsum), grad + OFF_q2, F->stream));
     {   // dzq = (Q2^T dy) * gelu'(zq)
         GemmArgs g = gemm0();
         g.M = FNO_H; g.N = (int)P; g.K = FNO_OUT;
@@ -365,7 +366,7 @@ reg_status backward_impl(reg_fno* F, const float* th, const float* target, float
         CKS(gemm(F, g));
     }
     CKS(wgrad(F, FNO_H, FNO_C, dzq, F->f(L.h[FNO_L]), grad + OFF_Q1, FNO_C));
-    CK(launch_rowsum(FNO_H, P, dzq, grad + OFF_q1, F->stream));
+    CK(launch_rowsum(FNO_H, P, dzq, F->at<double>(L.rsum), grad + OFF_q1, F->stream));
     float* cur = F->f(L.dA);
     float* nxt = F->f(L.dB);
     {   // dh4 = Q1^T dzq (the last Fourier layer has no activation: this is dz_3)
@@ -379,7 +380,7 @@ reg_status backward_impl(reg_fno* F, const float* th, const float* target, float
     for (int l = FNO_L - 1; l >= 0; --l) {
         const float* dz = cur;
         CKS(wgrad(F, FNO_C, FNO_C, dz, F->f(L.h[l]), grad + off_W(l), FNO_C));
-        CK(launch_rowsum(FNO_C, P, dz, grad + off_B(l), F->stream));
+        CK(launch_rowsum(FNO_C, P, dz, F->at<double>(L.rsum), grad + off_B(l), F->stream));
         {   // dYp = dz . G2^T
             GemmArgs g = gemm0();
             g.M = S * n; g.N = 32; g.K = n;
@@ -447,7 +448,7 @@ reg_status backward_impl(reg_fno* F, const float* th, const float* target, float
         std::swap(cur, nxt);
     }
     CKS(wgrad(F, FNO_C, FNO_IN, cur, F->f(L.in), grad + OFF_WL, FNO_IN));
-    CK(launch_rowsum(FNO_C, P, cur, grad + OFF_BL, F->stream));
+    CK(launch_rowsum(FNO_C, P, cur, F->at<double>(L.rsum), grad + OFF_BL, F->stream));
     return REG_OK;
 }
 

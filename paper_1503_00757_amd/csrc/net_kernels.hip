@@ -180,13 +180,26 @@ __global__ void fold_w_kernel(const float* __restrict__ dW, float* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(TB) void rowsum_kernel(long len, const float* __restrict__ x, float* __restrict__ out) {
+// block (chunk, row): the chunk-th of RS_CHUNKS contiguous pieces of row `row`
+__global__ __launch_bounds__(TB) void rowsum_part_kernel(long len, const float* __restrict__ x,
+                                                         double* __restrict__ part) {
     __shared__ double sh[TB / 64];
-    const float* row = x + (long)blockIdx.x * len;
+    const long piece = (len + RS_CHUNKS - 1) / RS_CHUNKS;
+    const long lo = (long)blockIdx.x * piece;
+    const long hi = lo + piece < len ? lo + piece : len;
+    const float* row = x + (long)blockIdx.y * len;
     double acc = 0.0;
-    for (long i = threadIdx.x; i < len; i += TB) acc += (double)row[i];
+    for (long i = lo + threadIdx.x; i < hi; i += TB) acc += (double)row[i];
     const double s = block_sum<TB>(acc, sh);
-    if (threadIdx.x == 0) out[blockIdx.x] = (float)s;
+    if (threadIdx.x == 0) part[(long)blockIdx.y * RS_CHUNKS + blockIdx.x] = s;
+}
+
+__global__ void rowsum_final_kernel(int rows, const double* __restrict__ part, float* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    double s = 0.0;
+    for (int c = 0; c < RS_CHUNKS; ++c) s += part[(long)r * RS_CHUNKS + c];
+    out[r] = (float)s;
 }
 
 // block b: sample b's squared error and squared target over all channels
@@ -306,8 +319,10 @@ hipError_t launch_fno_fold_w(const float* dW, float* gR, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rowsum(int rows, long len, const float* x, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(rowsum_kernel, dim3(rows), dim3(TB), 0, s, len, x, out);
+hipError_t launch_rowsum(int rows, long len, const float* x, double* part, float* out, hipStream_t s) {
+    if (rows < 1 || rows > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rowsum_part_kernel, dim3(RS_CHUNKS, rows), dim3(TB), 0, s, len, x, part);
+    hipLaunchKernelGGL(rowsum_final_kernel, dim3((rows + 63) / 64), dim3(64), 0, s, rows, part, out);
     return hipGetLastError();
 }
 

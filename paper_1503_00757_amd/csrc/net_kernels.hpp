@@ -96,8 +96,10 @@ hipError_t launch_fno_fold_o(int S, const float* dOb, float* dO, hipStream_t s);
 hipError_t launch_fno_expand_w(int layers, const float* R, long lstride, float* W, hipStream_t s);
 // dRr = dW[c][o] + dW[32+c][32+o], dRi = dW[c][32+o] - dW[32+c][o] into grad (Rr block then Ri block)
 hipError_t launch_fno_fold_w(const float* dW, float* gR, hipStream_t s);
-// out[r] = sum_i x[r * len + i] (FP64 accumulation, fixed order)
-hipError_t launch_rowsum(int rows, long len, const float* x, float* out, hipStream_t s);
+// out[r] = sum_i x[r * len + i]: RS_CHUNKS blocks per row write FP64 partial sums to part
+// (rows * RS_CHUNKS doubles), a second pass adds them in a fixed order
+constexpr int RS_CHUNKS = 64;
+hipError_t launch_rowsum(int rows, long len, const float* x, double* part, float* out, hipStream_t s);
 // per-sample sums over channels of y - t and t (layout [ch][B][npos]); then dy = 2 (y - t) / (B den_b)
 // and loss = (1/B) sum_b num_b / den_b (device double, nullable)
 hipError_t launch_fno_loss(int ch, int B, long npos, const float* y, const float* t, double* sums, float* dy,

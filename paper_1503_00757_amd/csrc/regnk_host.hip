@@ -44,6 +44,7 @@ constexpr int NFIELD = 9;    // scalar scratch fields in transport precision
 constexpr int NSFIELD = 8;   // FP64 state-solve scratch fields
 constexpr int NPCG = 7;      // x, r, z, kr, s, st, kst
 constexpr int NSCAL = 32;
+constexpr int MAX_TIMED = 512;   // timed stage launches per reg_time_pass call
 
 struct Layout {
     size_t total = 0;
@@ -58,7 +59,7 @@ struct Offsets {
     size_t mT, mR, vT, vw, vtT, traj, fld[NFIELD], B, Bt;
     size_t mT64, mR64, sfld[NSFIELD];   // FP64 state-solve buffers (FP32 transport mode only)
     size_t tw1f, tw2f, tw1d, tw2d;
-    size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal;
+    size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal, clk;
     size_t total;
 };
 
@@ -84,6 +85,9 @@ reg_status check_params(const reg_params* p) {
     if (!ms && p->beta_w != 0.0) return fail(REG_EINVAL, "beta_w must be 0 unless constraint is REG_MASS_SOURCE");
     return REG_OK;
 }
+
+// timing slots per stage launch: one per block, at most (n1 + n2) / 2 blocks
+size_t clk_slots(const reg_params* p) { return (size_t)(p->n1 + p->n2) / 2; }
 
 Offsets layout(const reg_params* p) {
     Offsets o{};
@@ -121,6 +125,7 @@ Offsets layout(const reg_params* p) {
     o.spec = L.take(4 * (size_t)p->n1 * (p->n2 / 2) * 16);
     o.partial = L.take(4 * RED_BLOCKS * 8);
     o.scal = L.take(NSCAL * 8);
+    o.clk = L.take((size_t)MAX_TIMED * 2 * clk_slots(p) * sizeof(unsigned long long));
     o.total = L.total;
     return o;
 }
@@ -158,8 +163,9 @@ struct reg_problem {
     hipGraphExec_t pcg_iter_graph = nullptr;   // one PCG iteration (matvec + scalar updates)
     // measurement hook: hipEvents around every launch of one stage op during real matvecs
     int timing_op = -1;
-    std::vector<hipEvent_t> tev;
-    size_t tev_used = 0;
+    int clk_used = 0;   // timed launches recorded so far (reg_time_pass)
+    size_t clk_stride = 0;
+    std::vector<hipEvent_t> tev;   // dispatch-stamped start / end events of the timed launches
 
     template <typename X>
     X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
@@ -219,10 +225,14 @@ StageArgs<T> base_args(const reg_problem* P) {
 
 template <typename T>
 reg_status stage(reg_problem* P, int op, const StageArgs<T>& a) {
-    const bool timed = op == P->timing_op && P->tev_used + 2 <= P->tev.size();
-    if (timed) CK(hipEventRecord(P->tev[P->tev_used++], P->stream));
-    CK(launch_stage<T>(op, P->var[op], a, P->stream));
-    if (timed) CK(hipEventRecord(P->tev[P->tev_used++], P->stream));
+    if (op == P->timing_op && P->clk_used < MAX_TIMED && 2 * (size_t)P->clk_used + 2 <= P->tev.size()) {
+        StageArgs<T> t = a;   // the blocks stamp their own start and end; the dispatch stamps two events
+        t.clk = P->at<unsigned long long>(P->o.clk) + P->clk_stride * P->clk_used;
+        CK(launch_stage<T>(op, P->var[op], t, P->stream, P->tev[2 * P->clk_used], P->tev[2 * P->clk_used + 1]));
+        ++P->clk_used;
+    } else {
+        CK(launch_stage<T>(op, P->var[op], a, P->stream));
+    }
     return REG_OK;
 }
 
@@ -823,39 +833,64 @@ reg_status time_launches(reg_problem* P, int op, int var, const StageArgs<T>& a,
     return REG_OK;
 }
 
-// Mean device time of the selected stage's launches inside `reps` real matvecs (direct launches,
-// hipEvents recorded on the problem's stream right before and after each launch of that stage).
+// Mean device time of the selected stage's launches inside `reps` real matvecs (direct launches):
+//  * ms: the dispatch interval, from start / end events that the dispatch itself stamps
+//    (hipExtLaunchKernelGGL) -- what a profiler reports as the kernel's duration;
+//  * exec_ms: the blocks' execution interval: every block records its start and its end after its
+//    stores completed on the device wall clock; latest end minus earliest start.
+// The difference is the workgroup dispatch ramp and the end-of-kernel completion.
 template <typename T>
-reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes) {
+reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes, double* exec_ms) {
     if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
     if (reps < 1 || reps > 1000) return fail(REG_EINVAL, "reps must be in [1, 1000]");
+    if ((long)reps * P->nt > MAX_TIMED)
+        return fail(REG_EINVAL, "reps * nt = %ld timed launches exceed %d", (long)reps * P->nt, MAX_TIMED);
     StageArgs<T> a;
     int op;
     double fields;
     CKS(stage_spec<T>(P, which, a, op, fields));
-    const size_t need = 2 * (size_t)P->nt * reps;
-    while (P->tev.size() < need) {
+    int dev = 0, khz = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(REG_EDEVICE, "device wall-clock rate unavailable");
+    const size_t slots = clk_slots(&P->p);
+    P->clk_stride = 2 * slots;
+    const int launches = reps * P->nt;
+    while (P->tev.size() < 2 * (size_t)launches) {
         hipEvent_t e;
         CK(hipEventCreate(&e));
         P->tev.push_back(e);
     }
+    unsigned long long* clk = P->at<unsigned long long>(P->o.clk);
+    CK(launch_clk_init(clk, (int)(launches * slots), P->stream));
     P->timing_op = op;
-    P->tev_used = 0;
+    P->clk_used = 0;
     reg_status st = REG_OK;
     for (int r = 0; r < reps && st == REG_OK; ++r)
         st = matvec_t<T>(P, P->at<double>(P->o.vt64), P->pcg(PST), nullptr);
     P->timing_op = -1;
     CKS(st);
+    const int timed = P->clk_used;
+    if (timed == 0) return fail(REG_EINVAL, "no launches of the selected stage");
+    std::vector<unsigned long long> h((size_t)timed * 2 * slots);
+    CK(hipMemcpyAsync(h.data(), clk, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, P->stream));
     CK(hipStreamSynchronize(P->stream));
-    double total = 0;
-    const size_t pairs = P->tev_used / 2;
-    for (size_t i = 0; i < pairs; ++i) {
+    double ticks = 0, ev_ms = 0;
+    for (int i = 0; i < timed; ++i) {
         float t = 0;
         CK(hipEventElapsedTime(&t, P->tev[2 * i], P->tev[2 * i + 1]));
-        total += t;
+        ev_ms += t;
+        unsigned long long t0 = ~0ull, t1 = 0;
+        for (size_t b = 0; b < slots; ++b) {
+            const unsigned long long s0 = h[(i * slots + b) * 2], s1 = h[(i * slots + b) * 2 + 1];
+            if (s0 != ~0ull) t0 = std::min(t0, s0);   // untouched slots keep the sentinels
+            if (s1 != 0ull) t1 = std::max(t1, s1);
+        }
+        if (t0 == ~0ull || t1 < t0) return fail(REG_EDEVICE, "timed launch %d recorded no interval", i);
+        ticks += (double)(t1 - t0);
     }
-    if (pairs == 0) return fail(REG_EINVAL, "no launches of the selected stage");
-    *ms = total / (double)pairs;
+    *ms = ev_ms / timed;
+    if (exec_ms) *exec_ms = ticks / timed / (double)khz;   // khz ticks per millisecond
     *bytes = fields * (double)P->nn * sizeof(T);
     return REG_OK;
 }
@@ -1007,8 +1042,8 @@ reg_status reg_set_images(reg_problem* h, const double* m_T, const double* m_R) 
 reg_status reg_destroy(reg_problem* h) {
     if (!h) return REG_OK;
     drop_graphs(h);
-    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     delete h;
     return REG_OK;
 }
@@ -1148,9 +1183,10 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
     return REG_OK;
 }
 
-reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes) {
+reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes, double* exec_ms) {
     if (!h || !ms || !bytes) return fail(REG_EINVAL, "NULL argument");
-    return DISPATCH(h, time_pass_t<float>(h, which, reps, ms, bytes), time_pass_t<double>(h, which, reps, ms, bytes));
+    return DISPATCH(h, time_pass_t<float>(h, which, reps, ms, bytes, exec_ms),
+                    time_pass_t<double>(h, which, reps, ms, bytes, exec_ms));
 }
 
 reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes) {

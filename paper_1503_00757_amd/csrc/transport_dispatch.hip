@@ -4,41 +4,57 @@
 
 namespace regnk {
 
-extern template hipError_t launch_stage_op<float, OP_A1>(int, const StageArgs<float>&, hipStream_t);
-extern template hipError_t launch_stage_op<float, OP_A2>(int, const StageArgs<float>&, hipStream_t);
-extern template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t);
-extern template hipError_t launch_stage_op<float, OP_I2>(int, const StageArgs<float>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_S2>(int, const StageArgs<double>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_A1>(int, const StageArgs<double>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_A2>(int, const StageArgs<double>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_I1>(int, const StageArgs<double>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_I2>(int, const StageArgs<double>&, hipStream_t);
-extern template hipError_t launch_stage_op<double, OP_GRAD>(int, const StageArgs<double>&, hipStream_t);
+extern template hipError_t launch_stage_op<float, OP_A1>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<float, OP_A2>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<float, OP_I2>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_S2>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_A1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_A2>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_I1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_I2>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_GRAD>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <>
-hipError_t launch_stage<float>(int op, int var, const StageArgs<float>& a, hipStream_t s) {
+hipError_t launch_stage<float>(int op, int var, const StageArgs<float>& a, hipStream_t s, hipEvent_t t0,
+                               hipEvent_t t1) {
     switch (op) {
-        case OP_A1: return launch_stage_op<float, OP_A1>(var, a, s);
-        case OP_A2: return launch_stage_op<float, OP_A2>(var, a, s);
-        case OP_I1: return launch_stage_op<float, OP_I1>(var, a, s);
-        case OP_I2: return launch_stage_op<float, OP_I2>(var, a, s);
+        case OP_A1: return launch_stage_op<float, OP_A1>(var, a, s, t0, t1);
+        case OP_A2: return launch_stage_op<float, OP_A2>(var, a, s, t0, t1);
+        case OP_I1: return launch_stage_op<float, OP_I1>(var, a, s, t0, t1);
+        case OP_I2: return launch_stage_op<float, OP_I2>(var, a, s, t0, t1);
     }
     return hipErrorInvalidValue;
 }
 
 template <>
-hipError_t launch_stage<double>(int op, int var, const StageArgs<double>& a, hipStream_t s) {
+hipError_t launch_stage<double>(int op, int var, const StageArgs<double>& a, hipStream_t s, hipEvent_t t0,
+                                hipEvent_t t1) {
     switch (op) {
-        case OP_S1: return launch_stage_op<double, OP_S1>(var, a, s);
-        case OP_S2: return launch_stage_op<double, OP_S2>(var, a, s);
-        case OP_A1: return launch_stage_op<double, OP_A1>(var, a, s);
-        case OP_A2: return launch_stage_op<double, OP_A2>(var, a, s);
-        case OP_I1: return launch_stage_op<double, OP_I1>(var, a, s);
-        case OP_I2: return launch_stage_op<double, OP_I2>(var, a, s);
-        case OP_GRAD: return launch_stage_op<double, OP_GRAD>(var, a, s);
+        case OP_S1: return launch_stage_op<double, OP_S1>(var, a, s, t0, t1);
+        case OP_S2: return launch_stage_op<double, OP_S2>(var, a, s, t0, t1);
+        case OP_A1: return launch_stage_op<double, OP_A1>(var, a, s, t0, t1);
+        case OP_A2: return launch_stage_op<double, OP_A2>(var, a, s, t0, t1);
+        case OP_I1: return launch_stage_op<double, OP_I1>(var, a, s, t0, t1);
+        case OP_I2: return launch_stage_op<double, OP_I2>(var, a, s, t0, t1);
+        case OP_GRAD: return launch_stage_op<double, OP_GRAD>(var, a, s, t0, t1);
     }
     return hipErrorInvalidValue;
+}
+
+__global__ void clk_init_kernel(unsigned long long* clk, int pairs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < pairs) {
+        clk[2 * i] = ~0ull;
+        clk[2 * i + 1] = 0ull;
+    }
+}
+
+hipError_t launch_clk_init(unsigned long long* clk, int pairs, hipStream_t s) {
+    if (pairs < 1) return hipSuccess;
+    hipLaunchKernelGGL(clk_init_kernel, dim3((pairs + 255) / 256), dim3(256), 0, s, clk, pairs);
+    return hipGetLastError();
 }
 
 static inline int pointwise_blocks(long nn) {

@@ -20,6 +20,8 @@
 // Rows pack two real rows as one complex transform, columns pack two adjacent columns; i k~ maps
 // real sequences to real sequences, so real and imaginary parts carry the two derivatives.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -286,6 +288,22 @@ __device__ __forceinline__ void col_part(const StageArgs<T>& a, int cb, int ncb,
     }
 }
 
+// Timing (only when clk is given; the test is uniform over the grid): block b writes its start and
+// its end on the device wall clock to clk[2b], clk[2b+1] (plain stores, one slot per block: no
+// contention); the end is taken after every wave's stores were acknowledged (s_waitcnt 0: stores
+// count in vmcnt; no cache write-back, unlike a device-scope fence, which costs an L2 flush per
+// block here).  The caller takes the earliest start and the latest end.
+__device__ __forceinline__ void clk_start(unsigned long long* clk) {
+    if (clk && threadIdx.x == 0) clk[2 * blockIdx.x] = wall_clock64();
+}
+__device__ __forceinline__ void clk_end(unsigned long long* clk) {
+    if (clk) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) clk[2 * blockIdx.x + 1] = wall_clock64();
+    }
+}
+
 // Square grids: one launch, blocks [0, nrb) do row pairs, the rest column tiles.
 template <typename T, int N, int ER, int FPW, int EC, int G, int OP>
 __global__ __launch_bounds__(FPW * N / ER) void stage_fused_kernel(StageArgs<T> a, int nrb) {
@@ -293,20 +311,26 @@ __global__ __launch_bounds__(FPW * N / ER) void stage_fused_kernel(StageArgs<T> 
     constexpr int LR = FPW * 2 * LdsSize<N>::value;
     constexpr int LC = G * 2 * LdsSize<N>::value;
     __shared__ cpx<T> lds[LR > LC ? LR : LC];
+    clk_start(a.clk);
     if ((int)blockIdx.x < nrb) row_part<T, N, ER, FPW, OP>(a, blockIdx.x, lds);
     else col_part<T, N, EC, G, OP>(a, blockIdx.x - nrb, gridDim.x - nrb, lds);
+    clk_end(a.clk);
 }
 
 // Non-square grids: the two parts as two launches.
 template <typename T, int N, int E, int FPW, int OP>
 __global__ __launch_bounds__(FPW * N / E) void stage_row_kernel(StageArgs<T> a) {
     __shared__ cpx<T> lds[FPW * 2 * LdsSize<N>::value];
+    clk_start(a.clk);
     row_part<T, N, E, FPW, OP>(a, blockIdx.x, lds);
+    clk_end(a.clk);
 }
 template <typename T, int N, int E, int G, int OP>
 __global__ __launch_bounds__(G * N / E) void stage_col_kernel(StageArgs<T> a) {
     __shared__ cpx<T> lds[G * 2 * LdsSize<N>::value];
+    clk_start(a.clk);
     col_part<T, N, E, G, OP>(a, blockIdx.x, gridDim.x, lds);
+    clk_end(a.clk);
 }
 
 // Pointwise helpers of the state solve and the trapezoid end point.
@@ -335,9 +359,9 @@ __global__ void body_end_kernel(long nn, T w, const T* __restrict__ Q, const T* 
 // G = BS/(N/EC) column pairs per block).  Variant 0 is the default; an autotuner may pick another.
 // FP64 and non-square or short grids use one fixed shape.
 // ---------------------------------------------------------------------------------------------
-constexpr int var_ER(int v) { return (v == 1 || v == 2 || v == 5) ? 4 : (v == 7 ? 16 : 8); }
-constexpr int var_EC(int v) { return (v == 0 || v == 1 || v == 6 || v == 7) ? 16 : (v == 5 ? 4 : 8); }
-constexpr int var_BS(int v) { return (v == 0 || v == 3 || v == 7) ? 128 : 256; }
+constexpr int var_ER(int v) { return (v == 1 || v == 2 || v == 5 || v == 8) ? 4 : (v == 7 ? 16 : 8); }
+constexpr int var_EC(int v) { return (v == 0 || v == 1 || v == 6 || v == 7) ? 16 : ((v == 5 || v == 8) ? 4 : 8); }
+constexpr int var_BS(int v) { return (v == 0 || v == 3 || v == 7) ? 128 : (v == 8 ? 512 : 256); }
 
 template <typename T, int N, int ER, int EC, int BS>
 constexpr bool fused_ok() {
@@ -346,14 +370,23 @@ constexpr bool fused_ok() {
            (BS / (N / EC)) * 2 * LdsSize<N>::value * (int)sizeof(cpx<T>) <= 160 * 1024;
 }
 
+// A launch; with timing events it goes through hipExtLaunchKernelGGL, whose events are stamped by
+// the dispatch itself (the interval a profiler reports for the kernel).
+template <typename K, typename... Args>
+static inline void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
+                            Args... args) {
+    if (t0 || t1) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t0, t1, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 template <typename T, int N, int OP, int ER, int EC, int BS>
-static hipError_t launch_fused(const StageArgs<T>& a, hipStream_t s) {
+static hipError_t launch_fused(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if constexpr (fused_ok<T, N, ER, EC, BS>()) {
         constexpr int FPW = BS / (N / ER);
         constexpr int G = BS / (N / EC);
         const int nrb = (a.n1 / 2 + FPW - 1) / FPW;
         const int ncb = (a.n2 + 2 * G - 1) / (2 * G);
-        hipLaunchKernelGGL((stage_fused_kernel<T, N, ER, FPW, EC, G, OP>), dim3(nrb + ncb), dim3(BS), 0, s, a, nrb);
+        launch_k(stage_fused_kernel<T, N, ER, FPW, EC, G, OP>, dim3(nrb + ncb), dim3(BS), s, t0, t1, a, nrb);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -366,51 +399,52 @@ template <int N, int E>
 constexpr int min_block(int want) { return (N / E) >= want ? 1 : want / (N / E); }
 
 template <typename T, int N, int OP>
-static hipError_t launch_row_fixed(const StageArgs<T>& a, hipStream_t s) {
+static hipError_t launch_row_fixed(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     constexpr int E = sizeof(T) == 8 ? 4 : small_E<N>();
     constexpr int FPW = min_block<N, E>(64);
-    hipLaunchKernelGGL((stage_row_kernel<T, N, E, FPW, OP>), dim3((a.n1 / 2 + FPW - 1) / FPW), dim3(FPW * N / E), 0, s, a);
+    launch_k(stage_row_kernel<T, N, E, FPW, OP>, dim3((a.n1 / 2 + FPW - 1) / FPW), dim3(FPW * N / E), s, t0, t1, a);
     return hipGetLastError();
 }
 template <typename T, int N, int OP>
-static hipError_t launch_col_fixed(const StageArgs<T>& a, hipStream_t s) {
+static hipError_t launch_col_fixed(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     constexpr int E = sizeof(T) == 8 ? (N >= 16 ? 8 : 4) : small_E<N>();
     constexpr int G0 = min_block<N, E>(64);
     constexpr int G = G0 < 2 ? 2 : G0;
-    hipLaunchKernelGGL((stage_col_kernel<T, N, E, G, OP>), dim3((a.n2 + 2 * G - 1) / (2 * G)), dim3(G * N / E), 0, s, a);
+    launch_k(stage_col_kernel<T, N, E, G, OP>, dim3((a.n2 + 2 * G - 1) / (2 * G)), dim3(G * N / E), s, t0, t1, a);
     return hipGetLastError();
 }
 
 template <typename T, int N, int OP>
-static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s) {
+static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if constexpr (sizeof(T) == 8 || N < 64) {
         (void)var;
         constexpr int ER = sizeof(T) == 8 ? 4 : small_E<N>();
         constexpr int EC = sizeof(T) == 8 ? (N >= 16 ? 8 : 4) : small_E<N>();
         constexpr int BS0 = (N / ER) > (N / EC) ? (N / ER) : (N / EC);
         constexpr int BS = BS0 < 64 ? 64 : BS0;
-        return launch_fused<T, N, OP, ER, EC, BS>(a, s);
+        return launch_fused<T, N, OP, ER, EC, BS>(a, s, t0, t1);
     } else {
         switch (var) {
-            case 0: return launch_fused<T, N, OP, var_ER(0), var_EC(0), var_BS(0)>(a, s);
-            case 1: return launch_fused<T, N, OP, var_ER(1), var_EC(1), var_BS(1)>(a, s);
-            case 2: return launch_fused<T, N, OP, var_ER(2), var_EC(2), var_BS(2)>(a, s);
-            case 3: return launch_fused<T, N, OP, var_ER(3), var_EC(3), var_BS(3)>(a, s);
-            case 4: return launch_fused<T, N, OP, var_ER(4), var_EC(4), var_BS(4)>(a, s);
-            case 5: return launch_fused<T, N, OP, var_ER(5), var_EC(5), var_BS(5)>(a, s);
-            case 6: return launch_fused<T, N, OP, var_ER(6), var_EC(6), var_BS(6)>(a, s);
-            case 7: return launch_fused<T, N, OP, var_ER(7), var_EC(7), var_BS(7)>(a, s);
+            case 0: return launch_fused<T, N, OP, var_ER(0), var_EC(0), var_BS(0)>(a, s, t0, t1);
+            case 1: return launch_fused<T, N, OP, var_ER(1), var_EC(1), var_BS(1)>(a, s, t0, t1);
+            case 2: return launch_fused<T, N, OP, var_ER(2), var_EC(2), var_BS(2)>(a, s, t0, t1);
+            case 3: return launch_fused<T, N, OP, var_ER(3), var_EC(3), var_BS(3)>(a, s, t0, t1);
+            case 4: return launch_fused<T, N, OP, var_ER(4), var_EC(4), var_BS(4)>(a, s, t0, t1);
+            case 5: return launch_fused<T, N, OP, var_ER(5), var_EC(5), var_BS(5)>(a, s, t0, t1);
+            case 6: return launch_fused<T, N, OP, var_ER(6), var_EC(6), var_BS(6)>(a, s, t0, t1);
+            case 7: return launch_fused<T, N, OP, var_ER(7), var_EC(7), var_BS(7)>(a, s, t0, t1);
+            case 8: return launch_fused<T, N, OP, var_ER(8), var_EC(8), var_BS(8)>(a, s, t0, t1);
         }
         return hipErrorInvalidValue;
     }
 }
 
 template <typename T, int OP, int AXIS>
-static hipError_t launch_axis(const StageArgs<T>& a, hipStream_t s) {
+static hipError_t launch_axis(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const int n = AXIS == 2 ? a.n2 : a.n1;
 #define REGNK_AX(NN)                                                                         \
     case NN:                                                                                 \
-        return AXIS == 2 ? launch_row_fixed<T, NN, OP>(a, s) : launch_col_fixed<T, NN, OP>(a, s);
+        return AXIS == 2 ? launch_row_fixed<T, NN, OP>(a, s, t0, t1) : launch_col_fixed<T, NN, OP>(a, s, t0, t1);
     switch (n) {
         REGNK_AX(8) REGNK_AX(16) REGNK_AX(32) REGNK_AX(64) REGNK_AX(128) REGNK_AX(256) REGNK_AX(512)
         REGNK_AX(1024) REGNK_AX(2048)
@@ -420,25 +454,28 @@ static hipError_t launch_axis(const StageArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T, int OP>
-hipError_t launch_stage_op(int var, const StageArgs<T>& a, hipStream_t s) {
+hipError_t launch_stage_op(int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if (a.n1 == a.n2) {
         switch (a.n1) {
-            case 8: return launch_square<T, 8, OP>(var, a, s);
-            case 16: return launch_square<T, 16, OP>(var, a, s);
-            case 32: return launch_square<T, 32, OP>(var, a, s);
-            case 64: return launch_square<T, 64, OP>(var, a, s);
-            case 128: return launch_square<T, 128, OP>(var, a, s);
-            case 256: return launch_square<T, 256, OP>(var, a, s);
-            case 512: return launch_square<T, 512, OP>(var, a, s);
-            case 1024: return launch_square<T, 1024, OP>(var, a, s);
-            case 2048: return launch_square<T, 2048, OP>(var, a, s);
+            case 8: return launch_square<T, 8, OP>(var, a, s, t0, t1);
+            case 16: return launch_square<T, 16, OP>(var, a, s, t0, t1);
+            case 32: return launch_square<T, 32, OP>(var, a, s, t0, t1);
+            case 64: return launch_square<T, 64, OP>(var, a, s, t0, t1);
+            case 128: return launch_square<T, 128, OP>(var, a, s, t0, t1);
+            case 256: return launch_square<T, 256, OP>(var, a, s, t0, t1);
+            case 512: return launch_square<T, 512, OP>(var, a, s, t0, t1);
+            case 1024: return launch_square<T, 1024, OP>(var, a, s, t0, t1);
+            case 2048: return launch_square<T, 2048, OP>(var, a, s, t0, t1);
         }
         return hipErrorInvalidValue;
     }
-    // independent parts: two launches in stream order
-    hipError_t e = launch_axis<T, OP, 2>(a, s);
+    // independent parts: two launches in stream order (a timed stage spans both; timing slots of the
+    // column launch follow the at most n1/2 row blocks)
+    hipError_t e = launch_axis<T, OP, 2>(a, s, t0, nullptr);
     if (e != hipSuccess) return e;
-    return launch_axis<T, OP, 1>(a, s);
+    StageArgs<T> ac = a;
+    if (ac.clk) ac.clk += 2 * (a.n1 / 2);
+    return launch_axis<T, OP, 1>(ac, s, nullptr, t1);
 }
 
 }  // namespace regnk

@@ -3,6 +3,6 @@
 #include "transport_kernels.hpp"
 
 namespace regnk {
-template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t);
-template hipError_t launch_stage_op<double, OP_I1>(int, const StageArgs<double>&, hipStream_t);
+template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_stage_op<double, OP_I1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 }  // namespace regnk

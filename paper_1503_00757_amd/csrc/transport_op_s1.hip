@@ -3,5 +3,5 @@
 #include "transport_kernels.hpp"
 
 namespace regnk {
-template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t);
+template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 }  // namespace regnk

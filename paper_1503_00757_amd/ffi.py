@@ -90,7 +90,7 @@ def lib():
         L.reg_precond_apply.argtypes = [vp, vp, vp]
         L.reg_pcg.argtypes = [vp, vp, d, i32, i32, vp, C.POINTER(i32), dp]
         L.reg_solve.argtypes = [vp, C.POINTER(RegSolveOpts), vp, C.POINTER(RegSolveStats)]
-        L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp]
+        L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp, dp]
         L.reg_autotune.argtypes = [vp, i32, C.c_char_p, sz]
         L.reg_batch_solve.argtypes = [i32, C.POINTER(vp), C.POINTER(RegSolveOpts), C.POINTER(vp),
                                       C.POINTER(RegSolveStats)]
@@ -175,10 +175,12 @@ def reg_solve(h, opts: RegSolveOpts, v_out: int, raise_on_error: bool = True):
 
 
 def reg_time_pass(h, which: int, reps: int):
+    """(dispatch ms per launch, bytes per launch, execution ms per launch)"""
     ms = C.c_double(0)
     by = C.c_double(0)
-    _check(lib().reg_time_pass(h, which, reps, C.byref(ms), C.byref(by)))
-    return ms.value, by.value
+    ex = C.c_double(0)
+    _check(lib().reg_time_pass(h, which, reps, C.byref(ms), C.byref(by), C.byref(ex)))
+    return ms.value, by.value, ex.value
 
 
 def reg_autotune(h, reps: int = 50) -> str:

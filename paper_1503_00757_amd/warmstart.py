@@ -203,7 +203,8 @@ def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settin
 
     Returns (feats [N][9][n][n], labels [N][2][n][n], stats list); the labels are the velocities of the
     plain solves (v0 = 0) to ||g|| / ||g(0)|| <= label_gtol divided by each pair's misfit scale,
-    solved `pool` at a time with reg_batch_solve on handles reused through reg_set_images."""
+    solved `pool` at a time with reg_batch_solve on handles reused through reg_set_images (pool 1:
+    one after another on the calling thread)."""
     import torch
     s = dict(SOLVER, **settings)
     N = len(pairs)
@@ -230,12 +231,19 @@ def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settin
             probs.append(Problem(imgs[len(probs)][0], imgs[len(probs)][1], nt, **s))
         for p, (mT, mR) in zip(probs, imgs):
             p.set_images(mT, mR)
-        vs_out, st = batch_solve(probs[:len(chunk)], raise_on_error=False, gtol_rel=label_gtol)
+        if pool > 1:
+            vs_out, st = batch_solve(probs[:len(chunk)], raise_on_error=False, gtol_rel=label_gtol)
+        else:
+            vs_out, st = [], []
+            for p in probs[:len(chunk)]:
+                v, s_ = p.solve(gtol_rel=label_gtol, raise_on_error=False)
+                vs_out.append(v)
+                st.append(s_)
         for i, (v, (mT, mR)) in enumerate(zip(vs_out, imgs)):
             net.features(mT, mR, feats[c0 + i], scale)
             net.target(v, scale, labels[c0 + i])
         all_stats += st
-        if log and (c0 // pool) % 64 == 0:
+        if log and (c0 // pool) % max(1, 1024 // pool) == 0:
             log(f"labels {c0 + len(chunk)}/{N} ({time.perf_counter() - t0:.1f} s)")
     for p in probs:
         p.close()

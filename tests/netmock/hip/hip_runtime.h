@@ -9,6 +9,7 @@
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidConfiguration = 9 };
 typedef void* hipStream_t;
+typedef void* hipEvent_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
 
 bool mock_range_ok(const void* p, size_t bytes);   // defined by the harness

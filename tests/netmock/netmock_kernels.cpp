@@ -331,8 +331,10 @@ hipError_t launch_fno_fold_w(const float* dW, float* gR, hipStream_t) {
     return hipSuccess;
 }
 
-hipError_t launch_rowsum(int rows, long len, const float* x, float* out, hipStream_t) {
-    if (!span_ok(x, {{rows * len, 1}}) || !span_ok(out, {{rows, 1}})) return hipErrorInvalidValue;
+hipError_t launch_rowsum(int rows, long len, const float* x, double* part, float* out, hipStream_t) {
+    if (!span_ok(x, {{rows * len, 1}}) || !span_ok(out, {{rows, 1}}) ||
+        !mock_range_ok(part, (size_t)rows * RS_CHUNKS * sizeof(double)))
+        return hipErrorInvalidValue;
     for (int r = 0; r < rows; ++r) {
         double s = 0.0;
         for (long i = 0; i < len; ++i) s += x[r * len + i];

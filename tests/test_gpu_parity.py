@@ -159,7 +159,7 @@ def test_every_launch_shape_matches_oracle(problems, name):
     ref = oracle_results(case)
     P.gradient(dev(vlin), want_J=False)
     tol = max(case.tol, 10 * ref["sens_H"])
-    for v in range(8):
+    for v in range(9):
         P.set_pass_variants([v] * 7)
         try:
             H = P.hessian_matvec(dev(vt))

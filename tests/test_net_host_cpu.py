@@ -23,7 +23,8 @@ def lib(tmp_path_factory):
            "-I", os.path.join(ROOT, "paper_1503_00757_amd", "csrc"),
            "-x", "c++", os.path.join(ROOT, "paper_1503_00757_amd", "csrc", "net_host.hip"),
            "-x", "c++", os.path.join(ROOT, "tests", "netmock", "netmock_kernels.cpp"), "-o", out]
-    subprocess.run(cmd, check=True, capture_output=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
     L = ctypes.CDLL(out)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     L.mock_register.argtypes = [vp, sz]
