@@ -13,7 +13,19 @@ Readings (listed in the design notes):
   * if <s, H s>_W <= 0 PCG stops (on its first step it returns the preconditioned steepest-descent
     direction);
   * Armijo: alpha_0 = 1, rho = 1/2, c_1 = 1e-4, at most ``max_backtracks`` halvings; slope = dJ[v~];
-  * the relative gradient is ||g(v_k)|| / ||g(0)||, with g(0) taken at v = 0 even for a warm start.
+  * the relative gradient is ||g(v_k)|| / ||g(0)||, with g(0) taken at v = 0 even for a warm start;
+  * a warm start is kept only if J(v_0) < J(0) (the globalisation needs descent from the plain
+    start), otherwise the solve starts from v = 0;
+  * optional low-rank correction of the preconditioner (not in the paper): a deflation set of
+    directions z_i with H z_i and e_i > 0 feeds the balancing (deflation) preconditioner
+    (``corrected_precond``), which stays SPD for any such set.  The set starts with the
+    Rayleigh-Ritz pairs (theta_i, z_i) of the GN Hessian on span(U) relative to M (z_i orthonormal
+    in <., M .>_W, M = beta_v A with the modified kernel, e_i = theta_i), computed at the point
+    where the first Newton step is taken, for caller directions U; with ``recycle`` = q > 0 the
+    first q search directions of every PCG solve (with H s and e = <s, H s>_W, mutually
+    H-conjugate within that solve) are appended, until ``lowrank_capacity`` directions are held.
+    The plain spectral form M^{-1} + sum (1/theta - 1) z z^* was tried first and made PCG slower
+    whenever span(U) is not an invariant subspace.
 """
 from __future__ import annotations
 
@@ -23,7 +35,7 @@ import math
 import numpy as np
 
 from .spectral import Grid, Params
-from . import reduced
+from . import reduced, spectral
 
 OK, ENOTCONV, ENONFINITE = 0, -4, -5
 
@@ -38,6 +50,9 @@ class SolveOpts:
     armijo_c1: float = 1e-4
     armijo_rho: float = 0.5
     v0: np.ndarray | None = None
+    precond_U: np.ndarray | None = None   # (r, 2, n1, n2) directions of the low-rank correction
+    recycle: int = 0                      # PCG directions of each Newton step kept for the next ones
+    lowrank_capacity: int = 16            # most directions the correction holds
 
 
 @dataclass
@@ -51,14 +66,19 @@ class SolveStats:
     g0_norm: float = 0.0
     g_rel: float = 1.0
     J: float = 0.0
+    fallback_used: int = 0
+    lowrank_dim: int = 0                  # directions in the correction at the end of the solve
+    lowrank: tuple | None = None          # (Ritz values theta, Ritz vectors z) from precond_U
     history: list = field(default_factory=list)
 
 
-def pcg(matvec, prec, winner, norm, rhs, eta, max_pcg, fixed_iters=0):
+def pcg(matvec, prec, winner, norm, rhs, eta, max_pcg, fixed_iters=0, record=None, record_max=0):
     """Alg. 2: preconditioned CG on H x = rhs (rhs = -g_k), x_0 = 0.
 
     Returns (x, iterations, ||r|| / ||r_0||).  ``winner`` is the inner product that makes H and the
-    preconditioner self-adjoint; ``norm`` is the residual norm of the stopping test.
+    preconditioner self-adjoint; ``norm`` is the residual norm of the stopping test.  If ``record`` is
+    a list, the first ``record_max`` search directions that complete a step are appended to it as
+    (s, H s, <s, H s>_W).
     """
     x = np.zeros_like(rhs)
     r = rhs.copy()
@@ -77,6 +97,8 @@ def pcg(matvec, prec, winner, norm, rhs, eta, max_pcg, fixed_iters=0):
             if l == 1:
                 x = s.copy()
             break
+        if record is not None and l <= record_max:
+            record.append((s.copy(), st.copy(), sHs))
         kappa = rz / sHs
         x = x + kappa * s
         r = r - kappa * st
@@ -91,6 +113,69 @@ def pcg(matvec, prec, winner, norm, rhs, eta, max_pcg, fixed_iters=0):
     return x, l, (rn / r0 if r0 > 0 else 0.0)
 
 
+def admissible(g: Grid, p: Params, u):
+    """A direction in the space PCG works in: Nyquist-free, and Leray-projected (K) for w = 0."""
+    u = spectral.nyquist_project(g, u)
+    return spectral.apply_K(g, p, u) if p.constraint == "divfree" else u
+
+
+def precond_op(g: Grid, p: Params, u):
+    """M u = F_Nyq (beta_v A with the modified kernel) u, the operator whose inverse PCG applies."""
+    sym = spectral.precond_symbol(g, p)
+    return np.stack([g.ifft(g.keep * sym * g.fft(u[c])) for c in range(2)])
+
+
+def lowrank_setup(g: Grid, p: Params, matvec, U, rel_tol=1e-10):
+    """Rayleigh-Ritz on span(U): returns (theta, Z, HZ) with Z^T W M Z = I, Z^T W H Z = diag(theta)
+    and HZ = H Z.
+
+    Directions are made admissible, then orthonormalised in <., M .>_W through the eigenvectors of
+    their Gram matrix (directions whose Gram eigenvalue is at most rel_tol times the largest are
+    dropped); H is applied to the orthonormal basis, the projected Hessian is diagonalised, and
+    Ritz pairs with non-positive (or non-finite) theta are dropped, so that E = Z^T W H Z is SPD."""
+    W = lambda a, b: reduced.w_inner(g, p, a, b)   # noqa: E731
+    U = [admissible(g, p, u) for u in U]
+    r = len(U)
+    if r == 0:
+        return np.zeros(0), [], []
+    MU = [precond_op(g, p, u) for u in U]
+    G = np.array([[W(U[i], MU[j]) for j in range(r)] for i in range(r)])
+    G = 0.5 * (G + G.T)
+    lam, E = np.linalg.eigh(G)
+    keep = lam > rel_tol * max(lam.max(), 0.0)
+    if not keep.any():
+        return np.zeros(0), [], []
+    C = E[:, keep] / np.sqrt(lam[keep])                       # Q = U C is M-orthonormal
+    Q = [sum(C[j, i] * U[j] for j in range(r)) for i in range(C.shape[1])]
+    HQ = [matvec(q) for q in Q]
+    T = np.array([[W(Q[i], HQ[j]) for j in range(len(Q))] for i in range(len(Q))])
+    T = 0.5 * (T + T.T)
+    theta, V = np.linalg.eigh(T)
+    ok = np.isfinite(theta) & (theta > 0.0)
+    theta, V = theta[ok], V[:, ok]
+    Z = [sum(V[j, i] * Q[j] for j in range(len(Q))) for i in range(V.shape[1])]
+    HZ = [sum(V[j, i] * HQ[j] for j in range(len(Q))) for i in range(V.shape[1])]
+    return theta, Z, HZ
+
+
+def corrected_precond(g: Grid, p: Params, theta, Z, HZ):
+    """Balancing (deflation) correction of M^{-1} on span(Z), with E = Z^T W H Z = diag(theta):
+
+        P r = Pi M^{-1} Pi^* r + Z E^{-1} Z^* r,   Pi = I - Z E^{-1} (H Z)^*,
+
+    adjoints taken in <., .>_W.  P H is the identity on span(Z); P is SPD whenever M and E are (also
+    when H has moved on from the point where HZ was taken)."""
+    W = lambda a, b: reduced.w_inner(g, p, a, b)   # noqa: E731
+
+    def prec(r):
+        a = [W(zi, r) / th for zi, th in zip(Z, theta)]
+        rt = r - sum((ai * hz for ai, hz in zip(a, HZ)), np.zeros_like(r))
+        y = reduced.precond(g, p, rt)
+        b = [W(hz, y) / th for hz, th in zip(HZ, theta)]
+        return y + sum(((ai - bi) * zi for ai, bi, zi in zip(a, b, Z)), np.zeros_like(r))
+    return prec
+
+
 def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
     """Alg. 1: inexact reduced-space Gauss-Newton-Krylov with Armijo line search.
 
@@ -101,12 +186,29 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
     st.n_pde += 2
     g0 = g.norm(lin0.g)
     st.g0_norm = g0
+    lin = lin0
     if opts.v0 is not None:
-        lin = reduced.gradient(g, p, mT, mR, opts.v0)
+        lin_ws = reduced.gradient(g, p, mT, mR, opts.v0)
         st.n_pde += 2
-    else:
-        lin = lin0
+        if np.isfinite(lin_ws.J) and lin_ws.J < lin0.J:
+            lin = lin_ws
+        else:
+            st.fallback_used = 1
     v = lin.v
+    # deflation set of the preconditioner correction: directions z, H z and e = <z, H z>_W
+    E, Zs, HZs = [], [], []
+    cap = opts.lowrank_capacity
+    if opts.precond_U is not None and len(opts.precond_U) > 0:
+        if len(opts.precond_U) > cap:
+            raise ValueError("more directions than the correction holds")
+
+        def mv0(s, _lin=lin):
+            st.n_matvec += 1
+            st.n_pde += 2
+            return reduced.hessian_matvec(g, p, _lin, s)
+        theta, Z, HZ = lowrank_setup(g, p, mv0, list(opts.precond_U))
+        st.lowrank = (theta, Z)
+        E, Zs, HZs = list(theta), list(Z), list(HZ)
     k = 0
     while True:
         grel = g.norm(lin.g) / g0 if g0 > 0 else 0.0
@@ -123,9 +225,19 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
             st.n_pde += 2
             return reduced.hessian_matvec(g, p, _lin, s)
 
-        vt, its, relres = pcg(mv, lambda r: reduced.precond(g, p, r),
+        if Zs:
+            prec = corrected_precond(g, p, E, Zs, HZs)
+        else:
+            prec = lambda r: reduced.precond(g, p, r)   # noqa: E731
+        rec = []
+        vt, its, relres = pcg(mv, prec,
                       lambda a, b: reduced.w_inner(g, p, a, b), g.norm,
-                      -lin.g, eta, opts.max_pcg, opts.fixed_pcg_iters)
+                      -lin.g, eta, opts.max_pcg, opts.fixed_pcg_iters,
+                      record=rec, record_max=min(opts.recycle, cap - len(Zs)))
+        for s_, hs_, e_ in rec:
+            Zs.append(s_)
+            HZs.append(hs_)
+            E.append(e_)
         st.pcg_iters += its
         slope = reduced.directional_derivative(g, p, lin.g, vt)
         alpha = 1.0
@@ -150,4 +262,5 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         st.n_pde += 2
         k += 1
     st.newton_iters = k
+    st.lowrank_dim = len(Zs)
     return lin.v, st
