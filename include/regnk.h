@@ -64,7 +64,9 @@ typedef struct {
     int32_t constraint;   /* REG_UNCONSTRAINED | REG_DIVFREE | REG_MASS_SOURCE */
     int32_t precision;    /* REG_FP64 | REG_FP32_TRANSPORT */
     int32_t adjoint;      /* REG_ADJ_DISCRETE | REG_ADJ_PAPER */
-    int32_t reserved;     /* must be 0 */
+    int32_t lowrank_capacity; /* 0..64: directions the low-rank preconditioner correction of
+                                 reg_solve can hold (workspace grows by 2 vector fields per direction,
+                                 4 for REG_MASS_SOURCE); 0 = no correction */
     double beta_v;        /* weight of the v seminorm (> 0) */
     double beta_w;        /* weight of the mass-source norm (> 0 iff REG_MASS_SOURCE) */
 } reg_params;
@@ -139,11 +141,30 @@ typedef struct {
     double armijo_rho;        /* backtracking factor (0.5) */
     const double* v0;         /* nullable device vector field: warm start (kept if J(v0) < J(0),
                                  otherwise the solve starts from v = 0: stats.fallback_used) */
+    /* Low-rank correction of the PCG preconditioner (an extension; the paper uses the spectral
+     * preconditioner alone).  A set of directions z_k with H z_k and e_k = <z_k, H z_k>_W > 0 turns
+     * M^{-1} = (beta_v A)^{-1} into the balancing (deflation) preconditioner
+     *   P r = Pi M^{-1} Pi^* r + sum_k z_k <z_k, r>_W / e_k,   Pi = I - sum_k z_k <H z_k, .>_W / e_k,
+     * which is SPD in <., .>_W for any such set and maps span{z_k} to itself under P H.  The set is
+     * built in two ways, both bounded by params.lowrank_capacity: */
+    const double* precond_U;  /* nullable device [rank][2][n1][n2]: caller directions.  At the
+                                 point where the first Newton step is taken their admissible parts
+                                 (Nyquist-free; Leray-projected for REG_DIVFREE) are orthonormalised
+                                 in <., M .>_W (near-dependent ones dropped), H is applied to that
+                                 basis (one matvec each, counted in stats) and Rayleigh-Ritz gives the
+                                 z_k; Ritz values <= 0 are dropped. */
+    double* precond_d;        /* nullable host [rank] (output): the kept Ritz values theta_k of H
+                                 relative to M, ascending, then zeros */
+    int32_t rank;             /* 0..min(8, lowrank_capacity) caller directions */
+    int32_t recycle;          /* >= 0: the first `recycle` search directions of each Newton step's
+                                 PCG solve (mutually H-conjugate) are added to the set for the later
+                                 steps, until it is full; no extra matvecs.  Needs capacity > 0. */
 } reg_solve_opts;
 
 typedef struct {
     int32_t newton_iters, pcg_iters, n_matvec, n_pde, backtracks, status;
     int32_t fallback_used;    /* 1: the warm start v0 did not lower J below J(0); solved from v = 0 */
+    int32_t lowrank_dim;      /* directions in the preconditioner correction when the solve ended */
     double g0_norm;           /* ||g(0)|| at v = 0 (also for a warm start) */
     double g_rel;             /* final ||g|| / ||g(0)|| */
     double J;                 /* final objective */

@@ -61,7 +61,9 @@ template <typename T>
 hipError_t launch_body_end(long nn, T w, const T* Q, const T* C, const T* G, T* B, hipStream_t s);
 
 // ---- 2D spectral operators (FP64) -----------------------------------------------------------
-enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG };
+// SPEC_LR: first result = admissible part of x (Leray projection for w = 0, x otherwise), second
+// result = K^{-1} P^ of that part (the preconditioner operator, weighted for <., .>_W).
+enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG, SPEC_LR };
 
 struct SpecParams {
     int n1, n2;
@@ -107,6 +109,25 @@ hipError_t launch_convert(long n, const double* in, TO* out, hipStream_t s);
 template <typename TI>
 hipError_t launch_widen(long n, const TI* in, double* out, hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
+
+// ---- low-rank deflation correction of the PCG preconditioner ------------------------------------
+// A set of vector fields holds slot k at F + k * stride.  cnt points to the number of valid slots
+// (a device double), so captured launch graphs stay valid while the set grows.
+constexpr int LR_MAX = 64;       // most directions a correction holds
+constexpr int LR_MIX_MAX = 8;    // most caller directions (Rayleigh-Ritz basis)
+struct LrMix {
+    double m[LR_MIX_MAX][LR_MIX_MAX];   // out_j = sum_i m[i][j] in_i
+};
+// out[k] = sum_i x[i] F_k[i] for k < *cnt (deterministic); partial: cap * RED_BLOCKS doubles
+hipError_t launch_lr_dots(long n, const double* x, const double* F, long stride, const double* cnt, int cap,
+                          double* partial, double* out, hipStream_t s);
+// out = base + sign * sum_{k < *cnt} (da[k] - db[k]) / e[k] * F_k   (db nullable = 0; out may alias base)
+// (*cnt is clamped to [0, cap] in both kernels)
+hipError_t launch_lr_combine(long n, const double* base, double* out, const double* F, long stride,
+                             const double* cnt, int cap, const double* da, const double* db, const double* e,
+                             double sign, hipStream_t s);
+// in place: F_j <- sum_{i < rin} m[i][j] F_i for j < rout (rin, rout <= LR_MIX_MAX)
+hipError_t launch_lr_mix(long n, double* F, long stride, int rin, int rout, const LrMix& m, hipStream_t s);
 
 // ---- PCG with device-side scalars (Alg. 2) ----------------------------------------------------
 // Slots of the FP64 scalar array shared by the PCG kernels.

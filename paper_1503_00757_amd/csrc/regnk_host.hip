@@ -45,6 +45,9 @@ constexpr int NSFIELD = 8;   // FP64 state-solve scratch fields
 constexpr int NPCG = 7;      // x, r, z, kr, s, st, kst
 constexpr int NSCAL = 32;
 constexpr int MAX_TIMED = 512;   // timed stage launches per reg_time_pass call
+// scalars of the low-rank correction: valid-slot count, a spare count, e_k, <z_k, r>_W, <Hz_k, y>_W
+enum { LRS_CNT = 0, LRS_CNT2 = 1, LRS_E = 8, LRS_DA = LRS_E + LR_MAX, LRS_DB = LRS_DA + LR_MAX,
+       LRS_G = LRS_DB + LR_MAX, LRS_N = LRS_G + LR_MIX_MAX * LR_MIX_MAX };
 
 struct Layout {
     size_t total = 0;
@@ -60,6 +63,7 @@ struct Offsets {
     size_t mT64, mR64, sfld[NSFIELD];   // FP64 state-solve buffers (FP32 transport mode only)
     size_t tw1f, tw2f, tw1d, tw2d;
     size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal, clk;
+    size_t lr[4], lrtmp, lrsc, lrpart;   // low-rank correction: sets Z, HZ, K^-1 Z, K^-1 HZ; scratch
     size_t total;
 };
 
@@ -77,7 +81,8 @@ reg_status check_params(const reg_params* p) {
         return fail(REG_EINVAL, "precision=%d", p->precision);
     if (p->adjoint != REG_ADJ_DISCRETE && p->adjoint != REG_ADJ_PAPER)
         return fail(REG_EINVAL, "adjoint=%d", p->adjoint);
-    if (p->reserved != 0) return fail(REG_EINVAL, "reserved must be 0");
+    if (p->lowrank_capacity < 0 || p->lowrank_capacity > LR_MAX)
+        return fail(REG_EINVAL, "lowrank_capacity=%d out of range [0, %d]", p->lowrank_capacity, LR_MAX);
     if (!(p->beta_v > 0.0) || !std::isfinite(p->beta_v)) return fail(REG_EINVAL, "beta_v must be > 0");
     const bool ms = p->constraint == REG_MASS_SOURCE;
     if (ms && !(p->beta_w > 0.0 && std::isfinite(p->beta_w)))
@@ -126,6 +131,13 @@ Offsets layout(const reg_params* p) {
     o.partial = L.take(4 * RED_BLOCKS * 8);
     o.scal = L.take(NSCAL * 8);
     o.clk = L.take((size_t)MAX_TIMED * 2 * clk_slots(p) * sizeof(unsigned long long));
+    // low-rank correction: Z and H Z (and their K^{-1} images for the mass-source model)
+    const size_t cap = (size_t)p->lowrank_capacity;
+    const int sets = p->constraint == REG_MASS_SOURCE ? 4 : 2;
+    for (int i = 0; i < 4; ++i) o.lr[i] = L.take(i < sets ? cap * 2 * nn * 8 : 0);
+    o.lrtmp = L.take(cap ? 2 * nn * 8 : 0);
+    o.lrsc = L.take(cap ? LRS_N * 8 : 0);
+    o.lrpart = L.take(cap ? (size_t)LR_MAX * RED_BLOCKS * 8 : 0);
     o.total = L.total;
     return o;
 }
@@ -161,6 +173,9 @@ struct reg_problem {
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t pcg_iter_graph = nullptr;   // one PCG iteration (matvec + scalar updates)
+    hipGraphExec_t pcg_iter_graph_lr = nullptr;   // the same with the low-rank correction
+    bool lr_active = false;   // PCG applies the low-rank correction (inside reg_solve only)
+    int lr_count = 0;         // valid directions (host copy of the device count)
     // measurement hook: hipEvents around every launch of one stage op during real matvecs
     int timing_op = -1;
     int clk_used = 0;   // timed launches recorded so far (reg_time_pass)
@@ -176,6 +191,9 @@ struct reg_problem {
     double* sF(int i) const { return at<double>(f64 ? o.fld[i] : o.sfld[i]); }
     double* scal() const { return at<double>(o.scal); }
     double* partial() const { return at<double>(o.partial); }
+    double* lr_set(int set) const { return at<double>(o.lr[set]); }
+    double* lr_slot(int set, int k) const { return lr_set(set) + (size_t)k * 2 * nn; }
+    double* lr_sc() const { return at<double>(o.lrsc); }
     cpx<double>* spec() const { return at<cpx<double>>(o.spec); }
 };
 
@@ -499,6 +517,8 @@ void drop_graphs(reg_problem* P) {
     P->graph_next = 0;
     if (P->pcg_iter_graph) (void)hipGraphExecDestroy(P->pcg_iter_graph);
     P->pcg_iter_graph = nullptr;
+    if (P->pcg_iter_graph_lr) (void)hipGraphExecDestroy(P->pcg_iter_graph_lr);
+    P->pcg_iter_graph_lr = nullptr;
 }
 
 // Capture the work `enqueue` puts on the problem's stream into an executable graph (on the private
@@ -565,6 +585,169 @@ reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
     return REG_OK;
 }
 
+// ---- low-rank deflation correction of the preconditioner -----------------------------------------
+// With directions z_k, H z_k and e_k > 0 (k < count; <z_i, H z_j>_W = e_i delta_ij for directions from
+// one Rayleigh-Ritz basis or one PCG solve), the balancing preconditioner is
+//     z = Pi M^{-1} Pi^* r + sum_k a_k z_k,   a_k = <z_k, r>_W / e_k,   Pi = I - sum_k z_k <H z_k, .>_W / e_k,
+// evaluated as r~ = r - sum a_k H z_k, y = M^{-1} r~, b_k = <H z_k, y>_W / e_k, z = y + sum (a_k - b_k) z_k.
+// It is symmetric positive definite in <., .>_W for any such set.  For the mass-source model the
+// W-products use the stored K^{-1} images and K^{-1} r = K^{-1} r~ + sum a_k K^{-1} H z_k.
+reg_status precond_pcg(reg_problem* P, const double* r, double* z, double* kr) {
+    if (!P->lr_active) return precond_t(P, r, z, kr);
+    const long n = 2 * P->nn;
+    const bool ms = P->p.constraint == REG_MASS_SOURCE;
+    const int cap = P->p.lowrank_capacity;
+    double* sc = P->lr_sc();
+    double* part = P->at<double>(P->o.lrpart);
+    double* rt = P->at<double>(P->o.lrtmp);
+    const double* Zw = P->lr_set(ms ? 2 : 0);
+    const double* HZw = P->lr_set(ms ? 3 : 1);
+    CK(launch_lr_dots(n, r, Zw, n, sc + LRS_CNT, cap, part, sc + LRS_DA, P->stream));
+    CK(launch_lr_combine(n, r, rt, P->lr_set(1), n, sc + LRS_CNT, cap, sc + LRS_DA, nullptr, sc + LRS_E, -1.0,
+                         P->stream));
+    CKS(precond_t(P, rt, z, kr));
+    CK(launch_lr_dots(n, z, HZw, n, sc + LRS_CNT, cap, part, sc + LRS_DB, P->stream));
+    CK(launch_lr_combine(n, z, z, P->lr_set(0), n, sc + LRS_CNT, cap, sc + LRS_DA, sc + LRS_DB, sc + LRS_E, 1.0,
+                         P->stream));
+    if (kr)
+        CK(launch_lr_combine(n, kr, kr, P->lr_set(3), n, sc + LRS_CNT, cap, sc + LRS_DA, nullptr, sc + LRS_E, 1.0,
+                             P->stream));
+    return REG_OK;
+}
+
+reg_status lr_set_count(reg_problem* P, int count) {
+    CK(launch_fill(1, (double)count, P->lr_sc() + LRS_CNT, P->stream));
+    P->lr_count = count;
+    return REG_OK;
+}
+
+// Symmetric eigen-decomposition of a small matrix (cyclic Jacobi rotations): A = V diag(w) V^T with
+// w ascending.  A (n x n, row-major) is overwritten.
+void sym_eig(int n, double* A, double* w, double* V) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V[i * n + j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                const double th = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {   // A <- J^T A J
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - sn * akq;
+                    A[k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - sn * aqk;
+                    A[q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - sn * vkq;
+                    V[k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * n + a] < A[b * n + b]; });
+    std::vector<double> Vs(n * n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = A[idx[j] * n + idx[j]];
+        for (int i = 0; i < n; ++i) Vs[i * n + j] = V[i * n + idx[j]];
+    }
+    for (int i = 0; i < n * n; ++i) V[i] = Vs[i];
+}
+
+// Gram matrix G_ij = sum X_i . Y_j (raw sums) of the first r slots of two sets, read back to the host.
+reg_status lr_gram(reg_problem* P, int setx, int sety, int r, double* G) {
+    const long n = 2 * P->nn;
+    double* sc = P->lr_sc();
+    CK(launch_fill(1, (double)r, sc + LRS_CNT2, P->stream));
+    for (int i = 0; i < r; ++i)
+        CK(launch_lr_dots(n, P->lr_slot(setx, i), P->lr_set(sety), n, sc + LRS_CNT2, P->p.lowrank_capacity,
+                          P->at<double>(P->o.lrpart), sc + LRS_G + i * r, P->stream));
+    CK(hipMemcpyAsync(G, sc + LRS_G, sizeof(double) * r * r, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    for (int i = 0; i < r; ++i)
+        for (int j = 0; j < i; ++j) G[i * r + j] = G[j * r + i] = 0.5 * (G[i * r + j] + G[j * r + i]);
+    return REG_OK;
+}
+
+// Rayleigh-Ritz on the caller directions U (r <= LR_MIX_MAX) at the current linearisation point:
+// admissible parts Z, orthonormalised in <., M .>_W (Gram eigenvalues <= 1e-10 of the largest
+// dropped), H applied to that basis, the projected Hessian diagonalised, Ritz pairs with theta <= 0
+// dropped.  Fills slots [0, kept) with Z, H Z (and K^{-1} images), e = theta.  theta_out (host,
+// nullable, r entries): the kept Ritz values ascending, then zeros.
+template <typename T>
+reg_status lr_setup_t(reg_problem* P, const double* U, int r, double* theta_out, int* nmv) {
+    const long n = 2 * P->nn;
+    const bool ms = P->p.constraint == REG_MASS_SOURCE;
+    for (int j = 0; j < r; ++j) {
+        CKS(spec_fwd<double>(P, 0, U + (size_t)j * n));
+        CKS(spec_col(P, SPEC_LR, false, true));
+        CKS(spec_inv<double>(P, 0, P->lr_slot(0, j), (double*)nullptr));
+        CKS(spec_inv<double>(P, 1, P->lr_slot(1, j), (double*)nullptr));   // K^{-1} M z_j (scratch)
+    }
+    double G[LR_MIX_MAX * LR_MIX_MAX], lam[LR_MIX_MAX], E[LR_MIX_MAX * LR_MIX_MAX];
+    CKS(lr_gram(P, 0, 1, r, G));
+    for (int i = 0; i < r * r; ++i)
+        if (!std::isfinite(G[i])) return fail(REG_ENONFINITE, "precond_U is not finite");
+    sym_eig(r, G, lam, E);
+    const double lmax = r > 0 ? lam[r - 1] : 0.0;
+    LrMix C{};
+    int r1 = 0;
+    for (int j = 0; j < r; ++j) {
+        if (!(lmax > 0.0) || !(lam[j] > 1e-10 * lmax)) continue;
+        for (int i = 0; i < r; ++i) C.m[i][r1] = E[i * r + j] / std::sqrt(lam[j]);
+        ++r1;
+    }
+    if (theta_out)
+        for (int j = 0; j < r; ++j) theta_out[j] = 0.0;
+    if (r1 == 0) return lr_set_count(P, 0);
+    CK(launch_lr_mix(n, P->lr_set(0), n, r, r1, C, P->stream));
+    for (int k = 0; k < r1; ++k) {
+        CKS(matvec_t<T>(P, P->lr_slot(0, k), P->lr_slot(1, k), ms ? P->lr_slot(3, k) : nullptr));
+        if (nmv) ++*nmv;
+    }
+    double Tm[LR_MIX_MAX * LR_MIX_MAX], th[LR_MIX_MAX], V[LR_MIX_MAX * LR_MIX_MAX];
+    CKS(lr_gram(P, 0, ms ? 3 : 1, r1, Tm));
+    for (int i = 0; i < r1 * r1; ++i)
+        if (!std::isfinite(Tm[i])) return fail(REG_ENONFINITE, "Hessian on precond_U is not finite");
+    sym_eig(r1, Tm, th, V);
+    LrMix R{};
+    double e[LR_MIX_MAX];
+    int r2 = 0;
+    for (int j = 0; j < r1; ++j) {
+        if (!(th[j] > 0.0) || !std::isfinite(th[j])) continue;
+        for (int i = 0; i < r1; ++i) R.m[i][r2] = V[i * r1 + j];
+        e[r2] = th[j];
+        if (theta_out) theta_out[r2] = th[j];
+        ++r2;
+    }
+    if (r2 == 0) return lr_set_count(P, 0);
+    CK(launch_lr_mix(n, P->lr_set(0), n, r1, r2, R, P->stream));
+    CK(launch_lr_mix(n, P->lr_set(1), n, r1, r2, R, P->stream));
+    if (ms) {
+        CK(launch_lr_mix(n, P->lr_set(3), n, r1, r2, R, P->stream));
+        for (int k = 0; k < r2; ++k)
+            CKS(precond_t(P, P->lr_slot(0, k), P->at<double>(P->o.lrtmp), P->lr_slot(2, k)));   // K^{-1} z_k
+    }
+    CK(hipMemcpyAsync(P->lr_sc() + LRS_E, e, sizeof(double) * r2, hipMemcpyHostToDevice, P->stream));
+    CK(hipStreamSynchronize(P->stream));   // e is a host stack array
+    return lr_set_count(P, r2);
+}
+
 // ---- PCG (Alg. 2) -----------------------------------------------------------------------------
 enum { PX = 0, PR, PZ, PKR, PS, PST, PKST };
 
@@ -585,7 +768,7 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
     }
     CK(launch_pcg_scalar(PCG_KAPPA, sc, P->stream));
     CK(launch_pcg_update(n, x, r, s, st, sc, P->stream));
-    CKS(precond_t(P, r, z, W ? kr : nullptr));
+    CKS(precond_pcg(P, r, z, W ? kr : nullptr));
     {
         const double* a[2] = {r, W ? kr : r};
         const double* b[2] = {r, z};
@@ -598,21 +781,25 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
 
 template <typename T>
 reg_status pcg_iter_run(reg_problem* P) {
-    if (P->use_graphs && !P->pcg_iter_graph) {
-        P->pcg_iter_graph = capture_graph(P, [&]() { return pcg_iter_enqueue<T>(P); });
-        if (!P->pcg_iter_graph) P->use_graphs = false;
+    hipGraphExec_t& graph = P->lr_active ? P->pcg_iter_graph_lr : P->pcg_iter_graph;
+    if (P->use_graphs && !graph) {
+        graph = capture_graph(P, [&]() { return pcg_iter_enqueue<T>(P); });
+        if (!graph) P->use_graphs = false;
     }
-    if (P->pcg_iter_graph) {
-        CK(hipGraphLaunch(P->pcg_iter_graph, P->stream));
+    if (graph) {
+        CK(hipGraphLaunch(graph, P->stream));
         P->matvec_done = true;
         return REG_OK;
     }
     return pcg_iter_enqueue<T>(P);
 }
 
+// record > 0: the first `record` search directions s_l that complete a step are copied with H s_l
+// (and K^{-1} H s_l) and e_l = <s_l, H s_l>_W into the correction slots lr_count + l; *recorded
+// receives how many are valid (the directions of one PCG solve are mutually H-conjugate).
 template <typename T>
 reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, int fixed_iters, double* xout,
-                 int* iters, double* relres, int* nmv) {
+                 int* iters, double* relres, int* nmv, int record = 0, int* recorded = nullptr) {
     const long n = 2 * P->nn;
     const bool W = P->p.constraint == REG_MASS_SOURCE;
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
@@ -621,7 +808,7 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     double* sc = P->scal();
     CK(hipMemcpyAsync(r, rhs, n * 8, hipMemcpyDeviceToDevice, P->stream));
     CK(launch_fill(n, 0.0, x, P->stream));
-    CKS(precond_t(P, r, z, W ? kr : nullptr));
+    CKS(precond_pcg(P, r, z, W ? kr : nullptr));
     CK(hipMemcpyAsync(s, z, n * 8, hipMemcpyDeviceToDevice, P->stream));
     {
         const double* a[2] = {W ? kr : r, r};
@@ -636,8 +823,17 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     if (!std::isfinite(r0)) return fail(REG_ENONFINITE, "PCG: right-hand side is not finite");
     const int nit = fixed_iters > 0 ? fixed_iters : max_iters;
     int l = 0;
+    if (recorded) *recorded = 0;
+    if (record > P->p.lowrank_capacity - P->lr_count) record = P->p.lowrank_capacity - P->lr_count;
     while (l < nit) {
+        const int slot = P->lr_count + l;
+        if (l < record) CK(hipMemcpyAsync(P->lr_slot(0, slot), s, n * 8, hipMemcpyDeviceToDevice, P->stream));
         CKS(pcg_iter_run<T>(P));
+        if (l < record) {
+            CK(hipMemcpyAsync(P->lr_slot(1, slot), P->pcg(PST), n * 8, hipMemcpyDeviceToDevice, P->stream));
+            if (W) CK(hipMemcpyAsync(P->lr_slot(3, slot), P->pcg(PKST), n * 8, hipMemcpyDeviceToDevice, P->stream));
+            CK(hipMemcpyAsync(P->lr_sc() + LRS_E + slot, sc + S_SHS, 8, hipMemcpyDeviceToDevice, P->stream));
+        }
         ++l;
         if (fixed_iters > 0) continue;   // fixed schedule: no stop test, no host round trip
         CK(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, P->stream));
@@ -651,6 +847,10 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     if (!std::isfinite(h[S_RR]) || !std::isfinite(h[S_RZ])) return fail(REG_ENONFINITE, "PCG: not finite");
     const int done = (int)h[S_ITER];
     if (nmv) *nmv += done;
+    if (recorded && record > 0) {
+        const int ok = h[S_BREAK] > 0 ? (int)h[S_BREAK] - 1 : done;   // steps with <s, H s>_W > 0
+        *recorded = std::max(0, std::min(record, ok));
+    }
     if (xout != x) CK(hipMemcpyAsync(xout, x, n * 8, hipMemcpyDeviceToDevice, P->stream));
     if (iters) *iters = done;
     if (relres) *relres = r0 > 0 ? std::sqrt(h[S_RR]) / r0 : 0.0;
@@ -703,6 +903,21 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
         }
     }
     CK(hipMemcpyAsync(v, P->at<double>(P->o.v64), n * 8, hipMemcpyDeviceToDevice, P->stream));
+    // low-rank correction of the PCG preconditioner: Rayleigh-Ritz on the caller directions at the
+    // first linearisation point, then (recycle > 0) the leading PCG directions of every Newton step
+    struct LrOff {
+        reg_problem* P;
+        ~LrOff() { P->lr_active = false; }
+    } lr_off{P};
+    const bool lr = o->rank > 0 || o->recycle > 0;
+    if (lr) {
+        CKS(lr_set_count(P, 0));
+        int nmv = 0;
+        if (o->rank > 0) CKS(lr_setup_t<T>(P, o->precond_U, o->rank, o->precond_d, &nmv));
+        S.n_matvec += nmv;
+        S.n_pde += 2 * nmv;
+        P->lr_active = true;
+    }
     int k = 0;
     reg_status status = REG_OK;
     double grel = 0;
@@ -715,9 +930,17 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
         CK(launch_axpby(n, -1.0, g, 0.0, rhs, P->stream));   // rhs = -g
         int its = 0;
         double rr = 0;
-        CKS(pcg_t<T>(P, rhs, eta, o->max_pcg, o->fixed_pcg_iters, vt, &its, &rr, &S.n_matvec));
+        int rec = 0;
+        CKS(pcg_t<T>(P, rhs, eta, o->max_pcg, o->fixed_pcg_iters, vt, &its, &rr, &S.n_matvec, lr ? o->recycle : 0,
+                     &rec));
         S.n_pde += 2 * its;
         S.pcg_iters += its;
+        if (rec > 0) {
+            if (W)
+                for (int q = P->lr_count; q < P->lr_count + rec; ++q)
+                    CKS(precond_t(P, P->lr_slot(0, q), P->at<double>(P->o.lrtmp), P->lr_slot(2, q)));
+            CKS(lr_set_count(P, P->lr_count + rec));
+        }
         double slope = 0;
         {
             const double* a[1] = {W ? kg : g};
@@ -752,6 +975,7 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
         ++k;
     }
     S.newton_iters = k;
+    S.lowrank_dim = lr ? P->lr_count : 0;
     S.g_rel = grel;
     S.J = J;
     S.status = status;
@@ -1115,11 +1339,22 @@ reg_status reg_pcg(reg_problem* h, const double* rhs, double eta, int32_t max_it
     return REG_OK;
 }
 
-reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out, reg_solve_stats* stats_host) {
-    if (!h || !opts || !v_out) return fail(REG_EINVAL, "NULL argument");
+static reg_status check_opts(const reg_problem* h, const reg_solve_opts* opts) {
     if (opts->max_newton < 0 || opts->max_pcg < 1 || opts->fixed_pcg_iters < 0 || opts->max_backtracks < 0 ||
         !(opts->armijo_rho > 0 && opts->armijo_rho < 1) || !(opts->armijo_c1 > 0 && opts->armijo_c1 < 1))
         return fail(REG_EINVAL, "bad solve options");
+    const int cap = h->p.lowrank_capacity;
+    if (opts->rank < 0 || opts->rank > std::min(cap, LR_MIX_MAX))
+        return fail(REG_EINVAL, "rank=%d: must be in [0, min(lowrank_capacity=%d, %d)]", opts->rank, cap, LR_MIX_MAX);
+    if (opts->rank > 0 && !opts->precond_U) return fail(REG_EINVAL, "rank > 0 needs precond_U");
+    if (opts->recycle < 0 || (opts->recycle > 0 && cap == 0))
+        return fail(REG_EINVAL, "recycle=%d needs lowrank_capacity > 0", opts->recycle);
+    return REG_OK;
+}
+
+reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out, reg_solve_stats* stats_host) {
+    if (!h || !opts || !v_out) return fail(REG_EINVAL, "NULL argument");
+    CKS(check_opts(h, opts));
     return DISPATCH(h, solve_t<float>(h, opts, v_out, stats_host), solve_t<double>(h, opts, v_out, stats_host));
 }
 
@@ -1132,6 +1367,7 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
     for (int i = 0; i < count; ++i)
         for (int k = 0; k < i; ++k)
             if (problems[i] == problems[k]) return fail(REG_EINVAL, "problem %d appears twice", i);
+    for (int i = 0; i < count; ++i) CKS(check_opts(problems[i], &opts[i]));
     // largest problems first (most work per pair), then a shared work counter
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;

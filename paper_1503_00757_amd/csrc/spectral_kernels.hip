@@ -16,6 +16,7 @@
 //   M^ = 1 + beta_v A^ / (beta_w |k|^2 (|k|^2 + 1))                 eq. (project-body-force)
 //   K^{-1} = I + c'(k) k k^T/|k|^2, c' = 1/(M^ - 1)                   (mass source only)
 //   P^ = beta_v A^, or beta_v where A^ = 0                          App. E.2
+// SPEC_LR returns the admissible part of a direction and K^{-1} P^ of it (low-rank correction).
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -152,6 +153,13 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
             o1 = {x1.x * pinv, x1.y * pinv};
             q0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
             q1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
+        } else if (mode == SPEC_LR) {
+            const double ca = p.constraint == 1 ? c : 0.0;   // Leray projection for w = 0
+            o0 = {x0.x - ca * (p11 * x0.x + p12 * x1.x), x0.y - ca * (p11 * x0.y + p12 * x1.y)};
+            o1 = {x1.x - ca * (p12 * x0.x + p22 * x1.x), x1.y - ca * (p12 * x0.y + p22 * x1.y)};
+            const double pm = p.beta_v * (A > 0.0 ? A : 1.0);
+            q0 = {pm * (o0.x + ci * (p11 * o0.x + p12 * o1.x)), pm * (o0.y + ci * (p11 * o0.y + p12 * o1.y))};
+            q1 = {pm * (o1.x + ci * (p12 * o0.x + p22 * o1.x)), pm * (o1.y + ci * (p12 * o0.y + p22 * o1.y))};
         } else {   // SPEC_REG: beta_v A v and beta_w (1 + |k|^2) k k^T v
             const double ba = p.beta_v * A;
             o0 = {ba * x0.x, ba * x0.y};

@@ -198,6 +198,98 @@ hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal
     return hipGetLastError();
 }
 
+// ---- low-rank deflation correction -------------------------------------------------------------
+// valid slots, clamped to [0, cap] (cap <= LR_MAX) so that no kernel reads past the set
+__device__ __forceinline__ int lr_count(const double* cnt, int cap) {
+    const double c = cnt[0];
+    return c >= 0.0 ? (c < (double)cap ? (int)c : cap) : 0;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void lr_dots_kernel(const double* __restrict__ x, const double* __restrict__ F,
+                                                             long stride, long n, const double* __restrict__ cnt,
+                                                             int cap, double* __restrict__ partial) {
+    __shared__ double sh[RED_THREADS / 64];
+    const int nk = lr_count(cnt, cap);
+    const long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
+    const long lo = (long)blockIdx.x * chunk;
+    const long hi = lo + chunk < n ? lo + chunk : n;
+    for (int k = 0; k < nk; ++k) {
+        const double* __restrict__ f = F + (long)k * stride;
+        double acc = 0.0;
+        for (long i = lo + threadIdx.x; i < hi; i += RED_THREADS) acc += x[i] * f[i];
+        const double s = block_sum<RED_THREADS>(acc, sh);
+        if (threadIdx.x == 0) partial[k * RED_BLOCKS + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(RED_THREADS) void lr_final_kernel(const double* __restrict__ partial,
+                                                              const double* __restrict__ cnt, int cap,
+                                                              double* __restrict__ out) {
+    __shared__ double sh[RED_THREADS / 64];
+    const int k = blockIdx.x;
+    if (k >= lr_count(cnt, cap)) return;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partial[k * RED_BLOCKS + i];
+    const double s = block_sum<RED_THREADS>(acc, sh);
+    if (threadIdx.x == 0) out[k] = s;
+}
+
+__global__ __launch_bounds__(256) void lr_combine_kernel(long n, const double* base, double* out,
+                                                        const double* __restrict__ F, long stride,
+                                                        const double* __restrict__ cnt, const double* __restrict__ da,
+                                                        const double* __restrict__ db, const double* __restrict__ e,
+                                                        double sign, int cap) {
+    __shared__ double c[LR_MAX];
+    const int nk = lr_count(cnt, cap);
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) c[k] = sign * (da[k] - (db ? db[k] : 0.0)) / e[k];
+    __syncthreads();
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double acc = base[i];
+        for (int k = 0; k < nk; ++k) acc += c[k] * F[(long)k * stride + i];
+        out[i] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void lr_mix_kernel(long n, double* F, long stride, int rin, int rout, LrMix m) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double in[LR_MIX_MAX];
+#pragma unroll
+        for (int k = 0; k < LR_MIX_MAX; ++k) in[k] = k < rin ? F[(long)k * stride + i] : 0.0;
+#pragma unroll
+        for (int j = 0; j < LR_MIX_MAX; ++j) {
+            if (j < rout) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < LR_MIX_MAX; ++k) acc += m.m[k][j] * in[k];
+                F[(long)j * stride + i] = acc;
+            }
+        }
+    }
+}
+
+hipError_t launch_lr_dots(long n, const double* x, const double* F, long stride, const double* cnt, int cap,
+                          double* partial, double* out, hipStream_t s) {
+    if (cap < 1 || cap > LR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lr_dots_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, F, stride, n, cnt, cap, partial);
+    hipLaunchKernelGGL(lr_final_kernel, dim3(cap), dim3(RED_THREADS), 0, s, partial, cnt, cap, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lr_combine(long n, const double* base, double* out, const double* F, long stride,
+                             const double* cnt, int cap, const double* da, const double* db, const double* e,
+                             double sign, hipStream_t s) {
+    if (cap < 0 || cap > LR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lr_combine_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, base, out, F, stride, cnt, da, db, e,
+                       sign, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_lr_mix(long n, double* F, long stride, int rin, int rout, const LrMix& m, hipStream_t s) {
+    if (rin < 0 || rin > LR_MIX_MAX || rout < 0 || rout > LR_MIX_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lr_mix_kernel, dim3(grid_for(n)), dim3(256), 0, s, n, F, stride, rin, rout, m);
+    return hipGetLastError();
+}
+
 template hipError_t launch_dots<double>(int, const double* const*, const double* const*, long, double*, double*,
                                         hipStream_t);
 template hipError_t launch_dots<float>(int, const float* const*, const float* const*, long, double*, double*,

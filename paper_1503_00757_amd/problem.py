@@ -14,14 +14,14 @@ _ADJ = {"dto": ffi.REG_ADJ_DISCRETE, "paper": ffi.REG_ADJ_PAPER}
 
 
 def make_params(n1, n2, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0, precision="fp32",
-                adjoint="dto") -> ffi.RegParams:
-    return ffi.RegParams(n1, n2, nt, _NORMS[norm], _CONS[constraint], _PREC[precision], _ADJ[adjoint], 0,
-                         float(beta_v), float(beta_w))
+                adjoint="dto", lowrank_capacity=0) -> ffi.RegParams:
+    return ffi.RegParams(n1, n2, nt, _NORMS[norm], _CONS[constraint], _PREC[precision], _ADJ[adjoint],
+                         int(lowrank_capacity), float(beta_v), float(beta_w))
 
 
 class Problem:
     def __init__(self, mT, mR, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0,
-                 precision="fp32", adjoint="dto", stream=None):
+                 precision="fp32", adjoint="dto", stream=None, lowrank_capacity=0):
         import torch
         self.torch = torch
         if mT.dtype != torch.float64 or mR.dtype != torch.float64 or not mT.is_cuda or not mR.is_cuda:
@@ -29,7 +29,8 @@ class Problem:
         n1, n2 = mT.shape
         self.n1, self.n2, self.nt = n1, n2, nt
         self.device = mT.device
-        self.params = make_params(n1, n2, nt, norm, constraint, beta_v, beta_w, precision, adjoint)
+        self.params = make_params(n1, n2, nt, norm, constraint, beta_v, beta_w, precision, adjoint,
+                                  lowrank_capacity)
         self.ws_bytes = ffi.reg_workspace_bytes(self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
@@ -102,19 +103,32 @@ class Problem:
         return x, it, rr
 
     def solve_opts(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
-                   armijo_c1=1e-4, armijo_rho=0.5, v0=None):
+                   armijo_c1=1e-4, armijo_rho=0.5, v0=None, precond_U=None, recycle=0, ritz_out=None):
+        """reg_solve_opts; v0 / precond_U must be contiguous float64 device tensors kept alive by the
+        caller, ritz_out a ctypes double array of len(precond_U) (or None)."""
+        rank = 0 if precond_U is None else int(precond_U.shape[0])
         return ffi.RegSolveOpts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
-                                armijo_rho, v0.data_ptr() if v0 is not None else None)
+                                armijo_rho, v0.data_ptr() if v0 is not None else None,
+                                precond_U.data_ptr() if precond_U is not None else None, ritz_out, rank,
+                                int(recycle))
 
     def solve(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
-              armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True):
+              armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True, precond_U=None, recycle=0):
+        """Alg. 1 (reg_solve).  precond_U: (r, 2, n1, n2) float64 directions of the preconditioner
+        correction; recycle: PCG directions kept per Newton step (both need lowrank_capacity > 0).
+        The stats dict carries the Ritz values of precond_U as "ritz"."""
+        import ctypes
         v0c = self._c(v0) if v0 is not None else None
-        opts = ffi.RegSolveOpts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
-                                armijo_rho, v0c.data_ptr() if v0c is not None else None)
+        Uc = self._c(precond_U) if precond_U is not None else None
+        ritz = (ctypes.c_double * int(Uc.shape[0]))() if Uc is not None and Uc.shape[0] > 0 else None
+        opts = self.solve_opts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
+                               armijo_rho, v0c, Uc, recycle, ritz)
         v = self.vec()
         status, st = ffi.reg_solve(self.h, opts, v.data_ptr(), raise_on_error)
         d = st.as_dict()
         d["return_status"] = status
+        if ritz is not None:
+            d["ritz"] = list(ritz)
         return v, d
 
     def time_pass(self, which, reps=100):
@@ -132,7 +146,7 @@ class Problem:
 def batch_solve(problems, raise_on_error=True, v0s=None, **opts):
     """Solve many problems concurrently (reg_batch_solve); returns ([v], [stats dict])."""
     outs = [p.vec() for p in problems]
-    v0s = v0s or [None] * len(problems)
-    o = [p.solve_opts(v0=(v0.contiguous() if v0 is not None else None), **opts) for p, v0 in zip(problems, v0s)]
+    v0s = [v0.contiguous() if v0 is not None else None for v0 in (v0s or [None] * len(problems))]
+    o = [p.solve_opts(v0=v0, **opts) for p, v0 in zip(problems, v0s)]
     status, st = ffi.reg_batch_solve([p.h for p in problems], o, [v.data_ptr() for v in outs], raise_on_error)
     return outs, [s.as_dict() for s in st]

@@ -40,8 +40,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(R.RegParams) == 8 * 4 + 2 * 8
-    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 8
-    assert ctypes.sizeof(R.RegSolveStats) == 7 * 4 + 4 + 3 * 8   # 4 bytes of padding before the doubles
+    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4
+    assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 3 * 8
 
 
 def test_workspace_bytes_scales_with_grid_and_steps():
@@ -69,15 +69,28 @@ def test_invalid_parameters_are_rejected(kw):
     assert len(R.reg_last_error()) > 0
 
 
-def test_bad_enum_and_reserved_rejected():
+def test_bad_enum_and_lowrank_capacity_rejected():
     p = make_params(64, 64, 4)
     p.norm = 3
     with pytest.raises(R.RegError):
         R.reg_workspace_bytes(p)
-    p = make_params(64, 64, 4)
-    p.reserved = 1
-    with pytest.raises(R.RegError):
-        R.reg_workspace_bytes(p)
+    for cap in (-1, 65):
+        p = make_params(64, 64, 4, lowrank_capacity=cap)
+        with pytest.raises(R.RegError) as e:
+            R.reg_workspace_bytes(p)
+        assert e.value.status == -1
+
+
+@pytest.mark.parametrize("constraint,beta_w,sets", [("divfree", 0.0, 2), ("mass_source", 1e-3, 4)])
+def test_workspace_grows_with_lowrank_capacity(constraint, beta_w, sets):
+    """Each direction of the correction holds z and H z (and their K^-1 images for the mass-source
+    model) as FP64 vector fields."""
+    n = 64
+    ws = [R.reg_workspace_bytes(make_params(n, n, 4, "H1", constraint, 1e-2, beta_w, lowrank_capacity=c))
+          for c in (0, 4, 8)]
+    field = 2 * n * n * 8
+    assert ws[1] - ws[0] >= sets * 4 * field
+    assert ws[2] - ws[1] == sets * 4 * field
 
 
 def test_create_rejects_null_and_small_workspace_without_device_work():

@@ -1,0 +1,163 @@
+"""GPU parity of the low-rank correction of the PCG preconditioner with the oracle.
+
+Rayleigh-Ritz on caller directions: the Ritz values returned through reg_solve_opts.precond_d match
+the oracle's at the first linearisation point.  Fixed-schedule solves (same Newton count, exactly
+``fixed_pcg_iters`` PCG steps per Newton step) with caller directions and with recycled PCG
+directions reach the oracle's velocity (1e-10 FP64, 1e-4 FP32 -- the final-velocity bound of the
+precision plan) with the same matvec and direction counts.  The adaptive 256^2 solve with recycling
+tracks the oracle's Newton count and needs fewer PCG iterations than the plain solve; the plain
+reg_pcg is unchanged after a corrected solve; bad options are rejected.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel
+from oracle import Grid, reduced, solver
+
+pytestmark = pytest.mark.gpu
+
+C1_64 = Case(64, 64, 4, "H1", "divfree", 1e-2, 0.0, "fp64", config=1)
+MS_64 = Case(32, 128, 5, "H2", "mass_source", 1e-3, 1e-4, "fp64", "dto", 1)
+UN_64 = Case(64, 64, 4, "H1", "none", 1e-2, 0.0, "fp64", seed=3)
+C2 = Case(256, 256, 16, "H2", "mass_source", 1e-3, 1e-4, "fp32", config=2)
+
+
+def directions(case, r, seed=7):
+    """Seeded smooth random directions (r, 2, n1, n2): low-pass filtered normal fields."""
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((r, 2, case.n1, case.n2))
+    k1 = np.fft.fftfreq(case.n1, 1.0 / case.n1)[:, None]
+    k2 = np.fft.rfftfreq(case.n2, 1.0 / case.n2)[None, :]
+    filt = np.exp(-(k1 ** 2 + k2 ** 2) / 18.0)
+    return np.fft.irfft2(np.fft.rfft2(U) * filt, s=(case.n1, case.n2))
+
+
+@pytest.mark.parametrize("case,tol", [(C1_64, 1e-9), (MS_64, 1e-9), (UN_64, 1e-9)])
+def test_ritz_values_and_fixed_schedule_parity(case, tol):
+    print(f"[case] lowrank ritz {case}", flush=True)
+    mT, mR, *_ = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    U = directions(case, 3)
+    lin0 = reduced.gradient(g, p, mT, mR, np.zeros((2, case.n1, case.n2)))
+    theta, _, _ = solver.lowrank_setup(g, p, lambda s: reduced.hessian_matvec(g, p, lin0, s), list(U))
+    assert len(theta) == 3
+    v_ref, st = solver.solve(g, p, mT, mR, solver.SolveOpts(max_newton=3, fixed_pcg_iters=6, gtol_rel=0.0,
+                                                            precond_U=U))
+    P = gpu_problem(case, lowrank_capacity=8)
+    try:
+        v, s = P.solve(max_newton=3, fixed_pcg_iters=6, gtol_rel=0.0, precond_U=dev(U))
+        assert s["status"] == 0 and s["newton_iters"] == 3
+        assert np.allclose(s["ritz"], np.sort(theta), rtol=tol, atol=0)
+        assert s["lowrank_dim"] == st.lowrank_dim == 3
+        assert s["n_matvec"] == st.n_matvec == 18 + 3
+        assert s["pcg_iters"] == st.pcg_iters and s["backtracks"] == st.backtracks
+        assert rel(host(v), v_ref) < 10 * tol
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("case,tol", [(C1_64, 1e-9), (MS_64, 1e-9), (C2, 1e-4)])
+def test_recycled_directions_fixed_schedule_parity(case, tol):
+    print(f"[case] lowrank recycle {case}", flush=True)
+    mT, mR, *_ = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    opts = dict(max_newton=3, fixed_pcg_iters=6, gtol_rel=0.0)
+    v_ref, st = solver.solve(g, p, mT, mR, solver.SolveOpts(recycle=4, lowrank_capacity=10, **opts))
+    assert st.status == solver.OK and st.lowrank_dim == 10
+    P = gpu_problem(case, lowrank_capacity=10)
+    try:
+        v, s = P.solve(recycle=4, **opts)
+        assert s["status"] == 0 and s["newton_iters"] == 3
+        assert s["lowrank_dim"] == 10 and s["n_matvec"] == s["pcg_iters"] == st.pcg_iters == 18
+        assert s["backtracks"] == st.backtracks
+        assert rel(host(v), v_ref) < tol
+        assert abs(s["g_rel"] - st.g_rel) <= 100 * tol * st.g_rel + 1e-12
+    finally:
+        P.close()
+
+
+def test_recycling_adaptive_c2_tracks_oracle_and_saves_iterations():
+    """Alg. 1 with the forcing term to ||g||/||g(0)|| <= 1e-2 on the 256^2 workload, recycling the first
+    4 directions of each PCG solve into a 16-direction correction."""
+    case = C2
+    mT, mR, *_ = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    v_ref, st = solver.solve(g, p, mT, mR, solver.SolveOpts(max_newton=50, gtol_rel=1e-2, recycle=4,
+                                                            lowrank_capacity=16))
+    P = gpu_problem(case, lowrank_capacity=16)
+    try:
+        v0, s0 = P.solve(max_newton=50, gtol_rel=1e-2)
+        v, s = P.solve(max_newton=50, gtol_rel=1e-2, recycle=4)
+        print({"plain": s0, "recycled": s, "oracle_pcg": st.pcg_iters, "oracle_newton": st.newton_iters})
+        assert s["status"] == 0 and s["g_rel"] <= 1e-2
+        assert s["newton_iters"] == st.newton_iters
+        assert abs(s["pcg_iters"] - st.pcg_iters) <= 2
+        assert rel(host(v), v_ref) < 1e-3
+        assert s["pcg_iters"] < s0["pcg_iters"] and s["n_pde"] < s0["n_pde"]
+        # both stop somewhere inside ||g|| <= 1e-2 ||g(0)||: the objective agrees far more closely
+        assert abs(s["J"] - s0["J"]) <= 1e-3 * s0["J"]
+    finally:
+        P.close()
+
+
+def test_plain_pcg_unchanged_after_corrected_solve():
+    case = MS_64
+    mT, mR, vlin, *_ = inputs(case)
+    P = gpu_problem(case, lowrank_capacity=8)
+    try:
+        g, _ = P.gradient(dev(vlin), want_J=False)
+        x1, it1, rr1 = P.pcg(-g, eta=0.0, max_iters=100, fixed_iters=5)
+        P.solve(max_newton=2, gtol_rel=0.0, recycle=3, precond_U=dev(directions(case, 2)))
+        g2, _ = P.gradient(dev(vlin), want_J=False)
+        x2, it2, rr2 = P.pcg(-g2, eta=0.0, max_iters=100, fixed_iters=5)
+        assert np.array_equal(host(g), host(g2))
+        assert np.array_equal(host(x1), host(x2)) and rr1 == rr2
+    finally:
+        P.close()
+
+
+def test_batch_solve_with_recycling_matches_single_solves():
+    from paper_1503_00757_amd import batch_solve
+    cases = [C1_64, UN_64]
+    probs = [gpu_problem(c, lowrank_capacity=8) for c in cases]
+    try:
+        singles = [P.solve(max_newton=20, gtol_rel=1e-3, recycle=2) for P in probs]
+        outs, stats = batch_solve(probs, max_newton=20, gtol_rel=1e-3, recycle=2)
+        for (v1, s1), v2, s2 in zip(singles, outs, stats):
+            assert s2["status"] == 0 and s2["lowrank_dim"] == s1["lowrank_dim"] > 0
+            assert s2["pcg_iters"] == s1["pcg_iters"]
+            assert np.array_equal(host(v1), host(v2))
+    finally:
+        for P in probs:
+            P.close()
+
+
+def test_lowrank_options_are_checked():
+    from paper_1503_00757_amd import ffi
+    case = C1_64
+    P0 = gpu_problem(case)
+    P = gpu_problem(case, lowrank_capacity=4)
+    U = dev(directions(case, 5))
+    try:
+        for prob, kw in [(P0, dict(recycle=1)), (P, dict(recycle=-1)), (P, dict(precond_U=U)),
+                         (P0, dict(precond_U=U[:1]))]:
+            with pytest.raises(ffi.RegError) as e:
+                prob.solve(max_newton=1, **kw)
+            assert e.value.status == ffi.REG_EINVAL
+        # rank > 0 with a NULL pointer
+        opts = P.solve_opts(max_newton=1)
+        opts.rank = 2
+        with pytest.raises(ffi.RegError) as e:
+            ffi.reg_solve(P.h, opts, P.vec().data_ptr())
+        assert e.value.status == ffi.REG_EINVAL
+        # a direction with nothing admissible (Nyquist only) is dropped, the solve goes on
+        nyq = np.zeros((1, 2, case.n1, case.n2))
+        nyq[0, 0] = (-1.0) ** np.arange(case.n1)[:, None]
+        v, s = P.solve(max_newton=2, gtol_rel=0.0, precond_U=dev(nyq))
+        assert s["status"] == 0 and s["lowrank_dim"] == 0 and s["ritz"] == [0.0]
+    finally:
+        P.close()
+        P0.close()
