@@ -87,7 +87,8 @@ def setup(config: int, precision: str = "fp32", tune_cache: str | None = None):
     P0 = Problem(mT, mT.clone(), w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, precision)
     mR = P0.state_forward(torch.tensor(w.vstar, device=dev))
     P0.close()
-    P = Problem(mT, mR, w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, precision)
+    P = Problem(mT, mR, w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, precision,
+                lowrank_capacity=LOWRANK_CAPACITY)
     vlin = torch.tensor(0.5 * w.vstar, device=dev)
     vt = torch.tensor(w.vtilde, device=dev)
     P.gradient(vlin, want_J=False)
@@ -140,11 +141,18 @@ def roofline(P, reps=None, workload="c2"):
             "exec_achieved": round(by / (ex * 1e-3) / 1e9, 2)}
 
 
-def bench_solve(P):
+LOWRANK_CAPACITY = 16   # directions of the preconditioner correction the bench problems can hold
+
+
+def bench_solve(P, recycle=0):
+    """Alg. 1 to ||g||/||g(0)|| <= 1e-2 from v = 0; recycle > 0 keeps that many PCG directions of each
+    Newton step in the low-rank correction of the preconditioner (one untimed run first: graph
+    capture)."""
     import torch
+    P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, recycle=recycle)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    v, st = P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2)
+    v, st = P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, recycle=recycle)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"seconds": round(dt, 4), "newton_iters": st["newton_iters"], "pcg_iters": st["pcg_iters"],
@@ -263,7 +271,7 @@ def bench_warmstart(train, test, epochs=60, label_gtol=1e-3, label_pool=16):
     torch.cuda.synchronize()
     t_inf = e0.elapsed_time(e1) / 20
     log(f"comparing plain vs learned on {len(test)} unseen pairs")
-    recs = W.compare_plain_vs_learned(test, 16, ws, dev, log=log)
+    recs = W.compare_plain_vs_learned(test, 16, ws, dev, log=log, recycle=4)
     s = W.summarize(recs)
     return {
         "protocol": f"train {len(train) - nval} pairs at {train[0][0].shape[0]}^2 (+{nval} held out), "
@@ -275,6 +283,8 @@ def bench_warmstart(train, test, epochs=60, label_gtol=1e-3, label_pool=16):
                                  "speedup_mean": round(s["plain_ms_mean"] / s["learned_ms_mean"], 3)},
         "newton_mean": {"plain": s["plain_newton_mean"], "learned": s["learned_newton_mean"]},
         "pcg_mean": {"plain": s["plain_pcg_mean"], "learned": s["learned_pcg_mean"]},
+        # the same solves with 4 recycled PCG directions per Newton step (16-direction correction)
+        "with_recycled_directions": s.get("recycle"),
         "converged": {"plain": s["plain_converged"], "learned": s["learned_converged"]},
         "fallback_rate": s["fallback_rate"], "faster_fraction": s["faster_fraction"],
         "label_seconds": round(t_labels, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
@@ -374,6 +384,7 @@ def main():
         extras["matvec_only_per_s"] = round(1.0 / bench_matvec(P, vt, 50), 2)
         print("[bench] solve", file=sys.stderr, flush=True)
         extras["solve_to_grel_1e-2_plain"] = bench_solve(P)
+        extras["solve_to_grel_1e-2_recycle4"] = bench_solve(P, recycle=4)
     P.close()
     if not args.no_extras and cfg == 2:
         print("[bench] 1024^2 nt=32", file=sys.stderr, flush=True)

@@ -253,12 +253,16 @@ def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settin
     return feats, labels, all_stats
 
 
-def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup=1, log=None, **settings):
+def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup=1, log=None, recycle=0,
+                             **settings):
     """Time to ||g|| / ||g(0)|| <= gtol for every (m_T, v*) pair: plain solve (v0 = 0) and learned solve
     (network inference + solve from its v0, which includes g(0) and g(v0)) on one problem handle.
-    Returns per-pair records."""
+    recycle > 0 also times both with that many PCG directions of each Newton step recycled into the
+    low-rank correction of the preconditioner.  Returns per-pair records."""
     import torch
     s = dict(SOLVER, **settings)
+    if recycle > 0:
+        s.setdefault("lowrank_capacity", 16)
     recs = []
     P = None
     gen = None
@@ -272,6 +276,8 @@ def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup
             P = Problem(mT, mR, nt, **s)
             for _ in range(warmup):   # graph capture and first-touch costs, not timed
                 P.solve(gtol_rel=gtol, raise_on_error=False)
+                if recycle > 0:
+                    P.solve(gtol_rel=gtol, raise_on_error=False, recycle=recycle)
                 ws.predict(mT, mR)
         P.set_images(mT, mR)
         torch.cuda.synchronize()
@@ -281,7 +287,16 @@ def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup
         v0 = ws.predict(mT, mR)
         _, sl = P.solve(gtol_rel=gtol, v0=v0, raise_on_error=False)
         t2 = time.perf_counter()
-        recs.append({"plain_s": t1 - t0, "learned_s": t2 - t1, "plain": sp, "learned": sl})
+        rec = {"plain_s": t1 - t0, "learned_s": t2 - t1, "plain": sp, "learned": sl}
+        if recycle > 0:
+            t0 = time.perf_counter()
+            _, spr = P.solve(gtol_rel=gtol, raise_on_error=False, recycle=recycle)
+            t1 = time.perf_counter()
+            v0 = ws.predict(mT, mR)
+            _, slr = P.solve(gtol_rel=gtol, v0=v0, raise_on_error=False, recycle=recycle)
+            t2 = time.perf_counter()
+            rec.update({"plain_rc_s": t1 - t0, "learned_rc_s": t2 - t1, "plain_rc": spr, "learned_rc": slr})
+        recs.append(rec)
         if log and i % 32 == 0:
             log(f"pair {i}: plain {1e3 * (t1 - t0):.1f} ms ({sp['newton_iters']} GN, {sp['pcg_iters']} PCG), "
                 f"learned {1e3 * (t2 - t1):.1f} ms ({sl['newton_iters']} GN, {sl['pcg_iters']} PCG, "
@@ -296,7 +311,19 @@ def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup
 def summarize(recs):
     import statistics as stt
     f = lambda k, sub: [r[sub][k] for r in recs]   # noqa: E731
-    return {
+    out = {}
+    if recs and "plain_rc" in recs[0]:
+        ok = lambda sub: sum(1 for r in recs if r[sub]["g_rel"] <= 1e-2 and r[sub]["status"] == 0)  # noqa: E731
+        out["recycle"] = {
+            "plain_ms_mean": round(1e3 * stt.mean(r["plain_rc_s"] for r in recs), 3),
+            "learned_ms_mean": round(1e3 * stt.mean(r["learned_rc_s"] for r in recs), 3),
+            "plain_pcg_mean": stt.mean(f("pcg_iters", "plain_rc")),
+            "learned_pcg_mean": stt.mean(f("pcg_iters", "learned_rc")),
+            "plain_newton_mean": stt.mean(f("newton_iters", "plain_rc")),
+            "learned_newton_mean": stt.mean(f("newton_iters", "learned_rc")),
+            "plain_converged": ok("plain_rc"), "learned_converged": ok("learned_rc"),
+        }
+    return out | {
         "pairs": len(recs),
         "plain_ms_mean": 1e3 * stt.mean(r["plain_s"] for r in recs),
         "learned_ms_mean": 1e3 * stt.mean(r["learned_s"] for r in recs),
