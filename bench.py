@@ -124,6 +124,26 @@ def bench_matvec(P, vt, reps):
     return (time.perf_counter() - t0) / reps
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Measured device-to-device copy bandwidth (read + write bytes / time) of a plain torch copy of
+    `mib` MiB, timed with events on the current stream: the practical HBM ceiling next to the 8 TB/s
+    specification."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)
+
+
 def roofline(P, reps=None, workload="c2"):
     """Dominant kernel: the fused GN incremental-adjoint stage-2 launch (stage_fused_kernel<..., OP_A2>):
     row blocks read 10 and write 3 fields (incl. the body-force accumulation), column blocks read 3
@@ -315,9 +335,31 @@ def cpu_baseline(budget_s=12.0):
         if dt > budget_s or n >= 200:
             break
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    return {"value": round(n / dt, 3), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} FP64 oracle GN matvecs (numpy/scipy.fft, all cores) on the 256^2, n_t=16 workload "
-                      f"at its linearisation point, {dt:.1f} s"}
+    out = {"value": round(n / dt, 3), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} FP64 oracle GN matvecs (numpy/scipy.fft, all cores) on the 256^2, n_t=16 workload "
+                     f"at its linearisation point, {dt:.1f} s"}
+    # the same matvec with one scipy.fft worker, and the oracle's full solves of configs 1 and 2
+    spectral.set_workers(1)
+    n1 = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 4.0 and n1 < 50:
+        reduced.hessian_matvec(g, p, lin, w.vtilde)
+        n1 += 1
+    out["single_worker_matvecs_per_s"] = round(n1 / (time.perf_counter() - t0), 3)
+    spectral.set_workers(-1)
+    from oracle import solver
+    w1 = sd.make_workload(1)
+    p1 = Params(w1.n1, w1.n2, w1.nt, w1.norm, w1.constraint, w1.beta_v, w1.beta_w)
+    g1 = Grid(w1.n1, w1.n2)
+    mR1 = transport.state_forward(g1, p1, w1.mT, w1.vstar).m[-1]
+    t0 = time.perf_counter()
+    solver.solve(g1, p1, w1.mT, mR1, solver.SolveOpts(max_newton=5, fixed_pcg_iters=10, gtol_rel=0.0))
+    out["solve_c1_5x10_seconds"] = round(time.perf_counter() - t0, 3)
+    t0 = time.perf_counter()
+    _, st = solver.solve(g, p, w.mT, mR, solver.SolveOpts(max_newton=50, gtol_rel=1e-2))
+    out["solve_c2_to_grel_1e-2_seconds"] = round(time.perf_counter() - t0, 3)
+    out["solve_c2_pcg_iters"] = st.pcg_iters
+    return out
 
 
 def main():
@@ -378,6 +420,9 @@ def main():
     dt = bench_pcg(P, vlin, args.steps, args.warmup)
     print(f"[bench] pcg {args.steps} steps {dt:.3f}s", file=sys.stderr, flush=True)
     rl = roofline(P, workload=args.workload)
+    copy_gbs = copy_bandwidth()
+    rl["measured_copy_GBs"] = copy_gbs
+    rl["frac_of_measured_copy"] = round(rl["achieved"] / copy_gbs, 4)
     tuned = P.tuned
     extras = {}
     if not args.no_extras:
@@ -398,6 +443,7 @@ def main():
         extras["c3_1024sq_nt32"] = {"matvecs_per_s": round(1.0 / t3, 2), "ms_per_matvec": round(t3 * 1e3, 3),
                                     "model_bytes_per_matvec": bmodel,
                                     "model_frac_of_8TBs": round(bmodel / t3 / 8e12, 4),
+                                    "model_frac_of_measured_copy": round(bmodel / t3 / (copy_gbs * 1e9), 4),
                                     "dominant_kernel": rl3}
     if ws_pairs is not None:
         print("[bench] c5 learned warm start", file=sys.stderr, flush=True)
