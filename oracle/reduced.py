@@ -4,7 +4,8 @@
 Paper: Sec. 2, eq. (objective) with eqs. (reg-v), (reg-w); Sec. 3.3, eq. (control-eq-elim)
 g = beta_v A[v] + K[b]; eq. (inc-control-eq-elim) H v~ = beta_v B[v~] + L[b~] with B = A and L = K for
 the quadratic seminorms; Sec. 4 (Gauss-Newton: every term carrying lam is dropped, which keeps H
-positive definite); App. E.2 (preconditioner (beta_v A)^{-1}).
+positive definite); App. E.2 (preconditioner (beta_v A)^{-1}).  ``hessian_matvec_full`` keeps the lam
+terms (full Newton, an extension).
 
 Readings (listed in the design notes):
   * every velocity-like input (v, v~) and output (g, H v~) has its Nyquist modes removed (F_Nyq);
@@ -21,7 +22,8 @@ import numpy as np
 from .spectral import (Grid, Params, apply_A, apply_K, apply_Kinv, apply_precond, nyquist_project,
                        div, penalty_grad_w)
 from .transport import (state_forward, adjoint_backward, body_force, inc_state_forward,
-                        inc_adjoint_backward_gn)
+                        inc_adjoint_backward_gn, inc_state_forward_stages, inc_adjoint_backward_full,
+                        inc_body_force_full)
 
 
 def objective_terms(g: Grid, p: Params, mT, mR, v, traj=None):
@@ -76,6 +78,21 @@ def hessian_matvec(g: Grid, p: Params, lin: Linearization, vt):
     vt = nyquist_project(g, vt)
     mt1 = inc_state_forward(g, p, lin.v, lin.traj, vt)
     bt = inc_adjoint_backward_gn(g, p, lin.v, lin.traj, mt1)
+    return nyquist_project(g, p.beta_v * apply_A(g, p, vt) + apply_K(g, p, bt))
+
+
+def hessian_matvec_full(g: Grid, p: Params, lin: Linearization, vt):
+    """Full-Newton reduced Hessian matvec (an extension of the paper's Gauss-Newton step): eq.
+    (inc-control-eq-elim) with every lam term of eqs. (inc-adj-eq-elim) and the incremental body force
+    kept, H v~ = F_Nyq[beta_v A v~ + K b~], b~ = int lam~ grad m + lam grad m~ dt.  Implemented as the
+    exact derivative of the 'dto' discrete gradient, so it is the Hessian of the discrete objective
+    (symmetric in <., .>_W, possibly indefinite away from a minimiser)."""
+    if p.adjoint != "dto":
+        raise ValueError("the full-Newton Hessian is defined for the 'dto' discretisation")
+    vt = nyquist_project(g, vt)
+    mt, mts = inc_state_forward_stages(g, p, lin.v, lin.traj, vt)
+    lt, lts = inc_adjoint_backward_full(g, p, lin.v, vt, lin.lam, lin.lam_star, mt[-1])
+    bt = inc_body_force_full(g, p, lin.traj, lin.lam, lin.lam_star, mt, mts, lt, lts)
     return nyquist_project(g, p.beta_v * apply_A(g, p, vt) + apply_K(g, p, bt))
 
 

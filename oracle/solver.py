@@ -14,6 +14,8 @@ Readings (listed in the design notes):
     direction);
   * Armijo: alpha_0 = 1, rho = 1/2, c_1 = 1e-4, at most ``max_backtracks`` halvings; slope = dJ[v~];
   * the relative gradient is ||g(v_k)|| / ||g(0)||, with g(0) taken at v = 0 even for a warm start;
+  * ``hessian="full"`` replaces the Gauss-Newton matvec by the exact Hessian of the discrete objective
+    (an extension); where it is not positive along a search direction PCG stops as above;
   * a warm start is kept only if J(v_0) < J(0) (the globalisation needs descent from the plain
     start), otherwise the solve starts from v = 0;
   * optional low-rank correction of the preconditioner (not in the paper): a deflation set of
@@ -52,6 +54,7 @@ class SolveOpts:
     v0: np.ndarray | None = None
     precond_U: np.ndarray | None = None   # (r, 2, n1, n2) directions of the low-rank correction
     recycle: int = 0                      # PCG directions of each Newton step kept for the next ones
+    hessian: str = "gn"                   # "gn" (the paper's Gauss-Newton) or "full" (exact Hessian)
     lowrank_capacity: int = 16            # most directions the correction holds
 
 
@@ -195,6 +198,9 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         else:
             st.fallback_used = 1
     v = lin.v
+    if opts.hessian not in ("gn", "full"):
+        raise ValueError("hessian must be 'gn' or 'full'")
+    hess = reduced.hessian_matvec_full if opts.hessian == "full" else reduced.hessian_matvec
     # deflation set of the preconditioner correction: directions z, H z and e = <z, H z>_W
     E, Zs, HZs = [], [], []
     cap = opts.lowrank_capacity
@@ -205,7 +211,7 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         def mv0(s, _lin=lin):
             st.n_matvec += 1
             st.n_pde += 2
-            return reduced.hessian_matvec(g, p, _lin, s)
+            return hess(g, p, _lin, s)
         theta, Z, HZ = lowrank_setup(g, p, mv0, list(opts.precond_U))
         st.lowrank = (theta, Z)
         E, Zs, HZs = list(theta), list(Z), list(HZ)
@@ -223,7 +229,7 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         def mv(s, _lin=lin):
             st.n_matvec += 1
             st.n_pde += 2
-            return reduced.hessian_matvec(g, p, _lin, s)
+            return hess(g, p, _lin, s)
 
         if Zs:
             prec = corrected_precond(g, p, E, Zs, HZs)

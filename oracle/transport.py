@@ -6,6 +6,11 @@ Sec. 3.2, eq. (newton-step) and the incremental body force; Sec. 3.3, eqs. (stat
 in time, trapezoidal quadrature, Gauss-Newton approximation: every term that carries lam is dropped
 from the incremental system).
 
+Full Newton (an extension; the paper uses Gauss-Newton): for the 'dto' discretisation the
+incremental system is differentiated exactly, keeping the terms that carry lam, so that the matvec is
+the exact Hessian of the discrete reduced objective (``inc_adjoint_backward_full``,
+``inc_body_force_full``).
+
 Discretisation (readings listed in the design notes):
   * h_t = 1/n_t, t_j = j h_t; the RK2 scheme is Heun's method (explicit trapezoid).  For the
     autonomous state and adjoint equations every two-stage RK2 gives I + h L + h^2 L^2 / 2.
@@ -125,3 +130,52 @@ def inc_adjoint_backward_gn(g: Grid, p: Params, v, traj: StateTrajectory, mt_fin
     """
     lam, lam_star = adjoint_backward(g, p, v, -mt_final)
     return body_force(p, traj, lam, lam_star)
+
+
+# ---- full Newton (second-order) incremental system, exact for the 'dto' discretisation ---------------
+def inc_state_forward_stages(g: Grid, p: Params, v, traj: StateTrajectory, vt):
+    """The incremental state of ``inc_state_forward`` with its stage values kept: returns
+    (mt, mt_star) with m~_j for j = 0..n_t and the predictors m~*_j for j < n_t."""
+    h = 1.0 / p.nt
+    mt = [np.zeros_like(traj.m[0])]
+    mts = []
+    for j in range(p.nt):
+        Sj = -(vt[0] * traj.G[j][0] + vt[1] * traj.G[j][1])
+        Gnext = traj.Gs[j] if p.adjoint == "dto" else traj.G[j + 1]
+        Ss = -(vt[0] * Gnext[0] + vt[1] * Gnext[1])
+        k1 = L(g, v, mt[-1]) + Sj
+        mstar = mt[-1] + h * k1
+        mts.append(mstar)
+        mt.append(mt[-1] + 0.5 * h * (k1 + L(g, v, mstar) + Ss))
+    return mt, mts
+
+
+def inc_adjoint_backward_full(g: Grid, p: Params, v, vt, lam, lam_star, mt_final):
+    """Full-Newton incremental adjoint: the derivative along v~ of the discrete adjoint recursion
+    (Heun on eq. (adj-eq-elim)), i.e. eq. (inc-adj-eq-elim) with the div(lam v~) term kept:
+
+        lam~*_j = lam~_{j+1} + h (L_v^T lam~_{j+1} + L_v~^T lam_{j+1}),
+        lam~_j  = (lam~_{j+1} + lam~*_j)/2 + (h/2)(L_v^T lam~*_j + L_v~^T lam*_j),
+
+    from lam~_{n_t} = -m~_{n_t}.  Returns (lam~, lam~*) like ``adjoint_backward``."""
+    h = 1.0 / p.nt
+    lt = [None] * (p.nt + 1)
+    lts = [None] * p.nt
+    lt[p.nt] = -mt_final
+    for j in range(p.nt - 1, -1, -1):
+        k1 = LT(g, v, lt[j + 1]) + LT(g, vt, lam[j + 1])
+        lts[j] = lt[j + 1] + h * k1
+        k2 = LT(g, v, lts[j]) + LT(g, vt, lam_star[j])
+        lt[j] = lt[j + 1] + 0.5 * h * (k1 + k2)
+    return lt, lts
+
+
+def inc_body_force_full(g: Grid, p: Params, traj: StateTrajectory, lam, lam_star, mt, mts, lt, lts):
+    """Derivative along v~ of the 'dto' body force sum (h/2)(lam*_j G_j + lam_{j+1} G*_j):
+    b~ = sum (h/2)(lam~*_j G_j + lam*_j grad m~_j + lam~_{j+1} G*_j + lam_{j+1} grad m~*_j)."""
+    h = 1.0 / p.nt
+    b = np.zeros_like(traj.G[0])
+    for j in range(p.nt):
+        b += 0.5 * h * (lts[j] * traj.G[j] + lam_star[j] * grad(g, mt[j])
+                        + lt[j + 1] * traj.Gs[j] + lam[j + 1] * grad(g, mts[j]))
+    return b
