@@ -57,6 +57,16 @@ enum { REG_FP64 = 0, REG_FP32_TRANSPORT = 1 };
  * REG_ADJ_PAPER uses the trapezoidal rule as printed. */
 enum { REG_ADJ_DISCRETE = 0, REG_ADJ_PAPER = 1 };
 
+/* Hessian of the matvec and of the solve's Newton steps.  REG_HESS_GN: the Gauss-Newton
+ * approximation of Sec. 4 (every term that carries lam dropped; positive definite).  REG_HESS_FULL:
+ * an extension -- eq. (inc-control-eq-elim) with the div(lam v~) term of eq. (inc-adj-eq-elim) and the
+ * lam grad m~ term of the incremental body force kept, discretised as the exact derivative of the
+ * REG_ADJ_DISCRETE gradient (the Hessian of the discrete objective: symmetric, possibly indefinite
+ * away from a minimiser, where PCG stops at the first direction of non-positive curvature).  Needs
+ * REG_ADJ_DISCRETE; the workspace also holds the adjoint stage values (2 n_t fields) and the
+ * incremental-state gradients (2 n_t vector fields) in the transport precision. */
+enum { REG_HESS_GN = 0, REG_HESS_FULL = 1 };
+
 typedef struct {
     int32_t n1, n2;       /* grid (powers of two, 8..2048) */
     int32_t nt;           /* RK2 time steps on [0, 1] */
@@ -64,9 +74,11 @@ typedef struct {
     int32_t constraint;   /* REG_UNCONSTRAINED | REG_DIVFREE | REG_MASS_SOURCE */
     int32_t precision;    /* REG_FP64 | REG_FP32_TRANSPORT */
     int32_t adjoint;      /* REG_ADJ_DISCRETE | REG_ADJ_PAPER */
+    int32_t hessian;      /* REG_HESS_GN | REG_HESS_FULL */
     int32_t lowrank_capacity; /* 0..64: directions the low-rank preconditioner correction of
                                  reg_solve can hold (workspace grows by 2 vector fields per direction,
                                  4 for REG_MASS_SOURCE); 0 = no correction */
+    int32_t reserved;     /* must be 0 */
     double beta_v;        /* weight of the v seminorm (> 0) */
     double beta_w;        /* weight of the mass-source norm (> 0 iff REG_MASS_SOURCE) */
 } reg_params;

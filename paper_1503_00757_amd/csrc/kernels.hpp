@@ -10,7 +10,11 @@ template <typename T>
 struct cpx;
 
 // Transport stage operations (see transport_kernels.hpp for the formulas).
-enum PassOp { OP_S1 = 0, OP_S2, OP_A1, OP_A2, OP_I1, OP_I2, OP_GRAD };
+// OP_A1F / OP_A2F: the incremental adjoint stages of the full-Newton Hessian (flux v lam~ + v~ lam
+// and the lam grad m~ body-force terms); they take the launch shapes tuned for OP_A1 / OP_A2.
+enum PassOp { OP_S1 = 0, OP_S2, OP_A1, OP_A2, OP_I1, OP_I2, OP_GRAD, OP_A1F, OP_A2F };
+constexpr int NUM_TUNED_OPS = 7;
+constexpr int op_base(int op) { return op == OP_A1F ? OP_A1 : (op == OP_A2F ? OP_A2 : op); }
 enum PassFlags { F_ZERO = 1, F_FIRST = 2, F_NEG = 4 };
 
 // One RK2 stage: input u = A + Bf (Bf nullable; negated with F_NEG; with F_ZERO u = -h v~ . G2).
@@ -31,10 +35,14 @@ struct StageArgs {
     const T* VT;             // v~ (vector field)
     const T* G;              // stored gradient (vector field)
     const T* G2;             // second stored gradient (vector field)
+    const T* LAM;            // full Newton: stored adjoint at the stage (lam_{j+1} in stage 1, lam*_j in 2)
+    const T* LAM2;           // full Newton, stage 2: lam_{j+1}
+    const T* GT;             // full Newton, stage 2: grad m~_j (vector field; nullable = 0)
+    const T* GT2;            // full Newton, stage 2: grad m~*_j (vector field)
     T* ROUT;
     T* UOUT;
     T* COUT;
-    T* GOUT;                 // grad m output of the state stages (vector field)
+    T* GOUT;                 // grad of the stage input (state and incremental-state stages; vector field)
     float* GOUTF;            // same, rounded to FP32 (FP64 state solve feeding an FP32 trajectory)
     T* B;                    // body-force accumulator (vector field)
     const cpx<T>* tw1;       // twiddles of length n1 (column transforms)

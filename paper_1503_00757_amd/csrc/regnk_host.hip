@@ -64,6 +64,7 @@ struct Offsets {
     size_t tw1f, tw2f, tw1d, tw2d;
     size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal, clk;
     size_t lr[4], lrtmp, lrsc, lrpart;   // low-rank correction: sets Z, HZ, K^-1 Z, K^-1 HZ; scratch
+    size_t lamtraj, gmt;                 // full Newton: lam_{j+1}, lam*_j; grad m~_j, grad m~*_j
     size_t total;
 };
 
@@ -81,6 +82,10 @@ reg_status check_params(const reg_params* p) {
         return fail(REG_EINVAL, "precision=%d", p->precision);
     if (p->adjoint != REG_ADJ_DISCRETE && p->adjoint != REG_ADJ_PAPER)
         return fail(REG_EINVAL, "adjoint=%d", p->adjoint);
+    if (p->hessian != REG_HESS_GN && p->hessian != REG_HESS_FULL) return fail(REG_EINVAL, "hessian=%d", p->hessian);
+    if (p->hessian == REG_HESS_FULL && p->adjoint != REG_ADJ_DISCRETE)
+        return fail(REG_EINVAL, "the full-Newton Hessian needs adjoint = REG_ADJ_DISCRETE");
+    if (p->reserved != 0) return fail(REG_EINVAL, "reserved must be 0");
     if (p->lowrank_capacity < 0 || p->lowrank_capacity > LR_MAX)
         return fail(REG_EINVAL, "lowrank_capacity=%d out of range [0, %d]", p->lowrank_capacity, LR_MAX);
     if (!(p->beta_v > 0.0) || !std::isfinite(p->beta_v)) return fail(REG_EINVAL, "beta_v must be > 0");
@@ -138,6 +143,9 @@ Offsets layout(const reg_params* p) {
     o.lrtmp = L.take(cap ? 2 * nn * 8 : 0);
     o.lrsc = L.take(cap ? LRS_N * 8 : 0);
     o.lrpart = L.take(cap ? (size_t)LR_MAX * RED_BLOCKS * 8 : 0);
+    const bool full = p->hessian == REG_HESS_FULL;
+    o.lamtraj = L.take(full ? (size_t)2 * p->nt * nn * ts : 0);
+    o.gmt = L.take(full ? (size_t)2 * p->nt * 2 * nn * ts : 0);
     o.total = L.total;
     return o;
 }
@@ -159,7 +167,7 @@ struct reg_problem {
     bool matvec_done = false;
     SpecParams sp;
     double h1h2;
-    int var[7] = {};   // launch-shape variant per stage op (FP32 square grids)
+    int var[NUM_TUNED_OPS] = {};   // launch-shape variant per stage op (FP32 square grids)
     // Captured Hessian-matvec launch sequences, one per (input, output, K^-1 output) pointer set.
     struct MvGraph {
         const double* in = nullptr;
@@ -212,6 +220,10 @@ struct TV {
     T* F(int i) const { return P->at<T>(P->o.fld[i]); }
     T* B() const { return P->at<T>(P->o.B); }
     T* Bt() const { return P->at<T>(P->o.Bt); }
+    // full Newton: lam_{j+1} at slot j, lam*_j at slot n_t + j; grad m~_j at slot j (j >= 1),
+    // grad m~*_j at slot n_t + j
+    T* Lam(int slot) const { return P->at<T>(P->o.lamtraj) + (size_t)slot * P->nn; }
+    T* Gm(int slot) const { return P->at<T>(P->o.gmt) + (size_t)slot * 2 * P->nn; }
     const cpx<T>* tw1() const;
     const cpx<T>* tw2() const;
 };
@@ -243,13 +255,14 @@ StageArgs<T> base_args(const reg_problem* P) {
 
 template <typename T>
 reg_status stage(reg_problem* P, int op, const StageArgs<T>& a) {
+    const int var = P->var[op_base(op)];
     if (op == P->timing_op && P->clk_used < MAX_TIMED && 2 * (size_t)P->clk_used + 2 <= P->tev.size()) {
         StageArgs<T> t = a;   // the blocks stamp their own start and end; the dispatch stamps two events
         t.clk = P->at<unsigned long long>(P->o.clk) + P->clk_stride * P->clk_used;
-        CK(launch_stage<T>(op, P->var[op], t, P->stream, P->tev[2 * P->clk_used], P->tev[2 * P->clk_used + 1]));
+        CK(launch_stage<T>(op, var, t, P->stream, P->tev[2 * P->clk_used], P->tev[2 * P->clk_used + 1]));
         ++P->clk_used;
     } else {
-        CK(launch_stage<T>(op, P->var[op], a, P->stream));
+        CK(launch_stage<T>(op, var, a, P->stream));
     }
     return REG_OK;
 }
@@ -307,9 +320,12 @@ reg_status state_forward(reg_problem* P, const double* v, bool store, double* m1
 
 // ---- adjoint solve backward (eq. (adj-eq-elim)); also the GN incremental adjoint ------------------
 // Terminal value lam(1) = sign (TA + TB) (TB nullable).  B: body force (vector, overwritten) in the
-// selected quadrature, using the stored trajectory.
+// selected quadrature, using the stored trajectory.  Full Newton: keep = true stores the stage values
+// lam_{j+1}, lam*_j (the gradient's adjoint sweep); vt != nullptr runs the full-Newton incremental
+// adjoint (stages OP_A1F / OP_A2F with the stored lam and grad m~).
 template <typename T>
-reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB, bool negate, T* B) {
+reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB, bool negate, T* B,
+                            bool keep = false, const T* vt = nullptr) {
     TV<T> tv{P};
     const long nn = P->nn;
     const T h = T(1.0 / P->nt);
@@ -323,23 +339,31 @@ reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB
         StageArgs<T> s1 = base_args<T>(P);
         s1.A = A; s1.Bf = Bf; s1.flags = (first && negate) ? F_NEG : 0;
         s1.V1 = v; s1.V2 = v + nn;
-        s1.ROUT = tv.F(2); s1.UOUT = tv.F(4); s1.COUT = tv.F(3);
+        T* u1 = keep ? tv.Lam(j) : tv.F(4);   // lam_{j+1} (materialised by stage 1)
+        s1.ROUT = tv.F(2); s1.UOUT = u1; s1.COUT = tv.F(3);
         if (paper) {
             s1.B = B; s1.G = tv.G(slot_G(P, j + 1));
             s1.bw = (j + 1 == P->nt) ? T(0.5) * h : h;
             s1.flags |= first ? F_FIRST : 0;
         }
-        CKS(stage<T>(P, OP_A1, s1));
+        if (vt) { s1.VT = vt; s1.LAM = tv.Lam(j); }
+        CKS(stage<T>(P, vt ? OP_A1F : OP_A1, s1));
         StageArgs<T> s2 = base_args<T>(P);
-        s2.A = tv.F(2); s2.Bf = tv.F(3); s2.X = tv.F(4);
+        s2.A = tv.F(2); s2.Bf = tv.F(3); s2.X = u1;
         s2.V1 = v; s2.V2 = v + nn;
         s2.ROUT = tv.F(nxt.r); s2.COUT = tv.F(nxt.c);
+        if (keep) s2.UOUT = tv.Lam(P->nt + j);   // lam*_j
         if (!paper) {
             s2.B = B; s2.G = tv.G(slot_G(P, j)); s2.G2 = tv.G(slot_Gs(P, j));
             s2.bw = T(0.5) * h;
             s2.flags = first ? F_FIRST : 0;
         }
-        CKS(stage<T>(P, OP_A2, s2));
+        if (vt) {
+            s2.VT = vt; s2.LAM = tv.Lam(P->nt + j); s2.LAM2 = tv.Lam(j);
+            s2.GT = j > 0 ? tv.Gm(j) : nullptr;   // grad m~_0 = 0
+            s2.GT2 = tv.Gm(P->nt + j);
+        }
+        CKS(stage<T>(P, vt ? OP_A2F : OP_A2, s2));
         A = tv.F(nxt.r);
         Bf = tv.F(nxt.c);
         nxt = (nxt.r == 0) ? Pair{5, 6} : Pair{0, 1};
@@ -350,8 +374,9 @@ reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB
 
 // ---- incremental state forward (eq. (inc-state-eq-elim)) ---------------------------------------
 // Leaves m~(1) = R + C; returns the scratch indices of the pair.
+// keep_grad (full Newton): store grad m~_j (j >= 1) and grad m~*_j from the stage transforms.
 template <typename T>
-reg_status inc_state_forward(reg_problem* P, const T* v, const T* vt, Pair* out) {
+reg_status inc_state_forward(reg_problem* P, const T* v, const T* vt, Pair* out, bool keep_grad = false) {
     TV<T> tv{P};
     const long nn = P->nn;
     const bool paper = P->p.adjoint == REG_ADJ_PAPER;
@@ -367,11 +392,13 @@ reg_status inc_state_forward(reg_problem* P, const T* v, const T* vt, Pair* out)
             s1.A = tv.F(cur.r); s1.Bf = tv.F(cur.c);
             s1.V1 = v; s1.V2 = v + nn; s1.VT = vt; s1.G = tv.G(slot_G(P, j));
             s1.ROUT = tv.F(2); s1.UOUT = tv.F(4); s1.COUT = tv.F(3);
+            if (keep_grad) s1.GOUT = tv.Gm(j);
             CKS(stage<T>(P, OP_I1, s1));
             s2.A = tv.F(2); s2.Bf = tv.F(3); s2.X = tv.F(4);
         }
         s2.V1 = v; s2.V2 = v + nn; s2.VT = vt; s2.G = Gsrc2;
         s2.ROUT = tv.F(nxt.r); s2.COUT = tv.F(nxt.c);
+        if (keep_grad) s2.GOUT = tv.Gm(P->nt + j);
         CKS(stage<T>(P, OP_I2, s2));
         std::swap(cur, nxt);
     }
@@ -475,7 +502,8 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
         CKS(data_term(P, P->sF(7), &d));
         CKS(reg_terms(P, v64, &rv, &rw));
     }
-    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(8), (const T*)nullptr, false, tv.B()));
+    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(8), (const T*)nullptr, false, tv.B(),
+                            P->p.hessian == REG_HESS_FULL));
     CKS(spec_fwd<double>(P, 0, v64));
     CKS(spec_fwd<T>(P, 1, tv.B()));
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
@@ -497,9 +525,11 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
     CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
     Pair mt;
-    CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), &mt));
+    const bool full = P->p.hessian == REG_HESS_FULL;
+    CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), &mt, full));
     // lam~(1) = -m~(1)
-    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(mt.r), tv.F(mt.c), true, tv.Bt()));
+    CKS(adjoint_backward<T>(P, tv.vT(), tv.F(mt.r), tv.F(mt.c), true, tv.Bt(), false,
+                            full ? (const T*)tv.vtT() : (const T*)nullptr));
     CKS(spec_fwd<double>(P, 0, vt64));
     CKS(spec_fwd<T>(P, 1, tv.Bt()));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
@@ -1066,6 +1096,7 @@ reg_status time_launches(reg_problem* P, int op, int var, const StageArgs<T>& a,
 template <typename T>
 reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes, double* exec_ms) {
     if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
+    if (P->p.hessian != REG_HESS_GN) return fail(REG_EINVAL, "the timing hook covers the Gauss-Newton stages");
     if (reps < 1 || reps > 1000) return fail(REG_EINVAL, "reps must be in [1, 1000]");
     if ((long)reps * P->nt > MAX_TIMED)
         return fail(REG_EINVAL, "reps * nt = %ld timed launches exceed %d", (long)reps * P->nt, MAX_TIMED);
@@ -1151,7 +1182,7 @@ reg_status autotune_f32(reg_problem* P, int reps, char* report, size_t cap) {
         P->var[op] = best;
     }
     js += ", \"chosen\": [";
-    for (int op = 0; op < 7; ++op) js += std::to_string(P->var[op]) + (op < 6 ? ", " : "");
+    for (int op = 0; op < NUM_TUNED_OPS; ++op) js += std::to_string(P->var[op]) + (op < NUM_TUNED_OPS - 1 ? ", " : "");
     js += "]}";
     g_err = "no error";
     if (report && cap > 0) {
@@ -1443,7 +1474,7 @@ reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_
     if (count != 7) return fail(REG_EINVAL, "count must be 7 (one launch shape per stage op)");
     for (int op = 0; op < 7; ++op)
         if (variants[op] < 0 || variants[op] >= NUM_STAGE_VARIANTS) return fail(REG_EINVAL, "variant index out of range");
-    for (int op = 0; op < 7; ++op) h->var[op] = variants[op];
+    for (int op = 0; op < NUM_TUNED_OPS; ++op) h->var[op] = variants[op];
     drop_graphs(h);
     return REG_OK;
 }

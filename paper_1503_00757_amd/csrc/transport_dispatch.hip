@@ -8,6 +8,8 @@ extern template hipError_t launch_stage_op<float, OP_A1>(int, const StageArgs<fl
 extern template hipError_t launch_stage_op<float, OP_A2>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<float, OP_I2>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<float, OP_A1F>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<float, OP_A2F>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<double, OP_S1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<double, OP_S2>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<double, OP_A1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
@@ -15,6 +17,8 @@ extern template hipError_t launch_stage_op<double, OP_A2>(int, const StageArgs<d
 extern template hipError_t launch_stage_op<double, OP_I1>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<double, OP_I2>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<double, OP_GRAD>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_A1F>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_stage_op<double, OP_A2F>(int, const StageArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <>
 hipError_t launch_stage<float>(int op, int var, const StageArgs<float>& a, hipStream_t s, hipEvent_t t0,
@@ -24,6 +28,8 @@ hipError_t launch_stage<float>(int op, int var, const StageArgs<float>& a, hipSt
         case OP_A2: return launch_stage_op<float, OP_A2>(var, a, s, t0, t1);
         case OP_I1: return launch_stage_op<float, OP_I1>(var, a, s, t0, t1);
         case OP_I2: return launch_stage_op<float, OP_I2>(var, a, s, t0, t1);
+        case OP_A1F: return launch_stage_op<float, OP_A1F>(var, a, s, t0, t1);
+        case OP_A2F: return launch_stage_op<float, OP_A2F>(var, a, s, t0, t1);
     }
     return hipErrorInvalidValue;
 }
@@ -39,6 +45,8 @@ hipError_t launch_stage<double>(int op, int var, const StageArgs<double>& a, hip
         case OP_I1: return launch_stage_op<double, OP_I1>(var, a, s, t0, t1);
         case OP_I2: return launch_stage_op<double, OP_I2>(var, a, s, t0, t1);
         case OP_GRAD: return launch_stage_op<double, OP_GRAD>(var, a, s, t0, t1);
+        case OP_A1F: return launch_stage_op<double, OP_A1F>(var, a, s, t0, t1);
+        case OP_A2F: return launch_stage_op<double, OP_A2F>(var, a, s, t0, t1);
     }
     return hipErrorInvalidValue;
 }

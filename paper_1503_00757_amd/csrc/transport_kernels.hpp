@@ -52,7 +52,11 @@ __device__ __forceinline__ void st2(T* __restrict__ p, long i, T a, T b) {
     *reinterpret_cast<typename V2T<T>::t*>(p + i) = v;
 }
 
-constexpr bool is_adj(int op) { return op == OP_A1 || op == OP_A2; }
+constexpr bool is_full(int op) { return op == OP_A1F || op == OP_A2F; }
+constexpr bool is_a1(int op) { return op == OP_A1 || op == OP_A1F; }
+constexpr bool is_a2(int op) { return op == OP_A2 || op == OP_A2F; }
+constexpr bool is_adj(int op) { return is_a1(op) || is_a2(op); }
+constexpr bool is_inc(int op) { return op == OP_I1 || op == OP_I2; }
 
 // ---------------------------------------------------------------------------------------------
 // Row part.  row_load issues every global load (transform input first, then epilogue operands) so
@@ -61,6 +65,7 @@ constexpr bool is_adj(int op) { return op == OP_A1 || op == OP_A2; }
 template <typename T>
 struct Rp {
     T u, v, x, g0, g1, h0, h1, b0, b1;
+    T l, l2, t0, t1, s0, s1;   // full Newton: lam, lam_{j+1}, grad m~_j, grad m~*_j
 };
 
 template <typename T, int OP>
@@ -74,7 +79,7 @@ __device__ __forceinline__ T row_load(const StageArgs<T>& a, long idx, Rp<T>& p)
         p.u = (a.flags & F_NEG) ? -u : u;
     }
     if constexpr (OP != OP_GRAD) p.v = a.V2[idx];
-    if constexpr (OP == OP_S2 || OP == OP_A2) p.x = a.X[idx];
+    if constexpr (OP == OP_S2 || is_a2(OP)) p.x = a.X[idx];
     if constexpr (OP == OP_I2) p.x = (a.flags & F_ZERO) ? T(0) : a.X[idx];
     if constexpr (OP == OP_I1 || OP == OP_I2) {
         p.g0 = a.VT[idx];
@@ -86,7 +91,7 @@ __device__ __forceinline__ T row_load(const StageArgs<T>& a, long idx, Rp<T>& p)
         if (a.B) {
             p.g0 = a.G[idx];
             p.g1 = a.G[nn + idx];
-            if constexpr (OP == OP_A2) {
+            if constexpr (is_a2(OP)) {
                 p.h0 = a.G2[idx];
                 p.h1 = a.G2[nn + idx];
             }
@@ -99,6 +104,18 @@ __device__ __forceinline__ T row_load(const StageArgs<T>& a, long idx, Rp<T>& p)
             }
         }
     }
+    if constexpr (is_full(OP)) {   // flux v lam~ + v~ lam (component 2 here)
+        p.l = a.LAM[idx];
+        const T w = a.VT[nn + idx];
+        if constexpr (OP == OP_A2F) {
+            p.l2 = a.LAM2[idx];
+            p.t0 = a.GT ? a.GT[idx] : T(0);
+            p.t1 = a.GT ? a.GT[nn + idx] : T(0);
+            p.s0 = a.GT2[idx];
+            p.s1 = a.GT2[nn + idx];
+        }
+        return p.v * p.u + w * p.l;
+    }
     return is_adj(OP) ? p.v * p.u : p.u;
 }
 
@@ -107,7 +124,7 @@ __device__ __forceinline__ void row_store(const StageArgs<T>& a, long idx, T d, 
     const long nn = a.nn;
     const T h = a.h;
     const T hh = T(0.5) * a.h;
-    if constexpr (OP == OP_S1 || OP == OP_S2 || OP == OP_GRAD) {   // d = d2 m: component 1 of grad m
+    if constexpr (OP == OP_S1 || OP == OP_S2 || OP == OP_GRAD || is_inc(OP)) {   // d = d2 u: component 1 of grad u
         if (a.GOUT) a.GOUT[nn + idx] = d;
         if (a.GOUTF) a.GOUTF[nn + idx] = (float)d;
     }
@@ -116,7 +133,7 @@ __device__ __forceinline__ void row_store(const StageArgs<T>& a, long idx, T d, 
         a.UOUT[idx] = p.u;                                             // m_j
     } else if constexpr (OP == OP_S2) {
         a.ROUT[idx] = T(0.5) * (p.x + p.u) - hh * p.v * d;             // R of m_{j+1}
-    } else if constexpr (OP == OP_A1) {
+    } else if constexpr (is_a1(OP)) {
         a.ROUT[idx] = p.u + h * d;                                     // R of l*
         a.UOUT[idx] = p.u;                                             // l_{j+1}
         if (a.B) {                                                     // trapezoid: w_{j+1} h l_{j+1} G_{j+1}
@@ -124,11 +141,17 @@ __device__ __forceinline__ void row_store(const StageArgs<T>& a, long idx, T d, 
             a.B[idx] = p.b0 + w * p.g0;
             a.B[nn + idx] = p.b1 + w * p.g1;
         }
-    } else if constexpr (OP == OP_A2) {
+    } else if constexpr (is_a2(OP)) {
         a.ROUT[idx] = T(0.5) * (p.x + p.u) + hh * d;                   // R of l_j (x = l_{j+1}, u = l*)
+        if (a.UOUT) a.UOUT[idx] = p.u;                                 // l*_j, kept for full Newton
         if (a.B) {                                                     // (h/2)(l* G_j + l_{j+1} G*_j)
-            a.B[idx] = p.b0 + a.bw * (p.u * p.g0 + p.x * p.h0);
-            a.B[nn + idx] = p.b1 + a.bw * (p.u * p.g1 + p.x * p.h1);
+            T b0 = p.u * p.g0 + p.x * p.h0, b1 = p.u * p.g1 + p.x * p.h1;
+            if constexpr (OP == OP_A2F) {                              // + lam*_j grad m~_j + lam_{j+1} grad m~*_j
+                b0 += p.l * p.t0 + p.l2 * p.s0;
+                b1 += p.l * p.t1 + p.l2 * p.s1;
+            }
+            a.B[idx] = p.b0 + a.bw * b0;
+            a.B[nn + idx] = p.b1 + a.bw * b1;
         }
     } else if constexpr (OP == OP_I1) {
         a.ROUT[idx] = p.u - h * (p.v * d + p.g0 * p.h0 + p.g1 * p.h1); // R of m~*
@@ -171,6 +194,12 @@ __device__ __forceinline__ cpx<T> col_load2(const StageArgs<T>& a, long idx, Cp<
         }
     }
     if constexpr (OP != OP_GRAD) ld2(a.V1, idx, p0.v, p1.v);
+    if constexpr (is_full(OP)) {   // flux v lam~ + v~ lam (component 1 here)
+        T l0, l1, w0, w1;
+        ld2(a.LAM, idx, l0, l1);
+        ld2(a.VT, idx, w0, w1);
+        return cpx<T>{p0.v * p0.u + w0 * l0, p1.v * p1.u + w1 * l1};
+    }
     return is_adj(OP) ? cpx<T>{p0.v * p0.u, p1.v * p1.u} : cpx<T>{p0.u, p1.u};
 }
 
@@ -179,7 +208,7 @@ __device__ __forceinline__ void col_store2(const StageArgs<T>& a, long idx, T d0
                                            const Cp<T>& p1) {
     const T h = a.h;
     const T hh = T(0.5) * a.h;
-    if constexpr (OP == OP_S1 || OP == OP_S2 || OP == OP_GRAD) {   // d = d1 m: component 0 of grad m
+    if constexpr (OP == OP_S1 || OP == OP_S2 || OP == OP_GRAD || is_inc(OP)) {   // d = d1 u: component 0 of grad u
         if (a.GOUT) st2(a.GOUT, idx, d0, d1);
         if (a.GOUTF) st2(a.GOUTF, idx, (float)d0, (float)d1);
     }
@@ -187,9 +216,9 @@ __device__ __forceinline__ void col_store2(const StageArgs<T>& a, long idx, T d0
         st2(a.COUT, idx, -h * p0.v * d0, -h * p1.v * d1);
     } else if constexpr (OP == OP_S2 || OP == OP_I2) {
         st2(a.COUT, idx, -hh * p0.v * d0, -hh * p1.v * d1);
-    } else if constexpr (OP == OP_A1) {
+    } else if constexpr (is_a1(OP)) {
         st2(a.COUT, idx, h * d0, h * d1);
-    } else if constexpr (OP == OP_A2) {
+    } else if constexpr (is_a2(OP)) {
         st2(a.COUT, idx, hh * d0, hh * d1);
     }
 }

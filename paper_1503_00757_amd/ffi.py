@@ -16,6 +16,7 @@ REG_H1, REG_H2 = 1, 2
 REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE = 0, 1, 2
 REG_FP64, REG_FP32_TRANSPORT = 0, 1
 REG_ADJ_DISCRETE, REG_ADJ_PAPER = 0, 1
+REG_HESS_GN, REG_HESS_FULL = 0, 1
 
 STATUS_NAMES = {0: "REG_OK", -1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVICE", -4: "REG_ENOTCONV",
                 -5: "REG_ENONFINITE", -6: "REG_ESTATE"}
@@ -24,7 +25,8 @@ STATUS_NAMES = {0: "REG_OK", -1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVIC
 class RegParams(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("nt", C.c_int32), ("norm", C.c_int32),
                 ("constraint", C.c_int32), ("precision", C.c_int32), ("adjoint", C.c_int32),
-                ("lowrank_capacity", C.c_int32), ("beta_v", C.c_double), ("beta_w", C.c_double)]
+                ("hessian", C.c_int32), ("lowrank_capacity", C.c_int32), ("reserved", C.c_int32),
+                ("beta_v", C.c_double), ("beta_w", C.c_double)]
 
 
 class RegSolveOpts(C.Structure):

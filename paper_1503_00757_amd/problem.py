@@ -13,15 +13,18 @@ _PREC = {"fp64": ffi.REG_FP64, "fp32": ffi.REG_FP32_TRANSPORT}
 _ADJ = {"dto": ffi.REG_ADJ_DISCRETE, "paper": ffi.REG_ADJ_PAPER}
 
 
+_HESS = {"gn": ffi.REG_HESS_GN, "full": ffi.REG_HESS_FULL}
+
+
 def make_params(n1, n2, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0, precision="fp32",
-                adjoint="dto", lowrank_capacity=0) -> ffi.RegParams:
+                adjoint="dto", lowrank_capacity=0, hessian="gn") -> ffi.RegParams:
     return ffi.RegParams(n1, n2, nt, _NORMS[norm], _CONS[constraint], _PREC[precision], _ADJ[adjoint],
-                         int(lowrank_capacity), float(beta_v), float(beta_w))
+                         _HESS[hessian], int(lowrank_capacity), 0, float(beta_v), float(beta_w))
 
 
 class Problem:
     def __init__(self, mT, mR, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0,
-                 precision="fp32", adjoint="dto", stream=None, lowrank_capacity=0):
+                 precision="fp32", adjoint="dto", stream=None, lowrank_capacity=0, hessian="gn"):
         import torch
         self.torch = torch
         if mT.dtype != torch.float64 or mR.dtype != torch.float64 or not mT.is_cuda or not mR.is_cuda:
@@ -30,7 +33,7 @@ class Problem:
         self.n1, self.n2, self.nt = n1, n2, nt
         self.device = mT.device
         self.params = make_params(n1, n2, nt, norm, constraint, beta_v, beta_w, precision, adjoint,
-                                  lowrank_capacity)
+                                  lowrank_capacity, hessian)
         self.ws_bytes = ffi.reg_workspace_bytes(self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()

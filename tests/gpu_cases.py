@@ -99,14 +99,14 @@ def oracle_results(case: Case):
                 sens_H=rel(H_n, H), sens_g=float(np.linalg.norm(g_n - lin.g)))
 
 
-def gpu_problem(case: Case, lowrank_capacity=0):
+def gpu_problem(case: Case, lowrank_capacity=0, hessian="gn"):
     import torch
     from paper_1503_00757_amd import Problem
     mT, mR, *_ = inputs(case)
     dev = torch.device("cuda:0")
     return Problem(torch.tensor(mT, device=dev), torch.tensor(mR, device=dev), case.nt, case.norm,
                    case.constraint, case.beta_v, case.beta_w, case.precision, case.adjoint,
-                   lowrank_capacity=lowrank_capacity)
+                   lowrank_capacity=lowrank_capacity, hessian=hessian)
 
 
 def dev(x):

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(R.RegParams) == 8 * 4 + 2 * 8
+    assert ctypes.sizeof(R.RegParams) == 10 * 4 + 2 * 8
     assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 3 * 8
 
@@ -102,3 +102,22 @@ def test_create_rejects_null_and_small_workspace_without_device_work():
     with pytest.raises(R.RegError) as e:
         R.reg_create(p, 256, 256, 256, need - 1, 0)   # never dereferenced: size is checked first
     assert e.value.status == -2
+
+
+def test_hessian_mode_checked_and_full_newton_workspace():
+    p = make_params(64, 64, 4)
+    p.hessian = 2
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(p)
+    p = make_params(64, 64, 4)
+    p.reserved = 1
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(p)
+    with pytest.raises(R.RegError) as e:   # full Newton is the derivative of the exact discrete adjoint
+        R.reg_workspace_bytes(make_params(64, 64, 4, adjoint="paper", hessian="full"))
+    assert e.value.status == -1
+    # full Newton stores lam_{j+1}, lam*_j (2 n_t fields) and grad m~_j, grad m~*_j (2 n_t vector fields)
+    for prec, ts in (("fp32", 4), ("fp64", 8)):
+        gn = R.reg_workspace_bytes(make_params(64, 64, 4, precision=prec))
+        full = R.reg_workspace_bytes(make_params(64, 64, 4, precision=prec, hessian="full"))
+        assert full - gn == 2 * 4 * 64 * 64 * ts + 2 * 4 * 2 * 64 * 64 * ts
