@@ -179,6 +179,39 @@ def bench_solve(P, recycle=0):
             "n_matvec": st["n_matvec"], "n_pde": st["n_pde"], "g_rel": st["g_rel"], "status": st["status"]}
 
 
+def bench_hessians(config=2):
+    """Alg. 1 on one workload with the Gauss-Newton Hessian of the paper and with the full-Newton
+    Hessian (REG_HESS_FULL), to ||g||/||g(0)|| <= 1e-2 and 1e-4 (one untimed solve first each), for
+    the reference m_T(v*) and for that reference plus an intensity change no velocity explains."""
+    import torch
+    import synthdata as sd
+    from paper_1503_00757_amd import Problem
+    w = sd.make_workload(config)
+    dev = torch.device("cuda:0")
+    mT = torch.tensor(w.mT, device=dev)
+    P0 = Problem(mT, mT.clone(), w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, "fp32")
+    mR = P0.state_forward(torch.tensor(w.vstar, device=dev))
+    P0.close()
+    out = {}
+    refs = {"exact_reference": mR,
+            "changed_reference": mR + torch.tensor(sd.reference_change(w.n1, w.n2), device=dev)}
+    for name, ref in refs.items():
+        for hess in ("gn", "full"):
+            P = Problem(mT, ref, w.nt, w.norm, w.constraint, w.beta_v, w.beta_w, "fp32", hessian=hess)
+            for gtol in (1e-2, 1e-4):
+                P.solve(max_newton=50, max_pcg=100, gtol_rel=gtol, raise_on_error=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = P.solve(max_newton=50, max_pcg=100, gtol_rel=gtol, raise_on_error=False)
+                torch.cuda.synchronize()
+                out.setdefault(name, {})[f"{hess}_to_{gtol:g}"] = {
+                    "seconds": round(time.perf_counter() - t0, 4), "newton_iters": st["newton_iters"],
+                    "pcg_iters": st["pcg_iters"], "n_pde": st["n_pde"], "g_rel": st["g_rel"],
+                    "status": st["status"]}
+            P.close()
+    return out
+
+
 def bench_batch(npairs=96):
     """Config 4: 96 pairs (32 each at 128^2, 256^2, 512^2; beta_v log-uniform in [1e-4, 1e-2]; n_t in
     {8, 16, 32}; H1 + divergence-free), all solved to ||g||/||g(0)|| <= 1e-2 by reg_batch_solve.
@@ -430,6 +463,8 @@ def main():
         print("[bench] solve", file=sys.stderr, flush=True)
         extras["solve_to_grel_1e-2_plain"] = bench_solve(P)
         extras["solve_to_grel_1e-2_recycle4"] = bench_solve(P, recycle=4)
+        print("[bench] Gauss-Newton vs full-Newton solves", file=sys.stderr, flush=True)
+        extras["gauss_newton_vs_full_newton"] = bench_hessians(cfg)
     P.close()
     if not args.no_extras and cfg == 2:
         print("[bench] 1024^2 nt=32", file=sys.stderr, flush=True)

@@ -251,6 +251,12 @@ def random_field(n1: int, n2: int, kmax: int, seed: int) -> np.ndarray:
     return t / np.abs(t).max()
 
 
+def reference_change(n1: int, n2: int, amp: float = 0.05, kmax: int = 32, seed: int = BASE_SEED + 91) -> np.ndarray:
+    """A seeded band-limited intensity change (max |.| = amp) added to a reference image so that no
+    velocity explains it (the residual stays finite at the minimiser, as with real image pairs)."""
+    return amp * random_field(n1, n2, min(kmax, min(n1, n2) // 2 - 1), seed)
+
+
 def random_vec(n1: int, n2: int, kmax: int, seed: int, divfree: bool = False) -> np.ndarray:
     """A seeded band-limited vector field with unit L2 norm (for operator tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))
