@@ -198,6 +198,19 @@ reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
 reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const reg_solve_opts* opts,
                            double* const* v_out, reg_solve_stats* stats_host);
 
+/* Deformation diagnostics of a velocity (appendix "Illustration of Deformation Map"): the
+ * displacement u with u(0) = 0 transported by v with source v (eq. (displacement); the Eulerian map
+ * is y = x - u_1) and the deformation gradient F with F(0) = I transported by v with source
+ * (grad v) F (eq. (def-grad)), integrated with the state equation's Heun steps (n_t) in FP64 for the
+ * Nyquist-projected v.  v: device vector field.  workspace: device memory of at least
+ * reg_deformation_workspace_bytes (37 FP64 scalar fields), 256-byte aligned, owned by the caller.
+ * Outputs, all nullable: u1 (device vector field), F1 (device [2][2][n1][n2], F1[i][k] = F_ik),
+ * detF1 (device scalar field det F_1), stats_host (host double[3]: min, max and mean of det F_1;
+ * then the stream is synchronised).  Does not change the linearisation point. */
+reg_status reg_deformation_workspace_bytes(const reg_params* params, size_t* bytes);
+reg_status reg_deformation(reg_problem* h, const double* v, void* workspace, size_t workspace_bytes,
+                           double* u1, double* F1, double* detF1, double* stats_host);
+
 /* Measurement hook: run `reps` (1..1000, reps * nt <= 512) Hessian matvecs at the current
  * linearisation point and time every launch of one of the four RK2-stage launches of a time step:
  * ms_per_launch_host = mean dispatch interval, from start / end events that the dispatch itself

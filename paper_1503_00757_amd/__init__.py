@@ -11,7 +11,8 @@ from .ffi import (  # noqa: F401
     REG_ADJ_DISCRETE, REG_ADJ_PAPER,
     reg_workspace_bytes, reg_create, reg_destroy, reg_set_stream, reg_state_forward, reg_objective,
     reg_gradient, reg_hessian_matvec, reg_precond_apply, reg_pcg, reg_solve, reg_time_pass,
-    reg_autotune, reg_set_pass_variants, reg_batch_solve, reg_set_images,
+    reg_autotune, reg_set_pass_variants, reg_batch_solve, reg_set_images, reg_deformation,
+    reg_deformation_workspace_bytes,
     reg_fno_param_count, reg_fno_workspace_bytes, reg_fno_create, reg_fno_destroy, reg_fno_features, reg_fno_target,
     reg_fno_gather, reg_fno_forward, reg_fno_backward, reg_fno_adam, reg_fno_train_step, reg_fno_predict,
     REG_FNO_PARAMS,

@@ -137,6 +137,26 @@ hipError_t launch_lr_combine(long n, const double* base, double* out, const doub
 // in place: F_j <- sum_{i < rin} m[i][j] F_i for j < rout (rin, rout <= LR_MIX_MAX)
 hipError_t launch_lr_mix(long n, double* F, long stride, int rin, int rout, const LrMix& m, hipStream_t s);
 
+// ---- deformation diagnostics (eqs. (displacement), (def-grad)) -----------------------------------
+// Components c = 0..5: u_1, u_2, F_11, F_12, F_21, F_22.
+struct DefPtrs {
+    const double* a[4];   // F_11, F_12, F_21, F_22 at the stage (first part)
+    const double* b[4];   // second part of an R + C pair (nullable)
+    double* out[6];       // R parts that receive w * source
+};
+struct DefPairs {
+    const double* r[6];
+    const double* c[6];
+};
+// out_c += w * S_c with S_{u_i} = v_i, S_{F_ik} = sum_l dv[i][l] F_lk; v: vector field, dv: 4 fields
+// (dv[i][l] = d_l v_i at (2 i + l) * nn)
+hipError_t launch_deform_source(long nn, double w, const double* v, const double* dv, const DefPtrs& p,
+                                hipStream_t s);
+// q_c = r_c + c_c; u1 = (q_0, q_1) and F1 = (q_2..q_5) (both nullable); det = q_2 q_5 - q_3 q_4
+hipError_t launch_deform_final(long nn, const DefPairs& p, double* u1, double* F1, double* det, hipStream_t s);
+// out3 = {min, max, sum} of x (deterministic); partial: 3 * RED_BLOCKS doubles
+hipError_t launch_minmaxsum(const double* x, long n, double* partial, double* out3, hipStream_t s);
+
 // ---- PCG with device-side scalars (Alg. 2) ----------------------------------------------------
 // Slots of the FP64 scalar array shared by the PCG kernels.
 enum PcgSlot {

@@ -1017,6 +1017,76 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
     return REG_OK;
 }
 
+// ---- deformation diagnostics (eqs. (displacement), (def-grad)) -----------------------------------
+// FP64 fields of the caller's diagnostics workspace: v (2), dv (4), then per component c < 6 the pair
+// R, C, the stage pair R*, C* and the stage input U; one more for det F.
+constexpr int DEF_FIELDS = 2 + 4 + 6 * 5 + 1;
+
+reg_status deformation_run(reg_problem* P, const double* v_in, double* ws, double* u1, double* F1, double* detF,
+                           double* stats) {
+    const long nn = P->nn;
+    auto f = [&](int i) { return ws + (size_t)i * nn; };
+    double* v = f(0);
+    double* dv = f(2);
+    auto R = [&](int c) { return f(6 + 5 * c); };
+    auto C = [&](int c) { return f(7 + 5 * c); };
+    auto Rs = [&](int c) { return f(8 + 5 * c); };
+    auto Cs = [&](int c) { return f(9 + 5 * c); };
+    auto U = [&](int c) { return f(10 + 5 * c); };
+    double* det = f(DEF_FIELDS - 1);
+    CKS(project<double>(P, v_in, v, (double*)nullptr));
+    for (int i = 0; i < 2; ++i) {   // dv[i][l] = d_l v_i
+        StageArgs<double> g = base_args<double>(P);
+        g.A = v + (size_t)i * nn;
+        g.GOUT = dv + (size_t)2 * i * nn;
+        CKS(stage<double>(P, OP_GRAD, g));
+    }
+    for (int c = 0; c < 6; ++c) {   // u(0) = 0, F(0) = I
+        CK(launch_fill(nn, (c == 2 || c == 5) ? 1.0 : 0.0, R(c), P->stream));
+        CK(launch_fill(nn, 0.0, C(c), P->stream));
+    }
+    const double h = 1.0 / P->nt;
+    for (int j = 0; j < P->nt; ++j) {
+        for (int c = 0; c < 6; ++c) {
+            StageArgs<double> s1 = base_args<double>(P);
+            s1.A = R(c); s1.Bf = C(c);
+            s1.V1 = v; s1.V2 = v + nn;
+            s1.ROUT = Rs(c); s1.UOUT = U(c); s1.COUT = Cs(c);
+            CKS(stage<double>(P, OP_S1, s1));
+        }
+        DefPtrs p1{};
+        for (int c = 0; c < 4; ++c) p1.a[c] = U(2 + c);
+        for (int c = 0; c < 6; ++c) p1.out[c] = Rs(c);
+        CK(launch_deform_source(nn, h, v, dv, p1, P->stream));        // stage 1: + h S(q_j)
+        for (int c = 0; c < 6; ++c) {
+            StageArgs<double> s2 = base_args<double>(P);
+            s2.A = Rs(c); s2.Bf = Cs(c); s2.X = U(c);
+            s2.V1 = v; s2.V2 = v + nn;
+            s2.ROUT = R(c); s2.COUT = C(c);
+            CKS(stage<double>(P, OP_S2, s2));
+        }
+        DefPtrs p2{};
+        for (int c = 0; c < 4; ++c) { p2.a[c] = Rs(2 + c); p2.b[c] = Cs(2 + c); }
+        for (int c = 0; c < 6; ++c) p2.out[c] = R(c);
+        CK(launch_deform_source(nn, 0.5 * h, v, dv, p2, P->stream));  // stage 2: + (h/2) S(q*)
+    }
+    DefPairs fin{};
+    for (int c = 0; c < 6; ++c) { fin.r[c] = R(c); fin.c[c] = C(c); }
+    CK(launch_deform_final(nn, fin, u1, F1, detF ? detF : det, P->stream));
+    if (stats) {
+        double h3[3];
+        CK(launch_minmaxsum(detF ? detF : det, nn, P->partial(), P->scal(), P->stream));
+        CK(hipMemcpyAsync(h3, P->scal(), sizeof h3, hipMemcpyDeviceToHost, P->stream));
+        CK(hipStreamSynchronize(P->stream));
+        stats[0] = h3[0];
+        stats[1] = h3[1];
+        stats[2] = h3[2] / (double)nn;
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(stats[k])) return fail(REG_ENONFINITE, "det F is not finite");
+    }
+    return REG_OK;
+}
+
 // ---- measurement hook and autotuner ------------------------------------------------------------
 // The four stage launches of one matvec time step, set up on live buffers at a middle time step:
 // which = 0 GN adjoint stage 2, 1 incremental state stage 2, 2 GN adjoint stage 1, 3 incremental
@@ -1448,6 +1518,22 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
     for (int i = 0; i < count; ++i)
         if (status[i] == REG_ENOTCONV) return fail(REG_ENOTCONV, "pair %d: %s", i, errs[i].c_str());
     return REG_OK;
+}
+
+reg_status reg_deformation_workspace_bytes(const reg_params* params, size_t* bytes) {
+    CKS(check_params(params));
+    if (!bytes) return fail(REG_EINVAL, "bytes is NULL");
+    *bytes = (size_t)DEF_FIELDS * params->n1 * params->n2 * sizeof(double);
+    return REG_OK;
+}
+
+reg_status reg_deformation(reg_problem* h, const double* v, void* workspace, size_t workspace_bytes, double* u1,
+                           double* F1, double* detF1, double* stats_host) {
+    if (!h || !v || !workspace) return fail(REG_EINVAL, "NULL argument");
+    const size_t need = (size_t)DEF_FIELDS * h->nn * sizeof(double);
+    if (workspace_bytes < need) return fail(REG_ENOMEM, "diagnostics workspace of %zu bytes, %zu needed", workspace_bytes, need);
+    if ((uintptr_t)workspace % 256 != 0) return fail(REG_EINVAL, "workspace must be 256-byte aligned");
+    return deformation_run(h, v, (double*)workspace, u1, F1, detF1, stats_host);
 }
 
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes, double* exec_ms) {

@@ -98,11 +98,14 @@ def lib():
         L.reg_batch_solve.argtypes = [i32, C.POINTER(vp), C.POINTER(RegSolveOpts), C.POINTER(vp),
                                       C.POINTER(RegSolveStats)]
         L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
+        L.reg_deformation_workspace_bytes.argtypes = [C.POINTER(RegParams), C.POINTER(sz)]
+        L.reg_deformation.argtypes = [vp, vp, vp, sz, vp, vp, vp, dp]
         L.reg_last_error.argtypes = []
         L.reg_last_error.restype = C.c_char_p
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
-                     "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve"):
+                     "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve",
+                     "reg_deformation_workspace_bytes", "reg_deformation"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -207,6 +210,19 @@ def reg_batch_solve(handles, opts, v_outs, raise_on_error: bool = True):
     if raise_on_error:
         _check(status)
     return status, [S[i] for i in range(n)]
+
+
+def reg_deformation_workspace_bytes(params: RegParams) -> int:
+    out = C.c_size_t(0)
+    _check(lib().reg_deformation_workspace_bytes(C.byref(params), C.byref(out)))
+    return out.value
+
+
+def reg_deformation(h, v: int, workspace: int, workspace_bytes: int, u1, F1, detF1, want_stats=True):
+    """Returns (min, max, mean) of det F_1 (or None)."""
+    st = (C.c_double * 3)()
+    _check(lib().reg_deformation(h, v, workspace, workspace_bytes, u1, F1, detF1, st if want_stats else None))
+    return tuple(st) if want_stats else None
 
 
 def reg_set_images(h, m_T: int, m_R: int):

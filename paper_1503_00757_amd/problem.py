@@ -134,6 +134,20 @@ class Problem:
             d["ritz"] = list(ritz)
         return v, d
 
+    def deformation(self, v):
+        """Deformation diagnostics of v (reg_deformation): (u_1, F_1, det F_1, (min, max, mean) of det F_1);
+        the diagnostics workspace is allocated through torch on first use and kept."""
+        v = self._c(v)
+        nb = ffi.reg_deformation_workspace_bytes(self.params)
+        if getattr(self, "_dws", None) is None:
+            self._dws = self.torch.empty(nb + 256, dtype=self.torch.uint8, device=self.device)
+        ptr = (self._dws.data_ptr() + 255) // 256 * 256
+        u1 = self.vec()
+        F1 = self.torch.empty((2, 2, self.n1, self.n2), dtype=self.torch.float64, device=self.device)
+        det = self.torch.empty((self.n1, self.n2), dtype=self.torch.float64, device=self.device)
+        stats = ffi.reg_deformation(self.h, v.data_ptr(), ptr, nb, u1.data_ptr(), F1.data_ptr(), det.data_ptr())
+        return u1, F1, det, stats
+
     def time_pass(self, which, reps=100):
         return ffi.reg_time_pass(self.h, which, reps)
 

@@ -121,3 +121,12 @@ def test_hessian_mode_checked_and_full_newton_workspace():
         gn = R.reg_workspace_bytes(make_params(64, 64, 4, precision=prec))
         full = R.reg_workspace_bytes(make_params(64, 64, 4, precision=prec, hessian="full"))
         assert full - gn == 2 * 4 * 64 * 64 * ts + 2 * 4 * 2 * 64 * 64 * ts
+
+
+def test_deformation_workspace_and_null_checks():
+    assert R.reg_deformation_workspace_bytes(make_params(64, 32, 4)) == 37 * 64 * 32 * 8
+    with pytest.raises(R.RegError):
+        R.reg_deformation_workspace_bytes(make_params(64, 30, 4))
+    with pytest.raises(R.RegError) as e:
+        R.reg_deformation(None, 256, 256, 1 << 20, None, None, None)
+    assert e.value.status == -1
