@@ -164,10 +164,10 @@ def roofline(P, reps=None, workload="c2"):
 LOWRANK_CAPACITY = 16   # directions of the preconditioner correction the bench problems can hold
 
 
-def bench_solve(P, recycle=0):
+def bench_solve(P, recycle=0, diagnostics=False):
     """Alg. 1 to ||g||/||g(0)|| <= 1e-2 from v = 0; recycle > 0 keeps that many PCG directions of each
     Newton step in the low-rank correction of the preconditioner (one untimed run first: graph
-    capture)."""
+    capture).  diagnostics: also det F_1 of the solution (reg_deformation) and its time."""
     import torch
     P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, recycle=recycle)
     torch.cuda.synchronize()
@@ -175,8 +175,16 @@ def bench_solve(P, recycle=0):
     v, st = P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, recycle=recycle)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"seconds": round(dt, 4), "newton_iters": st["newton_iters"], "pcg_iters": st["pcg_iters"],
-            "n_matvec": st["n_matvec"], "n_pde": st["n_pde"], "g_rel": st["g_rel"], "status": st["status"]}
+    out = {"seconds": round(dt, 4), "newton_iters": st["newton_iters"], "pcg_iters": st["pcg_iters"],
+           "n_matvec": st["n_matvec"], "n_pde": st["n_pde"], "g_rel": st["g_rel"], "status": st["status"]}
+    if diagnostics:
+        P.deformation(v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, (mn, mx, mean) = P.deformation(v)
+        out["det_F1"] = {"min": round(mn, 5), "max": round(mx, 5), "mean": round(mean, 6),
+                         "diagnostics_ms": round(1e3 * (time.perf_counter() - t0), 3)}
+    return out
 
 
 def bench_hessians(config=2):
@@ -461,7 +469,7 @@ def main():
     if not args.no_extras:
         extras["matvec_only_per_s"] = round(1.0 / bench_matvec(P, vt, 50), 2)
         print("[bench] solve", file=sys.stderr, flush=True)
-        extras["solve_to_grel_1e-2_plain"] = bench_solve(P)
+        extras["solve_to_grel_1e-2_plain"] = bench_solve(P, diagnostics=True)
         extras["solve_to_grel_1e-2_recycle4"] = bench_solve(P, recycle=4)
         print("[bench] Gauss-Newton vs full-Newton solves", file=sys.stderr, flush=True)
         extras["gauss_newton_vs_full_newton"] = bench_hessians(cfg)
