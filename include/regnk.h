@@ -44,8 +44,9 @@ typedef enum {
     REG_ESTATE = -6       /* Hessian matvec requested before any linearisation point was set */
 } reg_status;
 
-/* Seminorm on v (Sec. 2, eq. (reg-v)); A = -Lap (H1) or Lap^2 (H2), eq. (var-reg-v). */
-enum { REG_H1 = 1, REG_H2 = 2 };
+/* Seminorm on v (Sec. 2, eq. (reg-v)); A = -Lap (H1) or Lap^2 (H2), eq. (var-reg-v); REG_H3 is the
+ * H3 seminorm the paper names as an option (A = -Lap^3, a triharmonic reduced gradient). */
+enum { REG_H1 = 1, REG_H2 = 2, REG_H3 = 3 };
 /* Constraint on div v (Sec. 2): gamma = 0; gamma = 1 with w = 0 (incompressible); gamma = 1 with a
  * mass source w penalised by its H1 norm (eq. (reg-w)), beta_w > 0. */
 enum { REG_UNCONSTRAINED = 0, REG_DIVFREE = 1, REG_MASS_SOURCE = 2 };
@@ -70,7 +71,7 @@ enum { REG_HESS_GN = 0, REG_HESS_FULL = 1 };
 typedef struct {
     int32_t n1, n2;       /* grid (powers of two, 8..2048) */
     int32_t nt;           /* RK2 time steps on [0, 1] */
-    int32_t norm;         /* REG_H1 | REG_H2 */
+    int32_t norm;         /* REG_H1 | REG_H2 | REG_H3 */
     int32_t constraint;   /* REG_UNCONSTRAINED | REG_DIVFREE | REG_MASS_SOURCE */
     int32_t precision;    /* REG_FP64 | REG_FP32_TRANSPORT */
     int32_t adjoint;      /* REG_ADJ_DISCRETE | REG_ADJ_PAPER */
@@ -180,6 +181,7 @@ typedef struct {
     double g0_norm;           /* ||g(0)|| at v = 0 (also for a warm start) */
     double g_rel;             /* final ||g|| / ||g(0)|| */
     double J;                 /* final objective */
+    double cfl;               /* CFL number of the final velocity (see reg_cfl) */
 } reg_solve_stats;
 
 /* Alg. 1: globalised inexact reduced-space Gauss-Newton-Krylov solve from v0 (or 0): PCG Newton
@@ -197,6 +199,14 @@ reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
  * (REG_ENOTCONV after all others); stats carry each pair's own status. */
 reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const reg_solve_opts* opts,
                            double* const* v_out, reg_solve_stats* stats_host);
+
+/* CFL number of a velocity for this problem's n_t (Sec. 4: the explicit RK2 steps are only
+ * conditionally stable, and the paper monitors the CFL condition to adapt n_t):
+ * C = h_t (max|v_1| n1/2 + max|v_2| n2/2), the largest |h_t k . v| over the resolved modes, of the
+ * Nyquist-projected v.  A caller that wants the paper's adaptive n_t re-creates the problem with a
+ * larger n_t when C exceeds its limit.  v: device vector field; cfl_host: host double.
+ * Synchronises the stream. */
+reg_status reg_cfl(reg_problem* h, const double* v, double* cfl_host);
 
 /* Deformation diagnostics of a velocity (appendix "Illustration of Deformation Map"): the
  * displacement u with u(0) = 0 transported by v with source v (eq. (displacement); the Eulerian map

@@ -71,6 +71,7 @@ class SolveStats:
     J: float = 0.0
     fallback_used: int = 0
     lowrank_dim: int = 0                  # directions in the correction at the end of the solve
+    cfl: float = 0.0                      # CFL number of the final velocity (``cfl_number``)
     lowrank: tuple | None = None          # (Ritz values theta, Ritz vectors z) from precond_U
     history: list = field(default_factory=list)
 
@@ -114,6 +115,13 @@ def pcg(matvec, prec, winner, norm, rhs, eta, max_pcg, fixed_iters=0, record=Non
         rz = rz_new
         s = z + mu * s
     return x, l, (rn / r0 if r0 > 0 else 0.0)
+
+
+def cfl_number(g: Grid, p: Params, v):
+    """C(v) = h_t (max|v_1| n1/2 + max|v_2| n2/2): the largest |h_t k . v| over the resolved modes, the
+    quantity the explicit RK2 step has to keep below about one (Sec. 4 monitors the CFL condition)."""
+    v = spectral.nyquist_project(g, v)
+    return (np.abs(v[0]).max() * (g.n1 / 2) + np.abs(v[1]).max() * (g.n2 / 2)) / p.nt
 
 
 def admissible(g: Grid, p: Params, u):
@@ -269,4 +277,5 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         k += 1
     st.newton_iters = k
     st.lowrank_dim = len(Zs)
+    st.cfl = cfl_number(g, p, lin.v)
     return lin.v, st

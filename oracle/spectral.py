@@ -20,7 +20,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.fft as sfft
 
-NORMS = ("H1", "H2")
+NORMS = ("H1", "H2", "H3")
 CONSTRAINTS = ("none", "divfree", "mass_source")
 ADJOINT_MODES = ("dto", "paper")
 
@@ -29,7 +29,8 @@ ADJOINT_MODES = ("dto", "paper")
 class Params:
     """Problem parameters.
 
-    norm        'H1' or 'H2' seminorm on v (eq. (reg-v))
+    norm        'H1' or 'H2' seminorm on v (eq. (reg-v)); 'H3' (triharmonic A) is the variant the paper
+                names with the Stokes model
     constraint  'none'        gamma = 0 (no constraint on div v)
                 'divfree'     gamma = 1, w = 0 (incompressible)
                 'mass_source' gamma = 1, beta_w > 0 (near-incompressible, eq. (reg-w))
@@ -125,8 +126,9 @@ def nyquist_project(g: Grid, v):
 # ---- Fourier symbols (all diagonal in k; K mixes the two vector components) -----------------
 
 def A_symbol(g: Grid, p: Params):
-    """First variation of the v-seminorm, eq. (var-reg-v): A = -Lap (H1) -> |k|^2, A = Lap^2 (H2) -> |k|^4."""
-    return g.ksq if p.norm == "H1" else g.ksq ** 2
+    """First variation of the v-seminorm, eq. (var-reg-v): A = -Lap (H1) -> |k|^2, A = Lap^2 (H2) -> |k|^4;
+    the H3 seminorm (triharmonic reduced gradient, App. A) gives A = -Lap^3 -> |k|^6."""
+    return {"H1": g.ksq, "H2": g.ksq ** 2, "H3": g.ksq ** 3}[p.norm]
 
 
 def M_symbol(g: Grid, p: Params):

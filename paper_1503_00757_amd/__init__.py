@@ -12,11 +12,11 @@ from .ffi import (  # noqa: F401
     reg_workspace_bytes, reg_create, reg_destroy, reg_set_stream, reg_state_forward, reg_objective,
     reg_gradient, reg_hessian_matvec, reg_precond_apply, reg_pcg, reg_solve, reg_time_pass,
     reg_autotune, reg_set_pass_variants, reg_batch_solve, reg_set_images, reg_deformation,
-    reg_deformation_workspace_bytes,
+    reg_deformation_workspace_bytes, reg_cfl, REG_H3,
     reg_fno_param_count, reg_fno_workspace_bytes, reg_fno_create, reg_fno_destroy, reg_fno_features, reg_fno_target,
     reg_fno_gather, reg_fno_forward, reg_fno_backward, reg_fno_adam, reg_fno_train_step, reg_fno_predict,
     REG_FNO_PARAMS,
     reg_last_error,
 )
-from .problem import Problem, batch_solve  # noqa: F401
+from .problem import Problem, batch_solve, solve_adaptive_nt  # noqa: F401
 from .warmstart import Network, WarmStart  # noqa: F401

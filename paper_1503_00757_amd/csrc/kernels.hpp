@@ -75,7 +75,7 @@ enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG, SPEC_LR };
 
 struct SpecParams {
     int n1, n2;
-    int norm;                // 1 = H1, 2 = H2
+    int norm;                // 1 = H1, 2 = H2, 3 = H3
     int constraint;          // 0 none, 1 divfree, 2 mass source
     double beta_v, beta_w;
 };

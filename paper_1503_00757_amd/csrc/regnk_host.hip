@@ -75,7 +75,7 @@ reg_status check_params(const reg_params* p) {
     if (!is_pow2_in_range(p->n1) || !is_pow2_in_range(p->n2))
         return fail(REG_EINVAL, "n1=%d n2=%d: grid sizes must be powers of two in [8, 2048]", p->n1, p->n2);
     if (p->nt < 1 || p->nt > 4096) return fail(REG_EINVAL, "nt=%d out of range [1, 4096]", p->nt);
-    if (p->norm != REG_H1 && p->norm != REG_H2) return fail(REG_EINVAL, "norm=%d", p->norm);
+    if (p->norm != REG_H1 && p->norm != REG_H2 && p->norm != REG_H3) return fail(REG_EINVAL, "norm=%d", p->norm);
     if (p->constraint < REG_UNCONSTRAINED || p->constraint > REG_MASS_SOURCE)
         return fail(REG_EINVAL, "constraint=%d", p->constraint);
     if (p->precision != REG_FP64 && p->precision != REG_FP32_TRANSPORT)
@@ -887,6 +887,21 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     return REG_OK;
 }
 
+// ---- CFL number -------------------------------------------------------------------------------
+// C(v) = h_t (max|v_1| n1/2 + max|v_2| n2/2) of a device vector field (taken as given).
+reg_status cfl_t(reg_problem* P, const double* v, double* out) {
+    double r[2][3];
+    for (int c = 0; c < 2; ++c) {
+        CK(launch_minmaxsum(v + (size_t)c * P->nn, P->nn, P->partial(), P->scal() + 3 * c, P->stream));
+    }
+    CK(hipMemcpyAsync(r, P->scal(), sizeof r, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    const double a1 = std::max(-r[0][0], r[0][1]), a2 = std::max(-r[1][0], r[1][1]);
+    *out = (a1 * (P->n1 / 2) + a2 * (P->n2 / 2)) / P->nt;
+    if (!std::isfinite(*out)) return fail(REG_ENONFINITE, "velocity is not finite");
+    return REG_OK;
+}
+
 // ---- Newton (Alg. 1) --------------------------------------------------------------------------
 template <typename T>
 reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_solve_stats* st) {
@@ -1006,6 +1021,7 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
     }
     S.newton_iters = k;
     S.lowrank_dim = lr ? P->lr_count : 0;
+    CKS(cfl_t(P, P->at<double>(P->o.v64), &S.cfl));
     S.g_rel = grel;
     S.J = J;
     S.status = status;
@@ -1518,6 +1534,13 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
     for (int i = 0; i < count; ++i)
         if (status[i] == REG_ENOTCONV) return fail(REG_ENOTCONV, "pair %d: %s", i, errs[i].c_str());
     return REG_OK;
+}
+
+reg_status reg_cfl(reg_problem* h, const double* v, double* cfl_host) {
+    if (!h || !v || !cfl_host) return fail(REG_EINVAL, "NULL argument");
+    double* vp = h->at<double>(h->o.vtrial);
+    CKS(project<double>(h, v, vp, (double*)nullptr));
+    return cfl_t(h, vp, cfl_host);
 }
 
 reg_status reg_deformation_workspace_bytes(const reg_params* params, size_t* bytes) {

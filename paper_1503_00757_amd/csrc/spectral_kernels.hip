@@ -11,7 +11,7 @@
 //                  transformed along x2; real part -> component 0, imaginary part -> component 1.
 //
 // Symbols (k~ = integer wavenumber with Nyquist -> 0, |k|^2 = k~1^2 + k~2^2):
-//   A^ = |k|^2 (H1) or |k|^4 (H2)                                  eq. (var-reg-v)
+//   A^ = |k|^2 (H1), |k|^4 (H2) or |k|^6 (H3)                      eq. (var-reg-v)
 //   K^ = I - c(k) k k^T/|k|^2, c = 0 (no constraint), 1 (w = 0), 1/M^ (mass source) with
 //   M^ = 1 + beta_v A^ / (beta_w |k|^2 (|k|^2 + 1))                 eq. (project-body-force)
 //   K^{-1} = I + c'(k) k k^T/|k|^2, c' = 1/(M^ - 1)                   (mass source only)
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
         const int e = t + r * Q;
         const double k1 = (double)kwave<N>(e);
         const double kk = k1 * k1 + k2d * k2d;
-        const double A = (p.norm == 1) ? kk : kk * kk;
+        const double A = (p.norm == 1) ? kk : (p.norm == 2 ? kk * kk : kk * kk * kk);
         const double ik = kk > 0.0 ? 1.0 / kk : 0.0;
         const double p11 = k1 * k1 * ik, p12 = k1 * k2d * ik, p22 = k2d * k2d * ik;
         double c = 0.0, ci = 0.0;   // K = I - c P, K^{-1} = I + ci P

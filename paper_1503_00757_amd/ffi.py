@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 REG_OK, REG_EINVAL, REG_ENOMEM, REG_EDEVICE, REG_ENOTCONV, REG_ENONFINITE, REG_ESTATE = 0, -1, -2, -3, -4, -5, -6
-REG_H1, REG_H2 = 1, 2
+REG_H1, REG_H2, REG_H3 = 1, 2, 3
 REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE = 0, 1, 2
 REG_FP64, REG_FP32_TRANSPORT = 0, 1
 REG_ADJ_DISCRETE, REG_ADJ_PAPER = 0, 1
@@ -40,7 +40,7 @@ class RegSolveStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("n_matvec", C.c_int32),
                 ("n_pde", C.c_int32), ("backtracks", C.c_int32), ("status", C.c_int32),
                 ("fallback_used", C.c_int32), ("lowrank_dim", C.c_int32),
-                ("g0_norm", C.c_double), ("g_rel", C.c_double), ("J", C.c_double)]
+                ("g0_norm", C.c_double), ("g_rel", C.c_double), ("J", C.c_double), ("cfl", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -99,13 +99,14 @@ def lib():
                                       C.POINTER(RegSolveStats)]
         L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
         L.reg_deformation_workspace_bytes.argtypes = [C.POINTER(RegParams), C.POINTER(sz)]
+        L.reg_cfl.argtypes = [vp, vp, dp]
         L.reg_deformation.argtypes = [vp, vp, vp, sz, vp, vp, vp, dp]
         L.reg_last_error.argtypes = []
         L.reg_last_error.restype = C.c_char_p
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
                      "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve",
-                     "reg_deformation_workspace_bytes", "reg_deformation"):
+                     "reg_deformation_workspace_bytes", "reg_deformation", "reg_cfl"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -210,6 +211,12 @@ def reg_batch_solve(handles, opts, v_outs, raise_on_error: bool = True):
     if raise_on_error:
         _check(status)
     return status, [S[i] for i in range(n)]
+
+
+def reg_cfl(h, v: int) -> float:
+    c = C.c_double(0)
+    _check(lib().reg_cfl(h, v, C.byref(c)))
+    return c.value
 
 
 def reg_deformation_workspace_bytes(params: RegParams) -> int:

@@ -7,7 +7,7 @@ from __future__ import annotations
 
 from . import ffi
 
-_NORMS = {"H1": ffi.REG_H1, "H2": ffi.REG_H2}
+_NORMS = {"H1": ffi.REG_H1, "H2": ffi.REG_H2, "H3": ffi.REG_H3}
 _CONS = {"none": ffi.REG_UNCONSTRAINED, "divfree": ffi.REG_DIVFREE, "mass_source": ffi.REG_MASS_SOURCE}
 _PREC = {"fp64": ffi.REG_FP64, "fp32": ffi.REG_FP32_TRANSPORT}
 _ADJ = {"dto": ffi.REG_ADJ_DISCRETE, "paper": ffi.REG_ADJ_PAPER}
@@ -134,6 +134,10 @@ class Problem:
             d["ritz"] = list(ritz)
         return v, d
 
+    def cfl(self, v):
+        """CFL number of v for this problem's n_t (reg_cfl)."""
+        return ffi.reg_cfl(self.h, self._c(v).data_ptr())
+
     def deformation(self, v):
         """Deformation diagnostics of v (reg_deformation): (u_1, F_1, det F_1, (min, max, mean) of det F_1);
         the diagnostics workspace is allocated through torch on first use and kept."""
@@ -167,3 +171,24 @@ def batch_solve(problems, raise_on_error=True, v0s=None, **opts):
     o = [p.solve_opts(v0=v0, **opts) for p, v0 in zip(problems, v0s)]
     status, st = ffi.reg_batch_solve([p.h for p in problems], o, [v.data_ptr() for v in outs], raise_on_error)
     return outs, [s.as_dict() for s in st]
+
+
+def solve_adaptive_nt(mT, mR, nt, cfl_max=1.0, max_rounds=4, problem_kw=None, **solve_kw):
+    """Alg. 1 with n_t adapted to the CFL condition (Sec. 4 monitors it): solve, and while the CFL
+    number of the solution exceeds cfl_max, re-create the problem with n_t raised in proportion
+    (times 1.25) and solve again from the previous solution.  Returns (v, stats, [n_t tried])."""
+    import math
+    problem_kw = problem_kw or {}
+    tried = []
+    v = None
+    for _ in range(max_rounds):
+        tried.append(nt)
+        P = Problem(mT, mR, nt, **problem_kw)
+        try:
+            v, st = P.solve(v0=v, **solve_kw)
+        finally:
+            P.close()
+        if st["cfl"] <= cfl_max:
+            break
+        nt = int(math.ceil(nt * st["cfl"] / cfl_max * 1.25))
+    return v, st, tried

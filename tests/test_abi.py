@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(R.RegParams) == 10 * 4 + 2 * 8
     assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4
-    assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 3 * 8
+    assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 4 * 8
 
 
 def test_workspace_bytes_scales_with_grid_and_steps():
@@ -71,7 +71,7 @@ def test_invalid_parameters_are_rejected(kw):
 
 def test_bad_enum_and_lowrank_capacity_rejected():
     p = make_params(64, 64, 4)
-    p.norm = 3
+    p.norm = 4
     with pytest.raises(R.RegError):
         R.reg_workspace_bytes(p)
     for cap in (-1, 65):

@@ -12,7 +12,8 @@ import synthdata as sd
 from oracle import Grid, Params, spectral, transport, reduced
 from dense_reference import Dense
 
-CASES = [("none", "H1"), ("divfree", "H1"), ("mass_source", "H2"), ("mass_source", "H1"), ("none", "H2")]
+CASES = [("none", "H1"), ("divfree", "H1"), ("mass_source", "H2"), ("mass_source", "H1"), ("none", "H2"),
+         ("mass_source", "H3")]
 
 
 def problem(constraint, norm, n=16, nt=3, mode="dto", amp=0.5, seed=1, n2=None):
@@ -146,7 +147,7 @@ def test_q12_dense_brute_force(constraint, norm, n1, n2, nt):
     assert np.abs(lin.traj.m[-1].reshape(-1) - m1).max() < 1e-13
 
 
-@pytest.mark.parametrize("norm", ["H1", "H2"])
+@pytest.mark.parametrize("norm", ["H1", "H2", "H3"])
 def test_z5_mass_source_gradient_is_projected_penalty_gradient(norm):
     g, p, mT, mR, vs = problem("mass_source", norm)
     lin = reduced.gradient(g, p, mT, mR, 0.5 * vs)

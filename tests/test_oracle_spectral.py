@@ -98,10 +98,10 @@ def test_q6_mass_source_eigenvalues_and_limits(norm):
     assert np.abs(spectral.apply_Kinv(g, p, spectral.apply_K(g, p, b)) - b).max() < 1e-10
 
 
-@pytest.mark.parametrize("norm", ["H1", "H2"])
+@pytest.mark.parametrize("norm", ["H1", "H2", "H3"])
 def test_regulariser_matches_seminorm_definition(norm):
-    """<v, A v> equals |v|^2_{H1} = int grad v : grad v, or |v|^2_{H2} = int Lap v . Lap v (eq. (reg-v)),
-    both written with the (pinned) spectral derivative."""
+    """<v, A v> equals |v|^2_{H1} = int grad v : grad v, |v|^2_{H2} = int Lap v . Lap v (eq. (reg-v)), or
+    |v|^2_{H3} = int grad Lap v : grad Lap v, all written with the (pinned) spectral derivative."""
     g = Grid(16, 16)
     p = _params("none", norm)
     v = sd.random_vec(16, 16, 6, 4)
@@ -110,15 +110,18 @@ def test_regulariser_matches_seminorm_definition(norm):
         rhs = sum(g.inner(spectral.d(g, v[c], a), spectral.d(g, v[c], a)) for c in (0, 1) for a in (0, 1))
     else:
         lap = [spectral.d(g, spectral.d(g, v[c], 0), 0) + spectral.d(g, spectral.d(g, v[c], 1), 1) for c in (0, 1)]
-        rhs = sum(g.inner(l, l) for l in lap)
+        if norm == "H2":
+            rhs = sum(g.inner(l, l) for l in lap)
+        else:
+            rhs = sum(g.inner(spectral.d(g, l, a), spectral.d(g, l, a)) for l in lap for a in (0, 1))
     assert abs(lhs - rhs) < 1e-12 * rhs
     X1, X2, u = sinus(16, 16, 3, -2)
     w = np.stack([u, 0 * u])
-    fac = 13.0 if norm == "H1" else 169.0
-    assert np.abs(spectral.apply_A(g, p, w) - fac * w).max() < 1e-11
+    fac = {"H1": 13.0, "H2": 169.0, "H3": 2197.0}[norm]
+    assert np.abs(spectral.apply_A(g, p, w) - fac * w).max() < 1e-12 * fac
 
 
-@pytest.mark.parametrize("norm", ["H1", "H2"])
+@pytest.mark.parametrize("norm", ["H1", "H2", "H3"])
 def test_preconditioner_inverts_beta_A_and_fixes_kernel(norm):
     g = Grid(16, 16)
     p = Params(16, 16, 2, norm, "none", 3e-3, 0.0)
