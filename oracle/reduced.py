@@ -21,6 +21,7 @@ import numpy as np
 
 from .spectral import (Grid, Params, apply_A, apply_K, apply_Kinv, apply_precond, nyquist_project,
                        div, penalty_grad_w)
+from . import stokes
 from .transport import (state_forward, adjoint_backward, body_force, inc_state_forward,
                         inc_adjoint_backward_gn, inc_state_forward_stages, inc_adjoint_backward_full,
                         inc_body_force_full)
@@ -33,7 +34,10 @@ def objective_terms(g: Grid, p: Params, mT, mR, v, traj=None):
         traj = state_forward(g, p, mT, v)
     r = mR - traj.m[-1]
     data = 0.5 * g.inner(r, r)
-    reg_v = 0.5 * p.beta_v * g.inner(v, apply_A(g, p, v))
+    if p.norm == "stokes":
+        reg_v = p.beta_v * stokes.value(g, p.nu, p.eps, v)
+    else:
+        reg_v = 0.5 * p.beta_v * g.inner(v, apply_A(g, p, v))
     reg_w = 0.0
     if p.constraint == "mass_source":
         dv = div(g, v)
@@ -65,7 +69,10 @@ def gradient(g: Grid, p: Params, mT, mR, v) -> Linearization:
     J, terms, traj = objective_terms(g, p, mT, mR, v)
     lam, lam_star = adjoint_backward(g, p, v, mR - traj.m[-1])
     b = body_force(p, traj, lam, lam_star)
-    gr = nyquist_project(g, p.beta_v * apply_A(g, p, v) + apply_K(g, p, b))
+    if p.norm == "stokes":   # K (the Leray projection or I) of beta_v A[v] + b
+        gr = nyquist_project(g, apply_K(g, p, p.beta_v * stokes.first_variation(g, p.nu, p.eps, v) + b))
+    else:
+        gr = nyquist_project(g, p.beta_v * apply_A(g, p, v) + apply_K(g, p, b))
     return Linearization(v, traj, lam, lam_star, b, gr, J, terms)
 
 
@@ -78,6 +85,14 @@ def hessian_matvec(g: Grid, p: Params, lin: Linearization, vt):
     vt = nyquist_project(g, vt)
     mt1 = inc_state_forward(g, p, lin.v, lin.traj, vt)
     bt = inc_adjoint_backward_gn(g, p, lin.v, lin.traj, mt1)
+    return _assemble(g, p, lin, vt, bt)
+
+
+def _assemble(g: Grid, p: Params, lin, vt, bt):
+    """F_Nyq[beta_v B v~ + K b~] (quadratic seminorms: B = A) or F_Nyq K[beta_v B(v)[v~] + b~]
+    (shear-control model)."""
+    if p.norm == "stokes":
+        return nyquist_project(g, apply_K(g, p, p.beta_v * stokes.second_variation(g, p.nu, p.eps, lin.v, vt) + bt))
     return nyquist_project(g, p.beta_v * apply_A(g, p, vt) + apply_K(g, p, bt))
 
 
@@ -93,7 +108,7 @@ def hessian_matvec_full(g: Grid, p: Params, lin: Linearization, vt):
     mt, mts = inc_state_forward_stages(g, p, lin.v, lin.traj, vt)
     lt, lts = inc_adjoint_backward_full(g, p, lin.v, vt, lin.lam, lin.lam_star, mt[-1])
     bt = inc_body_force_full(g, p, lin.traj, lin.lam, lin.lam_star, mt, mts, lt, lts)
-    return nyquist_project(g, p.beta_v * apply_A(g, p, vt) + apply_K(g, p, bt))
+    return _assemble(g, p, lin, vt, bt)
 
 
 def precond(g: Grid, p: Params, r):

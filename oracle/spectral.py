@@ -20,7 +20,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.fft as sfft
 
-NORMS = ("H1", "H2", "H3")
+NORMS = ("H1", "H2", "H3", "stokes")
 CONSTRAINTS = ("none", "divfree", "mass_source")
 ADJOINT_MODES = ("dto", "paper")
 
@@ -30,7 +30,8 @@ class Params:
     """Problem parameters.
 
     norm        'H1' or 'H2' seminorm on v (eq. (reg-v)); 'H3' (triharmonic A) is the variant the paper
-                names with the Stokes model
+                names with the Stokes model; 'stokes' is the nonlinear shear-control model of eq.
+                (shear-control-reg-v) with exponent nu and strain regularisation eps (oracle/stokes.py)
     constraint  'none'        gamma = 0 (no constraint on div v)
                 'divfree'     gamma = 1, w = 0 (incompressible)
                 'mass_source' gamma = 1, beta_w > 0 (near-incompressible, eq. (reg-w))
@@ -45,6 +46,8 @@ class Params:
     beta_v: float = 1e-2
     beta_w: float = 0.0
     adjoint: str = "dto"
+    nu: float = 1.0
+    eps: float = 1e-6
 
     def __post_init__(self):
         if self.norm not in NORMS or self.constraint not in CONSTRAINTS or self.adjoint not in ADJOINT_MODES:
@@ -53,6 +56,8 @@ class Params:
             raise ValueError("bad sizes or weights")
         if (self.constraint == "mass_source") != (self.beta_w > 0):
             raise ValueError("beta_w > 0 exactly when constraint == 'mass_source'")
+        if self.norm == "stokes" and (self.constraint == "mass_source" or not (self.nu > 0 and self.eps > 0)):
+            raise ValueError("the shear-control model takes nu > 0, eps > 0 and no mass source")
 
 
 WORKERS = -1
@@ -127,8 +132,10 @@ def nyquist_project(g: Grid, v):
 
 def A_symbol(g: Grid, p: Params):
     """First variation of the v-seminorm, eq. (var-reg-v): A = -Lap (H1) -> |k|^2, A = Lap^2 (H2) -> |k|^4;
-    the H3 seminorm (triharmonic reduced gradient, App. A) gives A = -Lap^3 -> |k|^6."""
-    return {"H1": g.ksq, "H2": g.ksq ** 2, "H3": g.ksq ** 3}[p.norm]
+    the H3 seminorm (triharmonic reduced gradient, App. A) gives A = -Lap^3 -> |k|^6.  For the
+    shear-control model this is the vector Laplacian of its preconditioner (App. E.2); its own
+    variations are not Fourier multipliers (oracle/stokes.py)."""
+    return {"H1": g.ksq, "H2": g.ksq ** 2, "H3": g.ksq ** 3, "stokes": g.ksq}[p.norm]
 
 
 def M_symbol(g: Grid, p: Params):

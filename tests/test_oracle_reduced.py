@@ -13,13 +13,13 @@ from oracle import Grid, Params, spectral, transport, reduced
 from dense_reference import Dense
 
 CASES = [("none", "H1"), ("divfree", "H1"), ("mass_source", "H2"), ("mass_source", "H1"), ("none", "H2"),
-         ("mass_source", "H3")]
+         ("mass_source", "H3"), ("divfree", "stokes"), ("none", "stokes")]
 
 
 def problem(constraint, norm, n=16, nt=3, mode="dto", amp=0.5, seed=1, n2=None):
     n2 = n2 or n
     bw = 1e-3 if constraint == "mass_source" else 0.0
-    p = Params(n, n2, nt, norm, constraint, 1e-2, bw, mode)
+    p = Params(n, n2, nt, norm, constraint, 1e-2, bw, mode, nu=1.7 if norm == "stokes" else 1.0)
     g = Grid(n, n2)
     rng = np.random.default_rng(seed)
     mT = sd.template_image(n, n2, 4, 3, rng)
@@ -45,8 +45,17 @@ def test_q5_linearisation_at_zero(constraint, norm, mode):
     vt, _ = dirs(16, constraint)
     H = reduced.hessian_matvec(g, p, lin, vt)
     vtp = spectral.nyquist_project(g, vt)
-    expect = spectral.nyquist_project(g, p.beta_v * spectral.apply_A(g, p, vtp)
-                                      + spectral.apply_K(g, p, (vtp[0] * Gm[0] + vtp[1] * Gm[1]) * Gm))
+    gn = (vtp[0] * Gm[0] + vtp[1] * Gm[1]) * Gm
+    if norm == "stokes":
+        # E(0) = 0: constant viscosity eps^{(1-nu)/(2nu)} times -Lap - grad div (symbol |k|^2 I + k k^T),
+        # projected together with the body force
+        eta0 = p.eps ** ((1 - p.nu) / (2 * p.nu))
+        v1h, v2h = g.fft(vtp[0]), g.fft(vtp[1])
+        kv = g.k1 * v1h + g.k2 * v2h
+        B = eta0 * np.stack([g.ifft(g.ksq * v1h + g.k1 * kv), g.ifft(g.ksq * v2h + g.k2 * kv)])
+        expect = spectral.nyquist_project(g, spectral.apply_K(g, p, p.beta_v * B + gn))
+    else:
+        expect = spectral.nyquist_project(g, p.beta_v * spectral.apply_A(g, p, vtp) + spectral.apply_K(g, p, gn))
     assert np.abs(H - expect).max() < 1e-12 * np.abs(expect).max()
 
 
