@@ -46,7 +46,14 @@ typedef enum {
 
 /* Seminorm on v (Sec. 2, eq. (reg-v)); A = -Lap (H1) or Lap^2 (H2), eq. (var-reg-v); REG_H3 is the
  * H3 seminorm the paper names as an option (A = -Lap^3, a triharmonic reduced gradient). */
-enum { REG_H1 = 1, REG_H2 = 2, REG_H3 = 3 };
+enum { REG_H1 = 1, REG_H2 = 2, REG_H3 = 3, REG_STOKES = 4 };
+/* REG_STOKES: the nonlinear Stokes (shear-control) model of eq. (shear-control-reg-v),
+ * beta_v R(v) with R(v) = 2nu/(nu+1) int (E:E + eps)^{(1+nu)/(2nu)}, E = sym grad v; its first
+ * variation -div(2 eta E) (eq. (1st-var-reg-v-nls)) and second variation (eq. (2nd-var-reg-v-nls))
+ * enter the gradient and the Hessian, projected together with the body force under
+ * REG_DIVFREE; the preconditioner is the inverse vector Laplacian (App. E.2).  nu = stokes_nu > 0
+ * (nu > 1 thins, nu < 1 thickens under shear), eps = stokes_eps > 0 keeps eta finite where the
+ * strain vanishes.  Not with REG_MASS_SOURCE. */
 /* Constraint on div v (Sec. 2): gamma = 0; gamma = 1 with w = 0 (incompressible); gamma = 1 with a
  * mass source w penalised by its H1 norm (eq. (reg-w)), beta_w > 0. */
 enum { REG_UNCONSTRAINED = 0, REG_DIVFREE = 1, REG_MASS_SOURCE = 2 };
@@ -71,7 +78,7 @@ enum { REG_HESS_GN = 0, REG_HESS_FULL = 1 };
 typedef struct {
     int32_t n1, n2;       /* grid (powers of two, 8..2048) */
     int32_t nt;           /* RK2 time steps on [0, 1] */
-    int32_t norm;         /* REG_H1 | REG_H2 | REG_H3 */
+    int32_t norm;         /* REG_H1 | REG_H2 | REG_H3 | REG_STOKES */
     int32_t constraint;   /* REG_UNCONSTRAINED | REG_DIVFREE | REG_MASS_SOURCE */
     int32_t precision;    /* REG_FP64 | REG_FP32_TRANSPORT */
     int32_t adjoint;      /* REG_ADJ_DISCRETE | REG_ADJ_PAPER */
@@ -82,6 +89,8 @@ typedef struct {
     int32_t reserved;     /* must be 0 */
     double beta_v;        /* weight of the v seminorm (> 0) */
     double beta_w;        /* weight of the mass-source norm (> 0 iff REG_MASS_SOURCE) */
+    double stokes_nu;     /* REG_STOKES: nu > 0; otherwise 0 */
+    double stokes_eps;    /* REG_STOKES: eps > 0; otherwise 0 */
 } reg_params;
 
 typedef struct reg_problem reg_problem;   /* opaque handle */

@@ -75,7 +75,9 @@ enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG, SPEC_LR };
 
 struct SpecParams {
     int n1, n2;
-    int norm;                // 1 = H1, 2 = H2, 3 = H3
+    int norm;                // 1 = H1, 2 = H2, 3 = H3, 4 = shear-control model (its regularisation
+                             // term is formed in real space; the multipliers project it with K and
+                             // precondition with the vector Laplacian)
     int constraint;          // 0 none, 1 divfree, 2 mass source
     double beta_v, beta_w;
 };
@@ -136,6 +138,15 @@ hipError_t launch_lr_combine(long n, const double* base, double* out, const doub
                              double sign, hipStream_t s);
 // in place: F_j <- sum_{i < rin} m[i][j] F_i for j < rout (rin, rout <= LR_MIX_MAX)
 hipError_t launch_lr_mix(long n, double* F, long stride, int rin, int rout, const LrMix& m, hipStream_t s);
+
+// ---- nonlinear Stokes (shear-control) regularisation, FP64 ---------------------------------------
+// dv: the four partials d_l v_i at (2 i + l) * nn.  sig, E: 3 fields (11, 12, 22); eta, dens: 1 field.
+hipError_t launch_stokes_first(long nn, const double* dv, double nu, double eps, double* sig, double* E, double* eta,
+                               double* dens, hipStream_t s);
+hipError_t launch_stokes_second(long nn, const double* dvt, const double* E, const double* eta, double nu, double eps,
+                                double* sig, hipStream_t s);
+// out (vector) = scale * div sigma from ds = (grad s11, grad s12, grad s22)
+hipError_t launch_stokes_div(long nn, const double* ds, double scale, double* out, hipStream_t s);
 
 // ---- deformation diagnostics (eqs. (displacement), (def-grad)) -----------------------------------
 // Components c = 0..5: u_1, u_2, F_11, F_12, F_21, F_22.

@@ -45,6 +45,9 @@ constexpr int NSFIELD = 8;   // FP64 state-solve scratch fields
 constexpr int NPCG = 7;      // x, r, z, kr, s, st, kst
 constexpr int NSCAL = 32;
 constexpr int MAX_TIMED = 512;   // timed stage launches per reg_time_pass call
+// shear-control model, FP64 fields: partials dv (4), stress (3), stress gradients (6), E (3) and eta (1)
+// at the linearisation point, integrand (1), regularisation term (2)
+enum { STK_DV = 0, STK_SIG = 4, STK_DS = 7, STK_E = 13, STK_ETA = 16, STK_DENS = 17, STK_R = 18, STK_FIELDS = 20 };
 // scalars of the low-rank correction: valid-slot count, a spare count, e_k, <z_k, r>_W, <Hz_k, y>_W
 enum { LRS_CNT = 0, LRS_CNT2 = 1, LRS_E = 8, LRS_DA = LRS_E + LR_MAX, LRS_DB = LRS_DA + LR_MAX,
        LRS_G = LRS_DB + LR_MAX, LRS_N = LRS_G + LR_MIX_MAX * LR_MIX_MAX };
@@ -65,6 +68,7 @@ struct Offsets {
     size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal, clk;
     size_t lr[4], lrtmp, lrsc, lrpart;   // low-rank correction: sets Z, HZ, K^-1 Z, K^-1 HZ; scratch
     size_t lamtraj, gmt;                 // full Newton: lam_{j+1}, lam*_j; grad m~_j, grad m~*_j
+    size_t stk;                          // shear-control model: FP64 fields (see stokes_*)
     size_t total;
 };
 
@@ -75,7 +79,14 @@ reg_status check_params(const reg_params* p) {
     if (!is_pow2_in_range(p->n1) || !is_pow2_in_range(p->n2))
         return fail(REG_EINVAL, "n1=%d n2=%d: grid sizes must be powers of two in [8, 2048]", p->n1, p->n2);
     if (p->nt < 1 || p->nt > 4096) return fail(REG_EINVAL, "nt=%d out of range [1, 4096]", p->nt);
-    if (p->norm != REG_H1 && p->norm != REG_H2 && p->norm != REG_H3) return fail(REG_EINVAL, "norm=%d", p->norm);
+    if (p->norm < REG_H1 || p->norm > REG_STOKES) return fail(REG_EINVAL, "norm=%d", p->norm);
+    if (p->norm == REG_STOKES) {
+        if (!(p->stokes_nu > 0.0 && std::isfinite(p->stokes_nu)) || !(p->stokes_eps > 0.0 && std::isfinite(p->stokes_eps)))
+            return fail(REG_EINVAL, "REG_STOKES needs stokes_nu > 0 and stokes_eps > 0");
+        if (p->constraint == REG_MASS_SOURCE) return fail(REG_EINVAL, "REG_STOKES does not take a mass source");
+    } else if (p->stokes_nu != 0.0 || p->stokes_eps != 0.0) {
+        return fail(REG_EINVAL, "stokes_nu and stokes_eps must be 0 unless norm is REG_STOKES");
+    }
     if (p->constraint < REG_UNCONSTRAINED || p->constraint > REG_MASS_SOURCE)
         return fail(REG_EINVAL, "constraint=%d", p->constraint);
     if (p->precision != REG_FP64 && p->precision != REG_FP32_TRANSPORT)
@@ -146,6 +157,7 @@ Offsets layout(const reg_params* p) {
     const bool full = p->hessian == REG_HESS_FULL;
     o.lamtraj = L.take(full ? (size_t)2 * p->nt * nn * ts : 0);
     o.gmt = L.take(full ? (size_t)2 * p->nt * 2 * nn * ts : 0);
+    o.stk = L.take(p->norm == REG_STOKES ? (size_t)STK_FIELDS * nn * 8 : 0);
     o.total = L.total;
     return o;
 }
@@ -446,7 +458,13 @@ reg_status dots(reg_problem* P, int k, const double* const* a, const double* con
 }
 
 // Regularisation terms 1/2 beta_v <v, A v> and 1/2 beta_w <div v, (1 - Lap) div v> of a projected v.
+reg_status stokes_value(reg_problem* P, const double* v64, double* out);
+
 reg_status reg_terms(reg_problem* P, const double* v64, double* rv, double* rw) {
+    if (P->p.norm == REG_STOKES) {
+        *rw = 0.0;
+        return stokes_value(P, v64, rv);
+    }
     double* t0 = P->at<double>(P->o.tmp0);
     double* t1 = P->at<double>(P->o.tmp1);
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
@@ -468,6 +486,59 @@ reg_status data_term(reg_problem* P, const double* m1, double* out) {
     double s = 0;
     CKS(fetch(P, 1, &s));
     *out = P->h1h2 * s;
+    return REG_OK;
+}
+
+// ---- shear-control regulariser (eqs. (shear-control-reg-v), (1st-var-reg-v-nls), (2nd-var-reg-v-nls)) ---
+double* stk(reg_problem* P, int f) { return P->at<double>(P->o.stk) + (size_t)f * P->nn; }
+
+reg_status grad_fd(reg_problem* P, const double* field, double* out_vec) {   // FP64 spectral gradient
+    StageArgs<double> g = base_args<double>(P);
+    g.A = field;
+    g.GOUT = out_vec;
+    return stage<double>(P, OP_GRAD, g);
+}
+
+// partials of a vector field into STK_DV
+reg_status stokes_partials(reg_problem* P, const double* w) {
+    for (int i = 0; i < 2; ++i) CKS(grad_fd(P, w + (size_t)i * P->nn, stk(P, STK_DV + 2 * i)));
+    return REG_OK;
+}
+
+// STK_R = scale * div(stress in STK_SIG)
+reg_status stokes_divergence(reg_problem* P, double scale) {
+    for (int k = 0; k < 3; ++k) CKS(grad_fd(P, stk(P, STK_SIG + k), stk(P, STK_DS + 2 * k)));
+    CK(launch_stokes_div(P->nn, stk(P, STK_DS), scale, stk(P, STK_R), P->stream));
+    return REG_OK;
+}
+
+// beta_v A[v] into STK_R; keeps E and eta at v (the point of later Hessian matvecs)
+reg_status stokes_first(reg_problem* P, const double* v64) {
+    CKS(stokes_partials(P, v64));
+    CK(launch_stokes_first(P->nn, stk(P, STK_DV), P->p.stokes_nu, P->p.stokes_eps, stk(P, STK_SIG), stk(P, STK_E),
+                           stk(P, STK_ETA), nullptr, P->stream));
+    return stokes_divergence(P, -P->p.beta_v);
+}
+
+// beta_v B(v)[v~] into STK_R at the kept point
+reg_status stokes_second(reg_problem* P, const double* vt64) {
+    CKS(stokes_partials(P, vt64));
+    CK(launch_stokes_second(P->nn, stk(P, STK_DV), stk(P, STK_E), stk(P, STK_ETA), P->p.stokes_nu, P->p.stokes_eps,
+                            stk(P, STK_SIG), P->stream));
+    return stokes_divergence(P, -P->p.beta_v);
+}
+
+// beta_v R(v) (host), without touching the kept point
+reg_status stokes_value(reg_problem* P, const double* v64, double* out) {
+    CKS(stokes_partials(P, v64));
+    CK(launch_stokes_first(P->nn, stk(P, STK_DV), P->p.stokes_nu, P->p.stokes_eps, nullptr, nullptr, nullptr,
+                           stk(P, STK_DENS), P->stream));
+    double r[3];
+    CK(launch_minmaxsum(stk(P, STK_DENS), P->nn, P->partial(), P->scal(), P->stream));
+    CK(hipMemcpyAsync(r, P->scal(), sizeof r, hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    const double nu = P->p.stokes_nu;
+    *out = P->p.beta_v * 2.0 * nu / (nu + 1.0) * P->h1h2 * r[2];
     return REG_OK;
 }
 
@@ -504,7 +575,12 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
     }
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(8), (const T*)nullptr, false, tv.B(),
                             P->p.hessian == REG_HESS_FULL));
-    CKS(spec_fwd<double>(P, 0, v64));
+    if (P->p.norm == REG_STOKES) {   // the regularisation term is formed in real space
+        CKS(stokes_first(P, v64));
+        CKS(spec_fwd<double>(P, 0, stk(P, STK_R)));
+    } else {
+        CKS(spec_fwd<double>(P, 0, v64));
+    }
     CKS(spec_fwd<T>(P, 1, tv.B()));
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
     CKS(spec_col(P, SPEC_HESS, true, ms && kg));
@@ -530,7 +606,12 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     // lam~(1) = -m~(1)
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(mt.r), tv.F(mt.c), true, tv.Bt(), false,
                             full ? (const T*)tv.vtT() : (const T*)nullptr));
-    CKS(spec_fwd<double>(P, 0, vt64));
+    if (P->p.norm == REG_STOKES) {
+        CKS(stokes_second(P, vt64));
+        CKS(spec_fwd<double>(P, 0, stk(P, STK_R)));
+    } else {
+        CKS(spec_fwd<double>(P, 0, vt64));
+    }
     CKS(spec_fwd<T>(P, 1, tv.Bt()));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
     CKS(spec_inv<double>(P, 0, out, (double*)nullptr));

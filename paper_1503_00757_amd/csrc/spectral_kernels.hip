@@ -115,7 +115,10 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
         const int e = t + r * Q;
         const double k1 = (double)kwave<N>(e);
         const double kk = k1 * k1 + k2d * k2d;
-        const double A = (p.norm == 1) ? kk : (p.norm == 2 ? kk * kk : kk * kk * kk);
+        // regulariser symbol of the assembly (none for the shear-control model, whose term arrives in
+        // real space with the body force) and of the preconditioner (the vector Laplacian for it)
+        const double A = (p.norm == 1) ? kk : (p.norm == 2 ? kk * kk : (p.norm == 3 ? kk * kk * kk : 0.0));
+        const double Ap = p.norm == 4 ? kk : A;
         const double ik = kk > 0.0 ? 1.0 / kk : 0.0;
         const double p11 = k1 * k1 * ik, p12 = k1 * k2d * ik, p22 = k2d * k2d * ik;
         double c = 0.0, ci = 0.0;   // K = I - c P, K^{-1} = I + ci P
@@ -135,7 +138,11 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
             o0 = x0;
             o1 = x1;
         } else if (mode == SPEC_HESS) {
-            const cpx<double> y0 = Y0[r], y1 = Y1[r];
+            cpx<double> y0 = Y0[r], y1 = Y1[r];
+            if (p.norm == 4) {   // K (x + y): x is the real-space regularisation term
+                y0 = {y0.x + x0.x, y0.y + x0.y};
+                y1 = {y1.x + x1.x, y1.y + x1.y};
+            }
             const double ba = p.beta_v * A;
             // K y
             const cpx<double> ky0 = {y0.x - c * (p11 * y0.x + p12 * y1.x), y0.y - c * (p11 * y0.y + p12 * y1.y)};
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
             q0 = {ba * kx0.x + y0.x, ba * kx0.y + y0.y};
             q1 = {ba * kx1.x + y1.x, ba * kx1.y + y1.y};
         } else if (mode == SPEC_PREC) {
-            const double pinv = 1.0 / (p.beta_v * (A > 0.0 ? A : 1.0));
+            const double pinv = 1.0 / (p.beta_v * (Ap > 0.0 ? Ap : 1.0));
             o0 = {x0.x * pinv, x0.y * pinv};
             o1 = {x1.x * pinv, x1.y * pinv};
             q0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
@@ -157,7 +164,7 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
             const double ca = p.constraint == 1 ? c : 0.0;   // Leray projection for w = 0
             o0 = {x0.x - ca * (p11 * x0.x + p12 * x1.x), x0.y - ca * (p11 * x0.y + p12 * x1.y)};
             o1 = {x1.x - ca * (p12 * x0.x + p22 * x1.x), x1.y - ca * (p12 * x0.y + p22 * x1.y)};
-            const double pm = p.beta_v * (A > 0.0 ? A : 1.0);
+            const double pm = p.beta_v * (Ap > 0.0 ? Ap : 1.0);
             q0 = {pm * (o0.x + ci * (p11 * o0.x + p12 * o1.x)), pm * (o0.y + ci * (p11 * o0.y + p12 * o1.y))};
             q1 = {pm * (o1.x + ci * (p12 * o0.x + p22 * o1.x)), pm * (o1.y + ci * (p12 * o0.y + p22 * o1.y))};
         } else {   // SPEC_REG: beta_v A v and beta_w (1 + |k|^2) k k^T v

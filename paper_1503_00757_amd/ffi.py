@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 REG_OK, REG_EINVAL, REG_ENOMEM, REG_EDEVICE, REG_ENOTCONV, REG_ENONFINITE, REG_ESTATE = 0, -1, -2, -3, -4, -5, -6
-REG_H1, REG_H2, REG_H3 = 1, 2, 3
+REG_H1, REG_H2, REG_H3, REG_STOKES = 1, 2, 3, 4
 REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE = 0, 1, 2
 REG_FP64, REG_FP32_TRANSPORT = 0, 1
 REG_ADJ_DISCRETE, REG_ADJ_PAPER = 0, 1
@@ -26,7 +26,8 @@ class RegParams(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("nt", C.c_int32), ("norm", C.c_int32),
                 ("constraint", C.c_int32), ("precision", C.c_int32), ("adjoint", C.c_int32),
                 ("hessian", C.c_int32), ("lowrank_capacity", C.c_int32), ("reserved", C.c_int32),
-                ("beta_v", C.c_double), ("beta_w", C.c_double)]
+                ("beta_v", C.c_double), ("beta_w", C.c_double), ("stokes_nu", C.c_double),
+                ("stokes_eps", C.c_double)]
 
 
 class RegSolveOpts(C.Structure):

@@ -7,7 +7,7 @@ from __future__ import annotations
 
 from . import ffi
 
-_NORMS = {"H1": ffi.REG_H1, "H2": ffi.REG_H2, "H3": ffi.REG_H3}
+_NORMS = {"H1": ffi.REG_H1, "H2": ffi.REG_H2, "H3": ffi.REG_H3, "stokes": ffi.REG_STOKES}
 _CONS = {"none": ffi.REG_UNCONSTRAINED, "divfree": ffi.REG_DIVFREE, "mass_source": ffi.REG_MASS_SOURCE}
 _PREC = {"fp64": ffi.REG_FP64, "fp32": ffi.REG_FP32_TRANSPORT}
 _ADJ = {"dto": ffi.REG_ADJ_DISCRETE, "paper": ffi.REG_ADJ_PAPER}
@@ -17,14 +17,19 @@ _HESS = {"gn": ffi.REG_HESS_GN, "full": ffi.REG_HESS_FULL}
 
 
 def make_params(n1, n2, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0, precision="fp32",
-                adjoint="dto", lowrank_capacity=0, hessian="gn") -> ffi.RegParams:
+                adjoint="dto", lowrank_capacity=0, hessian="gn", nu=1.0, eps=1e-6) -> ffi.RegParams:
+    """reg_params; nu and eps are the shear-control model's exponent and strain regularisation (used
+    for norm="stokes" only)."""
+    st = norm == "stokes"
     return ffi.RegParams(n1, n2, nt, _NORMS[norm], _CONS[constraint], _PREC[precision], _ADJ[adjoint],
-                         _HESS[hessian], int(lowrank_capacity), 0, float(beta_v), float(beta_w))
+                         _HESS[hessian], int(lowrank_capacity), 0, float(beta_v), float(beta_w),
+                         float(nu) if st else 0.0, float(eps) if st else 0.0)
 
 
 class Problem:
     def __init__(self, mT, mR, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0,
-                 precision="fp32", adjoint="dto", stream=None, lowrank_capacity=0, hessian="gn"):
+                 precision="fp32", adjoint="dto", stream=None, lowrank_capacity=0, hessian="gn", nu=1.0,
+                 eps=1e-6):
         import torch
         self.torch = torch
         if mT.dtype != torch.float64 or mR.dtype != torch.float64 or not mT.is_cuda or not mR.is_cuda:
@@ -33,7 +38,7 @@ class Problem:
         self.n1, self.n2, self.nt = n1, n2, nt
         self.device = mT.device
         self.params = make_params(n1, n2, nt, norm, constraint, beta_v, beta_w, precision, adjoint,
-                                  lowrank_capacity, hessian)
+                                  lowrank_capacity, hessian, nu, eps)
         self.ws_bytes = ffi.reg_workspace_bytes(self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()

@@ -26,6 +26,8 @@ class Case:
     config: int = 0          # 1..5: the seeded workload of that configuration (full size)
     ktex: int = 8
     vmax: float = 0.0        # > 0: scale v* to this max |v| instead of CFL 0.8 (nt chosen to keep CFL < 1)
+    nu: float = 1.0          # shear-control model (norm "stokes"): exponent and strain regularisation
+    stokes_eps: float = 1e-6
 
     @property
     def tol(self):
@@ -70,7 +72,8 @@ def inputs(case: Case):
 
 
 def params(case: Case) -> Params:
-    return Params(case.n1, case.n2, case.nt, case.norm, case.constraint, case.beta_v, case.beta_w, case.adjoint)
+    return Params(case.n1, case.n2, case.nt, case.norm, case.constraint, case.beta_v, case.beta_w, case.adjoint,
+                  nu=case.nu, eps=case.stokes_eps)
 
 
 @functools.lru_cache(maxsize=None)
@@ -106,7 +109,7 @@ def gpu_problem(case: Case, lowrank_capacity=0, hessian="gn"):
     dev = torch.device("cuda:0")
     return Problem(torch.tensor(mT, device=dev), torch.tensor(mR, device=dev), case.nt, case.norm,
                    case.constraint, case.beta_v, case.beta_w, case.precision, case.adjoint,
-                   lowrank_capacity=lowrank_capacity, hessian=hessian)
+                   lowrank_capacity=lowrank_capacity, hessian=hessian, nu=case.nu, eps=case.stokes_eps)
 
 
 def dev(x):

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(R.RegParams) == 10 * 4 + 2 * 8
+    assert ctypes.sizeof(R.RegParams) == 10 * 4 + 4 * 8
     assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 4 * 8
 
@@ -71,7 +71,7 @@ def test_invalid_parameters_are_rejected(kw):
 
 def test_bad_enum_and_lowrank_capacity_rejected():
     p = make_params(64, 64, 4)
-    p.norm = 4
+    p.norm = 5
     with pytest.raises(R.RegError):
         R.reg_workspace_bytes(p)
     for cap in (-1, 65):
@@ -130,3 +130,17 @@ def test_deformation_workspace_and_null_checks():
     with pytest.raises(R.RegError) as e:
         R.reg_deformation(None, 256, 256, 1 << 20, None, None, None)
     assert e.value.status == -1
+
+
+def test_shear_control_parameters_checked():
+    assert R.reg_workspace_bytes(make_params(64, 64, 4, norm="stokes", nu=1.7, eps=1e-4)) > \
+        R.reg_workspace_bytes(make_params(64, 64, 4))
+    for kw in (dict(nu=0.0), dict(eps=0.0), dict(nu=float("nan"))):
+        with pytest.raises(R.RegError):
+            R.reg_workspace_bytes(make_params(64, 64, 4, norm="stokes", **kw))
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(make_params(64, 64, 4, norm="stokes", constraint="mass_source", beta_w=1e-3))
+    p = make_params(64, 64, 4)
+    p.stokes_nu = 1.0                      # only meaningful for the shear-control model
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(p)

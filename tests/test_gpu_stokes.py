@@ -1,0 +1,63 @@
+"""GPU parity of the nonlinear Stokes (shear-control) regularisation (REG_STOKES) with the oracle:
+objective, reduced gradient, Gauss-Newton and full-Newton matvecs, and a fixed-schedule solve, for a
+shear-thinning and a shear-thickening exponent, with and without incompressibility, in both transport
+precisions."""
+import numpy as np
+import pytest
+
+from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel, oracle_results
+from oracle import Grid, reduced, solver
+
+pytestmark = pytest.mark.gpu
+
+ST_DF = Case(64, 64, 4, "stokes", "divfree", 1e-2, 0.0, "fp64", seed=5, nu=1.7, stokes_eps=1e-4)
+ST_UN = Case(64, 64, 4, "stokes", "none", 1e-2, 0.0, "fp64", seed=6, nu=0.6, stokes_eps=1e-4)
+ST_32 = Case(64, 64, 4, "stokes", "divfree", 1e-2, 0.0, "fp32", seed=5, nu=1.7, stokes_eps=1e-4)
+ST_NS = Case(32, 128, 5, "stokes", "none", 1e-2, 0.0, "fp64", seed=7, nu=2.5, stokes_eps=1e-4)
+
+
+@pytest.mark.parametrize("case", [ST_DF, ST_UN, ST_32, ST_NS], ids=["divfree_nu1.7", "none_nu0.6", "fp32", "32x128"])
+def test_shear_control_gradient_objective_matvec(case):
+    print(f"[case] stokes {case}", flush=True)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    ref = oracle_results(case)
+    tol = max(case.tol, 10 * ref["sens_H"])
+    P = gpu_problem(case)
+    try:
+        g, J = P.gradient(dev(vlin))
+        assert rel(host(g), ref["g"]) < max(tol, 10 * ref["sens_g"] / np.linalg.norm(ref["g"]))
+        assert abs(J - ref["J"]) <= 1e-9 * abs(ref["J"]) + 10 * ref["Jscale"] * case.eps
+        Jt, terms = P.objective(dev(vtr))
+        assert abs(terms[1] - ref["terms"][1]) <= 1e-10 * abs(ref["terms"][1])
+        assert rel(host(P.hessian_matvec(dev(vt))), ref["H"]) < tol
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("case,tol", [(ST_DF, 1e-9), (ST_UN, 1e-9), (ST_32, 1e-4)], ids=["divfree", "none", "fp32"])
+def test_shear_control_fixed_schedule_solve(case, tol):
+    mT, mR, *_ = inputs(case)
+    g = Grid(case.n1, case.n2)
+    v_ref, st = solver.solve(g, params(case), mT, mR, solver.SolveOpts(max_newton=3, fixed_pcg_iters=6, gtol_rel=0.0))
+    P = gpu_problem(case)
+    try:
+        v, s = P.solve(max_newton=3, fixed_pcg_iters=6, gtol_rel=0.0)
+        assert s["status"] == 0 and s["pcg_iters"] == st.pcg_iters and s["backtracks"] == st.backtracks
+        assert rel(host(v), v_ref) < tol
+    finally:
+        P.close()
+
+
+def test_shear_control_full_newton_matvec():
+    case = ST_DF
+    mT, mR, vlin, vt, _ = inputs(case)
+    g = Grid(case.n1, case.n2)
+    p = params(case)
+    lin = reduced.gradient(g, p, mT, mR, vlin)
+    H_ref = reduced.hessian_matvec_full(g, p, lin, vt)
+    P = gpu_problem(case, hessian="full")
+    try:
+        P.gradient(dev(vlin), want_J=False)
+        assert rel(host(P.hessian_matvec(dev(vt))), H_ref) < max(case.tol, 10 * oracle_results(case)["sens_H"])
+    finally:
+        P.close()
