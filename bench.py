@@ -220,6 +220,37 @@ def bench_hessians(config=2):
     return out
 
 
+def bench_shear_control(config=2):
+    """Alg. 1 to ||g||/||g(0)|| <= 1e-2 on one workload's images with the incompressibility constraint:
+    the linear model (H1) against the nonlinear Stokes shear-control model (nu = 0.6 thickening,
+    nu = 1.7 thinning; eps = 1e-4), one untimed solve first each."""
+    import torch
+    import synthdata as sd
+    from paper_1503_00757_amd import Problem
+    w = sd.make_workload(config)
+    dev = torch.device("cuda:0")
+    mT = torch.tensor(w.mT, device=dev)
+    P0 = Problem(mT, mT.clone(), w.nt, "H1", "divfree", w.beta_v, 0.0, "fp32")
+    vs = torch.tensor(w.vstar, device=dev)
+    mR = P0.state_forward(vs)
+    P0.close()
+    out = {}
+    for name, kw in (("H1", dict(norm="H1")), ("stokes_nu0.6", dict(norm="stokes", nu=0.6, eps=1e-4)),
+                     ("stokes_nu1.7", dict(norm="stokes", nu=1.7, eps=1e-4))):
+        P = Problem(mT, mR, w.nt, constraint="divfree", beta_v=w.beta_v, beta_w=0.0, precision="fp32", **kw)
+        P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, raise_on_error=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, st = P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, raise_on_error=False)
+        torch.cuda.synchronize()
+        _, _, _, (mn, mx, mean) = P.deformation(v)
+        out[name] = {"seconds": round(time.perf_counter() - t0, 4), "newton_iters": st["newton_iters"],
+                     "pcg_iters": st["pcg_iters"], "g_rel": st["g_rel"], "status": st["status"],
+                     "det_F1_min_max": [round(mn, 5), round(mx, 5)]}
+        P.close()
+    return out
+
+
 def bench_batch(npairs=96):
     """Config 4: 96 pairs (32 each at 128^2, 256^2, 512^2; beta_v log-uniform in [1e-4, 1e-2]; n_t in
     {8, 16, 32}; H1 + divergence-free), all solved to ||g||/||g(0)|| <= 1e-2 by reg_batch_solve.
@@ -473,6 +504,8 @@ def main():
         extras["solve_to_grel_1e-2_recycle4"] = bench_solve(P, recycle=4)
         print("[bench] Gauss-Newton vs full-Newton solves", file=sys.stderr, flush=True)
         extras["gauss_newton_vs_full_newton"] = bench_hessians(cfg)
+        print("[bench] shear-control regularisation", file=sys.stderr, flush=True)
+        extras["shear_control_divfree"] = bench_shear_control(cfg)
     P.close()
     if not args.no_extras and cfg == 2:
         print("[bench] 1024^2 nt=32", file=sys.stderr, flush=True)
