@@ -254,7 +254,7 @@ reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms
 reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes);
 
 /* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): one shape index in
- * [0, 9) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
+ * [0, 12) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
  * state 2, gradient}; count must be 7. */
 reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count);
 

@@ -388,9 +388,13 @@ __global__ void body_end_kernel(long nn, T w, const T* __restrict__ Q, const T* 
 // G = BS/(N/EC) column pairs per block).  Variant 0 is the default; an autotuner may pick another.
 // FP64 and non-square or short grids use one fixed shape.
 // ---------------------------------------------------------------------------------------------
-constexpr int var_ER(int v) { return (v == 1 || v == 2 || v == 5 || v == 8) ? 4 : (v == 7 ? 16 : 8); }
-constexpr int var_EC(int v) { return (v == 0 || v == 1 || v == 6 || v == 7) ? 16 : ((v == 5 || v == 8) ? 4 : 8); }
-constexpr int var_BS(int v) { return (v == 0 || v == 3 || v == 7) ? 128 : (v == 8 ? 512 : 256); }
+// variant:                 0    1    2    3    4    5    6    7    8   9  10  11
+constexpr int VAR_ER[] = {8, 4, 4, 8, 8, 4, 8, 16, 4, 4, 8, 16};
+constexpr int VAR_EC[] = {16, 16, 8, 8, 8, 4, 16, 16, 4, 4, 8, 16};
+constexpr int VAR_BS[] = {128, 256, 256, 128, 256, 256, 256, 128, 512, 64, 64, 64};   // 9-11: one wave per block
+constexpr int var_ER(int v) { return VAR_ER[v]; }
+constexpr int var_EC(int v) { return VAR_EC[v]; }
+constexpr int var_BS(int v) { return VAR_BS[v]; }
 
 template <typename T, int N, int ER, int EC, int BS>
 constexpr bool fused_ok() {
@@ -463,6 +467,9 @@ static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s, h
             case 6: return launch_fused<T, N, OP, var_ER(6), var_EC(6), var_BS(6)>(a, s, t0, t1);
             case 7: return launch_fused<T, N, OP, var_ER(7), var_EC(7), var_BS(7)>(a, s, t0, t1);
             case 8: return launch_fused<T, N, OP, var_ER(8), var_EC(8), var_BS(8)>(a, s, t0, t1);
+            case 9: return launch_fused<T, N, OP, var_ER(9), var_EC(9), var_BS(9)>(a, s, t0, t1);
+            case 10: return launch_fused<T, N, OP, var_ER(10), var_EC(10), var_BS(10)>(a, s, t0, t1);
+            case 11: return launch_fused<T, N, OP, var_ER(11), var_EC(11), var_BS(11)>(a, s, t0, t1);
         }
         return hipErrorInvalidValue;
     }
