@@ -136,3 +136,27 @@ def test_c3_full_size_matvec_parity_symmetry_positivity():
         assert float((vt * host(Hx)).sum()) >= p.beta_v * xAx * (1 - 1e-6)
     finally:
         P.close()
+
+
+def test_c1_fixed_schedule_every_newton_step():
+    """Config 1 as specified: 5 GN steps of exactly 10 PCG iterations in FP64; after every step the
+    objective, the relative gradient and the iterate match the oracle's to 1e-10."""
+    case = C1_64
+    mT, mR, *_ = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    P = gpu_problem(case)
+    try:
+        for k in range(1, 6):
+            v_ref, st = solver.solve(g, p, mT, mR, solver.SolveOpts(max_newton=k, fixed_pcg_iters=10, gtol_rel=0.0))
+            v, s = P.solve(max_newton=k, fixed_pcg_iters=10, gtol_rel=0.0)
+            assert s["newton_iters"] == k and s["pcg_iters"] == 10 * k
+            assert rel(host(v), v_ref) < 1e-10, k
+            assert abs(s["J"] - st.J) <= 1e-10 * abs(st.J), k
+            # g shrinks while its rounding stays at the scale of g(0): compare relative to ||g(0)||
+            assert abs(s["g_rel"] - st.g_rel) <= 1e-10, k
+            gk, _ = P.gradient(v, want_J=False)
+            g_ref = reduced.gradient(g, p, mT, mR, v_ref).g
+            assert np.linalg.norm(host(gk) - g_ref) <= 1e-10 * st.g0_norm / np.sqrt(g.h1 * g.h2), k
+    finally:
+        P.close()
