@@ -244,6 +244,21 @@ def make_workload(config: int, pair: int = 0, n: int | None = None, nt: int | No
     raise ValueError(f"unknown config {config}")
 
 
+def sliding_pair(n: int, nt: int, cfl: float = 0.8, seed: int = BASE_SEED + 512, sharp: float = 4.0) -> Workload:
+    """A self-made sliding-interface pair in the spirit of the paper's shear experiments (Sec. 5.2, whose
+    images are not specified numerically): a textured blob template and the divergence-free shear flow
+    v* = (a tanh(sharp sin x2), 0), whose two bands slide past each other across smooth interfaces at
+    x2 = 0 and pi; a is set for the given CFL number at n_t steps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mT = template_image(n, n, 48, min(24, n // 2 - 1), rng)
+    _, x2 = grid_coords(n, n)
+    prof = np.tanh(sharp * np.sin(x2))
+    v = np.stack([np.tile(prof[None, :], (n, 1)), np.zeros((n, n))])
+    v = scale_to_cfl(v, nt, cfl)
+    vt = _direction(n, n, rng, "divfree")
+    return Workload("sliding", n, n, nt, "H1", "divfree", 1e-3, 0.0, mT, v, vt, seed)
+
+
 def random_field(n1: int, n2: int, kmax: int, seed: int) -> np.ndarray:
     """A seeded band-limited scalar field with unit max-norm (for operator tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))
