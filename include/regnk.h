@@ -21,8 +21,10 @@
  *  - Every velocity-like input (v, v~, r) has its Nyquist row and column (k1 = n1/2, k2 = n2/2)
  *    removed before use, and every velocity-like output has none (spectral derivatives use the
  *    Nyquist wavenumber 0 so that they are exactly skew-symmetric).
- *  - Sizes: n1, n2 powers of two in [8, 2048]; nt >= 1; beta_v > 0; beta_w > 0 exactly when
- *    constraint == REG_MASS_SOURCE.  Anything else is REG_EINVAL.
+ *  - Sizes: n1, n2 even in [8, 2048]; nt >= 1; beta_v > 0; beta_w > 0 exactly when
+ *    constraint == REG_MASS_SOURCE.  Anything else is REG_EINVAL.  Powers of two take the FFT
+ *    kernels; other even lengths take direct O(n^2)-per-line spectral sums along that axis (same
+ *    operators, slower).
  */
 #ifndef REGNK_H
 #define REGNK_H
@@ -76,7 +78,7 @@ enum { REG_ADJ_DISCRETE = 0, REG_ADJ_PAPER = 1 };
 enum { REG_HESS_GN = 0, REG_HESS_FULL = 1 };
 
 typedef struct {
-    int32_t n1, n2;       /* grid (powers of two, 8..2048) */
+    int32_t n1, n2;       /* grid (even, 8..2048; powers of two are the fast path) */
     int32_t nt;           /* RK2 time steps on [0, 1] */
     int32_t norm;         /* REG_H1 | REG_H2 | REG_H3 | REG_STOKES */
     int32_t constraint;   /* REG_UNCONSTRAINED | REG_DIVFREE | REG_MASS_SOURCE */

@@ -47,6 +47,8 @@ struct StageArgs {
     T* B;                    // body-force accumulator (vector field)
     const cpx<T>* tw1;       // twiddles of length n1 (column transforms)
     const cpx<T>* tw2;       // twiddles of length n2 (row transforms)
+    const T* dc1;            // axis lengths that are not powers of two: the circulant spectral
+    const T* dc2;            // derivative along x1 / x2 (length n1 / n2), else unused
     unsigned long long* clk; // timing (nullable): block b stores its start / end (device wall clock)
                              // to clk[2b], clk[2b+1]; a stage has at most (n1 + n2) / 2 blocks
 };

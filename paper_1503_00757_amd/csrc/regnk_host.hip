@@ -64,7 +64,7 @@ struct Layout {
 struct Offsets {
     size_t mT, mR, vT, vw, vtT, traj, fld[NFIELD], B, Bt;
     size_t mT64, mR64, sfld[NSFIELD];   // FP64 state-solve buffers (FP32 transport mode only)
-    size_t tw1f, tw2f, tw1d, tw2d;
+    size_t tw1f, tw2f, tw1d, tw2d, dc1f, dc2f, dc1d, dc2d;
     size_t v64, vtrial, g64, kg64, vt64, tmp0, tmp1, vcur, vtry, rhs, pcg[NPCG], spec, partial, scal, clk;
     size_t lr[4], lrtmp, lrsc, lrpart;   // low-rank correction: sets Z, HZ, K^-1 Z, K^-1 HZ; scratch
     size_t lamtraj, gmt;                 // full Newton: lam_{j+1}, lam*_j; grad m~_j, grad m~*_j
@@ -72,12 +72,12 @@ struct Offsets {
     size_t total;
 };
 
-bool is_pow2_in_range(int n) { return n >= 8 && n <= 2048 && (n & (n - 1)) == 0; }
+bool is_even_in_range(int n) { return n >= 8 && n <= 2048 && n % 2 == 0; }
 
 reg_status check_params(const reg_params* p) {
     if (!p) return fail(REG_EINVAL, "params is NULL");
-    if (!is_pow2_in_range(p->n1) || !is_pow2_in_range(p->n2))
-        return fail(REG_EINVAL, "n1=%d n2=%d: grid sizes must be powers of two in [8, 2048]", p->n1, p->n2);
+    if (!is_even_in_range(p->n1) || !is_even_in_range(p->n2))
+        return fail(REG_EINVAL, "n1=%d n2=%d: grid sizes must be even and in [8, 2048]", p->n1, p->n2);
     if (p->nt < 1 || p->nt > 4096) return fail(REG_EINVAL, "nt=%d out of range [1, 4096]", p->nt);
     if (p->norm < REG_H1 || p->norm > REG_STOKES) return fail(REG_EINVAL, "norm=%d", p->norm);
     if (p->norm == REG_STOKES) {
@@ -132,6 +132,10 @@ Offsets layout(const reg_params* p) {
     o.tw2f = L.take(p->n2 * 8);
     o.tw1d = L.take(p->n1 * 16);
     o.tw2d = L.take(p->n2 * 16);
+    o.dc1f = L.take(p->n1 * 4);
+    o.dc2f = L.take(p->n2 * 4);
+    o.dc1d = L.take(p->n1 * 8);
+    o.dc2d = L.take(p->n2 * 8);
     o.v64 = L.take(2 * nn * 8);
     o.vtrial = L.take(2 * nn * 8);
     o.g64 = L.take(2 * nn * 8);
@@ -238,6 +242,8 @@ struct TV {
     T* Gm(int slot) const { return P->at<T>(P->o.gmt) + (size_t)slot * 2 * P->nn; }
     const cpx<T>* tw1() const;
     const cpx<T>* tw2() const;
+    const T* dc1() const { return P->at<T>(sizeof(T) == 8 ? P->o.dc1d : P->o.dc1f); }
+    const T* dc2() const { return P->at<T>(sizeof(T) == 8 ? P->o.dc2d : P->o.dc2f); }
 };
 template <>
 const cpx<float>* TV<float>::tw1() const { return P->at<cpx<float>>(P->o.tw1f); }
@@ -262,6 +268,8 @@ StageArgs<T> base_args(const reg_problem* P) {
     a.h = T(1.0 / P->nt);
     a.tw1 = tv.tw1();
     a.tw2 = tv.tw2();
+    a.dc1 = tv.dc1();
+    a.dc2 = tv.dc2();
     return a;
 }
 
@@ -1370,6 +1378,25 @@ void twiddles(int n, std::vector<cpx<float>>& f, std::vector<cpx<double>>& d) {
     }
 }
 
+// Circulant spectral derivative of length n (used for lengths that are not powers of two):
+// c_m = (1/n) sum_k i k~ exp(2 pi i k m / n) = -(1/n) sum_k k~ sin(2 pi k m / n), k~ the signed
+// wavenumber with the Nyquist index set to 0 (the transform pair's operator written as a convolution).
+void circulant_derivative(int n, std::vector<float>& f, std::vector<double>& d) {
+    f.assign(n, 0.0f);
+    d.assign(n, 0.0);
+    const long double pi2 = 2.0L * 3.14159265358979323846264338327950288L;
+    for (int m = 0; m < n; ++m) {
+        long double acc = 0.0L;
+        for (int k = 0; k < n; ++k) {
+            const int kt = k < n / 2 ? k : (2 * k == n ? 0 : k - n);
+            if (kt == 0) continue;
+            acc -= (long double)kt * sinl(pi2 * (long double)(((long)k * m) % n) / (long double)n);
+        }
+        d[m] = (double)(acc / n);
+        f[m] = (float)d[m];
+    }
+}
+
 #define DISPATCH(P, call_f, call_d) ((P)->f64 ? (call_d) : (call_f))
 
 }  // namespace
@@ -1447,6 +1474,19 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
     CKC(hipMemcpyAsync(P->ws + o.tw2f, f2.data(), f2.size() * sizeof(f2[0]), hipMemcpyHostToDevice, P->stream));
     CKC(hipMemcpyAsync(P->ws + o.tw1d, d1.data(), d1.size() * sizeof(d1[0]), hipMemcpyHostToDevice, P->stream));
     CKC(hipMemcpyAsync(P->ws + o.tw2d, d2.data(), d2.size() * sizeof(d2[0]), hipMemcpyHostToDevice, P->stream));
+    std::vector<float> c1f, c2f;
+    std::vector<double> c1d, c2d;
+    if ((P->n1 & (P->n1 - 1)) != 0) circulant_derivative(P->n1, c1f, c1d);
+    if ((P->n2 & (P->n2 - 1)) != 0) circulant_derivative(P->n2, c2f, c2d);
+    if (!c1d.empty()) {
+        CKC(hipMemcpyAsync(P->ws + o.dc1f, c1f.data(), c1f.size() * sizeof(float), hipMemcpyHostToDevice, P->stream));
+        CKC(hipMemcpyAsync(P->ws + o.dc1d, c1d.data(), c1d.size() * sizeof(double), hipMemcpyHostToDevice, P->stream));
+    }
+    if (!c2d.empty()) {
+        CKC(hipMemcpyAsync(P->ws + o.dc2f, c2f.data(), c2f.size() * sizeof(float), hipMemcpyHostToDevice, P->stream));
+        CKC(hipMemcpyAsync(P->ws + o.dc2d, c2d.data(), c2d.size() * sizeof(double), hipMemcpyHostToDevice, P->stream));
+    }
+    CKC(hipStreamSynchronize(P->stream));   // the host tables go out of scope
     {
         reg_status st = load_images(P, m_T, m_R);
         if (st != REG_OK) return cleanup(st);

@@ -78,6 +78,74 @@ struct ModeCoef {
     double p11, p12, p22;   // k k^T / |k|^2
 };
 
+// The Fourier multiplier of `mode` at wavenumber (k1, k2) on the (scaled-later) spectra x, y of the
+// two components: first result o, second result q (see the file header).
+__device__ __forceinline__ void spec_multiplier(const SpecParams& p, int mode, double k1, double k2d, cpx<double> x0,
+                                                cpx<double> x1, cpx<double> y0, cpx<double> y1, cpx<double>& o0,
+                                                cpx<double>& o1, cpx<double>& q0, cpx<double>& q1) {
+    const double kk = k1 * k1 + k2d * k2d;
+    // regulariser symbol of the assembly (none for the shear-control model, whose term arrives in
+    // real space with the body force) and of the preconditioner (the vector Laplacian for it)
+    const double A = (p.norm == 1) ? kk : (p.norm == 2 ? kk * kk : (p.norm == 3 ? kk * kk * kk : 0.0));
+    const double Ap = p.norm == 4 ? kk : A;
+    const double ik = kk > 0.0 ? 1.0 / kk : 0.0;
+    const double p11 = k1 * k1 * ik, p12 = k1 * k2d * ik, p22 = k2d * k2d * ik;
+    double c = 0.0, ci = 0.0;   // K = I - c P, K^{-1} = I + ci P
+    if (kk > 0.0) {
+        if (p.constraint == 1) {
+            c = 1.0;
+        } else if (p.constraint == 2) {
+            const double q = p.beta_v * A / (p.beta_w * kk * (kk + 1.0));   // M^ - 1
+            c = 1.0 / (1.0 + q);
+            ci = 1.0 / q;
+        }
+    }
+    o0 = {0, 0};
+    o1 = {0, 0};
+    q0 = {0, 0};
+    q1 = {0, 0};
+    if (mode == SPEC_PROJ) {
+        o0 = x0;
+        o1 = x1;
+    } else if (mode == SPEC_HESS) {
+        if (p.norm == 4) {   // K (x + y): x is the real-space regularisation term
+            y0 = {y0.x + x0.x, y0.y + x0.y};
+            y1 = {y1.x + x1.x, y1.y + x1.y};
+        }
+        const double ba = p.beta_v * A;
+        // K y
+        const cpx<double> ky0 = {y0.x - c * (p11 * y0.x + p12 * y1.x), y0.y - c * (p11 * y0.y + p12 * y1.y)};
+        const cpx<double> ky1 = {y1.x - c * (p12 * y0.x + p22 * y1.x), y1.y - c * (p12 * y0.y + p22 * y1.y)};
+        o0 = {ba * x0.x + ky0.x, ba * x0.y + ky0.y};
+        o1 = {ba * x1.x + ky1.x, ba * x1.y + ky1.y};
+        // K^{-1}(beta_v A x + K y) = beta_v A K^{-1} x + y
+        const cpx<double> kx0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
+        const cpx<double> kx1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
+        q0 = {ba * kx0.x + y0.x, ba * kx0.y + y0.y};
+        q1 = {ba * kx1.x + y1.x, ba * kx1.y + y1.y};
+    } else if (mode == SPEC_PREC) {
+        const double pinv = 1.0 / (p.beta_v * (Ap > 0.0 ? Ap : 1.0));
+        o0 = {x0.x * pinv, x0.y * pinv};
+        o1 = {x1.x * pinv, x1.y * pinv};
+        q0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
+        q1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
+    } else if (mode == SPEC_LR) {
+        const double ca = p.constraint == 1 ? c : 0.0;   // Leray projection for w = 0
+        o0 = {x0.x - ca * (p11 * x0.x + p12 * x1.x), x0.y - ca * (p11 * x0.y + p12 * x1.y)};
+        o1 = {x1.x - ca * (p12 * x0.x + p22 * x1.x), x1.y - ca * (p12 * x0.y + p22 * x1.y)};
+        const double pm = p.beta_v * (Ap > 0.0 ? Ap : 1.0);
+        q0 = {pm * (o0.x + ci * (p11 * o0.x + p12 * o1.x)), pm * (o0.y + ci * (p11 * o0.y + p12 * o1.y))};
+        q1 = {pm * (o1.x + ci * (p12 * o0.x + p22 * o1.x)), pm * (o1.y + ci * (p12 * o0.y + p22 * o1.y))};
+    } else {   // SPEC_REG: beta_v A v and beta_w (1 + |k|^2) k k^T v
+        const double ba = p.beta_v * A;
+        o0 = {ba * x0.x, ba * x0.y};
+        o1 = {ba * x1.x, ba * x1.y};
+        const double w = p.beta_w * (1.0 + kk) * kk;
+        q0 = {w * (p11 * x0.x + p12 * x1.x), w * (p11 * x0.y + p12 * x1.y)};
+        q1 = {w * (p12 * x0.x + p22 * x1.x), w * (p12 * x0.y + p22 * x1.y)};
+    }
+}
+
 template <int N, int NF>
 __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int mode, int have_y, int want2,
                                                               cpx<double>* __restrict__ spec,
@@ -114,67 +182,10 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
     for (int r = 0; r < 4; ++r) {
         const int e = t + r * Q;
         const double k1 = (double)kwave<N>(e);
-        const double kk = k1 * k1 + k2d * k2d;
-        // regulariser symbol of the assembly (none for the shear-control model, whose term arrives in
-        // real space with the body force) and of the preconditioner (the vector Laplacian for it)
-        const double A = (p.norm == 1) ? kk : (p.norm == 2 ? kk * kk : (p.norm == 3 ? kk * kk * kk : 0.0));
-        const double Ap = p.norm == 4 ? kk : A;
-        const double ik = kk > 0.0 ? 1.0 / kk : 0.0;
-        const double p11 = k1 * k1 * ik, p12 = k1 * k2d * ik, p22 = k2d * k2d * ik;
-        double c = 0.0, ci = 0.0;   // K = I - c P, K^{-1} = I + ci P
-        if (kk > 0.0) {
-            if (p.constraint == 1) {
-                c = 1.0;
-            } else if (p.constraint == 2) {
-                const double q = p.beta_v * A / (p.beta_w * kk * (kk + 1.0));   // M^ - 1
-                c = 1.0 / (1.0 + q);
-                ci = 1.0 / q;
-            }
-        }
         const bool zero = (e == N / 2);   // Nyquist row of x1: projected out
-        cpx<double> x0 = X0[r], x1 = X1[r];
-        cpx<double> o0{0, 0}, o1{0, 0}, q0{0, 0}, q1{0, 0};
-        if (mode == SPEC_PROJ) {
-            o0 = x0;
-            o1 = x1;
-        } else if (mode == SPEC_HESS) {
-            cpx<double> y0 = Y0[r], y1 = Y1[r];
-            if (p.norm == 4) {   // K (x + y): x is the real-space regularisation term
-                y0 = {y0.x + x0.x, y0.y + x0.y};
-                y1 = {y1.x + x1.x, y1.y + x1.y};
-            }
-            const double ba = p.beta_v * A;
-            // K y
-            const cpx<double> ky0 = {y0.x - c * (p11 * y0.x + p12 * y1.x), y0.y - c * (p11 * y0.y + p12 * y1.y)};
-            const cpx<double> ky1 = {y1.x - c * (p12 * y0.x + p22 * y1.x), y1.y - c * (p12 * y0.y + p22 * y1.y)};
-            o0 = {ba * x0.x + ky0.x, ba * x0.y + ky0.y};
-            o1 = {ba * x1.x + ky1.x, ba * x1.y + ky1.y};
-            // K^{-1}(beta_v A x + K y) = beta_v A K^{-1} x + y
-            const cpx<double> kx0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
-            const cpx<double> kx1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
-            q0 = {ba * kx0.x + y0.x, ba * kx0.y + y0.y};
-            q1 = {ba * kx1.x + y1.x, ba * kx1.y + y1.y};
-        } else if (mode == SPEC_PREC) {
-            const double pinv = 1.0 / (p.beta_v * (Ap > 0.0 ? Ap : 1.0));
-            o0 = {x0.x * pinv, x0.y * pinv};
-            o1 = {x1.x * pinv, x1.y * pinv};
-            q0 = {x0.x + ci * (p11 * x0.x + p12 * x1.x), x0.y + ci * (p11 * x0.y + p12 * x1.y)};
-            q1 = {x1.x + ci * (p12 * x0.x + p22 * x1.x), x1.y + ci * (p12 * x0.y + p22 * x1.y)};
-        } else if (mode == SPEC_LR) {
-            const double ca = p.constraint == 1 ? c : 0.0;   // Leray projection for w = 0
-            o0 = {x0.x - ca * (p11 * x0.x + p12 * x1.x), x0.y - ca * (p11 * x0.y + p12 * x1.y)};
-            o1 = {x1.x - ca * (p12 * x0.x + p22 * x1.x), x1.y - ca * (p12 * x0.y + p22 * x1.y)};
-            const double pm = p.beta_v * (Ap > 0.0 ? Ap : 1.0);
-            q0 = {pm * (o0.x + ci * (p11 * o0.x + p12 * o1.x)), pm * (o0.y + ci * (p11 * o0.y + p12 * o1.y))};
-            q1 = {pm * (o1.x + ci * (p12 * o0.x + p22 * o1.x)), pm * (o1.y + ci * (p12 * o0.y + p22 * o1.y))};
-        } else {   // SPEC_REG: beta_v A v and beta_w (1 + |k|^2) k k^T v
-            const double ba = p.beta_v * A;
-            o0 = {ba * x0.x, ba * x0.y};
-            o1 = {ba * x1.x, ba * x1.y};
-            const double w = p.beta_w * (1.0 + kk) * kk;
-            q0 = {w * (p11 * x0.x + p12 * x1.x), w * (p11 * x0.y + p12 * x1.y)};
-            q1 = {w * (p12 * x0.x + p22 * x1.x), w * (p12 * x0.y + p22 * x1.y)};
-        }
+        cpx<double> o0, o1, q0, q1;
+        spec_multiplier(p, mode, k1, k2d, X0[r], X1[r], have_y ? Y0[r] : cpx<double>{0, 0},
+                        have_y ? Y1[r] : cpx<double>{0, 0}, o0, o1, q0, q1);
         const double sc = zero ? 0.0 : scale;
         O0[r] = {o0.x * sc, o0.y * sc};
         O1[r] = {o1.x * sc, o1.y * sc};
@@ -247,6 +258,141 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
 }
 
 // ---------------------------------------------------------------------------------------------
+// Any even length (grids that are not powers of two): the same three passes with direct DFT sums
+// over the twiddle table W[m] = exp(-2 pi i m / n) (index (j k) mod n), O(n^2) per line, one line per
+// block, the line staged in LDS.  Results equal the FFT passes up to rounding.
+constexpr int DENSE_THREADS = 256;
+
+// rows -> half spectra: block (i1, field, comp) writes spec[2 field + comp][i1][k], k < n2/2
+template <typename TI>
+__global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_fwd_kernel(int n1, int n2, const TI* __restrict__ in0,
+                                                                          const TI* __restrict__ in1,
+                                                                          cpx<double>* __restrict__ spec,
+                                                                          const cpx<double>* __restrict__ tw) {
+    extern __shared__ double xr[];
+    const int i1 = blockIdx.x, field = blockIdx.y, comp = blockIdx.z;
+    const TI* in = (field ? in1 : in0) + (long)comp * n1 * n2 + (long)i1 * n2;
+    for (int j = threadIdx.x; j < n2; j += DENSE_THREADS) xr[j] = (double)in[j];
+    __syncthreads();
+    const int H = n2 / 2;
+    cpx<double>* out = spec + (long)(2 * field + comp) * n1 * H + (long)i1 * H;
+    for (int k = threadIdx.x; k < H; k += DENSE_THREADS) {
+        double re = 0.0, im = 0.0;
+        int m = 0;   // (j k) mod n2
+        for (int j = 0; j < n2; ++j) {
+            const cpx<double> w = tw[m];
+            re += xr[j] * w.x;
+            im += xr[j] * w.y;
+            m += k;
+            if (m >= n2) m -= n2;
+        }
+        out[k] = {re, im};
+    }
+}
+
+// columns: per k2 < n2/2, DFT along x1 of the needed spectra, multiplier, inverse DFT, in place.  The
+// components pass through LDS one at a time (n1 entries); every global read of the column precedes
+// the first write back, and only this block touches column k2.
+__global__ __launch_bounds__(DENSE_THREADS) void spec_dense_col_kernel(SpecParams p, int mode, int have_y, int want2,
+                                                                      cpx<double>* __restrict__ spec,
+                                                                      const cpx<double>* __restrict__ tw) {
+    extern __shared__ cpx<double> col[];   // one component of the column
+    const int n1 = p.n1, H = p.n2 / 2, k2 = blockIdx.x;
+    const long hn = (long)n1 * H;
+    const int nc = have_y ? 4 : 2, no = want2 ? 4 : 2;
+    constexpr int EM = 8;   // n1 <= 2048 = EM * DENSE_THREADS
+    cpx<double> X[4][EM];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int m = 0; m < EM; ++m) X[c][m] = {0, 0};
+        if (c >= nc) continue;
+        __syncthreads();   // the previous component's sums are done with LDS
+        for (int i = threadIdx.x; i < n1; i += DENSE_THREADS) col[i] = spec[c * hn + (long)i * H + k2];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EM; ++m) {
+            const int e = threadIdx.x + m * DENSE_THREADS;
+            if (e < n1) {
+                cpx<double> acc = {0, 0};
+                int q = 0;   // (i e) mod n1
+                for (int i = 0; i < n1; ++i) {
+                    acc = cadd(acc, cmul(col[i], tw[q]));
+                    q += e;
+                    if (q >= n1) q -= n1;
+                }
+                X[c][m] = acc;
+            }
+        }
+    }
+    const double scale = 1.0 / ((double)n1 * (double)p.n2);
+#pragma unroll
+    for (int m = 0; m < EM; ++m) {
+        const int e = threadIdx.x + m * DENSE_THREADS;
+        if (e < n1) {
+            const double k1 = (double)(e < n1 / 2 ? e : (e == n1 / 2 ? 0 : e - n1));
+            cpx<double> o0, o1, q0, q1;
+            spec_multiplier(p, mode, k1, (double)k2, X[0][m], X[1][m], X[2][m], X[3][m], o0, o1, q0, q1);
+            const double sc = (e == n1 / 2) ? 0.0 : scale;   // Nyquist row of x1: projected out
+            X[0][m] = {o0.x * sc, o0.y * sc};
+            X[1][m] = {o1.x * sc, o1.y * sc};
+            X[2][m] = {q0.x * sc, q0.y * sc};
+            X[3][m] = {q1.x * sc, q1.y * sc};
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c >= no) continue;
+        __syncthreads();   // LDS free again
+#pragma unroll
+        for (int m = 0; m < EM; ++m) {
+            const int e = threadIdx.x + m * DENSE_THREADS;
+            if (e < n1) col[e] = X[c][m];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n1; i += DENSE_THREADS) {   // inverse DFT: conj(W)
+            cpx<double> acc = {0, 0};
+            int q = 0;
+            for (int e = 0; e < n1; ++e) {
+                acc = cadd(acc, ctw<double, true>(col[e], tw[q]));
+                q += i;
+                if (q >= n1) q -= n1;
+            }
+            spec[c * hn + (long)i * H + k2] = acc;
+        }
+    }
+}
+
+// half spectra -> real rows: x_j = Re Z_0 + 2 sum_{0<k<n2/2} Re(Z_k exp(2 pi i j k / n2)) (Nyquist 0)
+template <typename TO>
+__global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_inv_kernel(int n1, int n2,
+                                                                          const cpx<double>* __restrict__ spec,
+                                                                          double* __restrict__ out_d,
+                                                                          TO* __restrict__ out_t,
+                                                                          const cpx<double>* __restrict__ tw) {
+    extern __shared__ cpx<double> zr[];
+    const int i1 = blockIdx.x, comp = blockIdx.y, H = n2 / 2;
+    const cpx<double>* in = spec + (long)comp * n1 * H + (long)i1 * H;
+    for (int k = threadIdx.x; k < H; k += DENSE_THREADS) zr[k] = in[k];
+    __syncthreads();
+    const long off = (long)comp * n1 * n2 + (long)i1 * n2;
+    for (int j = threadIdx.x; j < n2; j += DENSE_THREADS) {
+        double acc = zr[0].x;
+        int q = j;   // (j k) mod n2 for k = 1
+        for (int k = 1; k < H; ++k) {
+            const cpx<double> w = tw[q];   // exp(-2 pi i j k / n2); Re(Z conj(w)) = Z.x w.x + Z.y w.y
+            acc += 2.0 * (zr[k].x * w.x + zr[k].y * w.y);
+            q += j;
+            if (q >= n2) q -= n2;
+        }
+        if (out_d) out_d[off + j] = acc;
+        if (out_t) out_t[off + j] = (TO)acc;
+    }
+}
+
+static inline bool pow2(int n) { return (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------------------------------------
 template <typename TI>
 hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1, cpx<double>* spec,
                                const cpx<double>* tw2, hipStream_t s) {
@@ -257,6 +403,11 @@ hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1
         hipLaunchKernelGGL((spec_row_fwd_kernel<TI, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf),      \
                            dim3(FPW * NN / 4), 0, s, p.n1, in0, in1, spec, tw2);                       \
         break;                                                                                         \
+    }
+    if (!pow2(p.n2)) {
+        hipLaunchKernelGGL((spec_dense_row_fwd_kernel<TI>), dim3(p.n1, nf, 2), dim3(DENSE_THREADS),
+                           p.n2 * sizeof(double), s, p.n1, p.n2, in0, in1, spec, tw2);
+        return hipGetLastError();
     }
     switch (p.n2) {
         ROWF(8) ROWF(16) ROWF(32) ROWF(64) ROWF(128) ROWF(256) ROWF(512) ROWF(1024) ROWF(2048)
@@ -276,6 +427,12 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
                            s, p, mode, (int)have_y, (int)want2, spec, tw1);                            \
         break;                                                                                         \
     }
+    if (!pow2(p.n1)) {
+        if (p.n1 > 8 * DENSE_THREADS) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(spec_dense_col_kernel, dim3(H), dim3(DENSE_THREADS), p.n1 * sizeof(cpx<double>), s, p,
+                           mode, (int)have_y, (int)want2, spec, tw1);
+        return hipGetLastError();
+    }
     switch (p.n1) {
         COLF(8) COLF(16) COLF(32) COLF(64) COLF(128) COLF(256) COLF(512) COLF(1024) COLF(2048)
         default: return hipErrorInvalidValue;
@@ -294,6 +451,11 @@ hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>
         hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW),          \
                            dim3(FPW * NN / 4), 0, s, p.n1, sp, out_d, out_t, tw2);                     \
         break;                                                                                         \
+    }
+    if (!pow2(p.n2)) {
+        hipLaunchKernelGGL((spec_dense_row_inv_kernel<TO>), dim3(p.n1, 2), dim3(DENSE_THREADS),
+                           (p.n2 / 2) * sizeof(cpx<double>), s, p.n1, p.n2, sp, out_d, out_t, tw2);
+        return hipGetLastError();
     }
     switch (p.n2) {
         ROWI(8) ROWI(16) ROWI(32) ROWI(64) ROWI(128) ROWI(256) ROWI(512) ROWI(1024) ROWI(2048)

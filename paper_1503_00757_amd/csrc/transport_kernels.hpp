@@ -362,6 +362,74 @@ __global__ __launch_bounds__(G * N / E) void stage_col_kernel(StageArgs<T> a) {
     clk_end(a.clk);
 }
 
+// Axis lengths that are not powers of two: the derivative along the axis is the product with the
+// circulant spectral differentiation matrix, d_e = sum_j c[(e - j) mod n] f_j, where c is the inverse
+// DFT of i k~ / n (the operator of the transform pair above, Nyquist wavenumber zeroed).  One row pair
+// (column pair) per block; the complex-packed line is staged in LDS, and the epilogue operands are read
+// again after the sum instead of being held in registers.  O(n^2) per line.
+constexpr int DENSE_STAGE_THREADS = 256;
+
+template <typename T, int OP>
+__global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_row_kernel(StageArgs<T> a) {
+    extern __shared__ unsigned char dsm[];
+    cpx<T>* f = reinterpret_cast<cpx<T>*>(dsm);
+    const int N = a.n2;
+    const long row0 = (long)(2 * blockIdx.x) * N, row1 = row0 + N;
+    clk_start(a.clk);
+    for (int e = threadIdx.x; e < N; e += DENSE_STAGE_THREADS) {
+        Rp<T> q0, q1;
+        const T p0 = row_load<T, OP>(a, row0 + e, q0);
+        const T p1 = row_load<T, OP>(a, row1 + e, q1);
+        f[e] = {p0, p1};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < N; e += DENSE_STAGE_THREADS) {
+        T dx = 0, dy = 0;
+        int m = e;   // (e - j) mod N
+        for (int j = 0; j < N; ++j) {
+            const T c = a.dc2[m];
+            dx += c * f[j].x;
+            dy += c * f[j].y;
+            m = m == 0 ? N - 1 : m - 1;
+        }
+        Rp<T> q0, q1;
+        row_load<T, OP>(a, row0 + e, q0);
+        row_load<T, OP>(a, row1 + e, q1);
+        row_store<T, OP>(a, row0 + e, dx, q0);
+        row_store<T, OP>(a, row1 + e, dy, q1);
+    }
+    clk_end(a.clk);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_col_kernel(StageArgs<T> a) {
+    extern __shared__ unsigned char dsm[];
+    cpx<T>* f = reinterpret_cast<cpx<T>*>(dsm);
+    const int N = a.n1;
+    const long c = 2 * (long)blockIdx.x, n2 = a.n2;
+    clk_start(a.clk);
+    for (int r = threadIdx.x; r < N; r += DENSE_STAGE_THREADS) {
+        Cp<T> q0, q1;
+        f[r] = col_load2<T, OP>(a, (long)r * n2 + c, q0, q1);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < N; r += DENSE_STAGE_THREADS) {
+        T dx = 0, dy = 0;
+        int m = r;
+        for (int j = 0; j < N; ++j) {
+            const T cc = a.dc1[m];
+            dx += cc * f[j].x;
+            dy += cc * f[j].y;
+            m = m == 0 ? N - 1 : m - 1;
+        }
+        Cp<T> q0, q1;
+        const long idx = (long)r * n2 + c;
+        col_load2<T, OP>(a, idx, q0, q1);
+        col_store2<T, OP>(a, idx, dx, dy, q0, q1);
+    }
+    clk_end(a.clk);
+}
+
 // Pointwise helpers of the state solve and the trapezoid end point.
 template <typename T>
 __global__ void finalize_state_kernel(long nn, const double* __restrict__ Q, const double* __restrict__ C,
@@ -406,10 +474,15 @@ constexpr bool fused_ok() {
 // A launch; with timing events it goes through hipExtLaunchKernelGGL, whose events are stamped by
 // the dispatch itself (the interval a profiler reports for the kernel).
 template <typename K, typename... Args>
+static inline void launch_ks(K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1, Args... args) {
+    if (t0 || t1) hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t0, t1, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
+template <typename K, typename... Args>
 static inline void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t t0, hipEvent_t t1,
                             Args... args) {
-    if (t0 || t1) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t0, t1, 0, args...);
-    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+    launch_ks(kernel, grid, block, 0, s, t0, t1, args...);
 }
 
 template <typename T, int N, int OP, int ER, int EC, int BS>
@@ -490,8 +563,24 @@ static hipError_t launch_axis(const StageArgs<T>& a, hipStream_t s, hipEvent_t t
 }
 
 template <typename T, int OP>
+static hipError_t launch_dense_axis(int axis, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (axis == 2) {
+        if (!a.dc2) return hipErrorInvalidValue;
+        launch_ks(stage_dense_row_kernel<T, OP>, dim3(a.n1 / 2), dim3(DENSE_STAGE_THREADS), a.n2 * sizeof(cpx<T>), s,
+                  t0, t1, a);
+    } else {
+        if (!a.dc1) return hipErrorInvalidValue;
+        launch_ks(stage_dense_col_kernel<T, OP>, dim3(a.n2 / 2), dim3(DENSE_STAGE_THREADS), a.n1 * sizeof(cpx<T>), s,
+                  t0, t1, a);
+    }
+    return hipGetLastError();
+}
+
+constexpr bool is_pow2_len(int n) { return (n & (n - 1)) == 0; }
+
+template <typename T, int OP>
 hipError_t launch_stage_op(int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    if (a.n1 == a.n2) {
+    if (a.n1 == a.n2 && is_pow2_len(a.n1)) {
         switch (a.n1) {
             case 8: return launch_square<T, 8, OP>(var, a, s, t0, t1);
             case 16: return launch_square<T, 16, OP>(var, a, s, t0, t1);
@@ -507,11 +596,12 @@ hipError_t launch_stage_op(int var, const StageArgs<T>& a, hipStream_t s, hipEve
     }
     // independent parts: two launches in stream order (a timed stage spans both; timing slots of the
     // column launch follow the at most n1/2 row blocks)
-    hipError_t e = launch_axis<T, OP, 2>(a, s, t0, nullptr);
+    hipError_t e = is_pow2_len(a.n2) ? launch_axis<T, OP, 2>(a, s, t0, nullptr)
+                                     : launch_dense_axis<T, OP>(2, a, s, t0, nullptr);
     if (e != hipSuccess) return e;
     StageArgs<T> ac = a;
     if (ac.clk) ac.clk += 2 * (a.n1 / 2);
-    return launch_axis<T, OP, 1>(ac, s, nullptr, t1);
+    return is_pow2_len(a.n1) ? launch_axis<T, OP, 1>(ac, s, nullptr, t1) : launch_dense_axis<T, OP>(1, ac, s, nullptr, t1);
 }
 
 }  // namespace regnk

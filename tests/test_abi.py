@@ -55,7 +55,7 @@ def test_workspace_bytes_scales_with_grid_and_steps():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(n1=60), dict(n2=4), dict(n1=4096), dict(nt=0), dict(beta_v=0.0), dict(beta_v=-1.0),
+    dict(n1=61), dict(n2=4), dict(n1=4096), dict(n2=2050), dict(nt=0), dict(beta_v=0.0), dict(beta_v=-1.0),
     dict(constraint="mass_source", beta_w=0.0), dict(constraint="divfree", beta_w=1e-3),
 ])
 def test_invalid_parameters_are_rejected(kw):
@@ -126,7 +126,7 @@ def test_hessian_mode_checked_and_full_newton_workspace():
 def test_deformation_workspace_and_null_checks():
     assert R.reg_deformation_workspace_bytes(make_params(64, 32, 4)) == 37 * 64 * 32 * 8
     with pytest.raises(R.RegError):
-        R.reg_deformation_workspace_bytes(make_params(64, 30, 4))
+        R.reg_deformation_workspace_bytes(make_params(64, 31, 4))
     with pytest.raises(R.RegError) as e:
         R.reg_deformation(None, 256, 256, 1 << 20, None, None, None)
     assert e.value.status == -1
@@ -144,3 +144,9 @@ def test_shear_control_parameters_checked():
     p.stokes_nu = 1.0                      # only meaningful for the shear-control model
     with pytest.raises(R.RegError):
         R.reg_workspace_bytes(p)
+
+
+def test_even_grids_that_are_not_powers_of_two_are_accepted():
+    """The paper's 128 x 150 slice (and 96^2 = 2^5 3 squared) take the direct-sum transforms."""
+    for n1, n2 in ((128, 150), (96, 96), (150, 128)):
+        assert R.reg_workspace_bytes(make_params(n1, n2, 4)) > 0

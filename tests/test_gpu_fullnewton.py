@@ -20,6 +20,7 @@ MS_64 = Case(32, 128, 5, "H2", "mass_source", 1e-3, 1e-4, "fp64", "dto", 1)
 UN_64 = Case(64, 64, 4, "H2", "none", 1e-3, 0.0, "fp64", seed=3)
 C1_32 = Case(64, 64, 4, "H1", "divfree", 1e-2, 0.0, "fp32", config=1)
 C2 = Case(256, 256, 16, "H2", "mass_source", 1e-3, 1e-4, "fp32", config=2)
+NP2 = Case(150, 96, 4, "H2", "none", 1e-3, 0.0, "fp64", seed=24)     # not powers of two
 
 
 def oracle_full(case):
@@ -30,7 +31,7 @@ def oracle_full(case):
     return g, p, lin, reduced.hessian_matvec_full(g, p, lin, vt), reduced.hessian_matvec(g, p, lin, vt)
 
 
-@pytest.mark.parametrize("case", [C1_64, MS_64, UN_64, C1_32, C2], ids=lambda c: f"{c.n1}x{c.n2}_{c.constraint}_{c.precision}")
+@pytest.mark.parametrize("case", [C1_64, MS_64, UN_64, C1_32, C2, NP2], ids=lambda c: f"{c.n1}x{c.n2}_{c.constraint}_{c.precision}")
 def test_full_newton_matvec_parity(case):
     print(f"[case] full-Newton matvec {case}", flush=True)
     mT, mR, vlin, vt, _ = inputs(case)

@@ -18,6 +18,8 @@ C1_32 = Case(64, 64, 4, "H1", "divfree", 1e-2, 0.0, "fp32", config=1)
 MS_64 = Case(32, 128, 5, "H2", "mass_source", 1e-3, 1e-4, "fp64", "dto", 1)
 C2 = Case(256, 256, 16, "H2", "mass_source", 1e-3, 1e-4, "fp32", config=2)
 C3 = Case(1024, 1024, 32, "H1", "divfree", 1e-4, 0.0, "fp32", config=3)
+NP2_64 = Case(150, 96, 4, "H2", "mass_source", 1e-3, 1e-4, "fp64", seed=21)     # not powers of two
+NP2_32 = Case(96, 150, 4, "H1", "divfree", 1e-2, 0.0, "fp32", seed=22)
 
 
 @pytest.mark.parametrize("case,tol", [(C1_64, 1e-10), (MS_64, 1e-9), (C1_32, 1e-5)])
@@ -48,7 +50,8 @@ def test_pcg_fixed_iterations_parity(case, tol):
         P.close()
 
 
-@pytest.mark.parametrize("case,newton,pcg,tol", [(C1_64, 5, 10, 1e-10), (MS_64, 3, 6, 1e-9), (C2, 3, 8, 1e-4)])
+@pytest.mark.parametrize("case,newton,pcg,tol", [(C1_64, 5, 10, 1e-10), (MS_64, 3, 6, 1e-9), (C2, 3, 8, 1e-4),
+                                                  (NP2_64, 3, 6, 1e-9), (NP2_32, 3, 6, 1e-4)])
 def test_solve_fixed_schedule_parity(case, newton, pcg, tol):
     print(f"[case] solve {case}", flush=True)
     mT, mR, *_ = inputs(case)

@@ -14,9 +14,11 @@ ST_DF = Case(64, 64, 4, "stokes", "divfree", 1e-2, 0.0, "fp64", seed=5, nu=1.7, 
 ST_UN = Case(64, 64, 4, "stokes", "none", 1e-2, 0.0, "fp64", seed=6, nu=0.6, stokes_eps=1e-4)
 ST_32 = Case(64, 64, 4, "stokes", "divfree", 1e-2, 0.0, "fp32", seed=5, nu=1.7, stokes_eps=1e-4)
 ST_NS = Case(32, 128, 5, "stokes", "none", 1e-2, 0.0, "fp64", seed=7, nu=2.5, stokes_eps=1e-4)
+ST_NP2 = Case(80, 96, 4, "stokes", "divfree", 1e-2, 0.0, "fp64", seed=8, nu=1.7, stokes_eps=1e-4)
 
 
-@pytest.mark.parametrize("case", [ST_DF, ST_UN, ST_32, ST_NS], ids=["divfree_nu1.7", "none_nu0.6", "fp32", "32x128"])
+@pytest.mark.parametrize("case", [ST_DF, ST_UN, ST_32, ST_NS, ST_NP2],
+                         ids=["divfree_nu1.7", "none_nu0.6", "fp32", "32x128", "80x96"])
 def test_shear_control_gradient_objective_matvec(case):
     print(f"[case] stokes {case}", flush=True)
     mT, mR, vlin, vt, vtr = inputs(case)
