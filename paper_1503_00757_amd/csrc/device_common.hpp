@@ -46,6 +46,15 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
 // LDS index padding: one pad slot every 16 complex entries breaks the power-of-two strides of the
 // Stockham scatter.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).  Column tiles that share
+// a 128-byte line go to blocks on the same XCD (same L2): tile for block b of nb, `group` tiles per
+// line (identity unless nb is a multiple of 8 * group).
+__device__ __forceinline__ int xcd_tile(int b, int nb, int group) {
+    if (group <= 1 || (nb % (8 * group)) != 0) return b;
+    const int x = b & 7, l = b >> 3;
+    return group * (x + 8 * (l / group)) + (l % group);
+}
+
 template <int N>
 struct LdsSize {
     static constexpr int value = N + (N >> 4);

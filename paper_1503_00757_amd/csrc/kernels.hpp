@@ -99,6 +99,14 @@ template <typename TO>
 hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>* spec, double* out_d,
                                TO* out_t, const cpx<double>* tw2, hipStream_t s);
 
+// Nyquist projection of a real vector field in real space (every mode with k1 = n1/2 or k2 = n2/2
+// removed): out_d (double, nullable), out_t (TO, nullable); `in` may equal out_d.  scratch: at
+// least nyquist_scratch_doubles(n1, n2) doubles.
+template <typename TO>
+hipError_t launch_nyquist_project(int n1, int n2, const double* in, double* out_d, TO* out_t, double* scratch,
+                                  hipStream_t s);
+size_t nyquist_scratch_doubles(int n1, int n2);
+
 // ---- FP64 reductions and vector updates -------------------------------------------------------
 constexpr int RED_BLOCKS = 512;
 constexpr int RED_THREADS = 256;

@@ -444,12 +444,11 @@ reg_status spec_inv(reg_problem* P, int field, double* out_d, TO* out_t) {
     return REG_OK;
 }
 
-// Nyquist projection of a caller vector field: out_d (double, nullable), out_t (T, nullable)
+// Nyquist projection of a caller vector field: out_d (double, nullable), out_t (T, nullable).  In
+// real space (alternating row and column sums); the spectral buffer serves as scratch.
 template <typename T>
 reg_status project(reg_problem* P, const double* in, double* out_d, T* out_t) {
-    CKS(spec_fwd<double>(P, 0, in));
-    CKS(spec_col(P, SPEC_PROJ, false, false));
-    CKS(spec_inv<T>(P, 0, out_d, out_t));
+    CK(launch_nyquist_project<T>(P->n1, P->n2, in, out_d, out_t, reinterpret_cast<double*>(P->spec()), P->stream));
     return REG_OK;
 }
 
@@ -603,11 +602,12 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
 }
 
 // ---- GN Hessian matvec on a projected FP64 input ------------------------------------------------
+// converted: the caller already wrote vt64 in T to tv.vtT().
 template <typename T>
-reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kout) {
+reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kout, bool converted = false) {
     TV<T> tv{P};
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
-    CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
+    if (!converted) CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
     Pair mt;
     const bool full = P->p.hessian == REG_HESS_FULL;
     CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), &mt, full));
@@ -663,6 +663,7 @@ hipGraphExec_t capture_graph(reg_problem* P, F enqueue) {
     return ok ? exec : nullptr;
 }
 
+// (reg_hessian_matvec only: vt64 comes from the projection, which also wrote its T copy.)
 // The matvec is a fixed chain of ~12 n_t + 10 kernels whose arguments depend only on workspace
 // pointers, so it is captured once into a HIP graph (on a private stream) and replayed on the
 // problem's stream; this removes the host launch cost per pass.  Falls back to direct launches if
@@ -675,7 +676,7 @@ reg_status matvec_run(reg_problem* P, const double* vt64, double* out, double* k
         for (auto& g : P->graph)
             if (g.exec && g.in == vt64 && g.out == out && g.kout == kout) hit = &g;
         if (!hit) {
-            hipGraphExec_t exec = capture_graph(P, [&]() { return matvec_t<T>(P, vt64, out, kout); });
+            hipGraphExec_t exec = capture_graph(P, [&]() { return matvec_t<T>(P, vt64, out, kout, true); });
             if (exec) {
                 reg_problem::MvGraph& slot = P->graph[P->graph_next];
                 if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
@@ -693,7 +694,7 @@ reg_status matvec_run(reg_problem* P, const double* vt64, double* out, double* k
             return REG_OK;
         }
     }
-    return matvec_t<T>(P, vt64, out, kout);
+    return matvec_t<T>(P, vt64, out, kout, true);
 }
 
 reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
@@ -1546,10 +1547,10 @@ reg_status reg_hessian_matvec(reg_problem* h, const double* vtilde, double* Hv) 
     if (!h->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
     double* vt64 = h->at<double>(h->o.vt64);
     if (h->f64) {
-        CKS(project<double>(h, vtilde, vt64, (double*)nullptr));
+        CKS(project<double>(h, vtilde, vt64, TV<double>{h}.vtT()));
         return matvec_run<double>(h, vt64, Hv, nullptr);
     }
-    CKS(project<float>(h, vtilde, vt64, (float*)nullptr));
+    CKS(project<float>(h, vtilde, vt64, TV<float>{h}.vtT()));
     return matvec_run<float>(h, vt64, Hv, nullptr);
 }
 

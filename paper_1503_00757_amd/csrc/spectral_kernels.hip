@@ -17,6 +17,8 @@
 //   K^{-1} = I + c'(k) k k^T/|k|^2, c' = 1/(M^ - 1)                   (mass source only)
 //   P^ = beta_v A^, or beta_v where A^ = 0                          App. E.2
 // SPEC_LR returns the admissible part of a direction and K^{-1} P^ of it (low-rank correction).
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -25,7 +27,7 @@ namespace regnk {
 template <int N>
 constexpr int spec_fpw() { return (N / 4) >= 64 ? 1 : 64 / (N / 4); }
 template <int N>
-constexpr int spec_nf() { return (N / 4) >= 128 ? 1 : ((N / 4) >= 32 ? 2 : 128 / (N / 4)); }
+constexpr int spec_nf() { return (N / 4) >= 32 ? 2 : 128 / (N / 4); }
 
 // ---------------------------------------------------------------------------------------------
 template <typename TI, int N, int FPW>
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
     __shared__ cpx<double> lds[NF][2][L];
     const int f = threadIdx.x % NF, t = threadIdx.x / NF;
     const int H = p.n2 / 2;
-    const int k2 = blockIdx.x * NF + f;
+    constexpr int GROUP = 16 * NF >= 128 ? 1 : 128 / (16 * NF);   // column tiles per 128-byte line
+    const int k2 = xcd_tile(blockIdx.x, gridDim.x, GROUP) * NF + f;
     const bool valid = k2 < H;
     const long hn = (long)N * H;
     const long col = valid ? k2 : 0;
@@ -465,6 +468,107 @@ hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------------
+// Nyquist projection in real space.  The modes k2 = n2/2 of row i1 and k1 = n1/2 of column i2 are
+// the alternating sums a(i1) = (1/n2) sum_i2 (-1)^i2 v and b(i2) = (1/n1) sum_i1 (-1)^i1 v, and the
+// corner mode c = (1/n1) sum_i1 (-1)^i1 a(i1) is counted in both, so the projection (every mode
+// with k1 = n1/2 or k2 = n2/2 removed) is
+//     v - (-1)^i2 a(i1) - (-1)^i1 b(i2) + (-1)^(i1 + i2) c.
+// Three passes over the field instead of three spectral passes; fixed summation order.
+constexpr int NYQ_THREADS = 256;
+constexpr int NYQ_ROWS = 8;   // rows per block of the first pass
+
+// pass 1: a(i1) for the block's rows, and the block's partial column sums colp[comp][blk][i2]
+__global__ __launch_bounds__(NYQ_THREADS) void nyq_rows_kernel(int n1, int n2, const double* __restrict__ in,
+                                                               double* __restrict__ a, double* __restrict__ colp) {
+    __shared__ double sh[NYQ_THREADS / 64];
+    const int blk = blockIdx.x, comp = blockIdx.y, nbr = gridDim.x;
+    const int r0 = blk * NYQ_ROWS, nr = min(NYQ_ROWS, n1 - r0);
+    const double* v = in + (long)comp * n1 * n2 + (long)r0 * n2;
+    double racc[NYQ_ROWS];
+#pragma unroll
+    for (int r = 0; r < NYQ_ROWS; ++r) racc[r] = 0.0;
+    for (int j = threadIdx.x; j < n2; j += NYQ_THREADS) {
+        const double sj = (j & 1) ? -1.0 : 1.0;
+        double col = 0.0;
+#pragma unroll
+        for (int r = 0; r < NYQ_ROWS; ++r) {
+            if (r < nr) {
+                const double x = v[(long)r * n2 + j];
+                col += ((r0 + r) & 1) ? -x : x;
+                racc[r] += sj * x;
+            }
+        }
+        colp[((long)comp * nbr + blk) * n2 + j] = col;
+    }
+#pragma unroll
+    for (int r = 0; r < NYQ_ROWS; ++r) {
+        const double t = block_sum<NYQ_THREADS>(racc[r], sh);
+        if (threadIdx.x == 0 && r < nr) a[(long)comp * n1 + r0 + r] = t / n2;
+    }
+}
+
+// pass 2: b(i2) from the partial sums; block `gridDim.x - 1` computes c
+__global__ __launch_bounds__(NYQ_THREADS) void nyq_cols_kernel(int n1, int n2, int nbr, const double* __restrict__ a,
+                                                               const double* __restrict__ colp, double* __restrict__ b,
+                                                               double* __restrict__ c) {
+    __shared__ double sh[NYQ_THREADS / 64];
+    const int comp = blockIdx.y;
+    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < n1; i += NYQ_THREADS) acc += (i & 1) ? -a[(long)comp * n1 + i] : a[(long)comp * n1 + i];
+        const double t = block_sum<NYQ_THREADS>(acc, sh);
+        if (threadIdx.x == 0) c[comp] = t / n1;
+        return;
+    }
+    const int j = blockIdx.x * NYQ_THREADS + threadIdx.x;
+    if (j >= n2) return;
+    double acc = 0.0;
+    for (int k = 0; k < nbr; ++k) acc += colp[((long)comp * nbr + k) * n2 + j];
+    b[(long)comp * n2 + j] = acc / n1;
+}
+
+// pass 3: the projected field
+template <typename TO>
+__global__ __launch_bounds__(NYQ_THREADS) void nyq_apply_kernel(int n1, int n2, const double* __restrict__ in,
+                                                                const double* __restrict__ a,
+                                                                const double* __restrict__ b,
+                                                                const double* __restrict__ c, double* __restrict__ out_d,
+                                                                TO* __restrict__ out_t) {
+    const long nn = (long)n1 * n2;
+    for (long idx = (long)blockIdx.x * NYQ_THREADS + threadIdx.x; idx < 2 * nn; idx += (long)gridDim.x * NYQ_THREADS) {
+        const int comp = idx >= nn;
+        const long e = idx - comp * nn;
+        const int i = (int)(e / n2), j = (int)(e - (long)i * n2);
+        const double si = (i & 1) ? -1.0 : 1.0, sj = (j & 1) ? -1.0 : 1.0;
+        const double y = in[idx] - sj * a[(long)comp * n1 + i] - si * b[(long)comp * n2 + j] + si * sj * c[comp];
+        if (out_d) out_d[idx] = y;
+        if (out_t) out_t[idx] = (TO)y;
+    }
+}
+
+template <typename TO>
+hipError_t launch_nyquist_project(int n1, int n2, const double* in, double* out_d, TO* out_t, double* scratch,
+                                  hipStream_t s) {
+    const int nbr = (n1 + NYQ_ROWS - 1) / NYQ_ROWS;
+    double* a = scratch;
+    double* b = a + 2 * n1;
+    double* c = b + 2 * n2;
+    double* colp = c + 2;
+    hipLaunchKernelGGL(nyq_rows_kernel, dim3(nbr, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, a, colp);
+    hipLaunchKernelGGL(nyq_cols_kernel, dim3((n2 + NYQ_THREADS - 1) / NYQ_THREADS + 1, 2), dim3(NYQ_THREADS), 0, s,
+                       n1, n2, nbr, a, colp, b, c);
+    const long work = 2L * n1 * n2;
+    const long blocks = std::min<long>((work + NYQ_THREADS - 1) / NYQ_THREADS, 4096);
+    hipLaunchKernelGGL((nyq_apply_kernel<TO>), dim3(blocks), dim3(NYQ_THREADS), 0, s, n1, n2, in, a, b, c, out_d,
+                       out_t);
+    return hipGetLastError();
+}
+
+size_t nyquist_scratch_doubles(int n1, int n2) {
+    return 2 * (size_t)n1 + 2 * (size_t)n2 + 2 + 2 * (size_t)((n1 + NYQ_ROWS - 1) / NYQ_ROWS) * n2;
+}
+
 template hipError_t launch_spec_row_fwd<float>(const SpecParams&, const float*, const float*, cpx<double>*,
                                                const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_fwd<double>(const SpecParams&, const double*, const double*,
@@ -473,5 +577,7 @@ template hipError_t launch_spec_row_inv<float>(const SpecParams&, int, const cpx
                                                const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_inv<double>(const SpecParams&, int, const cpx<double>*, double*,
                                                 double*, const cpx<double>*, hipStream_t);
+template hipError_t launch_nyquist_project<float>(int, int, const double*, double*, float*, double*, hipStream_t);
+template hipError_t launch_nyquist_project<double>(int, int, const double*, double*, double*, double*, hipStream_t);
 
 }  // namespace regnk

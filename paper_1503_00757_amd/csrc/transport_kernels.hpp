@@ -270,14 +270,6 @@ __device__ __forceinline__ void row_part(const StageArgs<T>& a, int rb, cpx<T>* 
     }
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8); column tiles that share
-// a 128-byte line are mapped to blocks on the same XCD (same L2).
-__device__ __forceinline__ int xcd_tile(int b, int nb, int group) {
-    if (group <= 1 || (nb % (8 * group)) != 0) return b;
-    const int x = b & 7, l = b >> 3;
-    return group * (x + 8 * (l / group)) + (l % group);
-}
-
 // Column part: a block owns TW = 2G adjacent columns (G transforms of length N = n1).
 template <typename T, int N, int E, int G, int OP>
 __device__ __forceinline__ void col_part(const StageArgs<T>& a, int cb, int ncb, cpx<T>* lds) {
