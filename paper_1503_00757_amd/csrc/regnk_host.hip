@@ -448,6 +448,8 @@ reg_status spec_inv(reg_problem* P, int field, double* out_d, TO* out_t) {
 // real space (alternating row and column sums); the spectral buffer serves as scratch.
 template <typename T>
 reg_status project(reg_problem* P, const double* in, double* out_d, T* out_t) {
+    if (nyquist_scratch_doubles(P->n1, P->n2) > 4 * (size_t)P->n1 * (P->n2 / 2) * 2)
+        return fail(REG_ENOMEM, "projection scratch exceeds the spectral buffer");
     CK(launch_nyquist_project<T>(P->n1, P->n2, in, out_d, out_t, reinterpret_cast<double*>(P->spec()), P->stream));
     return REG_OK;
 }

@@ -17,8 +17,6 @@
 //   K^{-1} = I + c'(k) k k^T/|k|^2, c' = 1/(M^ - 1)                   (mass source only)
 //   P^ = beta_v A^, or beta_v where A^ = 0                          App. E.2
 // SPEC_LR returns the admissible part of a direction and K^{-1} P^ of it (low-rank correction).
-#include <algorithm>
-
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -474,99 +472,134 @@ hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>
 // corner mode c = (1/n1) sum_i1 (-1)^i1 a(i1) is counted in both, so the projection (every mode
 // with k1 = n1/2 or k2 = n2/2 removed) is
 //     v - (-1)^i2 a(i1) - (-1)^i1 b(i2) + (-1)^(i1 + i2) c.
-// Three passes over the field instead of three spectral passes; fixed summation order.
+// Two reads and one write of the field; fixed summation order.
 constexpr int NYQ_THREADS = 256;
-constexpr int NYQ_ROWS = 8;   // rows per block of the first pass
+constexpr int NYQ_TR = 32, NYQ_TC = 64;   // tile of the first pass: 64 columns x 4 row groups of 8 rows
 
-// pass 1: a(i1) for the block's rows, and the block's partial column sums colp[comp][blk][i2]
-__global__ __launch_bounds__(NYQ_THREADS) void nyq_rows_kernel(int n1, int n2, const double* __restrict__ in,
-                                                               double* __restrict__ a, double* __restrict__ colp) {
-    __shared__ double sh[NYQ_THREADS / 64];
-    const int blk = blockIdx.x, comp = blockIdx.y, nbr = gridDim.x;
-    const int r0 = blk * NYQ_ROWS, nr = min(NYQ_ROWS, n1 - r0);
-    const double* v = in + (long)comp * n1 * n2 + (long)r0 * n2;
-    double racc[NYQ_ROWS];
+// pass 1, per 32 x 64 tile: partial alternating row sums rowp[comp][cb][i1] over the tile's columns,
+// partial alternating column sums colp[comp][rb][i2] over its rows, and the tile's corner sum
+// cpart[comp][rb][cb].  Every load is issued before the first use; the row sums go through LDS.
+__global__ __launch_bounds__(NYQ_THREADS) void nyq_tile_kernel(int n1, int n2, const double* __restrict__ in,
+                                                               double* __restrict__ rowp, double* __restrict__ colp,
+                                                               double* __restrict__ cpart) {
+    constexpr int RG = NYQ_THREADS / NYQ_TC, K = NYQ_TR / RG;   // 4 row groups of 8 rows
+    __shared__ double tile[NYQ_TR][NYQ_TC + 1];
+    __shared__ double csum[RG][NYQ_TC];
+    __shared__ double rsum[NYQ_TR];
+    const int cb = blockIdx.x, rb = blockIdx.y, comp = blockIdx.z, ncb = gridDim.x, nrb = gridDim.y;
+    const int tx = threadIdx.x % NYQ_TC, ty = threadIdx.x / NYQ_TC;
+    const int j = cb * NYQ_TC + tx;
+    const bool jv = j < n2;
+    const double* v = in + (long)comp * n1 * n2;
+    double x[K];
 #pragma unroll
-    for (int r = 0; r < NYQ_ROWS; ++r) racc[r] = 0.0;
-    for (int j = threadIdx.x; j < n2; j += NYQ_THREADS) {
-        const double sj = (j & 1) ? -1.0 : 1.0;
-        double col = 0.0;
-#pragma unroll
-        for (int r = 0; r < NYQ_ROWS; ++r) {
-            if (r < nr) {
-                const double x = v[(long)r * n2 + j];
-                col += ((r0 + r) & 1) ? -x : x;
-                racc[r] += sj * x;
-            }
-        }
-        colp[((long)comp * nbr + blk) * n2 + j] = col;
+    for (int k = 0; k < K; ++k) {   // clamped addresses: every load in bounds, masked below
+        const int i = rb * NYQ_TR + ty + RG * k;
+        x[k] = v[(long)(i < n1 ? i : 0) * n2 + (jv ? j : 0)];
     }
+    double col = 0.0;
 #pragma unroll
-    for (int r = 0; r < NYQ_ROWS; ++r) {
-        const double t = block_sum<NYQ_THREADS>(racc[r], sh);
-        if (threadIdx.x == 0 && r < nr) a[(long)comp * n1 + r0 + r] = t / n2;
+    for (int k = 0; k < K; ++k) {
+        const int i = rb * NYQ_TR + ty + RG * k;
+        const double y = (i < n1 && jv) ? x[k] : 0.0;
+        col += (i & 1) ? -y : y;
+        tile[ty + RG * k][tx] = (j & 1) ? -y : y;
+    }
+    csum[ty][tx] = col;
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NYQ_TC) {
+        if (jv) colp[((long)comp * nrb + rb) * n2 + j] = ((csum[0][t] + csum[1][t]) + csum[2][t]) + csum[3][t];
+    } else if (t < NYQ_TC + NYQ_TR) {
+        const int r = t - NYQ_TC, i = rb * NYQ_TR + r;
+        double acc = 0.0;
+        for (int c = 0; c < NYQ_TC; ++c) acc += tile[r][c];
+        rsum[r] = acc;
+        if (i < n1) rowp[((long)comp * ncb + cb) * n1 + i] = acc;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double acc = 0.0;
+        for (int r = 0; r < NYQ_TR; ++r) acc += ((rb * NYQ_TR + r) & 1) ? -rsum[r] : rsum[r];   // rows >= n1 hold 0
+        cpart[((long)comp * nrb + rb) * ncb + cb] = acc;
     }
 }
 
-// pass 2: b(i2) from the partial sums; block `gridDim.x - 1` computes c
-__global__ __launch_bounds__(NYQ_THREADS) void nyq_cols_kernel(int n1, int n2, int nbr, const double* __restrict__ a,
-                                                               const double* __restrict__ colp, double* __restrict__ b,
-                                                               double* __restrict__ c) {
+// pass 2: a(i1) and b(i2) from the partial sums and c from the corner sums (fixed order); the last
+// block computes c
+__global__ __launch_bounds__(NYQ_THREADS) void nyq_sums_kernel(int n1, int n2, int ncb, int nrb,
+                                                               const double* __restrict__ rowp,
+                                                               const double* __restrict__ colp,
+                                                               const double* __restrict__ cpart, double* __restrict__ a,
+                                                               double* __restrict__ b, double* __restrict__ c) {
     __shared__ double sh[NYQ_THREADS / 64];
     const int comp = blockIdx.y;
     if ((int)blockIdx.x == (int)gridDim.x - 1) {
+        const double* cp = cpart + (long)comp * nrb * ncb;
         double acc = 0.0;
-        for (int i = threadIdx.x; i < n1; i += NYQ_THREADS) acc += (i & 1) ? -a[(long)comp * n1 + i] : a[(long)comp * n1 + i];
+        for (int k = threadIdx.x; k < nrb * ncb; k += NYQ_THREADS) acc += cp[k];
         const double t = block_sum<NYQ_THREADS>(acc, sh);
-        if (threadIdx.x == 0) c[comp] = t / n1;
+        if (threadIdx.x == 0) c[comp] = t / ((double)n1 * (double)n2);
         return;
     }
-    const int j = blockIdx.x * NYQ_THREADS + threadIdx.x;
-    if (j >= n2) return;
-    double acc = 0.0;
-    for (int k = 0; k < nbr; ++k) acc += colp[((long)comp * nbr + k) * n2 + j];
-    b[(long)comp * n2 + j] = acc / n1;
+    const int t = blockIdx.x * NYQ_THREADS + threadIdx.x;
+    if (t < n1) {
+        const double* rp = rowp + (long)comp * ncb * n1;
+        double r = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < ncb; ++k) r += rp[(long)k * n1 + t];
+        a[(long)comp * n1 + t] = r / n2;
+    } else if (t < n1 + n2) {
+        const int j = t - n1;
+        const double* cp = colp + (long)comp * nrb * n2;
+        double r = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < nrb; ++k) r += cp[(long)k * n2 + j];
+        b[(long)comp * n2 + j] = r / n1;
+    }
 }
 
-// pass 3: the projected field
+// pass 3: the projected field, one row per block
 template <typename TO>
 __global__ __launch_bounds__(NYQ_THREADS) void nyq_apply_kernel(int n1, int n2, const double* __restrict__ in,
                                                                 const double* __restrict__ a,
                                                                 const double* __restrict__ b,
                                                                 const double* __restrict__ c, double* __restrict__ out_d,
                                                                 TO* __restrict__ out_t) {
-    const long nn = (long)n1 * n2;
-    for (long idx = (long)blockIdx.x * NYQ_THREADS + threadIdx.x; idx < 2 * nn; idx += (long)gridDim.x * NYQ_THREADS) {
-        const int comp = idx >= nn;
-        const long e = idx - comp * nn;
-        const int i = (int)(e / n2), j = (int)(e - (long)i * n2);
-        const double si = (i & 1) ? -1.0 : 1.0, sj = (j & 1) ? -1.0 : 1.0;
-        const double y = in[idx] - sj * a[(long)comp * n1 + i] - si * b[(long)comp * n2 + j] + si * sj * c[comp];
-        if (out_d) out_d[idx] = y;
-        if (out_t) out_t[idx] = (TO)y;
+    const int i = blockIdx.x, comp = blockIdx.y;
+    const double si = (i & 1) ? -1.0 : 1.0;
+    const double ai = a[(long)comp * n1 + i], ci = si * c[comp];
+    const double* bc = b + (long)comp * n2;
+    const long row = ((long)comp * n1 + i) * n2;
+    for (int j = threadIdx.x; j < n2; j += NYQ_THREADS) {
+        const double sj = (j & 1) ? -1.0 : 1.0;
+        const double y = in[row + j] - sj * ai - si * bc[j] + sj * ci;
+        if (out_d) out_d[row + j] = y;
+        if (out_t) out_t[row + j] = (TO)y;
     }
 }
 
 template <typename TO>
 hipError_t launch_nyquist_project(int n1, int n2, const double* in, double* out_d, TO* out_t, double* scratch,
                                   hipStream_t s) {
-    const int nbr = (n1 + NYQ_ROWS - 1) / NYQ_ROWS;
+    const int ncb = (n2 + NYQ_TC - 1) / NYQ_TC, nrb = (n1 + NYQ_TR - 1) / NYQ_TR;
     double* a = scratch;
     double* b = a + 2 * n1;
     double* c = b + 2 * n2;
-    double* colp = c + 2;
-    hipLaunchKernelGGL(nyq_rows_kernel, dim3(nbr, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, a, colp);
-    hipLaunchKernelGGL(nyq_cols_kernel, dim3((n2 + NYQ_THREADS - 1) / NYQ_THREADS + 1, 2), dim3(NYQ_THREADS), 0, s,
-                       n1, n2, nbr, a, colp, b, c);
-    const long work = 2L * n1 * n2;
-    const long blocks = std::min<long>((work + NYQ_THREADS - 1) / NYQ_THREADS, 4096);
-    hipLaunchKernelGGL((nyq_apply_kernel<TO>), dim3(blocks), dim3(NYQ_THREADS), 0, s, n1, n2, in, a, b, c, out_d,
+    double* rowp = c + 2;
+    double* colp = rowp + 2L * ncb * n1;
+    double* cpart = colp + 2L * nrb * n2;
+    hipLaunchKernelGGL(nyq_tile_kernel, dim3(ncb, nrb, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, rowp, colp, cpart);
+    hipLaunchKernelGGL(nyq_sums_kernel, dim3((n1 + n2 + NYQ_THREADS - 1) / NYQ_THREADS + 1, 2), dim3(NYQ_THREADS), 0,
+                       s, n1, n2, ncb, nrb, rowp, colp, cpart, a, b, c);
+    hipLaunchKernelGGL((nyq_apply_kernel<TO>), dim3(n1, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, a, b, c, out_d,
                        out_t);
     return hipGetLastError();
 }
 
 size_t nyquist_scratch_doubles(int n1, int n2) {
-    return 2 * (size_t)n1 + 2 * (size_t)n2 + 2 + 2 * (size_t)((n1 + NYQ_ROWS - 1) / NYQ_ROWS) * n2;
+    const size_t ncb = (n2 + NYQ_TC - 1) / NYQ_TC, nrb = (n1 + NYQ_TR - 1) / NYQ_TR;
+    return 2 * (size_t)n1 + 2 * (size_t)n2 + 2 + 2 * ncb * n1 + 2 * nrb * n2 + 2 * nrb * ncb;
 }
 
 template hipError_t launch_spec_row_fwd<float>(const SpecParams&, const float*, const float*, cpx<double>*,
