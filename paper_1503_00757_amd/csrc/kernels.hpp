@@ -69,6 +69,11 @@ hipError_t launch_finalize_state(long nn, const double* Q, const double* C, cons
 // B += w (Q + C) G (vector fields B, G)
 template <typename T>
 hipError_t launch_body_end(long nn, T w, const T* Q, const T* C, const T* G, T* B, hipStream_t s);
+// Last Gauss-Newton adjoint step of the exact-transpose quadrature (lam_0 not formed):
+// B = (first ? 0 : B) + w ((Q + C) G + X G2), keep (nullable) = Q + C
+template <typename T>
+hipError_t launch_body_last(long nn, T w, bool first, const T* Q, const T* C, const T* X, const T* G, const T* G2,
+                            T* B, T* keep, hipStream_t s);
 
 // ---- 2D spectral operators (FP64) -----------------------------------------------------------
 // SPEC_LR: first result = admissible part of x (Leray projection for w = 0, x otherwise), second
@@ -89,6 +94,11 @@ struct SpecParams {
 template <typename TI>
 hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1, cpx<double>* spec,
                                const cpx<double>* tw2, hipStream_t s);
+// The same with two input types (field 0 from in0, field 1 from in1); instantiated for
+// (double, float) and through launch_spec_row_fwd for equal types.
+template <typename TI0, typename TI1>
+hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* in1, cpx<double>* spec,
+                                const cpx<double>* tw2, hipStream_t s);
 // Column pass: forward FFT along x1 of the needed spectra, Fourier multiplier of `mode`, inverse
 // FFT; in place in spec (outputs: field 0 = first result, field 1 = second result if want2).
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
@@ -200,5 +210,8 @@ hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, cons
                              hipStream_t stream);
 // s = z + mu s (mu from scal)
 hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal, hipStream_t stream);
+// s = z + mu s (scal == nullptr: s = z) and its copy sT = (T) s for the next matvec
+template <typename T>
+hipError_t launch_pcg_dir_copy(long n, double* s, T* sT, const double* z, const double* scal, hipStream_t stream);
 
 }  // namespace regnk

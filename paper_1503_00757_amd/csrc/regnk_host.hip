@@ -383,6 +383,11 @@ reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB
             s2.GT = j > 0 ? tv.Gm(j) : nullptr;   // grad m~_0 = 0
             s2.GT2 = tv.Gm(P->nt + j);
         }
+        if (j == 0 && !paper && !vt && B) {   // lam_0 is not needed: body force only
+            CK(launch_body_last<T>(nn, s2.bw, first, s2.A, s2.Bf, s2.X, s2.G, s2.G2, B, keep ? s2.UOUT : nullptr,
+                                   P->stream));
+            return REG_OK;
+        }
         CKS(stage<T>(P, vt ? OP_A2F : OP_A2, s2));
         A = tv.F(nxt.r);
         Bf = tv.F(nxt.c);
@@ -584,13 +589,12 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
     }
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(8), (const T*)nullptr, false, tv.B(),
                             P->p.hessian == REG_HESS_FULL));
+    const double* x0 = v64;
     if (P->p.norm == REG_STOKES) {   // the regularisation term is formed in real space
         CKS(stokes_first(P, v64));
-        CKS(spec_fwd<double>(P, 0, stk(P, STK_R)));
-    } else {
-        CKS(spec_fwd<double>(P, 0, v64));
+        x0 = stk(P, STK_R);
     }
-    CKS(spec_fwd<T>(P, 1, tv.B()));
+    CK((launch_spec_row_fwd2<double, T>(P->sp, x0, tv.B(), P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream)));
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
     CKS(spec_col(P, SPEC_HESS, true, ms && kg));
     CKS(spec_inv<double>(P, 0, g, (double*)nullptr));
@@ -616,13 +620,13 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     // lam~(1) = -m~(1)
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(mt.r), tv.F(mt.c), true, tv.Bt(), false,
                             full ? (const T*)tv.vtT() : (const T*)nullptr));
+    const double* x0 = vt64;
     if (P->p.norm == REG_STOKES) {
         CKS(stokes_second(P, vt64));
-        CKS(spec_fwd<double>(P, 0, stk(P, STK_R)));
-    } else {
-        CKS(spec_fwd<double>(P, 0, vt64));
+        x0 = stk(P, STK_R);
     }
-    CKS(spec_fwd<T>(P, 1, tv.Bt()));
+    // both fields' row transforms in one launch
+    CK((launch_spec_row_fwd2<double, T>(P->sp, x0, tv.Bt(), P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream)));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
     CKS(spec_inv<double>(P, 0, out, (double*)nullptr));
     if (kout) CKS(spec_inv<double>(P, 1, kout, (double*)nullptr));
@@ -882,7 +886,7 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
     double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
     double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
     double* sc = P->scal();
-    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr));
+    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr, true));   // s in T: written with s
     {
         const double* a[1] = {s};
         const double* b[1] = {W ? kst : st};
@@ -897,7 +901,7 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
         CK(launch_dots<double>(2, a, b, n, P->partial(), sc + S_RR, P->stream));
     }
     CK(launch_pcg_scalar(PCG_MU, sc, P->stream));
-    CK(launch_pcg_dir(n, s, z, sc, P->stream));
+    CK(launch_pcg_dir_copy<T>(n, s, TV<T>{P}.vtT(), z, sc, P->stream));
     return REG_OK;
 }
 
@@ -931,7 +935,7 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     CK(hipMemcpyAsync(r, rhs, n * 8, hipMemcpyDeviceToDevice, P->stream));
     CK(launch_fill(n, 0.0, x, P->stream));
     CKS(precond_pcg(P, r, z, W ? kr : nullptr));
-    CK(hipMemcpyAsync(s, z, n * 8, hipMemcpyDeviceToDevice, P->stream));
+    CK(launch_pcg_dir_copy<T>(n, s, TV<T>{P}.vtT(), z, nullptr, P->stream));   // s = z
     {
         const double* a[2] = {W ? kr : r, r};
         const double* b[2] = {z, r};

@@ -28,9 +28,9 @@ template <int N>
 constexpr int spec_nf() { return (N / 4) >= 32 ? 2 : 128 / (N / 4); }
 
 // ---------------------------------------------------------------------------------------------
-template <typename TI, int N, int FPW>
-__global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const TI* __restrict__ in0,
-                                                                  const TI* __restrict__ in1,
+template <typename TI0, typename TI1, int N, int FPW>
+__global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const TI0* __restrict__ in0,
+                                                                  const TI1* __restrict__ in1,
                                                                   cpx<double>* __restrict__ spec,
                                                                   const cpx<double>* __restrict__ tw) {
     constexpr int Q = N / 4, H = N / 2;
@@ -40,14 +40,15 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const
     const int i1 = blockIdx.x * FPW + f;
     const bool valid = i1 < n1;
     const int field = blockIdx.y;
-    const TI* in = field ? in1 : in0;
     const long nn = (long)n1 * N;
     const long row = (long)(valid ? i1 : 0) * N;
     cpx<double> x[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int e = t + r * Q;
-        x[r] = valid ? cpx<double>{(double)in[row + e], (double)in[nn + row + e]} : cpx<double>{0.0, 0.0};
+        if (!valid) x[r] = cpx<double>{0.0, 0.0};
+        else if (field) x[r] = cpx<double>{(double)in1[row + e], (double)in1[nn + row + e]};
+        else x[r] = cpx<double>{(double)in0[row + e], (double)in0[nn + row + e]};
     }
     int buf = 0;
     fft4<double, N, false>(x, lds[f][0], lds[f][1], t, tw, buf);
@@ -160,38 +161,45 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
     const bool valid = k2 < H;
     const long hn = (long)N * H;
     const long col = valid ? k2 : 0;
+    // every load first (up to four spectra), then the transforms; results overwrite the inputs
     cpx<double> X0[4], X1[4], Y0[4], Y1[4];
-    int buf = 0;
-    auto load_fft = [&](int comp, cpx<double>(&x)[4]) {
+    auto load = [&](int comp, cpx<double>(&x)[4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long idx = comp * hn + (long)(t + r * Q) * H + col;
             x[r] = valid ? spec[idx] : cpx<double>{0.0, 0.0};
         }
-        fft4<double, N, false>(x, lds[f][0], lds[f][1], t, tw, buf);
     };
-    load_fft(0, X0);
-    load_fft(1, X1);
+    load(0, X0);
+    load(1, X1);
     if (have_y) {
-        load_fft(2, Y0);
-        load_fft(3, Y1);
+        load(2, Y0);
+        load(3, Y1);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Y0[r] = Y1[r] = cpx<double>{0.0, 0.0};
+    }
+    int buf = 0;
+    fft4<double, N, false>(X0, lds[f][0], lds[f][1], t, tw, buf);
+    fft4<double, N, false>(X1, lds[f][0], lds[f][1], t, tw, buf);
+    if (have_y) {
+        fft4<double, N, false>(Y0, lds[f][0], lds[f][1], t, tw, buf);
+        fft4<double, N, false>(Y1, lds[f][0], lds[f][1], t, tw, buf);
     }
     const double scale = 1.0 / ((double)N * (double)p.n2);
     const double k2d = (double)k2;
-    cpx<double> O0[4], O1[4], P0[4], P1[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int e = t + r * Q;
         const double k1 = (double)kwave<N>(e);
         const bool zero = (e == N / 2);   // Nyquist row of x1: projected out
         cpx<double> o0, o1, q0, q1;
-        spec_multiplier(p, mode, k1, k2d, X0[r], X1[r], have_y ? Y0[r] : cpx<double>{0, 0},
-                        have_y ? Y1[r] : cpx<double>{0, 0}, o0, o1, q0, q1);
+        spec_multiplier(p, mode, k1, k2d, X0[r], X1[r], Y0[r], Y1[r], o0, o1, q0, q1);
         const double sc = zero ? 0.0 : scale;
-        O0[r] = {o0.x * sc, o0.y * sc};
-        O1[r] = {o1.x * sc, o1.y * sc};
-        P0[r] = {q0.x * sc, q0.y * sc};
-        P1[r] = {q1.x * sc, q1.y * sc};
+        X0[r] = {o0.x * sc, o0.y * sc};
+        X1[r] = {o1.x * sc, o1.y * sc};
+        Y0[r] = {q0.x * sc, q0.y * sc};
+        Y1[r] = {q1.x * sc, q1.y * sc};
     }
     auto ifft_store = [&](int comp, cpx<double>(&x)[4]) {
         fft4<double, N, true>(x, lds[f][0], lds[f][1], t, tw, buf);
@@ -200,11 +208,11 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
             for (int r = 0; r < 4; ++r) spec[comp * hn + (long)(t + r * Q) * H + col] = x[r];
         }
     };
-    ifft_store(0, O0);
-    ifft_store(1, O1);
+    ifft_store(0, X0);
+    ifft_store(1, X1);
     if (want2) {
-        ifft_store(2, P0);
-        ifft_store(3, P1);
+        ifft_store(2, Y0);
+        ifft_store(3, Y1);
     }
 }
 
@@ -265,15 +273,15 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
 constexpr int DENSE_THREADS = 256;
 
 // rows -> half spectra: block (i1, field, comp) writes spec[2 field + comp][i1][k], k < n2/2
-template <typename TI>
-__global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_fwd_kernel(int n1, int n2, const TI* __restrict__ in0,
-                                                                          const TI* __restrict__ in1,
+template <typename TI0, typename TI1>
+__global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_fwd_kernel(int n1, int n2, const TI0* __restrict__ in0,
+                                                                          const TI1* __restrict__ in1,
                                                                           cpx<double>* __restrict__ spec,
                                                                           const cpx<double>* __restrict__ tw) {
     extern __shared__ double xr[];
     const int i1 = blockIdx.x, field = blockIdx.y, comp = blockIdx.z;
-    const TI* in = (field ? in1 : in0) + (long)comp * n1 * n2 + (long)i1 * n2;
-    for (int j = threadIdx.x; j < n2; j += DENSE_THREADS) xr[j] = (double)in[j];
+    const long off = (long)comp * n1 * n2 + (long)i1 * n2;
+    for (int j = threadIdx.x; j < n2; j += DENSE_THREADS) xr[j] = field ? (double)in1[off + j] : (double)in0[off + j];
     __syncthreads();
     const int H = n2 / 2;
     cpx<double>* out = spec + (long)(2 * field + comp) * n1 * H + (long)i1 * H;
@@ -394,19 +402,19 @@ __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_inv_kernel(int n
 static inline bool pow2(int n) { return (n & (n - 1)) == 0; }
 
 // ---------------------------------------------------------------------------------------------
-template <typename TI>
-hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1, cpx<double>* spec,
-                               const cpx<double>* tw2, hipStream_t s) {
+template <typename TI0, typename TI1>
+hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* in1, cpx<double>* spec,
+                                const cpx<double>* tw2, hipStream_t s) {
     const int nf = in1 ? 2 : 1;
 #define ROWF(NN)                                                                                       \
     case NN: {                                                                                         \
         constexpr int FPW = spec_fpw<NN>();                                                            \
-        hipLaunchKernelGGL((spec_row_fwd_kernel<TI, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf),      \
+        hipLaunchKernelGGL((spec_row_fwd_kernel<TI0, TI1, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf), \
                            dim3(FPW * NN / 4), 0, s, p.n1, in0, in1, spec, tw2);                       \
         break;                                                                                         \
     }
     if (!pow2(p.n2)) {
-        hipLaunchKernelGGL((spec_dense_row_fwd_kernel<TI>), dim3(p.n1, nf, 2), dim3(DENSE_THREADS),
+        hipLaunchKernelGGL((spec_dense_row_fwd_kernel<TI0, TI1>), dim3(p.n1, nf, 2), dim3(DENSE_THREADS),
                            p.n2 * sizeof(double), s, p.n1, p.n2, in0, in1, spec, tw2);
         return hipGetLastError();
     }
@@ -416,6 +424,12 @@ hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1
     }
 #undef ROWF
     return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1, cpx<double>* spec,
+                               const cpx<double>* tw2, hipStream_t s) {
+    return launch_spec_row_fwd2<TI, TI>(p, in0, in1, spec, tw2, s);
 }
 
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
@@ -606,6 +620,10 @@ template hipError_t launch_spec_row_fwd<float>(const SpecParams&, const float*, 
                                                const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_fwd<double>(const SpecParams&, const double*, const double*,
                                                 cpx<double>*, const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_fwd2<double, float>(const SpecParams&, const double*, const float*,
+                                                        cpx<double>*, const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_fwd2<double, double>(const SpecParams&, const double*, const double*,
+                                                         cpx<double>*, const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_inv<float>(const SpecParams&, int, const cpx<double>*, double*, float*,
                                                const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_inv<double>(const SpecParams&, int, const cpx<double>*, double*,

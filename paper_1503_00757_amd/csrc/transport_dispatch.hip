@@ -83,6 +83,18 @@ hipError_t launch_body_end(long nn, T w, const T* Q, const T* C, const T* G, T* 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_body_last(long nn, T w, bool first, const T* Q, const T* C, const T* X, const T* G, const T* G2,
+                            T* B, T* keep, hipStream_t s) {
+    hipLaunchKernelGGL((body_last_kernel<T>), dim3(pointwise_blocks(nn)), dim3(256), 0, s, nn, w, first, Q, C, X, G,
+                       G2, B, keep);
+    return hipGetLastError();
+}
+
+template hipError_t launch_body_last<float>(long, float, bool, const float*, const float*, const float*,
+                                            const float*, const float*, float*, float*, hipStream_t);
+template hipError_t launch_body_last<double>(long, double, bool, const double*, const double*, const double*,
+                                             const double*, const double*, double*, double*, hipStream_t);
 template hipError_t launch_finalize_state<float>(long, const double*, const double*, const double*, double*, float*,
                                                  hipStream_t);
 template hipError_t launch_finalize_state<double>(long, const double*, const double*, const double*, double*, double*,

@@ -442,6 +442,25 @@ __global__ void body_end_kernel(long nn, T w, const T* __restrict__ Q, const T* 
     }
 }
 
+// The exact-transpose body force of the last adjoint step (j = 0): lam_0 itself is not needed, so
+// stage 2 reduces to B (+)= w (lam*_0 G_0 + lam_1 G*_0) with lam*_0 = Q + C; `keep` (nullable)
+// receives lam*_0.  The arithmetic is the stage-2 epilogue's.
+template <typename T>
+__global__ void body_last_kernel(long nn, T w, bool first, const T* __restrict__ Q, const T* __restrict__ C,
+                                 const T* __restrict__ X, const T* __restrict__ G, const T* __restrict__ G2,
+                                 T* __restrict__ B, T* __restrict__ keep) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (long)gridDim.x * blockDim.x) {
+        T u = Q[i];
+        u += C[i];
+        const T x = X[i];
+        if (keep) keep[i] = u;
+        const T b0 = u * G[i] + x * G2[i], b1 = u * G[nn + i] + x * G2[nn + i];
+        const T o0 = first ? T(0) : B[i], o1 = first ? T(0) : B[nn + i];
+        B[i] = o0 + w * b0;
+        B[nn + i] = o1 + w * b1;
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Launch shapes.  Square FP32 grids of 64+ points: variant v = (ER, EC, BS) with ER/EC elements per
 // thread of the row/column transforms and BS threads per block (FPW = BS/(N/ER) row pairs and

@@ -184,6 +184,17 @@ __global__ void pcg_dir_kernel(long n, double* __restrict__ s, const double* __r
         s[i] = z[i] + mu * s[i];
 }
 
+template <typename T>
+__global__ void pcg_dir_copy_kernel(long n, double* __restrict__ s, T* __restrict__ sT, const double* __restrict__ z,
+                                    const double* __restrict__ sc) {
+    const double mu = sc ? sc[S_MU] : 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = sc ? z[i] + mu * s[i] : z[i];
+        s[i] = v;
+        sT[i] = (T)v;
+    }
+}
+
 hipError_t launch_pcg_scalar(int mode, double* scal, hipStream_t s) {
     hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(64), 0, s, mode, scal);
     return hipGetLastError();
@@ -197,6 +208,13 @@ hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal
     hipLaunchKernelGGL(pcg_dir_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, s, z, scal);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_pcg_dir_copy(long n, double* s, T* sT, const double* z, const double* scal, hipStream_t stream) {
+    hipLaunchKernelGGL((pcg_dir_copy_kernel<T>), dim3(grid_for(n)), dim3(256), 0, stream, n, s, sT, z, scal);
+    return hipGetLastError();
+}
+template hipError_t launch_pcg_dir_copy<float>(long, double*, float*, const double*, const double*, hipStream_t);
+template hipError_t launch_pcg_dir_copy<double>(long, double*, double*, const double*, const double*, hipStream_t);
 
 // ---- low-rank deflation correction -------------------------------------------------------------
 // valid slots, clamped to [0, cap] (cap <= LR_MAX) so that no kernel reads past the set
