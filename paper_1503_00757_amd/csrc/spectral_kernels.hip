@@ -216,6 +216,55 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
     }
 }
 
+// The same column pass with the four spectra in parallel: one column per block, thread group c
+// (N/4 threads) transforms spectrum c, the multiplier runs once per wavenumber (one per thread) on
+// the spectra exchanged through LDS, and group c inverse-transforms result c.  Four times the threads
+// of spec_col_kernel at a quarter of the registers each.
+template <int N>
+__global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mode, int have_y, int want2,
+                                                           cpx<double>* __restrict__ spec,
+                                                           const cpx<double>* __restrict__ tw) {
+    constexpr int Q = N / 4;
+    constexpr int L = LdsSize<N>::value;
+    __shared__ cpx<double> lds[4][2][L];
+    const int c = threadIdx.x / Q, t = threadIdx.x % Q;
+    const int H = p.n2 / 2;
+    const int k2 = xcd_tile(blockIdx.x, gridDim.x, 8);   // 8 columns of 16 bytes share a line
+    const long hn = (long)N * H;
+    cpx<double> x[4];
+    const bool in_c = c < 2 || have_y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = in_c ? spec[c * hn + (long)(t + r * Q) * H + k2] : cpx<double>{0.0, 0.0};
+    int buf = 0;
+    fft4<double, N, false>(x, lds[c][0], lds[c][1], t, tw, buf);
+    const int b = buf;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lds[c][b][lpad(t + r * Q)] = x[r];
+    __syncthreads();
+    {
+        const int e = threadIdx.x;   // one wavenumber per thread
+        const double k1 = (double)kwave<N>(e);
+        cpx<double> o0, o1, q0, q1;
+        spec_multiplier(p, mode, k1, (double)k2, lds[0][b][lpad(e)], lds[1][b][lpad(e)], lds[2][b][lpad(e)],
+                        lds[3][b][lpad(e)], o0, o1, q0, q1);
+        const double sc = (e == N / 2) ? 0.0 : 1.0 / ((double)N * (double)p.n2);   // Nyquist row projected out
+        __syncthreads();
+        lds[0][b][lpad(e)] = {o0.x * sc, o0.y * sc};
+        lds[1][b][lpad(e)] = {o1.x * sc, o1.y * sc};
+        lds[2][b][lpad(e)] = {q0.x * sc, q0.y * sc};
+        lds[3][b][lpad(e)] = {q1.x * sc, q1.y * sc};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = lds[c][b][lpad(t + r * Q)];
+    buf = b ^ 1;   // the inverse's first exchange must not overwrite the buffer just read
+    fft4<double, N, true>(x, lds[c][0], lds[c][1], t, tw, buf);
+    if (c < 2 || want2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) spec[c * hn + (long)(t + r * Q) * H + k2] = x[r];
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 template <typename TO, int N, int FPW>
 __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const cpx<double>* __restrict__ spec,
@@ -448,10 +497,16 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
                            mode, (int)have_y, (int)want2, spec, tw1);
         return hipGetLastError();
     }
+#define COLS(NN)                                                                                       \
+    case NN:                                                                                           \
+        hipLaunchKernelGGL((spec_col_split_kernel<NN>), dim3(H), dim3(NN), 0, s, p, mode, (int)have_y,   \
+                           (int)want2, spec, tw1);                                                     \
+        break;
     switch (p.n1) {
-        COLF(8) COLF(16) COLF(32) COLF(64) COLF(128) COLF(256) COLF(512) COLF(1024) COLF(2048)
+        COLF(8) COLF(16) COLF(32) COLS(64) COLS(128) COLS(256) COLS(512) COLF(1024) COLF(2048)
         default: return hipErrorInvalidValue;
     }
+#undef COLS
 #undef COLF
     return hipGetLastError();
 }
