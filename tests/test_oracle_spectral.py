@@ -142,3 +142,22 @@ def test_nyquist_projection_removes_only_nyquist():
     v = np.stack([ny + low, low])
     out = spectral.nyquist_project(g, v)
     assert np.abs(out - np.stack([low, low])).max() < 1e-14
+
+
+@pytest.mark.parametrize("n1,n2", [(8, 8), (10, 12), (96, 150), (64, 32)])
+def test_nyquist_projection_real_space_form(n1, n2):
+    """The device path removes the Nyquist modes in real space: with the alternating sums
+    a(i1) = mean over i2 of (-1)^i2 v, b(i2) = mean over i1 of (-1)^i1 v and the corner
+    c = mean of (-1)^(i1+i2) v, the projection is v - (-1)^i2 a - (-1)^i1 b + (-1)^(i1+i2) c.
+    Check that identity against the oracle's FFT form."""
+    g = Grid(n1, n2)
+    v = np.random.default_rng(n1 * n2).standard_normal((2, n1, n2))
+    s1 = (-1.0) ** np.arange(n1)[:, None]
+    s2 = (-1.0) ** np.arange(n2)[None, :]
+    out = np.empty_like(v)
+    for c in range(2):
+        a = (v[c] * s2).mean(axis=1, keepdims=True)
+        b = (v[c] * s1).mean(axis=0, keepdims=True)
+        cc = (v[c] * s1 * s2).mean()
+        out[c] = v[c] - s2 * a - s1 * b + s1 * s2 * cc
+    assert np.abs(out - spectral.nyquist_project(g, v)).max() < 1e-13
