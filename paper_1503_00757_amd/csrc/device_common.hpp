@@ -65,15 +65,17 @@ struct LdsSize {
 // must be carried from one call to the next so that consecutive exchanges always alternate buffers
 // (a buffer is only rewritten after the barrier of the exchange that used the other one).  Must be
 // reached by every thread of the block the same number of times (it contains __syncthreads).
-template <typename T, int N, bool INV>
-__device__ __forceinline__ void fft4(cpx<T> (&x)[4], cpx<T>* __restrict__ lds0,
-                                     cpx<T>* __restrict__ lds1, int t,
+// SINGLE: one buffer (lds1 unused); every exchange then waits at a barrier before it writes, so that
+// the previous exchange's reads are done (half the LDS, one more barrier per exchange).
+template <typename T, int N, bool INV, bool SINGLE = false>
+__device__ __forceinline__ void fft4(cpx<T> (&x)[4], cpx<T>* lds0, cpx<T>* lds1, int t,
                                      const cpx<T>* __restrict__ tw, int& buf) {
     constexpr int Q = N / 4;
     constexpr int LOG = ilog2(N);
     int Ns = 1;
     if constexpr (LOG & 1) {
-        cpx<T>* o = buf ? lds1 : lds0;
+        if constexpr (SINGLE) __syncthreads();
+        cpx<T>* o = (buf && !SINGLE) ? lds1 : lds0;
         cpx<T> a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
         cpx<T> b0 = cadd(x[1], x[3]), b1 = csub(x[1], x[3]);
         o[lpad(2 * t)] = a0;
@@ -102,7 +104,8 @@ __device__ __forceinline__ void fft4(cpx<T> (&x)[4], cpx<T>* __restrict__ lds0,
         if (Ns == Q) {
             x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
         } else {
-            cpx<T>* o = buf ? lds1 : lds0;
+            if constexpr (SINGLE) __syncthreads();
+            cpx<T>* o = (buf && !SINGLE) ? lds1 : lds0;
             const int base = (t - k) * 4 + k;
             o[lpad(base)] = y0;
             o[lpad(base + Ns)] = y1;

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const
                                                                   const cpx<double>* __restrict__ tw) {
     constexpr int Q = N / 4, H = N / 2;
     constexpr int L = LdsSize<N>::value;
-    __shared__ cpx<double> lds[FPW][2][L];
+    __shared__ cpx<double> lds[FPW][L];   // one buffer per transform: more resident blocks
     const int f = threadIdx.x / Q, t = threadIdx.x % Q;
     const int i1 = blockIdx.x * FPW + f;
     const bool valid = i1 < n1;
@@ -51,8 +51,9 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const
         else x[r] = cpx<double>{(double)in0[row + e], (double)in0[nn + row + e]};
     }
     int buf = 0;
-    fft4<double, N, false>(x, lds[f][0], lds[f][1], t, tw, buf);
-    cpx<double>* o = buf ? lds[f][1] : lds[f][0];
+    fft4<double, N, false, true>(x, lds[f], lds[f], t, tw, buf);
+    cpx<double>* o = lds[f];
+    __syncthreads();   // the transform's last exchange has been read
 #pragma unroll
     for (int r = 0; r < 4; ++r) o[lpad(t + r * Q)] = x[r];
     __syncthreads();
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
                                                                   const cpx<double>* __restrict__ tw) {
     constexpr int Q = N / 4, H = N / 2;
     constexpr int L = LdsSize<N>::value;
-    __shared__ cpx<double> lds[FPW][2][L];
+    __shared__ cpx<double> lds[FPW][L];   // one buffer per transform: more resident blocks
     const int f = threadIdx.x / Q, t = threadIdx.x % Q;
     const int i1 = blockIdx.x * FPW + f;
     const bool valid = i1 < n1;
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
         x[r] = z;
     }
     int buf = 0;
-    fft4<double, N, true>(x, lds[f][0], lds[f][1], t, tw, buf);
+    fft4<double, N, true, true>(x, lds[f], lds[f], t, tw, buf);
     if (!valid) return;
     const long nn = (long)n1 * N;
     const long row = (long)i1 * N;
