@@ -44,6 +44,23 @@ def test_batch_equals_individual_solves_and_oracle():
             P.close()
 
 
+def test_batch_with_grids_that_are_not_powers_of_two():
+    """Direct-sum axes (96, 48) next to an FFT grid in one batch: the same results as one at a time."""
+    from paper_1503_00757_amd import batch_solve
+    specs = [(96, 4, 5e-3), (64, 4, 1e-2), (48, 8, 1e-2)]
+    pairs = [make_pair(n, nt, b, 10 + i) for i, (n, nt, b) in enumerate(specs)]
+    try:
+        vs, stats = batch_solve([P for P, *_ in pairs], max_newton=10, gtol_rel=1e-2)
+        for (P, p, mT, mR), v, st in zip(pairs, vs, stats):
+            assert st["status"] == 0 and st["g_rel"] <= 1e-2
+            v1, st1 = P.solve(max_newton=10, gtol_rel=1e-2)
+            assert np.array_equal(host(v), host(v1))
+            assert st1["pcg_iters"] == st["pcg_iters"] and st1["newton_iters"] == st["newton_iters"]
+    finally:
+        for P, *_ in pairs:
+            P.close()
+
+
 def test_batch_rejects_duplicates_and_reports_failures():
     import paper_1503_00757_amd as R
     P, *_ = make_pair(32, 4, 1e-2, 99)
