@@ -103,11 +103,10 @@ hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* 
 // FFT; in place in spec (outputs: field 0 = first result, field 1 = second result if want2).
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
                            const cpx<double>* tw1, hipStream_t s);
-// Inverse row pass: spec field f -> real vector field out_d (double, nullable) and out_t
-// (TO, nullable).
-template <typename TO>
-hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>* spec, double* out_d,
-                               TO* out_t, const cpx<double>* tw2, hipStream_t s);
+// Inverse row pass: fields 0 and 1 of spec -> real vector fields out0 and out1 (out1 nullable: field
+// 0 only) in one launch.
+hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
+                                const cpx<double>* tw2, hipStream_t s);
 
 // Nyquist projection of a real vector field in real space (every mode with k1 = n1/2 or k2 = n2/2
 // removed): out_d (double, nullable), out_t (TO, nullable); `in` may equal out_d.  scratch: at

@@ -442,10 +442,10 @@ reg_status spec_col(reg_problem* P, int mode, bool have_y, bool want2) {
     CK(launch_spec_col(P->sp, mode, have_y, want2, P->spec(), P->at<cpx<double>>(P->o.tw1d), P->stream));
     return REG_OK;
 }
-template <typename TO>
-reg_status spec_inv(reg_problem* P, int field, double* out_d, TO* out_t) {
-    CK(launch_spec_row_inv<TO>(P->sp, field, P->spec(), out_d, out_t, P->at<cpx<double>>(P->o.tw2d),
-                               P->stream));
+
+// Both result fields of the last column pass (the second only with out1) in one launch.
+reg_status spec_inv2(reg_problem* P, double* out0, double* out1) {
+    CK(launch_spec_row_inv2(P->sp, P->spec(), out0, out1, P->at<cpx<double>>(P->o.tw2d), P->stream));
     return REG_OK;
 }
 
@@ -484,8 +484,7 @@ reg_status reg_terms(reg_problem* P, const double* v64, double* rv, double* rw) 
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
     CKS(spec_fwd<double>(P, 0, v64));
     CKS(spec_col(P, SPEC_REG, false, ms));
-    CKS(spec_inv<double>(P, 0, t0, (double*)nullptr));
-    if (ms) CKS(spec_inv<double>(P, 1, t1, (double*)nullptr));
+    CKS(spec_inv2(P, t0, ms ? t1 : nullptr));
     const double* a[2] = {v64, v64};
     const double* b[2] = {t0, t1};
     double r[2] = {0, 0};
@@ -597,8 +596,7 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
     CK((launch_spec_row_fwd2<double, T>(P->sp, x0, tv.B(), P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream)));
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
     CKS(spec_col(P, SPEC_HESS, true, ms && kg));
-    CKS(spec_inv<double>(P, 0, g, (double*)nullptr));
-    if (ms && kg) CKS(spec_inv<double>(P, 1, kg, (double*)nullptr));
+    CKS(spec_inv2(P, g, (ms && kg) ? kg : nullptr));
     if (Jout) {
         *Jout = d + rv + rw;
         if (!std::isfinite(*Jout)) return fail(REG_ENONFINITE, "objective is not finite");
@@ -628,8 +626,7 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     // both fields' row transforms in one launch
     CK((launch_spec_row_fwd2<double, T>(P->sp, x0, tv.Bt(), P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream)));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
-    CKS(spec_inv<double>(P, 0, out, (double*)nullptr));
-    if (kout) CKS(spec_inv<double>(P, 1, kout, (double*)nullptr));
+    CKS(spec_inv2(P, out, kout));
     P->matvec_done = true;
     return REG_OK;
 }
@@ -706,8 +703,7 @@ reg_status matvec_run(reg_problem* P, const double* vt64, double* out, double* k
 reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
     CKS(spec_fwd<double>(P, 0, r));
     CKS(spec_col(P, SPEC_PREC, false, kr != nullptr));
-    CKS(spec_inv<double>(P, 0, z, (double*)nullptr));
-    if (kr) CKS(spec_inv<double>(P, 1, kr, (double*)nullptr));
+    CKS(spec_inv2(P, z, kr));
     return REG_OK;
 }
 
@@ -822,8 +818,7 @@ reg_status lr_setup_t(reg_problem* P, const double* U, int r, double* theta_out,
     for (int j = 0; j < r; ++j) {
         CKS(spec_fwd<double>(P, 0, U + (size_t)j * n));
         CKS(spec_col(P, SPEC_LR, false, true));
-        CKS(spec_inv<double>(P, 0, P->lr_slot(0, j), (double*)nullptr));
-        CKS(spec_inv<double>(P, 1, P->lr_slot(1, j), (double*)nullptr));   // K^{-1} M z_j (scratch)
+        CKS(spec_inv2(P, P->lr_slot(0, j), P->lr_slot(1, j)));   // and K^{-1} M z_j (scratch)
     }
     double G[LR_MIX_MAX * LR_MIX_MAX], lam[LR_MIX_MAX], E[LR_MIX_MAX * LR_MIX_MAX];
     CKS(lr_gram(P, 0, 1, r, G));

@@ -268,9 +268,11 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
 
 // ---------------------------------------------------------------------------------------------
 template <typename TO, int N, int FPW>
+// blockIdx.y = 1: the next field of spec (out_d1; no T copy)
 __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const cpx<double>* __restrict__ spec,
-                                                                  double* __restrict__ out_d,
-                                                                  TO* __restrict__ out_t,
+                                                                  double* __restrict__ out_d0,
+                                                                  TO* __restrict__ out_t0,
+                                                                  double* __restrict__ out_d1,
                                                                   const cpx<double>* __restrict__ tw) {
     constexpr int Q = N / 4, H = N / 2;
     constexpr int L = LdsSize<N>::value;
@@ -279,7 +281,10 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
     const int i1 = blockIdx.x * FPW + f;
     const bool valid = i1 < n1;
     const long hn = (long)n1 * H;
-    const cpx<double>* s0 = spec + (long)(valid ? i1 : 0) * H;
+    const int field = blockIdx.y;
+    double* out_d = field ? out_d1 : out_d0;
+    TO* out_t = field ? nullptr : out_t0;
+    const cpx<double>* s0 = spec + (long)(2 * field) * hn + (long)(valid ? i1 : 0) * H;
     const cpx<double>* s1 = s0 + hn;
     cpx<double> x[4];
 #pragma unroll
@@ -426,12 +431,15 @@ __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_col_kernel(SpecParam
 template <typename TO>
 __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_inv_kernel(int n1, int n2,
                                                                           const cpx<double>* __restrict__ spec,
-                                                                          double* __restrict__ out_d,
-                                                                          TO* __restrict__ out_t,
+                                                                          double* __restrict__ out_d0,
+                                                                          TO* __restrict__ out_t0,
+                                                                          double* __restrict__ out_d1,
                                                                           const cpx<double>* __restrict__ tw) {
     extern __shared__ cpx<double> zr[];
-    const int i1 = blockIdx.x, comp = blockIdx.y, H = n2 / 2;
-    const cpx<double>* in = spec + (long)comp * n1 * H + (long)i1 * H;
+    const int i1 = blockIdx.x, comp = blockIdx.y, field = blockIdx.z, H = n2 / 2;
+    double* out_d = field ? out_d1 : out_d0;
+    TO* out_t = field ? nullptr : out_t0;
+    const cpx<double>* in = spec + (long)(2 * field + comp) * n1 * H + (long)i1 * H;
     for (int k = threadIdx.x; k < H; k += DENSE_THREADS) zr[k] = in[k];
     __syncthreads();
     const long off = (long)comp * n1 * n2 + (long)i1 * n2;
@@ -512,20 +520,21 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
     return hipGetLastError();
 }
 
+// field 0 of spec at `spec` -> out_d / out_t; with out_d1, field 1 -> out_d1 in the same launch
 template <typename TO>
-hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>* spec, double* out_d,
-                               TO* out_t, const cpx<double>* tw2, hipStream_t s) {
-    const cpx<double>* sp = spec + (long)(2 * field) * p.n1 * (p.n2 / 2);
+static hipError_t row_inv_fields(const SpecParams& p, const cpx<double>* spec, double* out_d, TO* out_t,
+                                 double* out_d1, const cpx<double>* tw2, hipStream_t s) {
+    const int nf = out_d1 ? 2 : 1;
 #define ROWI(NN)                                                                                       \
     case NN: {                                                                                         \
         constexpr int FPW = spec_fpw<NN>();                                                            \
-        hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW),          \
-                           dim3(FPW * NN / 4), 0, s, p.n1, sp, out_d, out_t, tw2);                     \
+        hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf),      \
+                           dim3(FPW * NN / 4), 0, s, p.n1, spec, out_d, out_t, out_d1, tw2);           \
         break;                                                                                         \
     }
     if (!pow2(p.n2)) {
-        hipLaunchKernelGGL((spec_dense_row_inv_kernel<TO>), dim3(p.n1, 2), dim3(DENSE_THREADS),
-                           (p.n2 / 2) * sizeof(cpx<double>), s, p.n1, p.n2, sp, out_d, out_t, tw2);
+        hipLaunchKernelGGL((spec_dense_row_inv_kernel<TO>), dim3(p.n1, 2, nf), dim3(DENSE_THREADS),
+                           (p.n2 / 2) * sizeof(cpx<double>), s, p.n1, p.n2, spec, out_d, out_t, out_d1, tw2);
         return hipGetLastError();
     }
     switch (p.n2) {
@@ -534,6 +543,11 @@ hipError_t launch_spec_row_inv(const SpecParams& p, int field, const cpx<double>
     }
 #undef ROWI
     return hipGetLastError();
+}
+
+hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
+                                const cpx<double>* tw2, hipStream_t s) {
+    return row_inv_fields<double>(p, spec, out0, (double*)nullptr, out1, tw2, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -680,10 +694,6 @@ template hipError_t launch_spec_row_fwd2<double, float>(const SpecParams&, const
                                                         cpx<double>*, const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_fwd2<double, double>(const SpecParams&, const double*, const double*,
                                                          cpx<double>*, const cpx<double>*, hipStream_t);
-template hipError_t launch_spec_row_inv<float>(const SpecParams&, int, const cpx<double>*, double*, float*,
-                                               const cpx<double>*, hipStream_t);
-template hipError_t launch_spec_row_inv<double>(const SpecParams&, int, const cpx<double>*, double*,
-                                                double*, const cpx<double>*, hipStream_t);
 template hipError_t launch_nyquist_project<float>(int, int, const double*, double*, float*, double*, hipStream_t);
 template hipError_t launch_nyquist_project<double>(int, int, const double*, double*, double*, double*, hipStream_t);
 
