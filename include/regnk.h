@@ -247,8 +247,9 @@ reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms
                          double* bytes_per_launch_host, double* exec_ms_host);
 
 /* Launch-shape autotuner for the FP32 transport stages on square grids of 64+ points (elements per
- * thread of the row and column register FFTs, threads per block): times every available shape of
- * the four matvec stage launches `reps` times at the current linearisation point, keeps the fastest
+ * thread of the row and column register FFTs, threads per block): times every shape that fits the
+ * grid's line length for the four matvec stage launches `reps` times at the current linearisation
+ * point, keeps the fastest
  * per stage in the handle, and writes a JSON report of the timings (microseconds per launch) and
  * the choice to `report` (nullable, truncated to report_bytes).  Results are identical for every
  * shape up to rounding; only speed differs.  REG_ESTATE before the first reg_hessian_matvec.  FP64
@@ -257,7 +258,8 @@ reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t repor
 
 /* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): one shape index in
  * [0, 12) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
- * state 2, gradient}; count must be 7. */
+ * state 2, gradient}; count must be 7.  A shape that does not fit the grid's line length (too few
+ * threads for a 2048-point line, say) runs as the grid's default shape. */
 reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count);
 
 /* Thread-local description of the last error (never NULL). */

@@ -62,6 +62,9 @@ constexpr int NUM_STAGE_VARIANTS = 12;
 template <typename T>
 hipError_t launch_stage(int op, int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0 = nullptr,
                         hipEvent_t t1 = nullptr);
+// Whether FP32 launch shape `var` is a distinct, valid shape on an n1 x n2 grid (other indices fall
+// back to a valid default, or the grid has one fixed shape).
+bool stage_variant_fits_f32(int n1, int n2, int var);
 // m1 = Q + C (FP64); lam (nullable) = m_R - m1 in precision T
 template <typename T>
 hipError_t launch_finalize_state(long nn, const double* Q, const double* C, const double* mR, double* m1, T* lam,

@@ -1349,6 +1349,7 @@ reg_status autotune_f32(reg_problem* P, int reps, char* report, size_t cap) {
         bool firstv = true;
         for (int v = 0; v < NUM_STAGE_VARIANTS; ++v) {
             double ms = 0;
+            if (!stage_variant_fits_f32(P->n1, P->n2, v)) continue;
             if (time_launches<float>(P, op, v, a, reps, &ms) != REG_OK) continue;
             snprintf(buf, sizeof buf, "%s[%d, %.3f]", firstv ? "" : ", ", v, ms * 1e3);
             js += buf;

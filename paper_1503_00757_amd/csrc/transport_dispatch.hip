@@ -4,6 +4,19 @@
 
 namespace regnk {
 
+bool stage_variant_fits_f32(int n1, int n2, int var) {
+    if (n1 != n2 || !is_pow2_len(n1)) return var == 0;   // two launches with fixed shapes
+    switch (n1) {
+        case 64: return var_ok<float, 64>(var);
+        case 128: return var_ok<float, 128>(var);
+        case 256: return var_ok<float, 256>(var);
+        case 512: return var_ok<float, 512>(var);
+        case 1024: return var_ok<float, 1024>(var);
+        case 2048: return var_ok<float, 2048>(var);
+    }
+    return var == 0;   // short grids: one fixed shape
+}
+
 extern template hipError_t launch_stage_op<float, OP_A1>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<float, OP_A2>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 extern template hipError_t launch_stage_op<float, OP_I1>(int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);

@@ -531,6 +531,34 @@ static hipError_t launch_col_fixed(const StageArgs<T>& a, hipStream_t s, hipEven
     return hipGetLastError();
 }
 
+// Whether launch shape v fits length N (fused_ok), and the shape used when the requested one does not.
+template <typename T, int N>
+constexpr bool var_ok(int v) {
+    switch (v) {
+        case 0: return fused_ok<T, N, var_ER(0), var_EC(0), var_BS(0)>();
+        case 1: return fused_ok<T, N, var_ER(1), var_EC(1), var_BS(1)>();
+        case 2: return fused_ok<T, N, var_ER(2), var_EC(2), var_BS(2)>();
+        case 3: return fused_ok<T, N, var_ER(3), var_EC(3), var_BS(3)>();
+        case 4: return fused_ok<T, N, var_ER(4), var_EC(4), var_BS(4)>();
+        case 5: return fused_ok<T, N, var_ER(5), var_EC(5), var_BS(5)>();
+        case 6: return fused_ok<T, N, var_ER(6), var_EC(6), var_BS(6)>();
+        case 7: return fused_ok<T, N, var_ER(7), var_EC(7), var_BS(7)>();
+        case 8: return fused_ok<T, N, var_ER(8), var_EC(8), var_BS(8)>();
+        case 9: return fused_ok<T, N, var_ER(9), var_EC(9), var_BS(9)>();
+        case 10: return fused_ok<T, N, var_ER(10), var_EC(10), var_BS(10)>();
+        case 11: return fused_ok<T, N, var_ER(11), var_EC(11), var_BS(11)>();
+    }
+    return false;
+}
+template <typename T, int N>
+constexpr int default_var() {
+    if (var_ok<T, N>(0)) return 0;
+    if (var_ok<T, N>(8)) return 8;
+    for (int v = 1; v < NUM_STAGE_VARIANTS; ++v)
+        if (var_ok<T, N>(v)) return v;
+    return 0;
+}
+
 template <typename T, int N, int OP>
 static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if constexpr (sizeof(T) == 8 || N < 64) {
@@ -541,6 +569,7 @@ static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s, h
         constexpr int BS = BS0 < 64 ? 64 : BS0;
         return launch_fused<T, N, OP, ER, EC, BS>(a, s, t0, t1);
     } else {
+        if (!var_ok<T, N>(var)) var = default_var<T, N>();   // e.g. variant 0 has too few threads at 2048
         switch (var) {
             case 0: return launch_fused<T, N, OP, var_ER(0), var_EC(0), var_BS(0)>(a, s, t0, t1);
             case 1: return launch_fused<T, N, OP, var_ER(1), var_EC(1), var_BS(1)>(a, s, t0, t1);

@@ -1,0 +1,71 @@
+"""The largest supported grid, 2048 x 2048 (FP32 transport, n_t = 2 so that the oracle stays cheap):
+gradient and Gauss-Newton matvec against the oracle (1e-5, the per-matvec bound of the precision
+plan), <Hx, y> = <x, Hy> and <x, Hx> >= beta_v <x, A x>, before and after autotuning (whose candidate
+shapes must fit the 2048-point lines).  Every kernel runs at its largest shape:
+the 2048-point fused stages, the two-column FP64 spectral pass and the real-space projection."""
+import numpy as np
+import pytest
+
+import synthdata as sd
+from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel
+from oracle import Grid, reduced, spectral
+
+pytestmark = pytest.mark.gpu
+
+MAX = Case(2048, 2048, 2, "H1", "divfree", 1e-2, 0.0, "fp32", seed=31)
+
+
+def test_2048sq_gradient_matvec_parity_symmetry_positivity():
+    case = MAX
+    print(f"[case] {case}", flush=True)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    lin = reduced.gradient(g, p, mT, mR, vlin)
+    H_ref = reduced.hessian_matvec(g, p, lin, vt)
+    P = gpu_problem(case)
+    try:
+        gg, J = P.gradient(dev(vlin))
+        assert rel(host(gg), lin.g) < 1e-5
+        assert abs(J - lin.J) <= 1e-5 * abs(lin.J)
+        Hx = host(P.hessian_matvec(dev(vt)))
+        assert rel(Hx, H_ref) < 1e-5
+        y = sd.random_vec(case.n1, case.n2, 12, 98, divfree=True)
+        Hy = host(P.hessian_matvec(dev(y)))
+        a, b = float((Hx * y).sum()), float((vt * Hy).sum())
+        assert abs(a - b) <= 1e-5 * abs(a)
+        xAx = float((vt * spectral.apply_A(g, p, vt)).sum())
+        assert float((vt * Hx).sum()) >= p.beta_v * xAx * (1 - 1e-6)
+        # the autotuner only times shapes that fit 2048-point lines (256+ threads per transform), and
+        # the tuned matvec is the same operator
+        rep = P.autotune(reps=3)
+        fits = {4, 6, 7, 8}
+        for op in ("A1", "A2", "I1", "I2"):
+            assert {v for v, _ in rep[op]} <= fits, rep[op]
+        assert set(rep["chosen"][2:6]) <= fits
+        assert rel(host(P.hessian_matvec(dev(vt))), H_ref) < 1e-5
+    finally:
+        P.close()
+
+
+def test_2048sq_fp64_gradient_matvec_parity():
+    """FP64 transport at the largest grid.  Floor: 10x the oracle's own response to FP64 round-off in
+    its input (beta_v A with |k| up to 1024 amplifies it), measured from the oracle."""
+    case = Case(2048, 2048, 2, "H2", "none", 1e-3, 0.0, "fp64", seed=32)
+    print(f"[case] {case}", flush=True)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    lin = reduced.gradient(g, p, mT, mR, vlin)
+    H_ref = reduced.hessian_matvec(g, p, lin, vt)
+    rng = np.random.default_rng(1234)
+    H_n = reduced.hessian_matvec(g, p, lin, vt + 2.2e-16 * np.abs(vt).max() * rng.standard_normal(vt.shape))
+    g_n = reduced.gradient(g, p, mT, mR, vlin + 2.2e-16 * np.abs(vlin).max() * rng.standard_normal(vlin.shape)).g
+    P = gpu_problem(case)
+    try:
+        gg, J = P.gradient(dev(vlin))
+        assert rel(host(gg), lin.g) < max(1e-10, 10 * rel(g_n, lin.g))
+        Hx = host(P.hessian_matvec(dev(vt)))
+        assert rel(Hx, H_ref) < max(1e-10, 10 * rel(H_n, H_ref))
+    finally:
+        P.close()
