@@ -5,7 +5,7 @@ deformed template and preconditioner.  Two floors, both measured from the oracle
 the gradient and data term carry an absolute floor of 32 eps times the body force of an O(1) misfit
 (they are formed from m_R - m_1), and every bound is at least 10x the oracle's own response to FP64
 round-off in its input (beta_v A amplifies that by up to beta_v (n/2)^4 on a 2048-point H2 axis).  Sizes span several workgroup tiles, non-square grids, the
-smallest (8) and largest (2048) supported axis lengths, the full 64^2 / 256^2 / 1024^2
+smallest (8) and largest (2048) supported axis lengths, 512-point lines, the full 64^2 / 256^2 / 1024^2
 workloads, and even axis lengths that are not powers of two (10, 96, 150, 2046) on one or both axes."""
 import numpy as np
 import pytest
@@ -25,6 +25,9 @@ CASES = {
     "2048x16_nt128_H1_none_fp32": Case(2048, 16, 128, "H1", "none", 1e-2, 0.0, "fp32", "dto", 6, vmax=0.1),
     "16x2048_nt128_H2_divfree_fp64": Case(16, 2048, 128, "H2", "divfree", 1e-2, 0.0, "fp64", "dto", 7, vmax=0.1),
     "c2_256sq_nt16_H2_mass_fp32": Case(256, 256, 16, "H2", "mass_source", 1e-3, 1e-4, "fp32", config=2),
+    "512sq_nt4_H1_none_fp32": Case(512, 512, 4, "H1", "none", 1e-2, 0.0, "fp32", seed=17),
+    "512x32_nt4_H2_mass_fp32": Case(512, 32, 4, "H2", "mass_source", 1e-3, 1e-4, "fp32", seed=18),
+    "64x512_nt4_H1_divfree_fp64": Case(64, 512, 4, "H1", "divfree", 1e-2, 0.0, "fp64", seed=19),
     # axis lengths that are not powers of two (direct-sum spectral passes, circulant stage derivatives)
     "96x96_nt4_H1_divfree_fp64": Case(96, 96, 4, "H1", "divfree", 1e-2, 0.0, "fp64", seed=11),
     "150x128_nt6_H2_mass_fp32": Case(150, 128, 6, "H2", "mass_source", 1e-3, 1e-4, "fp32", seed=12),
