@@ -160,7 +160,8 @@ def test_constant_template_hessian_is_regulariser(problems):
         P.close()
 
 
-@pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "c1_64sq_nt4_H1_divfree_fp32", "128x32_nt3_H1_none_fp32"])
+@pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "c1_64sq_nt4_H1_divfree_fp32", "128x32_nt3_H1_none_fp32",
+                                  "128sq_nt3_H2_divfree_fp32", "512sq_nt4_H1_none_fp32"])
 def test_every_launch_shape_matches_oracle(problems, name):
     """The autotuner may pick any launch shape (elements per thread, transforms per block): every one
     must give an oracle-parity matvec; the tuned choice must too."""
