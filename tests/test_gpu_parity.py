@@ -25,6 +25,8 @@ CASES = {
     "2048x16_nt128_H1_none_fp32": Case(2048, 16, 128, "H1", "none", 1e-2, 0.0, "fp32", "dto", 6, vmax=0.1),
     "16x2048_nt128_H2_divfree_fp64": Case(16, 2048, 128, "H2", "divfree", 1e-2, 0.0, "fp64", "dto", 7, vmax=0.1),
     "c2_256sq_nt16_H2_mass_fp32": Case(256, 256, 16, "H2", "mass_source", 1e-3, 1e-4, "fp32", config=2),
+    "8sq_nt2_H1_divfree_fp32": Case(8, 8, 2, "H1", "divfree", 1e-2, 0.0, "fp32", seed=22),
+    "16sq_nt2_H2_mass_fp32": Case(16, 16, 2, "H2", "mass_source", 1e-2, 1e-3, "fp32", seed=23),
     "32sq_nt2_H1_none_fp32": Case(32, 32, 2, "H1", "none", 1e-2, 0.0, "fp32", seed=20),
     "128sq_nt3_H2_divfree_fp32": Case(128, 128, 3, "H2", "divfree", 1e-3, 0.0, "fp32", seed=21),
     "512sq_nt4_H1_none_fp32": Case(512, 512, 4, "H1", "none", 1e-2, 0.0, "fp32", seed=17),
