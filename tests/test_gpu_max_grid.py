@@ -69,3 +69,24 @@ def test_2048sq_fp64_gradient_matvec_parity():
         assert rel(Hx, H_ref) < max(1e-10, 10 * rel(H_n, H_ref))
     finally:
         P.close()
+
+
+def test_2048sq_deformation_shear_flow_closed_form():
+    """Deformation diagnostics at the largest grid: the shear flow v = (a sin x2, 0) has u_1 = v,
+    F_1 = [[1, a cos x2], [0, 1]] and det F_1 = 1 exactly (n_t = 512 keeps the time-step CFL at 0.8)."""
+    import torch
+    from paper_1503_00757_amd import Problem
+    n, nt, amp = 2048, 512, 0.4
+    img = torch.full((n, n), 0.5, dtype=torch.float64, device="cuda:0")
+    P = Problem(img, img.clone(), nt, "H1", "divfree", 1e-2, 0.0, "fp32")
+    try:
+        x2 = np.arange(n)[None, :] * 2 * np.pi / n + np.zeros((n, 1))
+        v = np.stack([amp * np.sin(x2), 0 * x2])
+        u1, F1, det, (mn, mx, mean) = P.deformation(dev(v))
+        assert np.abs(host(u1) - v).max() < 1e-11
+        F = host(F1)
+        assert np.abs(F[0, 0] - 1).max() < 1e-11 and np.abs(F[1, 1] - 1).max() < 1e-11
+        assert np.abs(F[0, 1] - amp * np.cos(x2)).max() < 1e-11 and np.abs(F[1, 0]).max() < 1e-11
+        assert np.abs(host(det) - 1).max() < 1e-11 and abs(mn - 1) < 1e-11 and abs(mx - 1) < 1e-11
+    finally:
+        P.close()
