@@ -90,3 +90,19 @@ def test_2048sq_deformation_shear_flow_closed_form():
         assert np.abs(host(det) - 1).max() < 1e-11 and abs(mn - 1) < 1e-11 and abs(mx - 1) < 1e-11
     finally:
         P.close()
+
+
+def test_2048sq_full_newton_matvec_parity():
+    """Full-Newton stages (the lam v~ flux terms) at the largest grid, FP32 transport."""
+    case = MAX
+    mT, mR, vlin, vt, vtr = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    lin = reduced.gradient(g, p, mT, mR, vlin)
+    H_ref = reduced.hessian_matvec_full(g, p, lin, vt)
+    P = gpu_problem(case, hessian="full")
+    try:
+        P.gradient(dev(vlin), want_J=False)
+        assert rel(host(P.hessian_matvec(dev(vt))), H_ref) < 1e-5
+    finally:
+        P.close()
