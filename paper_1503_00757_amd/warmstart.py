@@ -1,7 +1,7 @@
 """Learned warm start (``include/regnet.h``): a Fourier neural operator predicts the initial velocity of
 the Gauss-Newton solve (Alg. 1) from (m_T, m_R).  It is trained on the GPU by the library's own
 forward, reverse-pass and Adam kernels on registrations that the plain solver produced, and the
-plain solver stays the judge: ``reg_solve`` drops a warm start that does not lower the objective.
+plain solver has the last word: ``reg_solve`` drops a warm start that does not lower the objective.
 
 This module only holds device buffers (torch tensors), the training schedule (batch order, learning
 rate) and host timing; every arithmetic step runs in ``libregnk.so``.
