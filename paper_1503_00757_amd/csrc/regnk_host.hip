@@ -885,17 +885,15 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
     {
         const double* a[1] = {s};
         const double* b[1] = {W ? kst : st};
-        CK(launch_dots<double>(1, a, b, n, P->partial(), sc + S_SHS, P->stream));
+        CK(launch_dots_scalar(1, a, b, n, P->partial(), sc + S_SHS, PCG_KAPPA, sc, P->stream));
     }
-    CK(launch_pcg_scalar(PCG_KAPPA, sc, P->stream));
     CK(launch_pcg_update(n, x, r, s, st, sc, P->stream));
     CKS(precond_pcg(P, r, z, W ? kr : nullptr));
     {
         const double* a[2] = {r, W ? kr : r};
         const double* b[2] = {r, z};
-        CK(launch_dots<double>(2, a, b, n, P->partial(), sc + S_RR, P->stream));
+        CK(launch_dots_scalar(2, a, b, n, P->partial(), sc + S_RR, PCG_MU, sc, P->stream));
     }
-    CK(launch_pcg_scalar(PCG_MU, sc, P->stream));
     CK(launch_pcg_dir_copy<T>(n, s, TV<T>{P}.vtT(), z, sc, P->stream));
     return REG_OK;
 }
@@ -934,9 +932,8 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     {
         const double* a[2] = {W ? kr : r, r};
         const double* b[2] = {z, r};
-        CK(launch_dots<double>(2, a, b, n, P->partial(), sc + S_RZ, P->stream));   // S_RZ, S_RR0
+        CK(launch_dots_scalar(2, a, b, n, P->partial(), sc + S_RZ, PCG_INIT, sc, P->stream));   // S_RZ, S_RR0
     }
-    CK(launch_pcg_scalar(PCG_INIT, sc, P->stream));
     double h[NUM_PCG_SLOTS];
     CK(hipMemcpyAsync(h, sc, sizeof h, hipMemcpyDeviceToHost, P->stream));
     CK(hipStreamSynchronize(P->stream));

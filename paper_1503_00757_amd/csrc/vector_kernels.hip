@@ -133,9 +133,8 @@ hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One thread: the scalar recurrences of PCG.
-__global__ void pcg_scalar_kernel(int mode, double* __restrict__ sc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The scalar recurrences of PCG (one thread).
+__device__ __forceinline__ void pcg_scalar_step(int mode, double* __restrict__ sc) {
     if (mode == PCG_INIT) {
         sc[S_ACTIVE] = 1.0;
         sc[S_BREAK] = 0.0;
@@ -166,6 +165,26 @@ __global__ void pcg_scalar_kernel(int mode, double* __restrict__ sc) {
             sc[S_MU] = 0.0;
         }
     }
+}
+
+__global__ void pcg_scalar_kernel(int mode, double* __restrict__ sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    pcg_scalar_step(mode, sc);
+}
+
+// The second level of launch_dots for all nk sums in one block (the same partial order and tree as
+// finalize_kernel), then the PCG scalar step of `mode`: one launch instead of two.
+__global__ __launch_bounds__(RED_THREADS) void finalize_scalar_kernel(int nk, const double* __restrict__ partial,
+                                                                      double* __restrict__ out, int mode,
+                                                                      double* __restrict__ sc) {
+    __shared__ double sh[RED_THREADS / 64];
+    for (int k = 0; k < nk; ++k) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partial[k * RED_BLOCKS + i];
+        const double t = block_sum<RED_THREADS>(acc, sh);
+        if (threadIdx.x == 0) out[k] = t;
+    }
+    if (threadIdx.x == 0) pcg_scalar_step(mode, sc);
 }
 
 __global__ void pcg_update_kernel(long n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ s,
@@ -199,6 +218,19 @@ hipError_t launch_pcg_scalar(int mode, double* scal, hipStream_t s) {
     hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(64), 0, s, mode, scal);
     return hipGetLastError();
 }
+hipError_t launch_dots_scalar(int nk, const double* const* a, const double* const* b, long n, double* partial,
+                              double* out, int mode, double* scal, hipStream_t s) {
+    if (nk < 1 || nk > 4) return hipErrorInvalidValue;
+    DotPtrs<double> p{};
+    for (int k = 0; k < nk; ++k) {
+        p.a[k] = a[k];
+        p.b[k] = b[k];
+    }
+    hipLaunchKernelGGL((dots_kernel<double>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, nk, p, n, partial);
+    hipLaunchKernelGGL(finalize_scalar_kernel, dim3(1), dim3(RED_THREADS), 0, s, nk, partial, out, mode, scal);
+    return hipGetLastError();
+}
+
 hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
                              hipStream_t stream) {
     hipLaunchKernelGGL(pcg_update_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, x, r, s, st, scal);
