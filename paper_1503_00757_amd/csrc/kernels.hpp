@@ -206,15 +206,12 @@ enum PcgSlot {
     NUM_PCG_SLOTS
 };
 enum PcgScalarMode { PCG_INIT = 0, PCG_KAPPA, PCG_MU };
-hipError_t launch_pcg_scalar(int mode, double* scal, hipStream_t s);
 // launch_dots (FP64) followed by the PCG scalar step `mode`, the latter fused into the second level.
 hipError_t launch_dots_scalar(int nk, const double* const* a, const double* const* b, long n, double* partial,
                               double* out, int mode, double* scal, hipStream_t s);
 // x += kappa s, r -= kappa s~ (kappa from scal)
 hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
                              hipStream_t stream);
-// s = z + mu s (mu from scal)
-hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal, hipStream_t stream);
 // s = z + mu s (scal == nullptr: s = z) and its copy sT = (T) s for the next matvec
 template <typename T>
 hipError_t launch_pcg_dir_copy(long n, double* s, T* sT, const double* z, const double* scal, hipStream_t stream);

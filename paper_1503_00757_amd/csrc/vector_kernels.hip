@@ -167,11 +167,6 @@ __device__ __forceinline__ void pcg_scalar_step(int mode, double* __restrict__ s
     }
 }
 
-__global__ void pcg_scalar_kernel(int mode, double* __restrict__ sc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    pcg_scalar_step(mode, sc);
-}
-
 // The second level of launch_dots for all nk sums in one block (the same partial order and tree as
 // finalize_kernel), then the PCG scalar step of `mode`: one launch instead of two.
 __global__ __launch_bounds__(RED_THREADS) void finalize_scalar_kernel(int nk, const double* __restrict__ partial,
@@ -197,12 +192,6 @@ __global__ void pcg_update_kernel(long n, double* __restrict__ x, double* __rest
     }
 }
 
-__global__ void pcg_dir_kernel(long n, double* __restrict__ s, const double* __restrict__ z, const double* __restrict__ sc) {
-    const double mu = sc[S_MU];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        s[i] = z[i] + mu * s[i];
-}
-
 template <typename T>
 __global__ void pcg_dir_copy_kernel(long n, double* __restrict__ s, T* __restrict__ sT, const double* __restrict__ z,
                                     const double* __restrict__ sc) {
@@ -214,10 +203,6 @@ __global__ void pcg_dir_copy_kernel(long n, double* __restrict__ s, T* __restric
     }
 }
 
-hipError_t launch_pcg_scalar(int mode, double* scal, hipStream_t s) {
-    hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(64), 0, s, mode, scal);
-    return hipGetLastError();
-}
 hipError_t launch_dots_scalar(int nk, const double* const* a, const double* const* b, long n, double* partial,
                               double* out, int mode, double* scal, hipStream_t s) {
     if (nk < 1 || nk > 4) return hipErrorInvalidValue;
@@ -234,10 +219,6 @@ hipError_t launch_dots_scalar(int nk, const double* const* a, const double* cons
 hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
                              hipStream_t stream) {
     hipLaunchKernelGGL(pcg_update_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, x, r, s, st, scal);
-    return hipGetLastError();
-}
-hipError_t launch_pcg_dir(long n, double* s, const double* z, const double* scal, hipStream_t stream) {
-    hipLaunchKernelGGL(pcg_dir_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, s, z, scal);
     return hipGetLastError();
 }
 template <typename T>
