@@ -267,7 +267,8 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
                 alpha *= opts.armijo_rho
         st.backtracks += nbt
         st.history.append(dict(k=k, J=lin.J, g_rel=grel, pcg=its, eta=eta, pcg_relres=relres,
-                               alpha=alpha if accepted else 0.0, slope=slope))
+                               alpha=alpha if accepted else 0.0, slope=slope, backtracks=nbt,
+                               v=v.copy(), step=vt.copy()))
         if not accepted:
             st.status = ENOTCONV
             break

@@ -115,3 +115,78 @@ def test_q14_pcg_stops_at_first_iterate_below_forcing_term():
             checked += 1
         assert h["pcg_relres"] <= eta
     assert checked >= 2
+
+
+# ---- CFL number (Sec. 4: n_t is chosen by monitoring the CFL condition of the explicit RK2 steps) ---
+def test_cfl_number_hand_values():
+    """C = h_t (max|v_1| n1/2 + max|v_2| n2/2), values worked out by hand for fields whose maxima are
+    exact on the grid."""
+    n1, n2 = 16, 32
+    g = Grid(n1, n2)
+    x1 = 2 * np.pi * np.arange(n1)[:, None] / n1
+    x2 = 2 * np.pi * np.arange(n2)[None, :] / n2
+    one = np.ones((n1, n2))
+    # constant velocity (0.3, -0.2), n_t = 4: (0.3 * 8 + 0.2 * 16) / 4 = 1.4
+    p4 = Params(n1, n2, 4, "H1", "none", 1e-2, 0.0)
+    assert solver.cfl_number(g, p4, np.stack([0.3 * one, -0.2 * one])) == pytest.approx(1.4, rel=1e-13)
+    # v = (0.25 sin x2, -0.1 cos 3 x1), n_t = 2: sin reaches 1 at x2 = pi/2, |cos| reaches 1 at x1 = 0:
+    # (0.25 * 8 + 0.1 * 16) / 2 = 1.8
+    p2 = Params(n1, n2, 2, "H1", "none", 1e-2, 0.0)
+    v = np.stack([0.25 * np.sin(x2) * one, -0.1 * np.cos(3 * x1) * one])
+    assert solver.cfl_number(g, p2, v) == pytest.approx(1.8, rel=1e-13)
+    # a Nyquist mode is not resolved and does not count: 0.1 + 0.5 (-1)^i2 in v_1 leaves 0.1,
+    # (0.1 * 8 + 0) / 2 = 0.4
+    alt = np.where(np.arange(n2)[None, :] % 2 == 0, 1.0, -1.0) * one
+    v = np.stack([0.1 * one + 0.5 * alt, 0 * one])
+    assert solver.cfl_number(g, p2, v) == pytest.approx(0.4, rel=1e-12)
+
+
+def test_cfl_number_bounds_spectral_radius_of_the_step_operator():
+    """For a constant velocity, h_t L_v (L_v u = -v . grad u, built here from explicit DFT matrices)
+    has eigenvalues -i h_t k~ . v; its spectral radius h_t (|v1|(n1/2 - 1) + |v2|(n2/2 - 1)) (the
+    largest resolved wavenumbers) is below C and approaches it as the grid grows."""
+    from dense_reference import Dense
+    for (n1, n2, nt, a, b) in [(8, 8, 3, 0.7, -0.4), (8, 12, 2, -0.25, 0.9), (12, 8, 5, 1.1, 0.3)]:
+        d = Dense(n1, n2, nt, "H1", "none", 1e-2, 0.0)
+        L = -(a * d.D1 + b * d.D2) / nt
+        rho = np.abs(np.linalg.eigvals(L)).max()
+        assert rho == pytest.approx((abs(a) * (n1 / 2 - 1) + abs(b) * (n2 / 2 - 1)) / nt, rel=1e-10)
+        p = Params(n1, n2, nt, "H1", "none", 1e-2, 0.0)
+        C = solver.cfl_number(Grid(n1, n2), p, np.stack([a * np.ones((n1, n2)), b * np.ones((n1, n2))]))
+        assert rho < C <= rho * min(n1, n2) / (min(n1, n2) - 2) * (1 + 1e-12)
+
+
+# ---- Armijo backtracking (Sec. 4: Armijo condition with default parameters, N&W Alg. 3.1) --------
+def translated_sinusoids(n=16, nt=8, shift=2.0):
+    """A pair whose reference is the template shifted by (shift, shift/2): the Gauss-Newton model of a
+    shift this large overshoots, so the full step is rejected."""
+    p = Params(n, n, nt, "H1", "none", 1e-3, 0.0)
+    g = Grid(n, n)
+    x1 = 2 * np.pi * np.arange(n)[:, None] / n
+    x2 = 2 * np.pi * np.arange(n)[None, :] / n
+    mT = 0.5 + 0.25 * np.sin(x1) + 0.2 * np.cos(x2) + 0 * x1 * x2
+    mR = 0.5 + 0.25 * np.sin(x1 - shift) + 0.2 * np.cos(x2 - 0.5 * shift) + 0 * x1 * x2
+    return g, p, mT, mR
+
+
+def test_armijo_backtracking_accepts_first_halving_that_decreases_enough():
+    """Default line search (reading: alpha_0 = 1, rho = 1/2, c_1 = 1e-4): every accepted step is
+    alpha = (1/2)^k after k rejections, satisfies J(v + alpha v~) <= J(v) + c_1 alpha dJ(v)[v~], and
+    the previous trial alpha / rho = 2 alpha does not."""
+    g, p, mT, mR = translated_sinusoids()
+    opts = solver.SolveOpts(max_newton=4, fixed_pcg_iters=6, gtol_rel=0.0)
+    assert opts.armijo_c1 == 1e-4 and opts.max_backtracks == 10
+    v, st = solver.solve(g, p, mT, mR, opts)
+    assert st.status == solver.OK and st.backtracks >= 4
+    assert any(h["backtracks"] >= 2 for h in st.history)
+    for h in st.history:
+        a, k = h["alpha"], h["backtracks"]
+        assert a == 0.5 ** k
+        J = lambda t: reduced.objective(g, p, mT, mR, h["v"] + t * h["step"])[0]   # noqa: E731
+        slope = g.inner(reduced.gradient(g, p, mT, mR, h["v"]).g, h["step"])
+        assert slope == pytest.approx(h["slope"], rel=1e-12)
+        assert slope < 0
+        assert J(a) <= h["J"] + 1e-4 * a * slope
+        if k > 0:
+            assert J(2 * a) > h["J"] + 1e-4 * 2 * a * slope
+    assert st.backtracks == sum(h["backtracks"] for h in st.history)
