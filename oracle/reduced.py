@@ -17,6 +17,8 @@ Readings (listed in the design notes):
 """
 from __future__ import annotations
 
+from dataclasses import replace
+
 import numpy as np
 
 from .spectral import (Grid, Params, apply_A, apply_K, apply_Kinv, apply_precond, nyquist_project,
@@ -54,9 +56,10 @@ class Linearization:
     """Everything the GN matvec needs at a linearisation point v: the state trajectory (with the
     stored gradients G_j, G*_j), plus J and g at v."""
 
-    def __init__(self, v, traj, lam, lam_star, b, g, J, terms):
+    def __init__(self, v, traj, lam, lam_star, b, g, J, terms, p=None):
         self.v, self.traj, self.lam, self.lam_star = v, traj, lam, lam_star
         self.b, self.g, self.J, self.terms = b, g, J, terms
+        self.p = p   # the parameters at this point (with eta_bar for the shear-control mass-source K)
 
 
 def gradient(g: Grid, p: Params, mT, mR, v) -> Linearization:
@@ -69,11 +72,21 @@ def gradient(g: Grid, p: Params, mT, mR, v) -> Linearization:
     J, terms, traj = objective_terms(g, p, mT, mR, v)
     lam, lam_star = adjoint_backward(g, p, v, mR - traj.m[-1])
     b = body_force(p, traj, lam, lam_star)
-    if p.norm == "stokes":   # K (the Leray projection or I) of beta_v A[v] + b
-        gr = nyquist_project(g, apply_K(g, p, p.beta_v * stokes.first_variation(g, p.nu, p.eps, v) + b))
+    if p.norm == "stokes":   # K (the Leray projection, I, or K_v with a mass source) of grad J_pen
+        p = at_point(g, p, v)
+        gr = nyquist_project(g, apply_K(g, p, p.beta_v * stokes.first_variation(g, p.nu, p.eps, v) + b
+                                        + penalty_grad_w(g, p, v)))
     else:
         gr = nyquist_project(g, p.beta_v * apply_A(g, p, v) + apply_K(g, p, b))
-    return Linearization(v, traj, lam, lam_star, b, gr, J, terms)
+    return Linearization(v, traj, lam, lam_star, b, gr, J, terms, p)
+
+
+def at_point(g: Grid, p: Params, v):
+    """Parameters with the mean viscosity of v (used by K_v of the shear-control model with a mass
+    source; unchanged otherwise)."""
+    if p.norm == "stokes" and p.constraint == "mass_source":
+        return replace(p, eta_bar=stokes.mean_viscosity(g, p.nu, p.eps, v))
+    return p
 
 
 def hessian_matvec(g: Grid, p: Params, lin: Linearization, vt):
@@ -92,7 +105,9 @@ def _assemble(g: Grid, p: Params, lin, vt, bt):
     """F_Nyq[beta_v B v~ + K b~] (quadratic seminorms: B = A) or F_Nyq K[beta_v B(v)[v~] + b~]
     (shear-control model)."""
     if p.norm == "stokes":
-        return nyquist_project(g, apply_K(g, p, p.beta_v * stokes.second_variation(g, p.nu, p.eps, lin.v, vt) + bt))
+        p = lin.p if lin.p is not None else at_point(g, p, lin.v)
+        return nyquist_project(g, apply_K(g, p, p.beta_v * stokes.second_variation(g, p.nu, p.eps, lin.v, vt) + bt
+                                          + penalty_grad_w(g, p, vt)))
     return nyquist_project(g, p.beta_v * apply_A(g, p, vt) + apply_K(g, p, bt))
 
 

@@ -31,7 +31,7 @@ Readings (listed in the design notes):
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 import math
 
 import numpy as np
@@ -56,6 +56,8 @@ class SolveOpts:
     recycle: int = 0                      # PCG directions of each Newton step kept for the next ones
     hessian: str = "gn"                   # "gn" (the paper's Gauss-Newton) or "full" (exact Hessian)
     lowrank_capacity: int = 16            # most directions the correction holds
+    cfl_max: float = 0.0                  # > 0: n_t adapted to keep the CFL number of the iterate below
+    nt_max: int = 0                       # largest n_t the adaptation may reach (0: p.nt)
 
 
 @dataclass
@@ -71,7 +73,9 @@ class SolveStats:
     J: float = 0.0
     fallback_used: int = 0
     lowrank_dim: int = 0                  # directions in the correction at the end of the solve
-    cfl: float = 0.0                      # CFL number of the final velocity (``cfl_number``)
+    cfl: float = 0.0                      # CFL number of the final velocity (``cfl_number``), final n_t
+    nt: int = 0                           # n_t at the end (raised by the CFL adaptation)
+    nt_changes: int = 0
     lowrank: tuple | None = None          # (Ritz values theta, Ritz vectors z) from precond_U
     history: list = field(default_factory=list)
 
@@ -187,10 +191,28 @@ def corrected_precond(g: Grid, p: Params, theta, Z, HZ):
     return prec
 
 
+def adapt_nt(g: Grid, p: Params, v, cfl_max: float, nt_max: int):
+    """Sec. 4 adapts the number of time steps by monitoring the CFL condition (Sec. 5 starts from
+    n_t = 2 max(n)).  Reading: when C(v) > cfl_max at the current n_t, n_t becomes the smallest value
+    with C(v) <= cfl_max, at most max(p.nt, nt_max); n_t never decreases.  Returns (params, changed)."""
+    if not cfl_max > 0:
+        return p, False
+    c = cfl_number(g, p, v)
+    cap = max(p.nt, nt_max)
+    if c <= cfl_max or p.nt >= cap:
+        return p, False
+    nt_new = min(cap, math.ceil(p.nt * (c / cfl_max) - 1e-9))
+    if nt_new <= p.nt:
+        return p, False
+    return replace(p, nt=nt_new), True
+
+
 def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
     """Alg. 1: inexact reduced-space Gauss-Newton-Krylov with Armijo line search.
 
-    Returns (v, stats).
+    Returns (v, stats).  With opts.cfl_max > 0 the number of time steps follows ``adapt_nt`` before the
+    first Newton step and after every accepted one; the problem is then linearised again at the same
+    v (J and g depend on n_t; g(0) does not).
     """
     st = SolveStats()
     lin0 = reduced.gradient(g, p, mT, mR, np.zeros((2, p.n1, p.n2)))
@@ -206,9 +228,17 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         else:
             st.fallback_used = 1
     v = lin.v
+    p, changed = adapt_nt(g, p, v, opts.cfl_max, opts.nt_max)
+    if changed:
+        st.nt_changes += 1
+        lin = reduced.gradient(g, p, mT, mR, v)
+        st.n_pde += 2
     if opts.hessian not in ("gn", "full"):
         raise ValueError("hessian must be 'gn' or 'full'")
     hess = reduced.hessian_matvec_full if opts.hessian == "full" else reduced.hessian_matvec
+    if p.norm == "stokes" and p.constraint == "mass_source" and (opts.recycle > 0 or opts.precond_U is not None):
+        # the W-product of this model moves with the point (K_v); a stored correction would be stale
+        raise ValueError("no preconditioner correction for the shear-control model with a mass source")
     # deflation set of the preconditioner correction: directions z, H z and e = <z, H z>_W
     E, Zs, HZs = [], [], []
     cap = opts.lowrank_capacity
@@ -220,7 +250,7 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
             st.n_matvec += 1
             st.n_pde += 2
             return hess(g, p, _lin, s)
-        theta, Z, HZ = lowrank_setup(g, p, mv0, list(opts.precond_U))
+        theta, Z, HZ = lowrank_setup(g, lin.p or p, mv0, list(opts.precond_U))
         st.lowrank = (theta, Z)
         E, Zs, HZs = list(theta), list(Z), list(HZ)
     k = 0
@@ -240,12 +270,12 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
             return hess(g, p, _lin, s)
 
         if Zs:
-            prec = corrected_precond(g, p, E, Zs, HZs)
+            prec = corrected_precond(g, lin.p or p, E, Zs, HZs)
         else:
             prec = lambda r: reduced.precond(g, p, r)   # noqa: E731
         rec = []
         vt, its, relres = pcg(mv, prec,
-                      lambda a, b: reduced.w_inner(g, p, a, b), g.norm,
+                      lambda a, b: reduced.w_inner(g, lin.p or p, a, b), g.norm,
                       -lin.g, eta, opts.max_pcg, opts.fixed_pcg_iters,
                       record=rec, record_max=min(opts.recycle, cap - len(Zs)))
         for s_, hs_, e_ in rec:
@@ -253,7 +283,7 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
             HZs.append(hs_)
             E.append(e_)
         st.pcg_iters += its
-        slope = reduced.directional_derivative(g, p, lin.g, vt)
+        slope = reduced.directional_derivative(g, lin.p or p, lin.g, vt)
         alpha = 1.0
         accepted = False
         nbt = 0
@@ -268,15 +298,18 @@ def solve(g: Grid, p: Params, mT, mR, opts: SolveOpts):
         st.backtracks += nbt
         st.history.append(dict(k=k, J=lin.J, g_rel=grel, pcg=its, eta=eta, pcg_relres=relres,
                                alpha=alpha if accepted else 0.0, slope=slope, backtracks=nbt,
-                               v=v.copy(), step=vt.copy()))
+                               v=v.copy(), step=vt.copy(), nt=p.nt))
         if not accepted:
             st.status = ENOTCONV
             break
         v = v + alpha * vt
+        p, changed = adapt_nt(g, p, v, opts.cfl_max, opts.nt_max)
+        st.nt_changes += int(changed)
         lin = reduced.gradient(g, p, mT, mR, v)
         st.n_pde += 2
         k += 1
     st.newton_iters = k
     st.lowrank_dim = len(Zs)
     st.cfl = cfl_number(g, p, lin.v)
+    st.nt = p.nt
     return lin.v, st

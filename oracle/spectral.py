@@ -48,6 +48,7 @@ class Params:
     adjoint: str = "dto"
     nu: float = 1.0
     eps: float = 1e-6
+    eta_bar: float = 0.0   # shear-control model with a mass source: mean viscosity at the point of K
 
     def __post_init__(self):
         if self.norm not in NORMS or self.constraint not in CONSTRAINTS or self.adjoint not in ADJOINT_MODES:
@@ -56,8 +57,8 @@ class Params:
             raise ValueError("bad sizes or weights")
         if (self.constraint == "mass_source") != (self.beta_w > 0):
             raise ValueError("beta_w > 0 exactly when constraint == 'mass_source'")
-        if self.norm == "stokes" and (self.constraint == "mass_source" or not (self.nu > 0 and self.eps > 0)):
-            raise ValueError("the shear-control model takes nu > 0, eps > 0 and no mass source")
+        if self.norm == "stokes" and not (self.nu > 0 and self.eps > 0):
+            raise ValueError("the shear-control model takes nu > 0 and eps > 0")
 
 
 WORKERS = -1
@@ -140,11 +141,17 @@ def A_symbol(g: Grid, p: Params):
 
 def M_symbol(g: Grid, p: Params):
     """M of eq. (project-body-force) for the mass-source model, generalised to A (see module header).
+    For the shear-control model with a mass source (App. A, nonlinear Stokes with a relaxed
+    incompressibility constraint) M = 2 beta_v eta_bar (beta_w (-Lap + I))^{-1} + I with the mean
+    viscosity eta_bar of the point where K is taken (p.eta_bar).
 
     Defined where |k~| > 0; returns +inf at k~ = 0 (where the projection part vanishes anyway).
     """
     with np.errstate(divide="ignore", invalid="ignore"):
-        m = 1.0 + p.beta_v * A_symbol(g, p) / (p.beta_w * g.ksq * (g.ksq + 1.0))
+        if p.norm == "stokes":
+            m = 1.0 + 2.0 * p.beta_v * p.eta_bar / (p.beta_w * (g.ksq + 1.0))
+        else:
+            m = 1.0 + p.beta_v * A_symbol(g, p) / (p.beta_w * g.ksq * (g.ksq + 1.0))
     return np.where(g.ksq > 0, m, np.inf)
 
 

@@ -14,6 +14,15 @@ Readings (listed in the design notes):
     the control equation; for nu = 1 and divergence-free v this is 1/2 beta_v |v|^2_{H1} (+ beta_v eps |Omega|);
   * with the incompressibility constraint the reduced gradient is the Leray projection of
     beta_v A[v] + b (the elimination of the pressure), and the Hessian that of beta_v B[v~] + b~;
+  * with a mass source (relaxed incompressibility, App. A) the pressure elimination splits eta into
+    its mean eta_bar and the rest eta_hat and gives K[b, v] = grad M^{-1} Lap^{-1} div(div(2 beta_v
+    eta_hat E[v]) - b) + b with M = 2 beta_v eta_bar (beta_w(-Lap + I))^{-1} + I.  Since eta_bar is a
+    constant, M is a Fourier multiplier, and -div(2 beta_v eta E[v]) + K[b, v] equals
+    K_v[b + beta_v A[v] - beta_w grad (1 - Lap) div v] with K_v = I - grad M^{-1} Lap^{-1} div: the
+    projection of the gradient of the penalised objective (data + beta_v R + 1/2 beta_w
+    <div v, (1 - Lap) div v>), as for the quadratic seminorms.  The Hessian is K_v applied to beta_v
+    B(v)[v~] + b~ + the penalty's Hessian, with eta_bar of the linearisation point; the PCG inner
+    product is <K_v^{-1} ., .>;
   * the preconditioner is the inverse of beta_v times the vector Laplacian (App. E.2).
 """
 from __future__ import annotations
@@ -41,6 +50,12 @@ def value(g: Grid, nu: float, eps: float, v):
 
 def viscosity(nu: float, eps: float, E):
     return (_EE(E) + eps) ** ((1.0 - nu) / (2.0 * nu))
+
+
+def mean_viscosity(g: Grid, nu: float, eps: float, v):
+    """eta_bar[v] = (1/#Omega) int eta[v]: the constant part of the decomposition eta = eta_hat + eta_bar
+    that App. A uses to eliminate the pressure (the grid mean on the periodic grid)."""
+    return float(np.mean(viscosity(nu, eps, strain(g, v))))
 
 
 def _div_sym(g: Grid, s11, s12, s22):

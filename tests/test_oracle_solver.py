@@ -157,16 +157,21 @@ def test_cfl_number_bounds_spectral_radius_of_the_step_operator():
 
 
 # ---- Armijo backtracking (Sec. 4: Armijo condition with default parameters, N&W Alg. 3.1) --------
-def translated_sinusoids(n=16, nt=8, shift=2.0):
+def translated_sinusoids(n=16, nt=64, shift=1.5, kf=2, beta_v=1e-4):
     """A pair whose reference is the template shifted by (shift, shift/2): the Gauss-Newton model of a
-    shift this large overshoots, so the full step is rejected."""
-    p = Params(n, n, nt, "H1", "none", 1e-3, 0.0)
+    shift this large overshoots, so full steps are rejected (the defaults keep the CFL number of every
+    iterate below 0.9, where the RK2 transport is stable)."""
+    p = Params(n, n, nt, "H1", "none", beta_v, 0.0)
     g = Grid(n, n)
     x1 = 2 * np.pi * np.arange(n)[:, None] / n
     x2 = 2 * np.pi * np.arange(n)[None, :] / n
-    mT = 0.5 + 0.25 * np.sin(x1) + 0.2 * np.cos(x2) + 0 * x1 * x2
-    mR = 0.5 + 0.25 * np.sin(x1 - shift) + 0.2 * np.cos(x2 - 0.5 * shift) + 0 * x1 * x2
+    mT = 0.5 + 0.25 * np.sin(kf * x1) + 0.2 * np.cos(x2) + 0 * x1 * x2
+    mR = 0.5 + 0.25 * np.sin(kf * (x1 - shift)) + 0.2 * np.cos(x2 - 0.5 * shift) + 0 * x1 * x2
     return g, p, mT, mR
+
+
+# the schedule under which the default pair backtracks in its first two Newton steps (alpha = 1/2)
+BACKTRACK_OPTS = dict(max_newton=4, fixed_pcg_iters=6, gtol_rel=0.0)
 
 
 def test_armijo_backtracking_accepts_first_halving_that_decreases_enough():
@@ -174,11 +179,11 @@ def test_armijo_backtracking_accepts_first_halving_that_decreases_enough():
     alpha = (1/2)^k after k rejections, satisfies J(v + alpha v~) <= J(v) + c_1 alpha dJ(v)[v~], and
     the previous trial alpha / rho = 2 alpha does not."""
     g, p, mT, mR = translated_sinusoids()
-    opts = solver.SolveOpts(max_newton=4, fixed_pcg_iters=6, gtol_rel=0.0)
+    opts = solver.SolveOpts(**BACKTRACK_OPTS)
     assert opts.armijo_c1 == 1e-4 and opts.max_backtracks == 10
     v, st = solver.solve(g, p, mT, mR, opts)
-    assert st.status == solver.OK and st.backtracks >= 4
-    assert any(h["backtracks"] >= 2 for h in st.history)
+    assert st.status == solver.OK and st.backtracks >= 2
+    assert max(solver.cfl_number(g, p, h["v"]) for h in st.history) < 0.9
     for h in st.history:
         a, k = h["alpha"], h["backtracks"]
         assert a == 0.5 ** k
@@ -190,3 +195,34 @@ def test_armijo_backtracking_accepts_first_halving_that_decreases_enough():
         if k > 0:
             assert J(2 * a) > h["J"] + 1e-4 * 2 * a * slope
     assert st.backtracks == sum(h["backtracks"] for h in st.history)
+
+
+# ---- CFL-adapted n_t (Sec. 4 monitors the CFL condition and adapts n_t; Sec. 5 starts at 2 max(n)) --
+def test_cfl_adaptation_raises_nt_to_the_smallest_admissible_value():
+    from dataclasses import replace
+    g, p, mT, mR = small_problem(nt=2)
+    opts = solver.SolveOpts(max_newton=8, gtol_rel=1e-4, cfl_max=0.5, nt_max=64)
+    v, st = solver.solve(g, p, mT, mR, opts)
+    assert st.status == solver.OK and st.g_rel <= 1e-4
+    assert st.nt_changes >= 1 and st.nt > 2
+    assert st.cfl <= 0.5
+    nts = [h["nt"] for h in st.history] + [st.nt]
+    assert nts == sorted(nts)
+    iterates = [h["v"] for h in st.history] + [v]
+    for k in range(1, len(nts)):
+        if nts[k] != nts[k - 1]:       # raised after step k-1, at iterate k
+            c = lambda nt: solver.cfl_number(g, replace(p, nt=nt), iterates[k])   # noqa: E731
+            assert c(nts[k - 1]) > 0.5 >= c(nts[k]) and c(nts[k] - 1) > 0.5
+    # a limit never reached changes nothing
+    v0, st0 = solver.solve(g, p, mT, mR, solver.SolveOpts(max_newton=3, gtol_rel=1e-4))
+    v1, st1 = solver.solve(g, p, mT, mR, solver.SolveOpts(max_newton=3, gtol_rel=1e-4, cfl_max=1e3, nt_max=64))
+    assert st1.nt_changes == 0 and st1.nt == 2 and np.array_equal(v0, v1)
+    # the relative gradient's reference g(0) is the same at every n_t (the state is m_T at v = 0)
+    _, st8 = solver.solve(g, replace(p, nt=8), mT, mR, solver.SolveOpts(max_newton=0))
+    assert st8.g0_norm == pytest.approx(st0.g0_norm, rel=1e-13)
+
+
+def test_cfl_adaptation_stops_at_nt_max():
+    g, p, mT, mR = small_problem(nt=2)
+    v, st = solver.solve(g, p, mT, mR, solver.SolveOpts(max_newton=6, gtol_rel=1e-4, cfl_max=0.05, nt_max=5))
+    assert st.nt == 5 and st.cfl > 0.05
