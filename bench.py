@@ -97,19 +97,24 @@ def setup(config: int, precision: str = "fp32", tune_cache: str | None = None):
     return w, P, vlin, vt
 
 
-def bench_pcg(P, vlin, steps, warmup):
+def bench_pcg(P, vlin, steps, warmup, windows=5):
+    """`warmup` untimed PCG iterations, then `windows` timed windows of exactly `steps` iterations
+    each (fixed schedule: no host round trip inside a window), every window bracketed by device
+    synchronisation.  Returns the median window's seconds and all window times."""
     import torch
     g, _ = P.gradient(vlin, want_J=False)
     rhs = -g
     if warmup > 0:
         P.pcg(rhs, eta=0.0, max_iters=warmup, fixed_iters=warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, it, _ = P.pcg(rhs, eta=0.0, max_iters=steps, fixed_iters=steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert it == steps
-    return dt
+    times = []
+    for _ in range(windows):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it, _ = P.pcg(rhs, eta=0.0, max_iters=steps, fixed_iters=steps)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        assert it == steps
+    return sorted(times)[len(times) // 2], times
 
 
 def bench_matvec(P, vt, reps):
@@ -162,6 +167,16 @@ def roofline(P, reps=None, workload="c2"):
 
 
 LOWRANK_CAPACITY = 16   # directions of the preconditioner correction the bench problems can hold
+
+
+def moved_bytes_per_matvec(nt, nn):
+    """Compulsory bytes the implemented GN matvec moves (each operand read once, each result written
+    once), incompressible H1 case: 4 fused stage launches per time step with 13 + 13 + 9 + 17 = 52 FP32
+    fields (208 N), except that the last adjoint stage is the body-force-only pass (11 fields instead
+    of 17); the real-space Nyquist projection of the input (two FP64 reads, FP64 and FP32 writes: 56 N)
+    and the FP64 assembly (row forward 24 N in, 32 N out; column pass 32 N in, 16 N out; row inverse
+    16 N in, 16 N out: 136 N)."""
+    return (208 * nt - 24 + 56 + 136) * nn
 
 
 def bench_solve(P, recycle=0, diagnostics=False):
@@ -244,12 +259,16 @@ def bench_shear_control(n=256, nt=16, beta_v=1e-4):
         d = lambda u, ax: np.real(np.fft.ifft(1j * k * np.fft.fft(u, axis=ax), axis=ax))   # noqa: E731
         return float(np.abs(0.5 * (d(v[0], 1) + d(v[1], 0))).max())
 
-    out = {"workload": f"sliding interfaces {n}^2, n_t={nt}, beta_v={beta_v:g}, divergence-free",
+    out = {"workload": f"sliding interfaces {n}^2, n_t={nt}, beta_v={beta_v:g}; divergence-free unless named "
+                       "mass_source (relaxed incompressibility, beta_w=1e-3)",
            "vstar_max_shear": round(shear(w.vstar), 4)}
-    for name, kw in (("H1", dict(norm="H1")), ("stokes_nu0.5", dict(norm="stokes", nu=0.5, eps=1e-4)),
-                     ("stokes_nu3", dict(norm="stokes", nu=3.0, eps=1e-4)),
-                     ("stokes_nu5", dict(norm="stokes", nu=5.0, eps=1e-4))):
-        P = Problem(mT, mR, nt, constraint="divfree", beta_v=beta_v, beta_w=0.0, precision="fp32", **kw)
+    divfree = dict(constraint="divfree", beta_w=0.0)
+    for name, kw in (("H1", dict(norm="H1", **divfree)), ("stokes_nu0.5", dict(norm="stokes", nu=0.5, eps=1e-4, **divfree)),
+                     ("stokes_nu3", dict(norm="stokes", nu=3.0, eps=1e-4, **divfree)),
+                     ("stokes_nu5", dict(norm="stokes", nu=5.0, eps=1e-4, **divfree)),
+                     ("stokes_nu3_mass_source", dict(norm="stokes", nu=3.0, eps=1e-4, constraint="mass_source",
+                                                     beta_w=1e-3))):
+        P = Problem(mT, mR, nt, beta_v=beta_v, precision="fp32", **kw)
         P.solve(max_newton=50, max_pcg=100, gtol_rel=1e-2, raise_on_error=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -262,6 +281,41 @@ def bench_shear_control(n=256, nt=16, beta_v=1e-4):
                      "status": st["status"], "misfit_rel": round(float(torch.linalg.norm(mR - m1)) / mis0, 5),
                      "max_shear": round(shear(v.cpu().numpy()), 4), "det_F1_min_max": [round(mn, 5), round(mx, 5)]}
         P.close()
+    return out
+
+
+def bench_grid_sizes():
+    """Grids that are not powers of two (mixed-radix 2/3/5 transforms) against the nearest power of
+    two: GN matvec time per grid point at 128 x 150 vs 128 x 128 (n_t = 16) and 1000^2 vs 1024^2
+    (n_t = 32), H1 + divergence-free, FP32 transport, seeded blob-plus-texture images, default launch
+    shapes on both sides (median of 5 timed batches of graph-replayed matvecs)."""
+    import numpy as np
+    import torch
+    import synthdata as sd
+    from paper_1503_00757_amd import Problem
+    dev = torch.device("cuda:0")
+    out = {}
+    for (n1, n2, nt, ref) in ((128, 150, 16, (128, 128)), (1000, 1000, 32, (1024, 1024))):
+        per_point = {}
+        for (a, b) in ((n1, n2), ref):
+            rng = np.random.Generator(np.random.PCG64(sd.BASE_SEED + 600 + a + b))
+            mT = sd.template_image(a, b, 16, 16, rng)
+            vs = sd.scale_to_cfl(sd.random_velocity(a, b, 8, rng, divfree=True), nt, 0.8)
+            vt = sd.unit_l2(sd.random_velocity(a, b, 8, rng, divfree=True))
+            mTd = torch.tensor(mT, device=dev)
+            P0 = Problem(mTd, mTd.clone(), nt, "H1", "divfree", 1e-3, 0.0, "fp32")
+            mR = P0.state_forward(torch.tensor(vs, device=dev))
+            P0.close()
+            P = Problem(mTd, mR, nt, "H1", "divfree", 1e-3, 0.0, "fp32")
+            P.gradient(torch.tensor(0.5 * vs, device=dev), want_J=False)
+            reps = 20 if a * b > 500000 else 100
+            ts = sorted(bench_matvec(P, torch.tensor(vt, device=dev), reps) for _ in range(5))
+            P.close()
+            per_point[f"{a}x{b}"] = {"ms_per_matvec": round(ts[2] * 1e3, 4),
+                                     "ns_per_point": round(ts[2] * 1e9 / (a * b), 4)}
+        k0, k1 = f"{n1}x{n2}", f"{ref[0]}x{ref[1]}"
+        per_point["per_point_ratio"] = round(per_point[k0]["ns_per_point"] / per_point[k1]["ns_per_point"], 3)
+        out[f"{k0}_vs_{k1}_nt{nt}"] = per_point
     return out
 
 
@@ -330,6 +384,28 @@ def bench_batch(npairs=96):
             "speedup_vs_sequential": round(t_seq / t_batch, 2), "per_size": sizes, "launch_shapes": chosen,
             "with_recycled_directions": recycled,
             "data": "synthetic"}
+
+
+def c3_matvec(w3, P3, vlin3, vt3, copy_gbs):
+    """GN matvec throughput at 1024^2, n_t = 32 (reg_hessian_matvec: the Nyquist projection of the
+    input and the graph-replayed matvec), as the median of 5 timed batches of 20, against the survey's
+    byte model (248 N per step + 112 N) and against the bytes the kernels move."""
+    P3.gradient(vlin3, want_J=False)
+    reps3 = sorted(bench_matvec(P3, vt3, 20) for _ in range(5))
+    t3 = reps3[2]
+    nn = w3.n1 * w3.n2
+    bmodel = (248 * w3.nt + 112) * nn
+    bmoved = moved_bytes_per_matvec(w3.nt, nn)
+    rl3 = roofline(P3, workload="c3")
+    return {"matvecs_per_s": round(1.0 / t3, 2), "ms_per_matvec": round(t3 * 1e3, 3),
+            "ms_per_matvec_min_max_of_5": [round(reps3[0] * 1e3, 3), round(reps3[-1] * 1e3, 3)],
+            "model_bytes_per_matvec": bmodel,
+            "model_frac_of_8TBs": round(bmodel / t3 / 8e12, 4),
+            "model_frac_of_measured_copy": round(bmodel / t3 / (copy_gbs * 1e9), 4),
+            "moved_bytes_per_matvec": bmoved,
+            "moved_frac_of_8TBs": round(bmoved / t3 / 8e12, 4),
+            "launch_shapes": P3.tuned,
+            "dominant_kernel": rl3}
 
 
 def _single_thread():
@@ -442,18 +518,30 @@ def cpu_baseline(budget_s=12.0):
         if dt > budget_s or n >= 200:
             break
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    out = {"value": round(n / dt, 3), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
-           "sample": f"{n} FP64 oracle GN matvecs (numpy/scipy.fft, all cores) on the 256^2, n_t=16 workload "
-                     f"at its linearisation point, {dt:.1f} s"}
-    # the same matvec with one scipy.fft worker, and the oracle's full solves of configs 1 and 2
+    all_cores = n / dt
+    # the same matvec with one scipy.fft worker (faster on small transforms: no thread hand-off)
     spectral.set_workers(1)
     n1 = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < 4.0 and n1 < 50:
+    while time.perf_counter() - t0 < 6.0 and n1 < 80:
         reduced.hessian_matvec(g, p, lin, w.vtilde)
         n1 += 1
-    out["single_worker_matvecs_per_s"] = round(n1 / (time.perf_counter() - t0), 3)
+    dt1 = time.perf_counter() - t0
+    one = n1 / dt1
     spectral.set_workers(-1)
+    # the baseline is the faster of the two setups, with the threads that setup used
+    if one >= all_cores:
+        out = {"value": round(one, 3), "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n1} FP64 oracle GN matvecs (numpy/scipy.fft, one worker) on the 256^2, n_t=16 "
+                         f"workload at its linearisation point, {dt1:.1f} s"}
+    else:
+        out = {"value": round(all_cores, 3), "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+               "sample": f"{n} FP64 oracle GN matvecs (numpy/scipy.fft, all cores) on the 256^2, n_t=16 "
+                         f"workload at its linearisation point, {dt:.1f} s"}
+    out["all_cores_matvecs_per_s"] = round(all_cores, 3)
+    out["all_cores_threads"] = cores
+    out["single_worker_matvecs_per_s"] = round(one, 3)
+    # the oracle's full solves of configs 1 and 2
     from oracle import solver
     w1 = sd.make_workload(1)
     p1 = Params(w1.n1, w1.n2, w1.nt, w1.norm, w1.constraint, w1.beta_v, w1.beta_w)
@@ -476,7 +564,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the solve and 1024^2 measurements")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "grids"], default="c2",
                     help="c2: 256^2 headline workload (default); c3: 1024^2, n_t=32 (profiling); "
                          "c4: 96-pair batched solve; c5: learned warm start alone")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned warm-start leg (config 5)")
@@ -513,6 +601,9 @@ def main():
     if args.workload == "c4":
         print(json.dumps(bench_batch()))
         return
+    if args.workload == "grids":
+        print(json.dumps(bench_grid_sizes()))
+        return
     if args.workload == "c5":
         r = bench_warmstart(*ws_pairs, epochs=args.warmstart_epochs, label_pool=args.warmstart_label_pool)
         t = r["time_to_grel_1e-2_ms"]
@@ -524,8 +615,8 @@ def main():
     cfg = 2 if args.workload == "c2" else 3
     print(f"[bench] workload {args.workload} setup", file=sys.stderr, flush=True)
     w, P, vlin, vt = setup(cfg, tune_cache=args.tune_cache)
-    dt = bench_pcg(P, vlin, args.steps, args.warmup)
-    print(f"[bench] pcg {args.steps} steps {dt:.3f}s", file=sys.stderr, flush=True)
+    dt, windows = bench_pcg(P, vlin, args.steps, args.warmup)
+    print(f"[bench] pcg {len(windows)} windows of {args.steps} steps, median {dt:.4f}s", file=sys.stderr, flush=True)
     rl = roofline(P, workload=args.workload)
     copy_gbs = copy_bandwidth()
     rl["measured_copy_GBs"] = copy_gbs
@@ -541,23 +632,17 @@ def main():
         extras["gauss_newton_vs_full_newton"] = bench_hessians(cfg)
         print("[bench] shear-control regularisation", file=sys.stderr, flush=True)
         extras["shear_control_sliding"] = bench_shear_control()
+        extras["shear_control_sliding_512"] = bench_shear_control(n=512, nt=16)
+        print("[bench] grids that are not powers of two", file=sys.stderr, flush=True)
+        extras["non_power_of_two_grids"] = bench_grid_sizes()
+    if cfg == 3:
+        extras["c3_1024sq_nt32"] = c3_matvec(w, P, vlin, vt, copy_gbs)
     P.close()
     if not args.no_extras and cfg == 2:
         print("[bench] 1024^2 nt=32", file=sys.stderr, flush=True)
         w3, P3, vlin3, vt3 = setup(3)
-        P3.gradient(vlin3, want_J=False)
-        reps3 = sorted(bench_matvec(P3, vt3, 20) for _ in range(5))
-        t3 = reps3[2]   # median of 5 timed batches of 20 graph-replayed matvecs
-        nn = w3.n1 * w3.n2
-        bmodel = (248 * w3.nt + 112) * nn
-        rl3 = roofline(P3, workload="c3")
+        extras["c3_1024sq_nt32"] = c3_matvec(w3, P3, vlin3, vt3, copy_gbs)
         P3.close()
-        extras["c3_1024sq_nt32"] = {"matvecs_per_s": round(1.0 / t3, 2), "ms_per_matvec": round(t3 * 1e3, 3),
-                                    "ms_per_matvec_min_max_of_5": [round(reps3[0] * 1e3, 3), round(reps3[-1] * 1e3, 3)],
-                                    "model_bytes_per_matvec": bmodel,
-                                    "model_frac_of_8TBs": round(bmodel / t3 / 8e12, 4),
-                                    "model_frac_of_measured_copy": round(bmodel / t3 / (copy_gbs * 1e9), 4),
-                                    "dominant_kernel": rl3}
     if ws_pairs is not None:
         print("[bench] c5 learned warm start", file=sys.stderr, flush=True)
         extras["c5_warm_start"] = bench_warmstart(*ws_pairs, epochs=args.warmstart_epochs,
@@ -582,6 +667,8 @@ def main():
         "roofline": rl,
         "cpu_baseline": cpu,
         "launch_shapes": tuned,
+        # the timed region: 5 windows of exactly `steps` PCG iterations; `value` is from the median one
+        "window_ms": [round(t * 1e3, 4) for t in windows],
     }
     out.update(extras)
     print(json.dumps(out))

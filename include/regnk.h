@@ -22,9 +22,10 @@
  *    removed before use, and every velocity-like output has none (spectral derivatives use the
  *    Nyquist wavenumber 0 so that they are exactly skew-symmetric).
  *  - Sizes: n1, n2 even in [8, 2048]; nt >= 1; beta_v > 0; beta_w > 0 exactly when
- *    constraint == REG_MASS_SOURCE.  Anything else is REG_EINVAL.  Powers of two take the FFT
- *    kernels; other even lengths take direct O(n^2)-per-line spectral sums along that axis (same
- *    operators, slower).
+ *    constraint == REG_MASS_SOURCE.  Anything else is REG_EINVAL.  Powers of two take the
+ *    register FFT kernels; other lengths of the form 2^a 3^b 5^c take mixed-radix (2, 3, 4, 5, 8)
+ *    FFTs staged in LDS; the remaining even lengths take direct O(n^2)-per-line spectral sums along
+ *    that axis (same operators, slower).
  */
 #ifndef REGNK_H
 #define REGNK_H
@@ -55,7 +56,11 @@ enum { REG_H1 = 1, REG_H2 = 2, REG_H3 = 3, REG_STOKES = 4 };
  * enter the gradient and the Hessian, projected together with the body force under
  * REG_DIVFREE; the preconditioner is the inverse vector Laplacian (App. E.2).  nu = stokes_nu > 0
  * (nu > 1 thins, nu < 1 thickens under shear), eps = stokes_eps > 0 keeps eta finite where the
- * strain vanishes.  Not with REG_MASS_SOURCE. */
+ * strain vanishes.  With REG_MASS_SOURCE (relaxed incompressibility, App. A) the projection is
+ * K[b, v] with M = 2 beta_v eta_bar (beta_w(-Lap + I))^{-1} + I, eta_bar the mean viscosity at the
+ * linearisation point, applied to b, beta_v times the first (second) variation and the gradient
+ * (Hessian) of 1/2 beta_w <div v, (1 - Lap) div v>; PCG then uses <K^{-1} ., .> with that K, and the
+ * low-rank preconditioner correction is not available (REG_EINVAL). */
 /* Constraint on div v (Sec. 2): gamma = 0; gamma = 1 with w = 0 (incompressible); gamma = 1 with a
  * mass source w penalised by its H1 norm (eq. (reg-w)), beta_w > 0. */
 enum { REG_UNCONSTRAINED = 0, REG_DIVFREE = 1, REG_MASS_SOURCE = 2 };
@@ -88,7 +93,9 @@ typedef struct {
     int32_t lowrank_capacity; /* 0..64: directions the low-rank preconditioner correction of
                                  reg_solve can hold (workspace grows by 2 vector fields per direction,
                                  4 for REG_MASS_SOURCE); 0 = no correction */
-    int32_t reserved;     /* must be 0 */
+    int32_t nt_max;       /* 0, or nt..4096: the largest n_t that reg_solve's CFL adaptation
+                             (reg_solve_opts.cfl_max) may raise n_t to; the workspace holds the
+                             trajectory of max(nt, nt_max) steps */
     double beta_v;        /* weight of the v seminorm (> 0) */
     double beta_w;        /* weight of the mass-source norm (> 0 iff REG_MASS_SOURCE) */
     double stokes_nu;     /* REG_STOKES: nu > 0; otherwise 0 */
@@ -183,6 +190,14 @@ typedef struct {
     int32_t recycle;          /* >= 0: the first `recycle` search directions of each Newton step's
                                  PCG solve (mutually H-conjugate) are added to the set for the later
                                  steps, until it is full; no extra matvecs.  Needs capacity > 0. */
+    /* CFL-adapted n_t (Sec. 4 adapts the number of time steps by monitoring the CFL condition of the
+     * explicit RK2 steps; Sec. 5 starts from n_t = 2 max(n1, n2)).  cfl_max > 0: before the first
+     * Newton step and after every accepted one, C(v) = h_t (max|v_1| n1/2 + max|v_2| n2/2) of the
+     * iterate is checked; when C > cfl_max, n_t is raised to the smallest value with C <= cfl_max
+     * (at most params.nt_max) and the problem is re-linearised at the same v (J and g change with
+     * n_t; g(0) does not).  n_t never decreases; the new n_t stays with the handle after the solve.
+     * 0 = n_t fixed. */
+    double cfl_max;
 } reg_solve_opts;
 
 typedef struct {
@@ -192,7 +207,10 @@ typedef struct {
     double g0_norm;           /* ||g(0)|| at v = 0 (also for a warm start) */
     double g_rel;             /* final ||g|| / ||g(0)|| */
     double J;                 /* final objective */
-    double cfl;               /* CFL number of the final velocity (see reg_cfl) */
+    double cfl;               /* CFL number of the final velocity (see reg_cfl) at the final n_t */
+    int32_t nt;               /* n_t at the end of the solve (differs from params.nt after a CFL
+                                 adaptation) */
+    int32_t nt_changes;       /* how many times the CFL adaptation raised n_t */
 } reg_solve_stats;
 
 /* Alg. 1: globalised inexact reduced-space Gauss-Newton-Krylov solve from v0 (or 0): PCG Newton
@@ -204,19 +222,18 @@ reg_status reg_solve(reg_problem* h, const reg_solve_opts* opts, double* v_out,
 
 /* Batched Alg. 1: solve `count` independent problems (any mix of sizes, steps and weights), pair i
  * with opts[i] into v_out[i] (device vector field of that problem's size), stats into
- * stats_host[i] (nullable).  Pairs run concurrently on up to eight internal streams, largest
- * first; each problem's own stream is synchronised before its solve starts, and every solve has
+ * stats_host[i] (nullable).  Pairs run concurrently on up to eight internal streams (the environment
+ * variable REGNK_BATCH_WORKERS, 1..32, sets another count), largest first; each problem's own stream is synchronised before its solve starts, and every solve has
  * finished when the call returns.  A problem may appear only once.  Returns the first failure
  * (REG_ENOTCONV after all others); stats carry each pair's own status. */
 reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const reg_solve_opts* opts,
                            double* const* v_out, reg_solve_stats* stats_host);
 
-/* CFL number of a velocity for this problem's n_t (Sec. 4: the explicit RK2 steps are only
+/* CFL number of a velocity for this problem's current n_t (Sec. 4: the explicit RK2 steps are only
  * conditionally stable, and the paper monitors the CFL condition to adapt n_t):
  * C = h_t (max|v_1| n1/2 + max|v_2| n2/2), the largest |h_t k . v| over the resolved modes, of the
- * Nyquist-projected v.  A caller that wants the paper's adaptive n_t re-creates the problem with a
- * larger n_t when C exceeds its limit.  v: device vector field; cfl_host: host double.
- * Synchronises the stream. */
+ * Nyquist-projected v.  reg_solve adapts n_t itself with reg_solve_opts.cfl_max.  v: device vector
+ * field; cfl_host: host double.  Synchronises the stream. */
 reg_status reg_cfl(reg_problem* h, const double* v, double* cfl_host);
 
 /* Deformation diagnostics of a velocity (appendix "Illustration of Deformation Map"): the

@@ -18,5 +18,5 @@ from .ffi import (  # noqa: F401
     REG_FNO_PARAMS,
     reg_last_error,
 )
-from .problem import Problem, batch_solve, solve_adaptive_nt  # noqa: F401
+from .problem import Problem, batch_solve, paper_nt  # noqa: F401
 from .warmstart import Network, WarmStart  # noqa: F401

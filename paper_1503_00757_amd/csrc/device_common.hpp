@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mr_plan.hpp"
+
 namespace regnk {
 
 template <typename T>
@@ -292,6 +294,94 @@ __device__ __forceinline__ void fftE(cpx<T> (&x)[E], cpx<T>* __restrict__ lds0, 
     static_assert(N >= 2 * E, "N >= 2E");
     fft_stages<T, N, E, 1, INV, 0, NW>(x, lds0, lds1, t, W, buf);
 }
+
+// ---- mixed-radix FFT in LDS (axis lengths 2^a 3^b 5^c that are not powers of two; plan in mr_plan.hpp) --
+// In-place DFT of 3 and 5 points (forward: exp(-2 pi i n k / R); inverse: conjugate), from the
+// symmetric pairs a_r +- a_{R-r}: X_k = a_0 + sum_r cos(2 pi r k / R)(a_r + a_{R-r})
+//                                         -+ i sum_r sin(2 pi r k / R)(a_r - a_{R-r}).
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2) {
+    const T s = INV ? T(0.86602540378443864676) : T(-0.86602540378443864676);   // Im exp(-+2 pi i / 3)
+    const cpx<T> t1 = cadd(a1, a2), t2 = csub(a1, a2);
+    const cpx<T> m = {a0.x - T(0.5) * t1.x, a0.y - T(0.5) * t1.y};
+    const cpx<T> js = {-s * t2.y, s * t2.x};   // i s (a1 - a2)
+    a0 = cadd(a0, t1);
+    a1 = cadd(m, js);
+    a2 = csub(m, js);
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3, cpx<T>& a4) {
+    const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);   // cos(2 pi / 5), cos(4 pi / 5)
+    const T sg = INV ? T(1) : T(-1);
+    const T s1 = sg * T(0.95105651629515357212), s2 = sg * T(0.58778525229247312917);   // sin(2 pi / 5), sin(4 pi / 5)
+    const cpx<T> t1 = cadd(a1, a4), t2 = cadd(a2, a3), t3 = csub(a1, a4), t4 = csub(a2, a3);
+    const cpx<T> m1 = {a0.x + c1 * t1.x + c2 * t2.x, a0.y + c1 * t1.y + c2 * t2.y};
+    const cpx<T> m2 = {a0.x + c2 * t1.x + c1 * t2.x, a0.y + c2 * t1.y + c1 * t2.y};
+    const cpx<T> u = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};   // X1, X4: m1 +- i u
+    const cpx<T> w = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};   // X2, X3: m2 +- i w
+    a0 = cadd(a0, cadd(t1, t2));
+    a1 = {m1.x - u.y, m1.y + u.x};
+    a4 = {m1.x + u.y, m1.y - u.x};
+    a2 = {m2.x - w.y, m2.y + w.x};
+    a3 = {m2.x + w.y, m2.y - w.x};
+}
+
+// One Stockham stage of radix R (decimation in time): butterfly j < n/R of the stage with NS = product of
+// the earlier radices reads src[j + r n/R], multiplies input r by W_{NS R}^{r k} (k = j mod NS), takes the
+// R-point DFT and writes dst[(j - k) R + k + r NS].
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void mr_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst, int n, int ns_prev,
+                                         const cpx<T>* __restrict__ tw, int t, int nthr) {
+    const int m = n / R, step = n / (ns_prev * R);
+    for (int j = t; j < m; j += nthr) {
+        const int k = j % ns_prev;
+        cpx<T> a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = src[j + r * m];
+        if (ns_prev > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[r] = ctw<T, INV>(a[r], tw[r * k * step]);
+        }
+        if constexpr (R == 3) dft3<T, INV>(a[0], a[1], a[2]);
+        else if constexpr (R == 5) dft5<T, INV>(a[0], a[1], a[2], a[3], a[4]);
+        else dftR<T, R, INV>(a);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[base + r * ns_prev] = a[r];
+    }
+}
+
+// Length-pl.n DFT of the sequence in `a` (LDS), with `b` (LDS, same length) as the other buffer of the
+// ping-pong; nthr cooperating threads (index t).  Returns the buffer that holds the result (natural
+// order).  Every thread of the block must call it with the same plan (it contains __syncthreads); the
+// caller synchronises before the first stage reads `a`.  tw[m] = exp(-2 pi i m / n).
+// act = false: the thread only takes part in the barriers (a block may hold more threads than its
+// transforms use).
+template <typename T, bool INV>
+__device__ cpx<T>* fft_mr(cpx<T>* a, cpx<T>* b, const MrPlan& pl, const cpx<T>* __restrict__ tw, int t, int nthr,
+                          bool act = true) {
+    int ns = 1;
+    const int t0 = act ? t : pl.n;   // an inactive thread starts past every stage's last butterfly
+    for (int s = 0; s < pl.ns; ++s) {
+        const int R = pl.r[s];
+        switch (R) {
+            case 2: mr_stage<T, 2, INV>(a, b, pl.n, ns, tw, t0, nthr); break;
+            case 3: mr_stage<T, 3, INV>(a, b, pl.n, ns, tw, t0, nthr); break;
+            case 4: mr_stage<T, 4, INV>(a, b, pl.n, ns, tw, t0, nthr); break;
+            case 5: mr_stage<T, 5, INV>(a, b, pl.n, ns, tw, t0, nthr); break;
+            default: mr_stage<T, 8, INV>(a, b, pl.n, ns, tw, t0, nthr); break;
+        }
+        __syncthreads();
+        cpx<T>* c = a;
+        a = b;
+        b = c;
+        ns *= R;
+    }
+    return a;
+}
+
+// Signed wavenumber of DFT index e on a length-n axis (any even n), Nyquist index mapped to 0.
+__device__ __forceinline__ int kwave_n(int e, int n) { return e < n / 2 ? e : (2 * e == n ? 0 : e - n); }
 
 // Signed integer wavenumber of DFT index e on a length-N axis, with the Nyquist index mapped to 0.
 template <int N>

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mr_plan.hpp"
+
 namespace regnk {
 
 template <typename T>
@@ -49,6 +51,8 @@ struct StageArgs {
     const cpx<T>* tw2;       // twiddles of length n2 (row transforms)
     const T* dc1;            // axis lengths that are not powers of two: the circulant spectral
     const T* dc2;            // derivative along x1 / x2 (length n1 / n2), else unused
+    MrPlan mr1, mr2;         // mixed-radix plans of the two axis lengths (ns = 0: power of two, or a
+                             // length with another prime factor, which takes the circulant)
     unsigned long long* clk; // timing (nullable): block b stores its start / end (device wall clock)
                              // to clk[2b], clk[2b+1]; a stage has at most (n1 + n2) / 2 blocks
 };
@@ -90,6 +94,9 @@ struct SpecParams {
                              // precondition with the vector Laplacian)
     int constraint;          // 0 none, 1 divfree, 2 mass source
     double beta_v, beta_w;
+    MrPlan mr1, mr2;         // mixed-radix plans of n1, n2 (used for lengths that are not powers of two)
+    const double* eta_sum;   // shear-control model with a mass source: device sum of the viscosity
+                             // at the point of K (its mean eta_bar = sum / (n1 n2) enters M)
 };
 
 // Forward row pass: real vector fields -> half spectra (k2 < n2/2) in spec[field][comp][n1][n2/2].

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <thread>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,7 +48,11 @@ constexpr int NSCAL = 32;
 constexpr int MAX_TIMED = 512;   // timed stage launches per reg_time_pass call
 // shear-control model, FP64 fields: partials dv (4), stress (3), stress gradients (6), E (3) and eta (1)
 // at the linearisation point, integrand (1), regularisation term (2)
-enum { STK_DV = 0, STK_SIG = 4, STK_DS = 7, STK_E = 13, STK_ETA = 16, STK_DENS = 17, STK_R = 18, STK_FIELDS = 20 };
+// and the mass-source penalty's gradient (2)
+enum { STK_DV = 0, STK_SIG = 4, STK_DS = 7, STK_E = 13, STK_ETA = 16, STK_DENS = 17, STK_R = 18, STK_PEN = 20,
+       STK_FIELDS = 22 };
+// device scalars: {min, max, sum} of the shear-control viscosity at the linearisation point
+constexpr int SC_ETA = 28;
 // scalars of the low-rank correction: valid-slot count, a spare count, e_k, <z_k, r>_W, <Hz_k, y>_W
 enum { LRS_CNT = 0, LRS_CNT2 = 1, LRS_E = 8, LRS_DA = LRS_E + LR_MAX, LRS_DB = LRS_DA + LR_MAX,
        LRS_G = LRS_DB + LR_MAX, LRS_N = LRS_G + LR_MIX_MAX * LR_MIX_MAX };
@@ -83,7 +88,6 @@ reg_status check_params(const reg_params* p) {
     if (p->norm == REG_STOKES) {
         if (!(p->stokes_nu > 0.0 && std::isfinite(p->stokes_nu)) || !(p->stokes_eps > 0.0 && std::isfinite(p->stokes_eps)))
             return fail(REG_EINVAL, "REG_STOKES needs stokes_nu > 0 and stokes_eps > 0");
-        if (p->constraint == REG_MASS_SOURCE) return fail(REG_EINVAL, "REG_STOKES does not take a mass source");
     } else if (p->stokes_nu != 0.0 || p->stokes_eps != 0.0) {
         return fail(REG_EINVAL, "stokes_nu and stokes_eps must be 0 unless norm is REG_STOKES");
     }
@@ -96,7 +100,8 @@ reg_status check_params(const reg_params* p) {
     if (p->hessian != REG_HESS_GN && p->hessian != REG_HESS_FULL) return fail(REG_EINVAL, "hessian=%d", p->hessian);
     if (p->hessian == REG_HESS_FULL && p->adjoint != REG_ADJ_DISCRETE)
         return fail(REG_EINVAL, "the full-Newton Hessian needs adjoint = REG_ADJ_DISCRETE");
-    if (p->reserved != 0) return fail(REG_EINVAL, "reserved must be 0");
+    if (p->nt_max != 0 && (p->nt_max < p->nt || p->nt_max > 4096))
+        return fail(REG_EINVAL, "nt_max=%d: must be 0 or in [nt=%d, 4096]", p->nt_max, p->nt);
     if (p->lowrank_capacity < 0 || p->lowrank_capacity > LR_MAX)
         return fail(REG_EINVAL, "lowrank_capacity=%d out of range [0, %d]", p->lowrank_capacity, LR_MAX);
     if (!(p->beta_v > 0.0) || !std::isfinite(p->beta_v)) return fail(REG_EINVAL, "beta_v must be > 0");
@@ -110,17 +115,21 @@ reg_status check_params(const reg_params* p) {
 // timing slots per stage launch: one per block, at most (n1 + n2) / 2 blocks
 size_t clk_slots(const reg_params* p) { return (size_t)(p->n1 + p->n2) / 2; }
 
+// time steps the workspace holds: n_t, or the largest n_t the CFL adaptation may reach
+int nt_capacity(const reg_params* p) { return p->nt_max > p->nt ? p->nt_max : p->nt; }
+
 Offsets layout(const reg_params* p) {
     Offsets o{};
     Layout L;
     const size_t nn = (size_t)p->n1 * p->n2;
     const size_t ts = p->precision == REG_FP64 ? 8 : 4;
+    const size_t ntc = (size_t)nt_capacity(p);
     o.mT = L.take(nn * ts);
     o.mR = L.take(nn * ts);
     o.vT = L.take(2 * nn * ts);
     o.vw = L.take(2 * nn * ts);
     o.vtT = L.take(2 * nn * ts);
-    o.traj = L.take((size_t)(2 * p->nt + 1) * 2 * nn * ts);
+    o.traj = L.take((2 * ntc + 1) * 2 * nn * ts);
     for (int i = 0; i < NFIELD; ++i) o.fld[i] = L.take(nn * ts);
     o.B = L.take(2 * nn * ts);
     o.Bt = L.take(2 * nn * ts);
@@ -159,8 +168,8 @@ Offsets layout(const reg_params* p) {
     o.lrsc = L.take(cap ? LRS_N * 8 : 0);
     o.lrpart = L.take(cap ? (size_t)LR_MAX * RED_BLOCKS * 8 : 0);
     const bool full = p->hessian == REG_HESS_FULL;
-    o.lamtraj = L.take(full ? (size_t)2 * p->nt * nn * ts : 0);
-    o.gmt = L.take(full ? (size_t)2 * p->nt * 2 * nn * ts : 0);
+    o.lamtraj = L.take(full ? 2 * ntc * nn * ts : 0);
+    o.gmt = L.take(full ? 2 * ntc * 2 * nn * ts : 0);
     o.stk = L.take(p->norm == REG_STOKES ? (size_t)STK_FIELDS * nn * 8 : 0);
     o.total = L.total;
     return o;
@@ -270,6 +279,8 @@ StageArgs<T> base_args(const reg_problem* P) {
     a.tw2 = tv.tw2();
     a.dc1 = tv.dc1();
     a.dc2 = tv.dc2();
+    a.mr1 = P->sp.mr1;
+    a.mr2 = P->sp.mr2;
     return a;
 }
 
@@ -475,13 +486,15 @@ reg_status dots(reg_problem* P, int k, const double* const* a, const double* con
 reg_status stokes_value(reg_problem* P, const double* v64, double* out);
 
 reg_status reg_terms(reg_problem* P, const double* v64, double* rv, double* rw) {
-    if (P->p.norm == REG_STOKES) {
+    const bool ms = P->p.constraint == REG_MASS_SOURCE;
+    const bool st = P->p.norm == REG_STOKES;
+    if (st) {
         *rw = 0.0;
-        return stokes_value(P, v64, rv);
+        CKS(stokes_value(P, v64, rv));
+        if (!ms) return REG_OK;
     }
     double* t0 = P->at<double>(P->o.tmp0);
     double* t1 = P->at<double>(P->o.tmp1);
-    const bool ms = P->p.constraint == REG_MASS_SOURCE;
     CKS(spec_fwd<double>(P, 0, v64));
     CKS(spec_col(P, SPEC_REG, false, ms));
     CKS(spec_inv2(P, t0, ms ? t1 : nullptr));
@@ -489,7 +502,7 @@ reg_status reg_terms(reg_problem* P, const double* v64, double* rv, double* rw) 
     const double* b[2] = {t0, t1};
     double r[2] = {0, 0};
     CKS(dots(P, ms ? 2 : 1, a, b, r));
-    *rv = 0.5 * P->h1h2 * r[0];
+    if (!st) *rv = 0.5 * P->h1h2 * r[0];
     *rw = ms ? 0.5 * P->h1h2 * r[1] : 0.0;
     return REG_OK;
 }
@@ -525,20 +538,40 @@ reg_status stokes_divergence(reg_problem* P, double scale) {
     return REG_OK;
 }
 
-// beta_v A[v] into STK_R; keeps E and eta at v (the point of later Hessian matvecs)
+// Mass-source penalty gradient -beta_w grad (1 - Lap) div x (the second result of SPEC_REG) into out.
+reg_status penalty_grad(reg_problem* P, const double* x, double* out) {
+    CKS(spec_fwd<double>(P, 0, x));
+    CKS(spec_col(P, SPEC_REG, false, true));
+    CK(launch_spec_row_inv2(P->sp, P->spec(), nullptr, out, P->at<cpx<double>>(P->o.tw2d), P->stream));
+    return REG_OK;
+}
+
+// beta_v A[v] into STK_R; keeps E and eta at v (the point of later Hessian matvecs).  With a mass
+// source also the sum of eta at v (its mean enters M of K_v) and the penalty gradient, added to STK_R.
 reg_status stokes_first(reg_problem* P, const double* v64) {
     CKS(stokes_partials(P, v64));
     CK(launch_stokes_first(P->nn, stk(P, STK_DV), P->p.stokes_nu, P->p.stokes_eps, stk(P, STK_SIG), stk(P, STK_E),
                            stk(P, STK_ETA), nullptr, P->stream));
-    return stokes_divergence(P, -P->p.beta_v);
+    CKS(stokes_divergence(P, -P->p.beta_v));
+    if (P->p.constraint == REG_MASS_SOURCE) {
+        CK(launch_minmaxsum(stk(P, STK_ETA), P->nn, P->partial(), P->scal() + SC_ETA, P->stream));
+        CKS(penalty_grad(P, v64, stk(P, STK_PEN)));
+        CK(launch_add_scaled(2 * P->nn, stk(P, STK_R), 1.0, stk(P, STK_PEN), stk(P, STK_R), P->stream));
+    }
+    return REG_OK;
 }
 
-// beta_v B(v)[v~] into STK_R at the kept point
+// beta_v B(v)[v~] (+ the penalty's Hessian with a mass source) into STK_R at the kept point
 reg_status stokes_second(reg_problem* P, const double* vt64) {
     CKS(stokes_partials(P, vt64));
     CK(launch_stokes_second(P->nn, stk(P, STK_DV), stk(P, STK_E), stk(P, STK_ETA), P->p.stokes_nu, P->p.stokes_eps,
                             stk(P, STK_SIG), P->stream));
-    return stokes_divergence(P, -P->p.beta_v);
+    CKS(stokes_divergence(P, -P->p.beta_v));
+    if (P->p.constraint == REG_MASS_SOURCE) {
+        CKS(penalty_grad(P, vt64, stk(P, STK_PEN)));
+        CK(launch_add_scaled(2 * P->nn, stk(P, STK_R), 1.0, stk(P, STK_PEN), stk(P, STK_R), P->stream));
+    }
+    return REG_OK;
 }
 
 // beta_v R(v) (host), without touching the kept point
@@ -964,7 +997,9 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     CK(hipStreamSynchronize(P->stream));
     if (!std::isfinite(h[S_RR]) || !std::isfinite(h[S_RZ])) return fail(REG_ENONFINITE, "PCG: not finite");
     const int done = (int)h[S_ITER];
-    if (nmv) *nmv += done;
+    // matvecs that ran: with a fixed schedule the iterations after a breakdown still run (kappa = 0,
+    // x and r stay put), so count the launched iterations rather than the completed ones
+    if (nmv) *nmv += l;
     if (recorded && record > 0) {
         const int ok = h[S_BREAK] > 0 ? (int)h[S_BREAK] - 1 : done;   // steps with <s, H s>_W > 0
         *recorded = std::max(0, std::min(record, ok));
@@ -1036,6 +1071,33 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
         }
     }
     CK(hipMemcpyAsync(v, P->at<double>(P->o.v64), n * 8, hipMemcpyDeviceToDevice, P->stream));
+    // CFL-adapted n_t (Sec. 4): raise n_t when the iterate violates the limit, then re-linearise
+    const int ntc = nt_capacity(&P->p);
+    auto adapt_nt = [&](bool& changed) -> reg_status {
+        changed = false;
+        if (!(o->cfl_max > 0.0)) return REG_OK;
+        double c = 0;
+        CKS(cfl_t(P, v, &c));
+        if (c <= o->cfl_max || P->nt >= ntc) return REG_OK;
+        const double want = std::ceil(P->nt * (c / o->cfl_max) - 1e-9);
+        const int nt_new = (int)std::min((double)ntc, want);
+        if (nt_new <= P->nt) return REG_OK;
+        P->nt = P->p.nt = nt_new;
+        drop_graphs(P);   // the captured launch sequences have n_t steps
+        ++S.nt_changes;
+        changed = true;
+        return REG_OK;
+    };
+    {
+        bool changed = false;
+        CKS(adapt_nt(changed));
+        if (changed) {
+            CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
+            S.n_pde += 2;
+            const double* a[1] = {g};
+            CKS(dots(P, 1, a, a, &gg));
+        }
+    }
     // low-rank correction of the PCG preconditioner: Rayleigh-Ritz on the caller directions at the
     // first linearisation point, then (recycle > 0) the leading PCG directions of every Newton step
     struct LrOff {
@@ -1099,6 +1161,10 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
         S.backtracks += nbt;
         if (!accepted) { status = REG_ENOTCONV; break; }
         CK(launch_add_scaled(n, v, alpha, vt, v, P->stream));
+        {
+            bool changed = false;
+            CKS(adapt_nt(changed));
+        }
         CKS(gradient_t<T>(P, v, g, W ? kg : nullptr, &J));
         S.n_pde += 2;
         {
@@ -1113,6 +1179,7 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
     S.g_rel = grel;
     S.J = J;
     S.status = status;
+    S.nt = P->nt;
     CK(hipMemcpyAsync(vout, P->at<double>(P->o.v64), n * 8, hipMemcpyDeviceToDevice, P->stream));
     CK(hipStreamSynchronize(P->stream));
     if (st) *st = S;
@@ -1457,7 +1524,12 @@ reg_status reg_create(const reg_params* params, const double* m_T, const double*
     P->f64 = params->precision == REG_FP64;
     P->ws = (char*)workspace;
     P->o = o;
-    P->sp = SpecParams{params->n1, params->n2, params->norm, params->constraint, params->beta_v, params->beta_w};
+    P->sp = SpecParams{params->n1, params->n2, params->norm, params->constraint, params->beta_v, params->beta_w,
+                       MrPlan{}, MrPlan{}};
+    // mixed-radix plans for axis lengths that are not powers of two (ns = 0 otherwise)
+    if ((P->n1 & (P->n1 - 1)) != 0) P->sp.mr1 = mr_plan(P->n1);
+    if ((P->n2 & (P->n2 - 1)) != 0) P->sp.mr2 = mr_plan(P->n2);
+    P->sp.eta_sum = P->scal() + SC_ETA + 2;
     P->h1h2 = (2.0 * M_PI / params->n1) * (2.0 * M_PI / params->n2);
     std::vector<cpx<float>> f1, f2;
     std::vector<cpx<double>> d1, d2;
@@ -1587,6 +1659,10 @@ static reg_status check_opts(const reg_problem* h, const reg_solve_opts* opts) {
     if (opts->rank > 0 && !opts->precond_U) return fail(REG_EINVAL, "rank > 0 needs precond_U");
     if (opts->recycle < 0 || (opts->recycle > 0 && cap == 0))
         return fail(REG_EINVAL, "recycle=%d needs lowrank_capacity > 0", opts->recycle);
+    if (h->p.norm == REG_STOKES && h->p.constraint == REG_MASS_SOURCE && (opts->rank > 0 || opts->recycle > 0))
+        return fail(REG_EINVAL, "no preconditioner correction for REG_STOKES with REG_MASS_SOURCE (its W-product "
+                                "moves with the linearisation point)");
+    if (!(opts->cfl_max >= 0.0) || !std::isfinite(opts->cfl_max)) return fail(REG_EINVAL, "cfl_max must be >= 0");
     return REG_OK;
 }
 
@@ -1613,7 +1689,15 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
         const double wa = (double)problems[a]->nn * problems[a]->nt, wb = (double)problems[b]->nn * problems[b]->nt;
         return wa > wb;
     });
-    const int nworkers = std::min(count, 8);
+    // concurrent solves: REGNK_BATCH_WORKERS (1..32) if set, else 8.  Each worker drives its own
+    // stream; how many run at once on the GPU is bounded by the process's hardware queues
+    // (GPU_MAX_HW_QUEUES).
+    int want = 8;
+    if (const char* e = std::getenv("REGNK_BATCH_WORKERS")) {
+        const int w = std::atoi(e);
+        if (w >= 1 && w <= 32) want = w;
+    }
+    const int nworkers = std::min(count, want);
     std::atomic<int> next{0};
     std::vector<reg_status> status(count, REG_OK);
     std::vector<std::string> errs(count);

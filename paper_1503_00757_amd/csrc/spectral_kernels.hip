@@ -82,9 +82,15 @@ struct ModeCoef {
 
 // The Fourier multiplier of `mode` at wavenumber (k1, k2) on the (scaled-later) spectra x, y of the
 // two components: first result o, second result q (see the file header).
+// Mean viscosity of the shear-control model with a mass source (0 otherwise); read once per kernel.
+__device__ __forceinline__ double eta_bar_of(const SpecParams& p) {
+    return (p.norm == 4 && p.constraint == 2 && p.eta_sum) ? *p.eta_sum / ((double)p.n1 * (double)p.n2) : 0.0;
+}
+
 __device__ __forceinline__ void spec_multiplier(const SpecParams& p, int mode, double k1, double k2d, cpx<double> x0,
                                                 cpx<double> x1, cpx<double> y0, cpx<double> y1, cpx<double>& o0,
-                                                cpx<double>& o1, cpx<double>& q0, cpx<double>& q1) {
+                                                cpx<double>& o1, cpx<double>& q0, cpx<double>& q1,
+                                                double eta_bar = 0.0) {
     const double kk = k1 * k1 + k2d * k2d;
     // regulariser symbol of the assembly (none for the shear-control model, whose term arrives in
     // real space with the body force) and of the preconditioner (the vector Laplacian for it)
@@ -97,7 +103,10 @@ __device__ __forceinline__ void spec_multiplier(const SpecParams& p, int mode, d
         if (p.constraint == 1) {
             c = 1.0;
         } else if (p.constraint == 2) {
-            const double q = p.beta_v * A / (p.beta_w * kk * (kk + 1.0));   // M^ - 1
+            // M^ - 1: beta_v A^ / (beta_w |k|^2 (|k|^2 + 1)); for the shear-control model (App. A,
+            // relaxed incompressibility) 2 beta_v eta_bar / (beta_w (|k|^2 + 1))
+            const double q = p.norm == 4 ? 2.0 * p.beta_v * eta_bar / (p.beta_w * (kk + 1.0))
+                                         : p.beta_v * A / (p.beta_w * kk * (kk + 1.0));
             c = 1.0 / (1.0 + q);
             ci = 1.0 / q;
         }
@@ -152,6 +161,7 @@ template <int N, int NF>
 __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int mode, int have_y, int want2,
                                                               cpx<double>* __restrict__ spec,
                                                               const cpx<double>* __restrict__ tw) {
+    const double eb = eta_bar_of(p);
     constexpr int Q = N / 4;
     constexpr int L = LdsSize<N>::value;
     __shared__ cpx<double> lds[NF][2][L];
@@ -195,7 +205,7 @@ __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int 
         const double k1 = (double)kwave<N>(e);
         const bool zero = (e == N / 2);   // Nyquist row of x1: projected out
         cpx<double> o0, o1, q0, q1;
-        spec_multiplier(p, mode, k1, k2d, X0[r], X1[r], Y0[r], Y1[r], o0, o1, q0, q1);
+        spec_multiplier(p, mode, k1, k2d, X0[r], X1[r], Y0[r], Y1[r], o0, o1, q0, q1, eb);
         const double sc = zero ? 0.0 : scale;
         X0[r] = {o0.x * sc, o0.y * sc};
         X1[r] = {o1.x * sc, o1.y * sc};
@@ -225,6 +235,7 @@ template <int N>
 __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mode, int have_y, int want2,
                                                            cpx<double>* __restrict__ spec,
                                                            const cpx<double>* __restrict__ tw) {
+    const double eb = eta_bar_of(p);
     constexpr int Q = N / 4;
     constexpr int L = LdsSize<N>::value;
     __shared__ cpx<double> lds[4][2][L];
@@ -247,7 +258,7 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
         const double k1 = (double)kwave<N>(e);
         cpx<double> o0, o1, q0, q1;
         spec_multiplier(p, mode, k1, (double)k2, lds[0][b][lpad(e)], lds[1][b][lpad(e)], lds[2][b][lpad(e)],
-                        lds[3][b][lpad(e)], o0, o1, q0, q1);
+                        lds[3][b][lpad(e)], o0, o1, q0, q1, eb);
         const double sc = (e == N / 2) ? 0.0 : 1.0 / ((double)N * (double)p.n2);   // Nyquist row projected out
         __syncthreads();
         lds[0][b][lpad(e)] = {o0.x * sc, o0.y * sc};
@@ -360,6 +371,7 @@ __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_fwd_kernel(int n
 __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_col_kernel(SpecParams p, int mode, int have_y, int want2,
                                                                       cpx<double>* __restrict__ spec,
                                                                       const cpx<double>* __restrict__ tw) {
+    const double eb = eta_bar_of(p);
     extern __shared__ cpx<double> col[];   // one component of the column
     const int n1 = p.n1, H = p.n2 / 2, k2 = blockIdx.x;
     const long hn = (long)n1 * H;
@@ -396,7 +408,7 @@ __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_col_kernel(SpecParam
         if (e < n1) {
             const double k1 = (double)(e < n1 / 2 ? e : (e == n1 / 2 ? 0 : e - n1));
             cpx<double> o0, o1, q0, q1;
-            spec_multiplier(p, mode, k1, (double)k2, X[0][m], X[1][m], X[2][m], X[3][m], o0, o1, q0, q1);
+            spec_multiplier(p, mode, k1, (double)k2, X[0][m], X[1][m], X[2][m], X[3][m], o0, o1, q0, q1, eb);
             const double sc = (e == n1 / 2) ? 0.0 : scale;   // Nyquist row of x1: projected out
             X[0][m] = {o0.x * sc, o0.y * sc};
             X[1][m] = {o1.x * sc, o1.y * sc};
@@ -457,6 +469,155 @@ __global__ __launch_bounds__(DENSE_THREADS) void spec_dense_row_inv_kernel(int n
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Lengths 2^a 3^b 5^c that are not powers of two: the same three passes with the mixed-radix FFT in
+// LDS (fft_mr), one line per block of MR_THREADS threads (thread t holds entries t + MR_THREADS m).
+constexpr int MR_THREADS = 256;
+constexpr int MR_EM = 8;   // entries per thread: lengths up to 2048
+
+// The twiddle table copied to LDS behind the line buffers when it fits (twl), else read from global
+// memory; visible after the kernel's next barrier.
+__device__ __forceinline__ const cpx<double>* mr_table(const cpx<double>* __restrict__ tw, int n, cpx<double>* lds,
+                                                       int twl) {
+    if (!twl) return tw;
+    for (int i = threadIdx.x; i < n; i += MR_THREADS) lds[i] = tw[i];
+    return lds;
+}
+// LDS bytes of a mixed-radix spectral pass over a length-n line: two line buffers, plus the twiddle
+// table when the total stays within 64 KiB.
+static inline size_t mr_spec_lds(int n, int& twl) {
+    const size_t with = 3 * (size_t)n * sizeof(cpx<double>);
+    twl = with <= 64 * 1024 ? 1 : 0;
+    return twl ? with : 2 * (size_t)n * sizeof(cpx<double>);
+}
+
+// rows -> half spectra: block (i1, field); the row pair of components packed as c0 + i c1
+template <typename TI0, typename TI1>
+__global__ __launch_bounds__(MR_THREADS) void spec_mr_row_fwd_kernel(SpecParams p, const TI0* __restrict__ in0,
+                                                                    const TI1* __restrict__ in1,
+                                                                    cpx<double>* __restrict__ spec,
+                                                                    const cpx<double>* __restrict__ tw_g, int twl) {
+    extern __shared__ cpx<double> zl[];
+    const int n1 = p.n1, N = p.n2, H = N / 2;
+    const int i1 = blockIdx.x, field = blockIdx.y, t = threadIdx.x;
+    const long nn = (long)n1 * N, row = (long)i1 * N;
+    const cpx<double>* tw = mr_table(tw_g, N, zl + 2 * N, twl);
+    for (int e = t; e < N; e += MR_THREADS)
+        zl[e] = field ? cpx<double>{(double)in1[row + e], (double)in1[nn + row + e]}
+                      : cpx<double>{(double)in0[row + e], (double)in0[nn + row + e]};
+    __syncthreads();
+    const cpx<double>* Z = fft_mr<double, false>(zl, zl + N, p.mr2, tw, t, MR_THREADS);
+    const long hn = (long)n1 * H;
+    cpx<double>* s0 = spec + (long)(2 * field) * hn + (long)i1 * H;
+    cpx<double>* s1 = s0 + hn;
+    for (int e = t; e < H; e += MR_THREADS) {
+        const cpx<double> z = Z[e], zc = Z[e == 0 ? 0 : N - e];
+        const double dx = z.x - zc.x, dy = z.y + zc.y;   // Z_e - conj(Z_{N-e})
+        s0[e] = {0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y)};
+        s1[e] = {0.5 * dy, -0.5 * dx};
+    }
+}
+
+// columns: per k2 < n2/2, transform the needed spectra along x1, multiply, transform back; in place
+__global__ __launch_bounds__(MR_THREADS) void spec_mr_col_kernel(SpecParams p, int mode, int have_y, int want2,
+                                                                cpx<double>* __restrict__ spec,
+                                                                const cpx<double>* __restrict__ tw_g, int twl) {
+    const double eb = eta_bar_of(p);
+    extern __shared__ cpx<double> cl[];
+    const int N = p.n1, H = p.n2 / 2, k2 = blockIdx.x, t = threadIdx.x;
+    const cpx<double>* tw = mr_table(tw_g, N, cl + 2 * N, twl);
+    const long hn = (long)N * H;
+    const int nc = have_y ? 4 : 2, no = want2 ? 4 : 2;
+    cpx<double> X[4][MR_EM];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int m = 0; m < MR_EM; ++m) X[c][m] = {0.0, 0.0};
+        if (c >= nc) continue;
+        for (int e = t; e < N; e += MR_THREADS) cl[e] = spec[c * hn + (long)e * H + k2];
+        __syncthreads();
+        const cpx<double>* Z = fft_mr<double, false>(cl, cl + N, p.mr1, tw, t, MR_THREADS);
+#pragma unroll
+        for (int m = 0; m < MR_EM; ++m) {
+            const int e = t + MR_THREADS * m;
+            if (e < N) X[c][m] = Z[e];
+        }
+        __syncthreads();   // LDS free for the next component
+    }
+    const double scale = 1.0 / ((double)N * (double)p.n2);
+#pragma unroll
+    for (int m = 0; m < MR_EM; ++m) {
+        const int e = t + MR_THREADS * m;
+        if (e < N) {
+            cpx<double> o0, o1, q0, q1;
+            spec_multiplier(p, mode, (double)kwave_n(e, N), (double)k2, X[0][m], X[1][m], X[2][m], X[3][m], o0, o1,
+                            q0, q1, eb);
+            const double sc = (2 * e == N) ? 0.0 : scale;   // Nyquist row of x1: projected out
+            X[0][m] = {o0.x * sc, o0.y * sc};
+            X[1][m] = {o1.x * sc, o1.y * sc};
+            X[2][m] = {q0.x * sc, q0.y * sc};
+            X[3][m] = {q1.x * sc, q1.y * sc};
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c >= no) continue;
+#pragma unroll
+        for (int m = 0; m < MR_EM; ++m) {
+            const int e = t + MR_THREADS * m;
+            if (e < N) cl[e] = X[c][m];
+        }
+        __syncthreads();
+        const cpx<double>* Z = fft_mr<double, true>(cl, cl + N, p.mr1, tw, t, MR_THREADS);
+        for (int e = t; e < N; e += MR_THREADS) spec[c * hn + (long)e * H + k2] = Z[e];
+        __syncthreads();
+    }
+}
+
+// half spectra -> real rows: block (i1, field); Z_e = S0_e + i S1_e (e < n2/2, conjugate-symmetric
+// continuation above, Nyquist 0), inverse transform, real part -> component 0, imaginary -> 1
+template <typename TO>
+__global__ __launch_bounds__(MR_THREADS) void spec_mr_row_inv_kernel(SpecParams p, const cpx<double>* __restrict__ spec,
+                                                                    double* __restrict__ out_d0,
+                                                                    TO* __restrict__ out_t0,
+                                                                    double* __restrict__ out_d1,
+                                                                    const cpx<double>* __restrict__ tw_g, int twl) {
+    extern __shared__ cpx<double> zl[];
+    const int n1 = p.n1, N = p.n2, H = N / 2;
+    const int i1 = blockIdx.x, field = blockIdx.y, t = threadIdx.x;
+    const long hn = (long)n1 * H;
+    const cpx<double>* tw = mr_table(tw_g, N, zl + 2 * N, twl);
+    double* out_d = field ? out_d1 : out_d0;
+    TO* out_t = field ? nullptr : out_t0;
+    const cpx<double>* s0 = spec + (long)(2 * field) * hn + (long)i1 * H;
+    const cpx<double>* s1 = s0 + hn;
+    for (int e = t; e < N; e += MR_THREADS) {
+        cpx<double> z{0.0, 0.0};
+        if (e < H) {
+            const cpx<double> a = s0[e], b = s1[e];
+            z = {a.x - b.y, a.y + b.x};
+        } else if (e > H) {
+            const cpx<double> a = s0[N - e], b = s1[N - e];
+            z = {a.x + b.y, b.x - a.y};
+        }
+        zl[e] = z;
+    }
+    __syncthreads();
+    const cpx<double>* Z = fft_mr<double, true>(zl, zl + N, p.mr2, tw, t, MR_THREADS);
+    const long nn = (long)n1 * N, row = (long)i1 * N;
+    for (int e = t; e < N; e += MR_THREADS) {
+        const cpx<double> z = Z[e];
+        if (out_d) {
+            out_d[row + e] = z.x;
+            out_d[nn + row + e] = z.y;
+        }
+        if (out_t) {
+            out_t[row + e] = (TO)z.x;
+            out_t[nn + row + e] = (TO)z.y;
+        }
+    }
+}
+
 static inline bool pow2(int n) { return (n & (n - 1)) == 0; }
 
 // ---------------------------------------------------------------------------------------------
@@ -470,6 +631,13 @@ hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* 
         hipLaunchKernelGGL((spec_row_fwd_kernel<TI0, TI1, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf), \
                            dim3(FPW * NN / 4), 0, s, p.n1, in0, in1, spec, tw2);                       \
         break;                                                                                         \
+    }
+    if (!pow2(p.n2) && p.mr2.ns > 0) {
+        int twl = 0;
+        const size_t lds = mr_spec_lds(p.n2, twl);
+        hipLaunchKernelGGL((spec_mr_row_fwd_kernel<TI0, TI1>), dim3(p.n1, nf), dim3(MR_THREADS), lds, s, p, in0, in1,
+                           spec, tw2, twl);
+        return hipGetLastError();
     }
     if (!pow2(p.n2)) {
         hipLaunchKernelGGL((spec_dense_row_fwd_kernel<TI0, TI1>), dim3(p.n1, nf, 2), dim3(DENSE_THREADS),
@@ -499,6 +667,14 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
         hipLaunchKernelGGL((spec_col_kernel<NN, NF>), dim3((H + NF - 1) / NF), dim3(NF * NN / 4), 0,  \
                            s, p, mode, (int)have_y, (int)want2, spec, tw1);                            \
         break;                                                                                         \
+    }
+    if (!pow2(p.n1) && p.mr1.ns > 0) {
+        if (p.n1 > MR_EM * MR_THREADS) return hipErrorInvalidValue;
+        int twl = 0;
+        const size_t lds = mr_spec_lds(p.n1, twl);
+        hipLaunchKernelGGL(spec_mr_col_kernel, dim3(H), dim3(MR_THREADS), lds, s, p, mode, (int)have_y, (int)want2,
+                           spec, tw1, twl);
+        return hipGetLastError();
     }
     if (!pow2(p.n1)) {
         if (p.n1 > 8 * DENSE_THREADS) return hipErrorInvalidValue;
@@ -531,6 +707,13 @@ static hipError_t row_inv_fields(const SpecParams& p, const cpx<double>* spec, d
         hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf),      \
                            dim3(FPW * NN / 4), 0, s, p.n1, spec, out_d, out_t, out_d1, tw2);           \
         break;                                                                                         \
+    }
+    if (!pow2(p.n2) && p.mr2.ns > 0) {
+        int twl = 0;
+        const size_t lds = mr_spec_lds(p.n2, twl);
+        hipLaunchKernelGGL((spec_mr_row_inv_kernel<TO>), dim3(p.n1, nf), dim3(MR_THREADS), lds, s, p, spec, out_d,
+                           out_t, out_d1, tw2, twl);
+        return hipGetLastError();
     }
     if (!pow2(p.n2)) {
         hipLaunchKernelGGL((spec_dense_row_inv_kernel<TO>), dim3(p.n1, 2, nf), dim3(DENSE_THREADS),

@@ -22,6 +22,8 @@
 #pragma once
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -422,6 +424,214 @@ __global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_col_kernel(St
     clk_end(a.clk);
 }
 
+// Axis lengths 2^a 3^b 5^c that are not powers of two: the same stage with the mixed-radix FFT in LDS
+// (fft_mr) in place of the circulant sum.  Row part: fpw row pairs per block, tpt threads per
+// transform, thread t holds elements e = t + tpt m (m < EM) of both rows in registers (the epilogue
+// operands too) and stages them through LDS as one complex line.  Column part: G column pairs per
+// block, adjacent lanes on adjacent pairs.  LDS: two lines per transform.  Threads past the block's
+// transforms only join the barriers.
+// The twiddle table of the axis, copied to LDS behind the block's `nlines` line pairs when the launch
+// gave room for it (twl), else read from global memory.
+template <typename T>
+__device__ __forceinline__ const cpx<T>* mr_twiddles(const cpx<T>* __restrict__ tw, int n, cpx<T>* lds, int nlines,
+                                                     bool twl) {
+    if (!twl) return tw;
+    cpx<T>* t = lds + (size_t)nlines * 2 * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t[i] = tw[i];
+    return t;   // visible after the caller's next barrier
+}
+
+template <typename T, int OP, int EM>
+__device__ __forceinline__ void mr_row_part(const StageArgs<T>& a, int rb, int tpt, int fpw, cpx<T>* lds, int nlines,
+                                            bool twl) {
+    const int N = a.n2;
+    const cpx<T>* tw = mr_twiddles(a.tw2, N, lds, nlines, twl);
+    const int f = threadIdx.x / tpt, t = threadIdx.x % tpt;
+    const bool act = f < fpw;
+    const int pair = rb * fpw + f;
+    const bool valid = act && pair < (a.n1 >> 1);
+    cpx<T>* L0 = lds + (size_t)(act ? f : 0) * 2 * N;
+    cpx<T>* L1 = L0 + N;
+    const long row0 = (long)(valid ? 2 * pair : 0) * N, row1 = row0 + N;
+    Rp<T> q0[EM], q1[EM];
+#pragma unroll
+    for (int m = 0; m < EM; ++m) {
+        const int e = t + tpt * m;
+        if (act && e < N) {
+            T p0 = 0, p1 = 0;
+            if (valid) {
+                p0 = row_load<T, OP>(a, row0 + e, q0[m]);
+                p1 = row_load<T, OP>(a, row1 + e, q1[m]);
+            }
+            L0[e] = {p0, p1};
+        }
+    }
+    __syncthreads();
+    cpx<T>* X = fft_mr<T, false>(L0, L1, a.mr2, tw, t, tpt, act);
+    const T inv = T(1) / T(N);
+#pragma unroll
+    for (int m = 0; m < EM; ++m) {
+        const int e = t + tpt * m;
+        if (act && e < N) {
+            const T k = T(kwave_n(e, N)) * inv;
+            const cpx<T> z = X[e];
+            X[e] = {-z.y * k, z.x * k};   // times i k / N
+        }
+    }
+    __syncthreads();
+    cpx<T>* Y = fft_mr<T, true>(X, X == L0 ? L1 : L0, a.mr2, tw, t, tpt, act);
+    if (valid) {
+#pragma unroll
+        for (int m = 0; m < EM; ++m) {
+            const int e = t + tpt * m;
+            if (e < N) {
+                const cpx<T> y = Y[e];
+                row_store<T, OP>(a, row0 + e, y.x, q0[m]);
+                row_store<T, OP>(a, row1 + e, y.y, q1[m]);
+            }
+        }
+    }
+}
+
+template <typename T, int OP, int EM>
+__device__ __forceinline__ void mr_col_part(const StageArgs<T>& a, int cb, int tpt, int G, cpx<T>* lds, int nlines,
+                                            bool twl) {
+    const int N = a.n1;
+    const cpx<T>* tw = mr_twiddles(a.tw1, N, lds, nlines, twl);
+    const int f = threadIdx.x % G, t = threadIdx.x / G;
+    const bool act = t < tpt;
+    const int c = (cb * G + f) * 2;
+    const bool valid = act && c < a.n2;
+    const long n2 = a.n2;
+    cpx<T>* L0 = lds + (size_t)f * 2 * N;
+    cpx<T>* L1 = L0 + N;
+    Cp<T> q0[EM], q1[EM];
+#pragma unroll
+    for (int m = 0; m < EM; ++m) {
+        const int e = t + tpt * m;
+        if (act && e < N) L0[e] = valid ? col_load2<T, OP>(a, (long)e * n2 + c, q0[m], q1[m]) : cpx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    cpx<T>* X = fft_mr<T, false>(L0, L1, a.mr1, tw, t, tpt, act);
+    const T inv = T(1) / T(N);
+#pragma unroll
+    for (int m = 0; m < EM; ++m) {
+        const int e = t + tpt * m;
+        if (act && e < N) {
+            const T k = T(kwave_n(e, N)) * inv;
+            const cpx<T> z = X[e];
+            X[e] = {-z.y * k, z.x * k};
+        }
+    }
+    __syncthreads();
+    cpx<T>* Y = fft_mr<T, true>(X, X == L0 ? L1 : L0, a.mr1, tw, t, tpt, act);
+    if (valid) {
+#pragma unroll
+        for (int m = 0; m < EM; ++m) {
+            const int e = t + tpt * m;
+            if (e < N) {
+                const cpx<T> y = Y[e];
+                col_store2<T, OP>(a, (long)e * n2 + c, y.x, y.y, q0[m], q1[m]);
+            }
+        }
+    }
+}
+
+template <typename T, int OP, int EM>
+__global__ __launch_bounds__(256) void stage_mr_row_kernel(StageArgs<T> a, int tpt, int fpw, int twl) {
+    extern __shared__ unsigned char dsm[];
+    clk_start(a.clk);
+    mr_row_part<T, OP, EM>(a, blockIdx.x, tpt, fpw, reinterpret_cast<cpx<T>*>(dsm), fpw, twl != 0);
+    clk_end(a.clk);
+}
+template <typename T, int OP, int EM>
+__global__ __launch_bounds__(256) void stage_mr_col_kernel(StageArgs<T> a, int tpt, int G, int twl) {
+    extern __shared__ unsigned char dsm[];
+    clk_start(a.clk);
+    mr_col_part<T, OP, EM>(a, blockIdx.x, tpt, G, reinterpret_cast<cpx<T>*>(dsm), G, twl != 0);
+    clk_end(a.clk);
+}
+// Square grids of such a length: both parts in one launch (blocks [0, nrb) rows, the rest columns).
+template <typename T, int OP, int EMR, int EMC>
+__global__ __launch_bounds__(256) void stage_mr_fused_kernel(StageArgs<T> a, int nrb, int tpt_r, int fpw, int tpt_c,
+                                                            int G, int twl) {
+    extern __shared__ unsigned char dsm[];
+    const int nlines = fpw > G ? fpw : G;
+    clk_start(a.clk);
+    if ((int)blockIdx.x < nrb)
+        mr_row_part<T, OP, EMR>(a, blockIdx.x, tpt_r, fpw, reinterpret_cast<cpx<T>*>(dsm), nlines, twl != 0);
+    else mr_col_part<T, OP, EMC>(a, blockIdx.x - nrb, tpt_c, G, reinterpret_cast<cpx<T>*>(dsm), nlines, twl != 0);
+    clk_end(a.clk);
+}
+
+// LDS of a mixed-radix stage launch: `nlines` line pairs, plus the twiddle table when the total stays
+// within 64 KiB (twl).
+template <typename T>
+inline size_t mr_lds_bytes(int n, int nlines, int& twl) {
+    const size_t lines = (size_t)nlines * 2 * n * sizeof(cpx<T>);
+    const size_t with = lines + (size_t)n * sizeof(cpx<T>);
+    twl = with <= 64 * 1024 ? 1 : 0;
+    return twl ? with : lines;
+}
+
+// Launch shape of a mixed-radix axis of length n: EM elements per thread, tpt threads per transform
+// (tpt * EM >= n), and transforms per block (at most 256 threads and 64 KiB of LDS per block).
+struct MrShape {
+    int em, tpt, per_block;
+};
+template <typename T>
+inline MrShape mr_shape(int n, bool column) {
+    const int em = n > 1024 ? 8 : (n > 256 || column ? (n > 512 && column ? 8 : 4) : 2);
+    const int tpt = (n + em - 1) / em;
+    int pb = 256 / tpt;
+    const int lds_line = 2 * n * (int)sizeof(cpx<T>);
+    while (pb > 1 && pb * lds_line > 64 * 1024) --pb;
+    if (pb < 1) pb = 1;
+    return {em, tpt, pb};
+}
+
+template <typename T, int OP>
+static hipError_t launch_mr_axis(int axis, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    const int n = axis == 2 ? a.n2 : a.n1;
+    const MrShape sh = mr_shape<T>(n, axis == 1);
+    int twl = 0;
+    const size_t lds = mr_lds_bytes<T>(n, sh.per_block, twl);
+    const int lines = axis == 2 ? a.n1 / 2 : a.n2 / 2;
+    const dim3 grid((lines + sh.per_block - 1) / sh.per_block), block(sh.per_block * sh.tpt);
+#define REGNK_MR(EMV)                                                                                      \
+    if (sh.em == EMV) {                                                                                    \
+        if (axis == 2) launch_ks(stage_mr_row_kernel<T, OP, EMV>, grid, block, lds, s, t0, t1, a, sh.tpt,       \
+                                 sh.per_block, twl);                                                       \
+        else launch_ks(stage_mr_col_kernel<T, OP, EMV>, grid, block, lds, s, t0, t1, a, sh.tpt, sh.per_block,   \
+                       twl);                                                                               \
+        return hipGetLastError();                                                                          \
+    }
+    REGNK_MR(2) REGNK_MR(4) REGNK_MR(8)
+#undef REGNK_MR
+    return hipErrorInvalidValue;
+}
+
+// Square mixed-radix grids: one launch per stage (row and column shapes of the two-launch form, the
+// block as large as the larger of them).
+template <typename T, int OP>
+static hipError_t launch_mr_fused(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    const int n = a.n1;
+    const MrShape r = mr_shape<T>(n, false), c = mr_shape<T>(n, true);
+    const int bs = std::max(r.per_block * r.tpt, c.per_block * c.tpt);
+    const int nrb = (a.n1 / 2 + r.per_block - 1) / r.per_block, ncb = (a.n2 / 2 + c.per_block - 1) / c.per_block;
+    int twl = 0;
+    const size_t lds = mr_lds_bytes<T>(n, std::max(r.per_block, c.per_block), twl);
+#define REGNK_MRF(ER, EC)                                                                                  \
+    if (r.em == ER && c.em == EC) {                                                                        \
+        launch_ks(stage_mr_fused_kernel<T, OP, ER, EC>, dim3(nrb + ncb), dim3(bs), lds, s, t0, t1, a, nrb, r.tpt, \
+                  r.per_block, c.tpt, c.per_block, twl);                                                   \
+        return hipGetLastError();                                                                          \
+    }
+    REGNK_MRF(2, 4) REGNK_MRF(4, 4) REGNK_MRF(4, 8) REGNK_MRF(8, 8)
+#undef REGNK_MRF
+    return hipErrorInvalidValue;
+}
+
 // Pointwise helpers of the state solve and the trapezoid end point.
 template <typename T>
 __global__ void finalize_state_kernel(long nn, const double* __restrict__ Q, const double* __restrict__ C,
@@ -604,6 +814,7 @@ static hipError_t launch_axis(const StageArgs<T>& a, hipStream_t s, hipEvent_t t
 
 template <typename T, int OP>
 static hipError_t launch_dense_axis(int axis, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if ((axis == 2 ? a.mr2.ns : a.mr1.ns) > 0) return launch_mr_axis<T, OP>(axis, a, s, t0, t1);
     if (axis == 2) {
         if (!a.dc2) return hipErrorInvalidValue;
         launch_ks(stage_dense_row_kernel<T, OP>, dim3(a.n1 / 2), dim3(DENSE_STAGE_THREADS), a.n2 * sizeof(cpx<T>), s,
@@ -620,6 +831,15 @@ constexpr bool is_pow2_len(int n) { return (n & (n - 1)) == 0; }
 
 template <typename T, int OP>
 hipError_t launch_stage_op(int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (a.n1 == a.n2 && !is_pow2_len(a.n1) && a.mr1.ns > 0 && a.mr2.ns > 0) {
+        if (a.clk) {   // timing slots: both parts' blocks of the one launch
+            const MrShape r = mr_shape<T>(a.n1, false), c = mr_shape<T>(a.n1, true);
+            if ((a.n1 / 2 + r.per_block - 1) / r.per_block + (a.n2 / 2 + c.per_block - 1) / c.per_block >
+                (a.n1 + a.n2) / 2)
+                return hipErrorInvalidValue;
+        }
+        return launch_mr_fused<T, OP>(a, s, t0, t1);
+    }
     if (a.n1 == a.n2 && is_pow2_len(a.n1)) {
         switch (a.n1) {
             case 8: return launch_square<T, 8, OP>(var, a, s, t0, t1);

@@ -133,8 +133,9 @@ hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The scalar recurrences of PCG (one thread).
-__device__ __forceinline__ void pcg_scalar_step(int mode, double* __restrict__ sc) {
+// The scalar recurrences of PCG (one thread).  sc is read after the caller stored fresh sums into
+// it, so no pointer here is declared non-aliasing.
+__device__ __forceinline__ void pcg_scalar_step(int mode, double* sc) {
     if (mode == PCG_INIT) {
         sc[S_ACTIVE] = 1.0;
         sc[S_BREAK] = 0.0;
@@ -168,10 +169,11 @@ __device__ __forceinline__ void pcg_scalar_step(int mode, double* __restrict__ s
 }
 
 // The second level of launch_dots for all nk sums in one block (the same partial order and tree as
-// finalize_kernel), then the PCG scalar step of `mode`: one launch instead of two.
+// finalize_kernel), then the PCG scalar step of `mode`: one launch instead of two.  `out` points into
+// `sc` (out = sc + slot), and the scalar step reads the sums just stored through `out`, so neither
+// pointer is declared non-aliasing.
 __global__ __launch_bounds__(RED_THREADS) void finalize_scalar_kernel(int nk, const double* __restrict__ partial,
-                                                                      double* __restrict__ out, int mode,
-                                                                      double* __restrict__ sc) {
+                                                                      double* out, int mode, double* sc) {
     __shared__ double sh[RED_THREADS / 64];
     for (int k = 0; k < nk; ++k) {
         double acc = 0.0;

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "REG_OK", -1: "REG_EINVAL", -2: "REG_ENOMEM", -3: "REG_EDEVIC
 class RegParams(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("nt", C.c_int32), ("norm", C.c_int32),
                 ("constraint", C.c_int32), ("precision", C.c_int32), ("adjoint", C.c_int32),
-                ("hessian", C.c_int32), ("lowrank_capacity", C.c_int32), ("reserved", C.c_int32),
+                ("hessian", C.c_int32), ("lowrank_capacity", C.c_int32), ("nt_max", C.c_int32),
                 ("beta_v", C.c_double), ("beta_w", C.c_double), ("stokes_nu", C.c_double),
                 ("stokes_eps", C.c_double)]
 
@@ -34,14 +34,16 @@ class RegSolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("fixed_pcg_iters", C.c_int32),
                 ("max_backtracks", C.c_int32), ("gtol_rel", C.c_double), ("armijo_c1", C.c_double),
                 ("armijo_rho", C.c_double), ("v0", C.c_void_p), ("precond_U", C.c_void_p),
-                ("precond_d", C.POINTER(C.c_double)), ("rank", C.c_int32), ("recycle", C.c_int32)]
+                ("precond_d", C.POINTER(C.c_double)), ("rank", C.c_int32), ("recycle", C.c_int32),
+                ("cfl_max", C.c_double)]
 
 
 class RegSolveStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("n_matvec", C.c_int32),
                 ("n_pde", C.c_int32), ("backtracks", C.c_int32), ("status", C.c_int32),
                 ("fallback_used", C.c_int32), ("lowrank_dim", C.c_int32),
-                ("g0_norm", C.c_double), ("g_rel", C.c_double), ("J", C.c_double), ("cfl", C.c_double)]
+                ("g0_norm", C.c_double), ("g_rel", C.c_double), ("J", C.c_double), ("cfl", C.c_double),
+                ("nt", C.c_int32), ("nt_changes", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

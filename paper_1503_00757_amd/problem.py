@@ -17,19 +17,25 @@ _HESS = {"gn": ffi.REG_HESS_GN, "full": ffi.REG_HESS_FULL}
 
 
 def make_params(n1, n2, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0, precision="fp32",
-                adjoint="dto", lowrank_capacity=0, hessian="gn", nu=1.0, eps=1e-6) -> ffi.RegParams:
+                adjoint="dto", lowrank_capacity=0, hessian="gn", nu=1.0, eps=1e-6, nt_max=0) -> ffi.RegParams:
     """reg_params; nu and eps are the shear-control model's exponent and strain regularisation (used
-    for norm="stokes" only)."""
+    for norm="stokes" only); nt_max is the largest n_t the solve's CFL adaptation may reach."""
     st = norm == "stokes"
     return ffi.RegParams(n1, n2, nt, _NORMS[norm], _CONS[constraint], _PREC[precision], _ADJ[adjoint],
-                         _HESS[hessian], int(lowrank_capacity), 0, float(beta_v), float(beta_w),
+                         _HESS[hessian], int(lowrank_capacity), int(nt_max), float(beta_v), float(beta_w),
                          float(nu) if st else 0.0, float(eps) if st else 0.0)
+
+
+def paper_nt(n1, n2):
+    """The number of time steps the paper starts from before adapting it to the CFL condition:
+    n_t = 2 max(n1, n2) (Sec. 5)."""
+    return 2 * max(n1, n2)
 
 
 class Problem:
     def __init__(self, mT, mR, nt, norm="H1", constraint="divfree", beta_v=1e-2, beta_w=0.0,
                  precision="fp32", adjoint="dto", stream=None, lowrank_capacity=0, hessian="gn", nu=1.0,
-                 eps=1e-6):
+                 eps=1e-6, nt_max=0):
         import torch
         self.torch = torch
         if mT.dtype != torch.float64 or mR.dtype != torch.float64 or not mT.is_cuda or not mR.is_cuda:
@@ -38,7 +44,7 @@ class Problem:
         self.n1, self.n2, self.nt = n1, n2, nt
         self.device = mT.device
         self.params = make_params(n1, n2, nt, norm, constraint, beta_v, beta_w, precision, adjoint,
-                                  lowrank_capacity, hessian, nu, eps)
+                                  lowrank_capacity, hessian, nu, eps, nt_max)
         self.ws_bytes = ffi.reg_workspace_bytes(self.params)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
@@ -111,32 +117,36 @@ class Problem:
         return x, it, rr
 
     def solve_opts(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
-                   armijo_c1=1e-4, armijo_rho=0.5, v0=None, precond_U=None, recycle=0, ritz_out=None):
+                   armijo_c1=1e-4, armijo_rho=0.5, v0=None, precond_U=None, recycle=0, ritz_out=None,
+                   cfl_max=0.0):
         """reg_solve_opts; v0 / precond_U must be contiguous float64 device tensors kept alive by the
         caller, ritz_out a ctypes double array of len(precond_U) (or None)."""
         rank = 0 if precond_U is None else int(precond_U.shape[0])
         return ffi.RegSolveOpts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
                                 armijo_rho, v0.data_ptr() if v0 is not None else None,
                                 precond_U.data_ptr() if precond_U is not None else None, ritz_out, rank,
-                                int(recycle))
+                                int(recycle), float(cfl_max))
 
     def solve(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
-              armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True, precond_U=None, recycle=0):
+              armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True, precond_U=None, recycle=0,
+              cfl_max=0.0):
         """Alg. 1 (reg_solve).  precond_U: (r, 2, n1, n2) float64 directions of the preconditioner
-        correction; recycle: PCG directions kept per Newton step (both need lowrank_capacity > 0).
+        correction; recycle: PCG directions kept per Newton step (both need lowrank_capacity > 0);
+        cfl_max > 0: n_t raised (up to nt_max) whenever the iterate's CFL number exceeds it.
         The stats dict carries the Ritz values of precond_U as "ritz"."""
         import ctypes
         v0c = self._c(v0) if v0 is not None else None
         Uc = self._c(precond_U) if precond_U is not None else None
         ritz = (ctypes.c_double * int(Uc.shape[0]))() if Uc is not None and Uc.shape[0] > 0 else None
         opts = self.solve_opts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
-                               armijo_rho, v0c, Uc, recycle, ritz)
+                               armijo_rho, v0c, Uc, recycle, ritz, cfl_max)
         v = self.vec()
         status, st = ffi.reg_solve(self.h, opts, v.data_ptr(), raise_on_error)
         d = st.as_dict()
         d["return_status"] = status
         if ritz is not None:
             d["ritz"] = list(ritz)
+        self.nt = d["nt"]
         return v, d
 
     def cfl(self, v):
@@ -176,24 +186,3 @@ def batch_solve(problems, raise_on_error=True, v0s=None, **opts):
     o = [p.solve_opts(v0=v0, **opts) for p, v0 in zip(problems, v0s)]
     status, st = ffi.reg_batch_solve([p.h for p in problems], o, [v.data_ptr() for v in outs], raise_on_error)
     return outs, [s.as_dict() for s in st]
-
-
-def solve_adaptive_nt(mT, mR, nt, cfl_max=1.0, max_rounds=4, problem_kw=None, **solve_kw):
-    """Alg. 1 with n_t adapted to the CFL condition (Sec. 4 monitors it): solve, and while the CFL
-    number of the solution exceeds cfl_max, re-create the problem with n_t raised in proportion
-    (times 1.25) and solve again from the previous solution.  Returns (v, stats, [n_t tried])."""
-    import math
-    problem_kw = problem_kw or {}
-    tried = []
-    v = None
-    for _ in range(max_rounds):
-        tried.append(nt)
-        P = Problem(mT, mR, nt, **problem_kw)
-        try:
-            v, st = P.solve(v0=v, **solve_kw)
-        finally:
-            P.close()
-        if st["cfl"] <= cfl_max:
-            break
-        nt = int(math.ceil(nt * st["cfl"] / cfl_max * 1.25))
-    return v, st, tried

@@ -46,6 +46,37 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def elem(a, b):
+    """Largest pointwise error relative to the largest reference value."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0)) if b.size else 0.0
+
+
+# A localised error (one wrong tile of a large field) can hide in a relative L2 norm, so every parity
+# check also bounds the pointwise error: max|a - b| <= ELEM_FACTOR * tol * max|b|.
+ELEM_FACTOR = 10.0
+
+
+class Close:
+    """Outcome of a parity comparison; true when both bounds hold, printed with the measured errors."""
+
+    def __init__(self, r, e, tol):
+        self.r, self.e, self.tol = r, e, tol
+
+    def __bool__(self):
+        return bool(self.r < self.tol and self.e <= ELEM_FACTOR * self.tol)
+
+    def __repr__(self):
+        return f"Close(rel_l2={self.r:.3e}, pointwise={self.e:.3e}, tol={self.tol:.1e})"
+
+
+def close(a, b, tol):
+    """rel-L2 below tol and the pointwise error below ELEM_FACTOR * tol of the reference's maximum."""
+    return Close(rel(a, b), elem(a, b), tol)
+
+
 @functools.lru_cache(maxsize=None)
 def inputs(case: Case):
     """(mT, mR, v_lin, vtilde, v_trial) for a case; mR is the oracle's transport of mT by v*."""
@@ -100,6 +131,16 @@ def oracle_results(case: Case):
     g_n = reduced.gradient(g, p, mT, mR, vlin + 2.2e-16 * np.abs(vlin).max() * rng.standard_normal(vlin.shape)).g
     return dict(g=lin.g, J=lin.J, H=H, Jt=Jt, terms=terms, m1=m1, z=z, bscale=bscale, Jscale=Jscale,
                 sens_H=rel(H_n, H), sens_g=float(np.linalg.norm(g_n - lin.g)))
+
+
+@functools.lru_cache(maxsize=None)
+def tight_solution(case: Case, gtol: float):
+    """The oracle's Alg. 1 solve of a case to ||g||/||g(0)|| <= gtol: the converged velocity that
+    run-to-tolerance GPU solves (plain, recycled, full Newton, batched) are compared with."""
+    from oracle import solver
+    mT, mR, *_ = inputs(case)
+    return solver.solve(Grid(case.n1, case.n2), params(case), mT, mR,
+                        solver.SolveOpts(max_newton=50, max_pcg=300, gtol_rel=gtol))
 
 
 def gpu_problem(case: Case, lowrank_capacity=0, hessian="gn"):

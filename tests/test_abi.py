@@ -40,8 +40,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(R.RegParams) == 10 * 4 + 4 * 8
-    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4
-    assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 4 * 8
+    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 4 * 8 + 2 * 4
 
 
 def test_workspace_bytes_scales_with_grid_and_steps():
@@ -110,9 +110,15 @@ def test_hessian_mode_checked_and_full_newton_workspace():
     with pytest.raises(R.RegError):
         R.reg_workspace_bytes(p)
     p = make_params(64, 64, 4)
-    p.reserved = 1
+    p.nt_max = 3          # below nt
     with pytest.raises(R.RegError):
         R.reg_workspace_bytes(p)
+    p.nt_max = 4097
+    with pytest.raises(R.RegError):
+        R.reg_workspace_bytes(p)
+    # room for the CFL adaptation: the trajectory of nt_max steps (2 nt_max + 1 vector fields)
+    p.nt_max = 16
+    assert R.reg_workspace_bytes(p) - R.reg_workspace_bytes(make_params(64, 64, 4)) == 2 * 12 * 2 * 64 * 64 * 4
     with pytest.raises(R.RegError) as e:   # full Newton is the derivative of the exact discrete adjoint
         R.reg_workspace_bytes(make_params(64, 64, 4, adjoint="paper", hessian="full"))
     assert e.value.status == -1
@@ -138,8 +144,10 @@ def test_shear_control_parameters_checked():
     for kw in (dict(nu=0.0), dict(eps=0.0), dict(nu=float("nan"))):
         with pytest.raises(R.RegError):
             R.reg_workspace_bytes(make_params(64, 64, 4, norm="stokes", **kw))
-    with pytest.raises(R.RegError):
-        R.reg_workspace_bytes(make_params(64, 64, 4, norm="stokes", constraint="mass_source", beta_w=1e-3))
+    # with a mass source (relaxed incompressibility): two more FP64 fields for the penalty's gradient
+    ms = R.reg_workspace_bytes(make_params(64, 64, 4, norm="stokes", constraint="mass_source", beta_w=1e-3, nu=1.7,
+                                           eps=1e-4))
+    assert ms > R.reg_workspace_bytes(make_params(64, 64, 4, constraint="mass_source", beta_w=1e-3))
     p = make_params(64, 64, 4)
     p.stokes_nu = 1.0                      # only meaningful for the shear-control model
     with pytest.raises(R.RegError):
@@ -147,6 +155,6 @@ def test_shear_control_parameters_checked():
 
 
 def test_even_grids_that_are_not_powers_of_two_are_accepted():
-    """The paper's 128 x 150 slice (and 96^2 = 2^5 3 squared) take the direct-sum transforms."""
+    """The paper's 128 x 150 slice (and 96^2 = 2^5 3 squared) take the mixed-radix transforms."""
     for n1, n2 in ((128, 150), (96, 96), (150, 128)):
         assert R.reg_workspace_bytes(make_params(n1, n2, 4)) > 0

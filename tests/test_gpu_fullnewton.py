@@ -10,7 +10,7 @@ constraint, both norms and both transport precisions.
 import numpy as np
 import pytest
 
-from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel, oracle_results
+from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel, close, oracle_results
 from oracle import Grid, reduced, solver, spectral
 
 pytestmark = pytest.mark.gpu
@@ -41,7 +41,7 @@ def test_full_newton_matvec_parity(case):
     try:
         gg, J = P.gradient(dev(vlin))
         H = host(P.hessian_matvec(dev(vt)))
-        assert rel(H, H_ref) < tol
+        assert close(H, H_ref, tol)
         # the lam terms are really there: Gauss-Newton is far from the full matvec here
         assert rel(Hgn_ref, H_ref) > 10 * tol
         # symmetry in <., .>_W (exact for the discrete Hessian)
@@ -71,7 +71,7 @@ def test_full_newton_fixed_schedule_solve_parity(case, tol):
         assert s["status"] == 0 and s["newton_iters"] == 3
         assert s["pcg_iters"] == st.pcg_iters and s["n_matvec"] == st.n_matvec
         assert s["backtracks"] == st.backtracks
-        assert rel(host(v), v_ref) < tol
+        assert close(host(v), v_ref, tol)
         assert abs(s["J"] - st.J) <= 100 * tol * abs(st.J)
     finally:
         P.close()
@@ -92,8 +92,13 @@ def test_full_newton_adaptive_c2_tracks_oracle():
         assert s["status"] == 0 and s["g_rel"] <= 1e-4
         assert s["newton_iters"] == st.newton_iters
         assert abs(s["pcg_iters"] - st.pcg_iters) <= 2
-        assert rel(host(v), v_ref) < 1e-3
         assert s["newton_iters"] <= sg["newton_iters"]
+        # run to convergence, full Newton reaches the same minimiser as the oracle's Gauss-Newton solve
+        from gpu_cases import tight_solution
+        v_tight, _ = tight_solution(case, 1e-6)
+        v5, s5 = P.solve(max_newton=50, max_pcg=300, gtol_rel=1e-5)
+        assert s5["status"] == 0 and s5["g_rel"] <= 1e-5
+        assert close(host(v5), v_tight, 1e-4)
         with pytest.raises(Exception):
             P.time_pass(0, 1)          # the timing hook covers the Gauss-Newton stages
     finally:

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synthdata as sd
-from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel
+from gpu_cases import Case, dev, gpu_problem, host, inputs, params, rel, close
 from oracle import Grid, reduced, spectral
 
 pytestmark = pytest.mark.gpu
@@ -26,10 +26,10 @@ def test_2048sq_gradient_matvec_parity_symmetry_positivity():
     P = gpu_problem(case)
     try:
         gg, J = P.gradient(dev(vlin))
-        assert rel(host(gg), lin.g) < 1e-5
+        assert close(host(gg), lin.g, 1e-5)
         assert abs(J - lin.J) <= 1e-5 * abs(lin.J)
         Hx = host(P.hessian_matvec(dev(vt)))
-        assert rel(Hx, H_ref) < 1e-5
+        assert close(Hx, H_ref, 1e-5)
         y = sd.random_vec(case.n1, case.n2, 12, 98, divfree=True)
         Hy = host(P.hessian_matvec(dev(y)))
         a, b = float((Hx * y).sum()), float((vt * Hy).sum())
@@ -43,7 +43,7 @@ def test_2048sq_gradient_matvec_parity_symmetry_positivity():
         for op in ("A1", "A2", "I1", "I2"):
             assert {v for v, _ in rep[op]} <= fits, rep[op]
         assert set(rep["chosen"][2:6]) <= fits
-        assert rel(host(P.hessian_matvec(dev(vt))), H_ref) < 1e-5
+        assert close(host(P.hessian_matvec(dev(vt))), H_ref, 1e-5)
     finally:
         P.close()
 
@@ -64,9 +64,9 @@ def test_2048sq_fp64_gradient_matvec_parity():
     P = gpu_problem(case)
     try:
         gg, J = P.gradient(dev(vlin))
-        assert rel(host(gg), lin.g) < max(1e-10, 10 * rel(g_n, lin.g))
+        assert close(host(gg), lin.g, max(1e-10, 10 * rel(g_n, lin.g)))
         Hx = host(P.hessian_matvec(dev(vt)))
-        assert rel(Hx, H_ref) < max(1e-10, 10 * rel(H_n, H_ref))
+        assert close(Hx, H_ref, max(1e-10, 10 * rel(H_n, H_ref)))
     finally:
         P.close()
 
@@ -103,6 +103,6 @@ def test_2048sq_full_newton_matvec_parity():
     P = gpu_problem(case, hessian="full")
     try:
         P.gradient(dev(vlin), want_J=False)
-        assert rel(host(P.hessian_matvec(dev(vt))), H_ref) < 1e-5
+        assert close(host(P.hessian_matvec(dev(vt))), H_ref, 1e-5)
     finally:
         P.close()

@@ -6,11 +6,12 @@ the gradient and data term carry an absolute floor of 32 eps times the body forc
 (they are formed from m_R - m_1), and every bound is at least 10x the oracle's own response to FP64
 round-off in its input (beta_v A amplifies that by up to beta_v (n/2)^4 on a 2048-point H2 axis).  Sizes span several workgroup tiles, non-square grids, the
 smallest (8) and largest (2048) supported axis lengths, 512-point lines, the full 64^2 / 256^2 / 1024^2
-workloads, and even axis lengths that are not powers of two (10, 96, 150, 2046) on one or both axes."""
+workloads, and even axis lengths that are not powers of two: 2^a 3^b 5^c lengths (10, 90, 96, 150, 250,
+600, 1200: mixed-radix transforms) and 2046 = 2 * 3 * 11 * 31 (direct sums) on one or both axes."""
 import numpy as np
 import pytest
 
-from gpu_cases import Case, dev, gpu_problem, host, inputs, oracle_results, rel
+from gpu_cases import Case, dev, gpu_problem, host, inputs, oracle_results, rel, close
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +40,12 @@ CASES = {
     "10x8_nt2_H2_none_fp64": Case(10, 8, 2, "H2", "none", 1e-2, 0.0, "fp64", seed=14),
     "16x2046_nt128_H2_divfree_fp64": Case(16, 2046, 128, "H2", "divfree", 1e-2, 0.0, "fp64", seed=15, vmax=0.1),
     "2046x16_nt128_H1_none_fp32": Case(2046, 16, 128, "H1", "none", 1e-2, 0.0, "fp32", seed=16, vmax=0.1),
+    # square lengths 2^a 3^b 5^c (one launch per stage, mixed-radix transforms of up to 8 and 4 elements
+    # per thread in the row and column parts)
+    "250sq_nt4_H2_mass_fp32": Case(250, 250, 4, "H2", "mass_source", 1e-3, 1e-4, "fp32", seed=24),
+    "600sq_nt3_H1_divfree_fp32": Case(600, 600, 3, "H1", "divfree", 1e-3, 0.0, "fp32", seed=25),
+    "1200sq_nt2_H1_none_fp32": Case(1200, 1200, 2, "H1", "none", 1e-3, 0.0, "fp32", seed=26),
+    "90sq_nt3_H1_divfree_fp64": Case(90, 90, 3, "H1", "divfree", 1e-2, 0.0, "fp64", seed=27),
 }
 
 
@@ -83,7 +90,7 @@ def test_hessian_matvec_parity(problems, name):
     ref = oracle_results(case)
     P.gradient(dev(vlin), want_J=False)
     H = P.hessian_matvec(dev(vt))
-    assert rel(host(H), ref["H"]) < max(case.tol, 10 * ref["sens_H"])
+    assert close(host(H), ref["H"], max(case.tol, 10 * ref["sens_H"]))
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -93,9 +100,9 @@ def test_state_forward_and_preconditioner_parity(problems, name):
     mT, mR, vlin, vt, vtr = inputs(case)
     ref = oracle_results(case)
     m1 = P.state_forward(dev(vtr))
-    assert rel(host(m1), ref["m1"]) < case.tol
+    assert close(host(m1), ref["m1"], case.tol)
     z = P.precond(dev(ref["g"]))
-    assert rel(host(z), ref["z"]) < 1e-12   # FP64 spectral path in both precisions
+    assert close(host(z), ref["z"], 1e-12)   # FP64 spectral path in both precisions
 
 
 def test_matvec_is_bitwise_repeatable(problems):
@@ -157,16 +164,37 @@ def test_constant_template_hessian_is_regulariser(problems):
         P.gradient(dev(0.1 * vt), want_J=False)
         H = host(P.hessian_matvec(dev(vt)))
         expect = 2e-3 * np.stack([13.0 ** 2 * vt[0], 26.0 ** 2 * vt[1]])
-        assert rel(H, expect) < 1e-9   # b~ is FP32 round-off of the derivative of a constant
+        assert close(H, expect, 1e-9)   # b~ is FP32 round-off of the derivative of a constant
     finally:
         P.close()
+
+
+# Launch shapes of the FP32 fused stages: (elements per thread of the row transform, of the column
+# transform, threads per block).  A shape exists on a square power-of-two grid of N >= 64 points when
+# both transforms fit (E <= N/2, a block holds at least one transform of each kind, at most 1024
+# threads) and the transforms' LDS fits in 160 KiB; smaller or other grids have one fixed shape.
+SHAPES = [(8, 16, 128), (4, 16, 256), (4, 8, 256), (8, 8, 128), (8, 8, 256), (4, 4, 256), (8, 16, 256),
+          (16, 16, 128), (4, 4, 512), (4, 4, 64), (8, 8, 64), (16, 16, 64)]
+
+
+def expected_shapes(n1, n2):
+    if n1 != n2 or n1 & (n1 - 1) or n1 < 64:
+        return {0}
+    n, lds = n1, (n1 + n1 // 16) * 8
+    ok = set()
+    for v, (er, ec, bs) in enumerate(SHAPES):
+        if er <= n // 2 and ec <= n // 2 and n // er <= bs <= 1024 and n // ec <= bs and \
+                (bs // (n // er)) * 2 * lds <= 160 * 1024 and (bs // (n // ec)) * 2 * lds <= 160 * 1024:
+            ok.add(v)
+    return ok
 
 
 @pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "c1_64sq_nt4_H1_divfree_fp32", "128x32_nt3_H1_none_fp32",
                                   "128sq_nt3_H2_divfree_fp32", "512sq_nt4_H1_none_fp32"])
 def test_every_launch_shape_matches_oracle(problems, name):
-    """The autotuner may pick any launch shape (elements per thread, transforms per block): every one
-    must give an oracle-parity matvec; the tuned choice must too."""
+    """The autotuner may pick any launch shape (elements per thread, transforms per block): it must time
+    exactly the shapes that fit the grid, every one must give an oracle-parity matvec, and so must the
+    tuned choice."""
     import paper_1503_00757_amd as R
     case = CASES[name]
     P = get(problems, name)
@@ -174,18 +202,19 @@ def test_every_launch_shape_matches_oracle(problems, name):
     ref = oracle_results(case)
     P.gradient(dev(vlin), want_J=False)
     tol = max(case.tol, 10 * ref["sens_H"])
-    for v in range(12):
-        P.set_pass_variants([v] * 7)
-        try:
-            H = P.hessian_matvec(dev(vt))
-        except R.RegError:
-            continue   # shape not available for this grid
-        assert rel(host(H), ref["H"]) < tol, v
+    want = expected_shapes(case.n1, case.n2)
     P.set_pass_variants([0] * 7)
+    P.hessian_matvec(dev(vt))
     rep = P.autotune(reps=5)
-    assert "chosen" in rep
+    for op in ("A2", "I2", "A1", "I1"):
+        assert {v for v, _ in rep[op]} == want, (op, rep[op])
+    assert all(c in want for c in rep["chosen"][2:6])
     H = P.hessian_matvec(dev(vt))
-    assert rel(host(H), ref["H"]) < tol
+    assert close(host(H), ref["H"], tol)
+    for v in sorted(want):
+        P.set_pass_variants([v] * 7)
+        H = P.hessian_matvec(dev(vt))   # a shape that fits must launch (no fallback is expected here)
+        assert close(host(H), ref["H"], tol), v
     P.set_pass_variants([0] * 7)
     with pytest.raises(R.RegError):
         P.set_pass_variants([12] * 7)
