@@ -428,18 +428,20 @@ def _warmstart_pair(args):
     return w.mT, w.vstar
 
 
-def warmstart_pairs(ntrain, ntest, ntr=128, nte=256):
+def warmstart_pairs(ntrain, ntest, ntr=128, nte=256, nval=256):
     """Seeded pairs of the warm-start data set, drawn on the host cores before the GPU is touched:
-    training pairs 0..ntrain-1 at ntr^2, unseen test pairs from index 100000 on at nte^2."""
+    training pairs 0..ntrain-1 at ntr^2, a separate held-out set from index 50000 on at ntr^2, unseen
+    test pairs from index 100000 on at nte^2."""
     from concurrent.futures import ProcessPoolExecutor
     workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 4))
     with ProcessPoolExecutor(workers, initializer=_single_thread) as ex:
         train = list(ex.map(_warmstart_pair, [(p, ntr) for p in range(ntrain)], chunksize=32))
+        val = list(ex.map(_warmstart_pair, [(50000 + p, ntr) for p in range(nval)], chunksize=16))
         test = list(ex.map(_warmstart_pair, [(100000 + p, nte) for p in range(ntest)], chunksize=4))
-    return train, test
+    return train, val, test
 
 
-def bench_warmstart(train, test, epochs=60, label_gtol=1e-3, label_pool=16):
+def bench_warmstart(train, val, test, epochs=60, label_gtol=1e-3, label_pool=16):
     """Config 5: label the training pairs with the plain solver, train the warm-start network with the
     library's kernels (Adam, batch 16, grid-symmetry augmentation), then time the plain and the
     learned solve (network inference + solve from its v0, which includes g(0) and g(v0)) to
@@ -451,18 +453,19 @@ def bench_warmstart(train, test, epochs=60, label_gtol=1e-3, label_pool=16):
     log = lambda m: print(f"[bench] c5 {m}", file=sys.stderr, flush=True)   # noqa: E731
     t0 = time.perf_counter()
     feats, labels, st = W.build_dataset(train, 16, dev, label_gtol=label_gtol, pool=label_pool, log=log)
+    vfeats, vlabels, _ = W.build_dataset(val, 16, dev, label_gtol=label_gtol, pool=label_pool)
     torch.cuda.synchronize()
     t_labels = time.perf_counter() - t0
     ws = W.WarmStart(sd.network_init(), dev)
-    nval = max(16, len(train) // 16)
+    nval = len(val)
     t0 = time.perf_counter()
-    hist = ws.train(feats[:-nval], labels[:-nval], epochs, batch=16,
+    hist = ws.train(feats, labels, epochs, batch=16,
                     log=lambda m: log(m) if m.startswith("epoch") and int(m.split()[1].split("/")[0]) % 10 == 0 else None)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    steps = epochs * ((len(train) - nval) // 16)
-    val = ws.evaluate(feats[-nval:], labels[-nval:])
-    del feats, labels
+    steps = epochs * (len(train) // 16)
+    val = ws.evaluate(vfeats, vlabels)
+    del feats, labels, vfeats, vlabels
     # inference latency at the test size (features + network + rescale), events on the current stream
     mT = torch.tensor(test[0][0], device=dev)
     ws.predict(mT, mT)
@@ -477,7 +480,7 @@ def bench_warmstart(train, test, epochs=60, label_gtol=1e-3, label_pool=16):
     recs = W.compare_plain_vs_learned(test, 16, ws, dev, log=log, recycle=4)
     s = W.summarize(recs)
     return {
-        "protocol": f"train {len(train) - nval} pairs at {train[0][0].shape[0]}^2 (+{nval} held out), "
+        "protocol": f"train {len(train)} pairs at {train[0][0].shape[0]}^2 (a separate {nval} held out), "
                     f"{epochs} epochs; test {len(test)} unseen pairs at {test[0][0].shape[0]}^2; "
                     "H2 + mass source, beta_v=1e-3, beta_w=1e-4, n_t=16, FP32 transport",
         "time_to_grel_1e-2_ms": {"plain_mean": round(s["plain_ms_mean"], 3), "learned_mean": round(s["learned_ms_mean"], 3),
@@ -643,6 +646,8 @@ def main():
         w3, P3, vlin3, vt3 = setup(3)
         extras["c3_1024sq_nt32"] = c3_matvec(w3, P3, vlin3, vt3, copy_gbs)
         P3.close()
+        print("[bench] c4 batched solve of 96 pairs", file=sys.stderr, flush=True)
+        extras["c4_batched_96_pairs"] = bench_batch()
     if ws_pairs is not None:
         print("[bench] c5 learned warm start", file=sys.stderr, flush=True)
         extras["c5_warm_start"] = bench_warmstart(*ws_pairs, epochs=args.warmstart_epochs,
