@@ -249,6 +249,16 @@ reg_status reg_deformation_workspace_bytes(const reg_params* params, size_t* byt
 reg_status reg_deformation(reg_problem* h, const double* v, void* workspace, size_t workspace_bytes,
                            double* u1, double* F1, double* detF1, double* stats_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): reg_deformation without the workspace argument.  Its 37 FP64
+ * scratch fields live in a library-owned static device array (one per GPU, about 18.5 MiB, held
+ * until the process ends), so grids are limited to n1 * n2 <= 65536 (256 x 256); larger grids give
+ * REG_EINVAL.  The call allocates nothing.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be serialised by the caller.
+ * Outputs and their meaning as for reg_deformation. */
+reg_status reg_deformation_static(reg_problem* h, const double* v, double* u1, double* F1, double* detF1,
+                                  double* stats_host);
+
 /* Measurement hook: run `reps` (1..1000, reps * nt <= 512) Hessian matvecs at the current
  * linearisation point and time every launch of one of the four RK2-stage launches of a time step:
  * ms_per_launch_host = mean dispatch interval, from start / end events that the dispatch itself

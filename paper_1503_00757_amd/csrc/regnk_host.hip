@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
+#include <mutex>
 #include <thread>
 #include <cstdio>
 #include <cstdlib>
@@ -1762,6 +1763,51 @@ reg_status reg_deformation(reg_problem* h, const double* v, void* workspace, siz
     if (workspace_bytes < need) return fail(REG_ENOMEM, "diagnostics workspace of %zu bytes, %zu needed", workspace_bytes, need);
     if ((uintptr_t)workspace % 256 != 0) return fail(REG_EINVAL, "workspace must be 256-byte aligned");
     return deformation_run(h, v, (double*)workspace, u1, F1, detF1, stats_host);
+}
+
+// ---- allocation-free variant of reg_deformation ------------------------------------------------
+// The diagnostics workspace lives in a file-scope device array (one copy per GPU, kept until the
+// process ends).  In host code `scratch` only names the symbol: its device address on the current GPU
+// comes from hipGetSymbolAddress, taken once per device on the first call and kept.
+constexpr size_t DEF_STATIC_MAX_POINTS = 65536;   // grids up to 256 x 256 (n1 n2 <= 65536)
+static __device__ __align__(256) double scratch[(size_t)DEF_FIELDS * DEF_STATIC_MAX_POINTS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::atomic<double*> g_scratch[MAX_DEVICES];
+std::mutex g_scratch_mutex;
+
+reg_status static_scratch(double** out) {
+    int dev = -1;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(REG_EDEVICE, "device index %d out of range", dev);
+    double* p = g_scratch[dev].load();
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        p = g_scratch[dev].load();
+        if (!p) {
+            void* addr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !addr)
+                return fail(REG_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            p = static_cast<double*>(addr);
+            g_scratch[dev].store(p);
+        }
+    }
+    *out = p;
+    return REG_OK;
+}
+}  // namespace
+
+reg_status reg_deformation_static(reg_problem* h, const double* v, double* u1, double* F1, double* detF1,
+                                  double* stats_host) {
+    if (!h || !v) return fail(REG_EINVAL, "NULL argument");
+    if ((size_t)h->nn > DEF_STATIC_MAX_POINTS)
+        return fail(REG_EINVAL, "grid of %ld points exceeds the %zu points of the static diagnostics scratch (use "
+                                "reg_deformation with a caller workspace)", h->nn, DEF_STATIC_MAX_POINTS);
+    double* ws = nullptr;
+    CKS(static_scratch(&ws));
+    return deformation_run(h, v, ws, u1, F1, detF1, stats_host);
 }
 
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms, double* bytes, double* exec_ms) {

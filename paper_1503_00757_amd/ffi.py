@@ -104,12 +104,13 @@ def lib():
         L.reg_deformation_workspace_bytes.argtypes = [C.POINTER(RegParams), C.POINTER(sz)]
         L.reg_cfl.argtypes = [vp, vp, dp]
         L.reg_deformation.argtypes = [vp, vp, vp, sz, vp, vp, vp, dp]
+        L.reg_deformation_static.argtypes = [vp, vp, vp, vp, vp, dp]
         L.reg_last_error.argtypes = []
         L.reg_last_error.restype = C.c_char_p
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
                      "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve",
-                     "reg_deformation_workspace_bytes", "reg_deformation", "reg_cfl"):
+                     "reg_deformation_workspace_bytes", "reg_deformation", "reg_cfl", "reg_deformation_static"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -232,6 +233,13 @@ def reg_deformation(h, v: int, workspace: int, workspace_bytes: int, u1, F1, det
     """Returns (min, max, mean) of det F_1 (or None)."""
     st = (C.c_double * 3)()
     _check(lib().reg_deformation(h, v, workspace, workspace_bytes, u1, F1, detF1, st if want_stats else None))
+    return tuple(st) if want_stats else None
+
+
+def reg_deformation_static(h, v: int, u1, F1, detF1, want_stats=True):
+    """reg_deformation with the library's static scratch (no workspace); (min, max, mean) of det F_1."""
+    st = (C.c_double * 3)()
+    _check(lib().reg_deformation_static(h, v, u1, F1, detF1, st if want_stats else None))
     return tuple(st) if want_stats else None
 
 
