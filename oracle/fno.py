@@ -23,17 +23,24 @@ Network (arrays shaped (batch, channel, n1, n2); x = 2 pi i / n):
           H(k) = n^-2 sum_x h(x) e^{-i k.x} (Fourier coefficient); retained k1 in {0..15, -16..-1},
           k2 in {0..15}; w(0) = 1 and only the real part of the k2 = 0 column is kept (the
           inverse real FFT convention); w(k2 > 0) = 2 (Hermitian completion)
-  y     = B (Q2 gelu(Q1 h4 + q1) + q2)                          projection 32 -> 64 -> 2, then the
-          band limit B u = real( sum over retained k with |k| <= 12 of w(k2) U(k) e^{i k.x} ) (S with
-          identity weights on the disc |k| <= 12 and zero weights on the corners of the retained
-          square): the predicted velocity has no energy where the solutions have none, which the
-          H2 regulariser would weight by |k|^4
+  y     = B (Q2 gelu(Q1 h4 + q1) + q2)                          projection 32 -> 64 -> 2 + 2R, then
+          the band limit B u = real( sum over retained k with |k| <= 12 of w(k2) U(k) e^{i k.x} ) (S
+          with identity weights on the disc |k| <= 12 and zero weights on the corners of the
+          retained square): the predicted fields have no energy where the solutions have none,
+          which the H2 regulariser would weight by |k|^4
   gelu(x) = x Phi(x) (exact, with the normal CDF Phi)
-Loss over a batch: L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2 (Euclidean sums).
+Output channels: y[0:2] = v / s (the warm start); y[2 + 2k : 4 + 2k] = direction z_k, k < R = 4, a
+vector field for the low-rank correction of the PCG preconditioner (``solver.SolveOpts.precond_U``).
+Its training target is the k-th leading generalised eigenvector of (H, M) at the solved velocity
+(``solver.ritz_directions``); only the line it spans matters, so its loss is sign- and scale-free.
+Loss over a batch (Euclidean sums over points and the two components):
+  L = (1/B) sum_b [ ||y_b - t_b||^2 / ||t_b||^2 over channels 0, 1
+                    + (lambda / R) sum_k w_bk (1 - <t_bk, y_bk>^2 / (||t_bk||^2 max(||y_bk||^2, 1e-30))) ]
+with lambda = DIR_WEIGHT and w_bk = 1 if ||t_bk|| > 0, else 0 (no target: no term).
 
 Flat parameter vector (float), in this order:
   Wl[32][4], bl[32];  for l = 0..3: Rr_l[32][16][32][32], Ri_l[32][16][32][32], W_l[32][32], b_l[32];
-  Q1[64][32], q1[64], Q2[2][64], q2[2]
+  Q1[64][32], q1[64], Q2[2 + 2R][64], q2[2 + 2R]
   R index order: [k1 row j][k2][c in][c out], k1 = j for j < 16 and j - 32 otherwise.
 
 Two formulations of the same network:
@@ -58,7 +65,9 @@ WIDTH = 32
 MODES = 16
 LAYERS = 4
 IN_CH = 9
-OUT_CH = 2
+RANK = 4                 # directions of the low-rank head
+OUT_CH = 2 + 2 * RANK    # velocity (2) and RANK vector fields
+DIR_WEIGHT = 0.1         # lambda: weight of the direction terms in the loss
 HIDDEN = 64
 OUT_RADIUS = 12
 
@@ -129,10 +138,11 @@ def features(mT, mR):
 
 
 def predict(theta, mT, mR, bf16=False, spectral="gemm"):
-    """Warm start v0 = s y(features) for one pair."""
+    """Warm start v0 = s y[0:2] and the RANK directions y[2:] (shaped (RANK, 2, n1, n2)) for one pair."""
     a, s = features(mT, mR)
     y, _ = forward(theta, a[None], bf16=bf16, spectral=spectral)
-    return s * y[0]
+    n1, n2 = y.shape[-2:]
+    return s * y[0, :2], y[0, 2:].reshape(RANK, 2, n1, n2)
 
 
 def gelu(x):
@@ -300,15 +310,33 @@ def forward(theta, a, bf16=False, spectral="gemm"):
 
 
 def loss(y, t):
-    """(1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2 and its gradient with respect to y."""
+    """The loss L of the module docstring and its gradient with respect to y.
+
+    Velocity channels: relative squared error.  Direction k: 1 - cos^2 of the angle between y_k and
+    t_k, whose gradient is -2 c t / (a b) + 2 c^2 y / (a b^2) with a = ||t||^2, b = ||y||^2,
+    c = <t, y>."""
     y = np.asarray(y, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
     B = y.shape[0]
-    d = y - t
+    d = y[:, :2] - t[:, :2]
     num = (d * d).reshape(B, -1).sum(axis=1)
-    den = (t * t).reshape(B, -1).sum(axis=1)
+    den = (t[:, :2] * t[:, :2]).reshape(B, -1).sum(axis=1)
     L = float((num / den).sum() / B)
-    dy = 2.0 * d / (B * den[:, None, None, None])
+    dy = np.zeros_like(y)
+    dy[:, :2] = 2.0 * d / (B * den[:, None, None, None])
+    wdir = DIR_WEIGHT / RANK
+    for k in range(RANK):
+        ch = slice(2 + 2 * k, 4 + 2 * k)
+        yk, tk = y[:, ch], t[:, ch]
+        a = (tk * tk).reshape(B, -1).sum(axis=1)
+        b = np.maximum((yk * yk).reshape(B, -1).sum(axis=1), 1e-30)
+        c = (tk * yk).reshape(B, -1).sum(axis=1)
+        w = (a > 0).astype(np.float64)
+        a_ = np.where(a > 0, a, 1.0)
+        L += float(wdir * (w * (1.0 - c * c / (a_ * b))).sum() / B)
+        f = (w * wdir / B)[:, None, None, None]
+        dy[:, ch] = f * (-2.0 * (c / (a_ * b))[:, None, None, None] * tk
+                         + 2.0 * (c * c / (a_ * b * b))[:, None, None, None] * yk)
     return L, dy
 
 

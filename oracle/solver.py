@@ -173,6 +173,20 @@ def lowrank_setup(g: Grid, p: Params, matvec, U, rel_tol=1e-10):
     return theta, Z, HZ
 
 
+def ritz_directions(g: Grid, p: Params, matvec, U, iters: int):
+    """Leading generalised eigenpairs of (H, M) by subspace iteration (an extension: the targets of
+    the learned low-rank correction).  Rayleigh-Ritz on span(U) (``lowrank_setup``), then
+    U <- M^{-1} H Z with the preconditioner PCG applies, repeated ``iters`` times; each step damps
+    the components along eigenvectors with smaller theta by their ratio to the kept ones.  Returns
+    (theta, Z) with theta descending and Z orthonormal in <., M .>_W."""
+    theta, Z, HZ = lowrank_setup(g, p, matvec, U)
+    for _ in range(iters):
+        U = [reduced.precond(g, p, hz) for hz in HZ]
+        theta, Z, HZ = lowrank_setup(g, p, matvec, U)
+    order = np.argsort(-theta, kind="stable")
+    return theta[order], [Z[i] for i in order]
+
+
 def corrected_precond(g: Grid, p: Params, theta, Z, HZ):
     """Balancing (deflation) correction of M^{-1} on span(Z), with E = Z^T W H Z = diag(theta):
 

@@ -33,7 +33,8 @@ def test_bf16_rounding_matches_torch():
 def test_param_count():
     C, M = 32, 16
     per_layer = 2 * (2 * M * M * C * C) + C * C + C
-    assert fno.param_count() == C * 9 + C + 4 * per_layer + 64 * C + 64 + 2 * 64 + 2 == 4201090
+    assert fno.OUT_CH == 2 + 2 * fno.RANK == 10
+    assert fno.param_count() == C * 9 + C + 4 * per_layer + 64 * C + 64 + 10 * 64 + 10 == 4201610
     th = _theta(0)
     np.testing.assert_array_equal(fno.pack(fno.unpack(th)), th)
 
@@ -155,22 +156,59 @@ def test_features_closed_form():
     a0, s0 = fno.features(mT, mT)                     # identical images: no misfit channels
     assert s0 == 0.0 and not a0[6:].any()
     th = _theta(2)
-    assert not fno.predict(th, mT, mT).any()
-    v1 = fno.predict(th, mT, mR)
-    v2 = fno.predict(th, mT, mT + 3.0 * (mR - mT))    # the warm start scales with the misfit
+    assert not fno.predict(th, mT, mT)[0].any()
+    v1, z1 = fno.predict(th, mT, mR)
+    v2, z2 = fno.predict(th, mT, mT + 3.0 * (mR - mT))    # the warm start scales with the misfit,
     np.testing.assert_allclose(v2, 3.0 * v1, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(z2, z1, rtol=1e-12, atol=1e-15)    # the directions do not
+    assert z1.shape == (fno.RANK, 2) + mT.shape and np.abs(z1).max() > 0
 
 
 def test_loss_closed_form():
+    """Velocity channels: relative squared error.  Directions: 0 for any multiple of the target
+    (either sign), 1 for a field orthogonal to it, nothing for a zero target."""
     rng = np.random.default_rng(5)
-    t = rng.standard_normal((3, 2, 8, 8))
-    y = t * np.array([1.1, 0.8, 1.0])[:, None, None, None]
+    R = fno.RANK
+    t = rng.standard_normal((3, fno.OUT_CH, 8, 8))
+    t[2, 2:] = 0.0                                               # sample 2: no direction targets
+    y = rng.standard_normal(t.shape)
+    y[:, :2] = t[:, :2] * np.array([1.1, 0.8, 1.0])[:, None, None, None]
+    y[0, 2:] = -2.0 * t[0, 2:]                                    # sample 0: parallel
+    for k in range(R):                                           # sample 1: orthogonal
+        ch = slice(2 + 2 * k, 4 + 2 * k)
+        u = y[1, ch]
+        y[1, ch] = u - (u * t[1, ch]).sum() / (t[1, ch] ** 2).sum() * t[1, ch]
     L, dy = fno.loss(y, t)
-    assert abs(L - (0.01 + 0.04 + 0.0) / 3) < 1e-15
-    e = 1e-7
-    d = rng.standard_normal(y.shape)
+    assert abs(L - ((0.01 + 0.04 + 0.0) + fno.DIR_WEIGHT) / 3) < 1e-14
+    assert not dy[2, 2:].any()
+    # scale and sign of either side do not matter
+    t2, y2 = t.copy(), y.copy()
+    t2[:, 2:4] *= -3.0
+    y2[:, 4:6] *= 0.25
+    assert abs(fno.loss(y2, t2)[0] - L) < 1e-14
+
+
+def test_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(15)
+    t = rng.standard_normal((3, fno.OUT_CH, 8, 8))
+    t[1, 4:6] = 0.0                                              # one slot without a target
+    y = rng.standard_normal(t.shape)
+    L, dy = fno.loss(y, t)
+    for seed in range(3):
+        d = np.random.default_rng(100 + seed).standard_normal(y.shape)
+        e = 1e-6
+        fd = (fno.loss(y + e * d, t)[0] - fno.loss(y - e * d, t)[0]) / (2 * e)
+        assert abs(fd - (dy * d).sum()) < 1e-8 * max(1.0, abs(fd))
+    # the direction part alone (velocity channels held fixed), near alignment where the angle
+    # terms have a sizeable slope
+    y[:, 2:] = t[:, 2:] + 0.7 * rng.standard_normal(t[:, 2:].shape)
+    L, dy = fno.loss(y, t)
+    d = np.zeros_like(y)
+    d[:, 2:] = rng.standard_normal(d[:, 2:].shape)
+    e = 1e-5
     fd = (fno.loss(y + e * d, t)[0] - fno.loss(y - e * d, t)[0]) / (2 * e)
-    assert abs(fd - (dy * d).sum()) < 1e-8
+    an = (dy * d).sum()
+    assert abs(fd - an) < 1e-6 * abs(an) and abs(an) > 1e-3
 
 
 def test_gradient_matches_finite_differences_per_block():
@@ -180,7 +218,7 @@ def test_gradient_matches_finite_differences_per_block():
     rng = np.random.default_rng(6)
     th = _theta(7, 0.08)
     a = rng.standard_normal((2, 9, n, n))
-    t = rng.standard_normal((2, 2, n, n))
+    t = rng.standard_normal((2, fno.OUT_CH, n, n))
     y, cache = fno.forward(th, a)
     _, dy = fno.loss(y, t)
     g = fno.backward(cache, dy)
@@ -191,7 +229,7 @@ def test_gradient_matches_finite_differences_per_block():
         k = int(np.prod(shp))
         d = np.zeros_like(th)
         d[off:off + k] = rng.standard_normal(k)
-        eps = 1e-5 * np.linalg.norm(th[off:off + k]) / np.linalg.norm(d)   # relative to the block
+        eps = 3e-5 * np.linalg.norm(th[off:off + k]) / np.linalg.norm(d)   # relative to the block
         fd = (f(th + eps * d) - f(th - eps * d)) / (2 * eps)
         an = float(g @ d)
         # truncation O(eps^2) plus the rounding of L in the difference quotient
@@ -205,7 +243,7 @@ def test_bf16_network_stays_close_to_exact():
     rng = np.random.default_rng(8)
     th = _theta(9)
     a = rng.standard_normal((2, 9, n, n))
-    t = rng.standard_normal((2, 2, n, n))
+    t = rng.standard_normal((2, fno.OUT_CH, n, n))
     y, c = fno.forward(th, a)
     yb, cb = fno.forward(th, a, bf16=True)
     assert 1e-5 < np.linalg.norm(yb - y) / np.linalg.norm(y) < 1e-2

@@ -247,3 +247,30 @@ def test_warm_start_fallback_restarts_from_zero():
     assert stb.n_pde == st.n_pde + 2 and stb.newton_iters == st.newton_iters
     _, stg = solver.solve(g, p, mT, mR, solver.SolveOpts(v0=v, **opts))
     assert stg.fallback_used == 0 and stg.newton_iters == 0
+
+
+@pytest.mark.parametrize("constraint", ["none", "mass_source"])
+def test_subspace_iteration_finds_the_leading_eigenspaces(constraint):
+    """H = M S: the leading generalised eigenvectors are the Fourier modes with the largest s(k).
+    The (2, 2) class spans 8 real vector fields (cos and sin of 2x1 +- 2x2, two components) with
+    s = 40, the (1, 2) class another 8 with s = 7, everything else s <= 1.  Ten directions from
+    random fields must converge to all 8 of the first class and 2 of the second, in that order."""
+    g = Grid(16, 16)
+    bw = 1e-3 if constraint == "mass_source" else 0.0
+    p = Params(16, 16, 4, "H2", constraint, 1e-2, bw)
+    H = multiplier_operator(g, p, {(2, 2): 40.0, (1, 2): 7.0, (3, 1): 0.25})
+    rng = np.random.default_rng(11)
+    U = [rng.standard_normal((2, 16, 16)) for _ in range(10)]
+    theta, Z = solver.ritz_directions(g, p, H, U, iters=30)
+    assert np.allclose(theta[:8], 40.0, rtol=1e-9)
+    assert np.allclose(theta[8:], 7.0, rtol=1e-6)
+    assert np.all(np.diff(theta) <= 1e-9 * theta[0])
+    W = lambda a, b: reduced.w_inner(g, p, a, b)   # noqa: E731
+    for t, z in zip(theta, Z):
+        assert np.allclose(H(z), t * solver.precond_op(g, p, z), atol=1e-6 * t * np.abs(z).max())
+        assert abs(W(z, solver.precond_op(g, p, z)) - 1.0) < 1e-9
+    # no iteration: plain Rayleigh-Ritz on the random span, values sorted the same way
+    theta0, _ = solver.ritz_directions(g, p, H, U, iters=0)
+    ref, _, _ = solver.lowrank_setup(g, p, H, U)
+    assert np.allclose(theta0, np.sort(ref)[::-1], rtol=1e-12)
+    assert theta0[0] < 40.0 - 1e-3   # a random span is not invariant
