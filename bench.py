@@ -479,23 +479,25 @@ def bench_warmstart(train, val, test, epochs=60, label_gtol=1e-3, label_pool=16)
     log(f"comparing plain vs learned on {len(test)} unseen pairs")
     recs = W.compare_plain_vs_learned(test, 16, ws, dev, log=log, recycle=4)
     s = W.summarize(recs)
+    ratio = lambda a, b: round(s[b]["ms_mean"] / s[a]["ms_mean"], 3)   # noqa: E731  (speed-up of a over b)
     return {
         "protocol": f"train {len(train)} pairs at {train[0][0].shape[0]}^2 (a separate {nval} held out), "
                     f"{epochs} epochs; test {len(test)} unseen pairs at {test[0][0].shape[0]}^2; "
-                    "H2 + mass source, beta_v=1e-3, beta_w=1e-4, n_t=16, FP32 transport",
-        "time_to_grel_1e-2_ms": {"plain_mean": round(s["plain_ms_mean"], 3), "learned_mean": round(s["learned_ms_mean"], 3),
-                                 "plain_median": round(s["plain_ms_median"], 3),
-                                 "learned_median": round(s["learned_ms_median"], 3),
-                                 "speedup_mean": round(s["plain_ms_mean"] / s["learned_ms_mean"], 3)},
-        "newton_mean": {"plain": s["plain_newton_mean"], "learned": s["learned_newton_mean"]},
-        "pcg_mean": {"plain": s["plain_pcg_mean"], "learned": s["learned_pcg_mean"]},
-        # the same solves with 4 recycled PCG directions per Newton step (16-direction correction)
-        "with_recycled_directions": s.get("recycle"),
-        "converged": {"plain": s["plain_converged"], "learned": s["learned_converged"]},
-        "fallback_rate": s["fallback_rate"], "faster_fraction": s["faster_fraction"],
+                    "H2 + mass source, beta_v=1e-3, beta_w=1e-4, n_t=16, FP32 transport; targets: v/s and the "
+                    f"leading {W.ffi.REG_FNO_RANK} generalised eigenvectors of (H, M) at the label solution",
+        # means over the test pairs: plain (v0 = 0), learned v0, learned v0 + learned directions in
+        # the preconditioner correction; *_rc: the same with 4 recycled PCG directions per Newton step
+        "variants": {k: s[k] for k in ("plain", "learned", "learned_dirs", "plain_rc", "learned_rc",
+                                       "learned_dirs_rc")},
+        "speedup_mean": {"learned_vs_plain": ratio("learned", "plain"),
+                         "learned_dirs_vs_learned": ratio("learned_dirs", "learned"),
+                         "learned_dirs_vs_plain": ratio("learned_dirs", "plain"),
+                         "learned_rc_vs_plain_rc": ratio("learned_rc", "plain_rc"),
+                         "learned_dirs_rc_vs_learned_rc": ratio("learned_dirs_rc", "learned_rc"),
+                         "learned_dirs_rc_vs_plain_rc": ratio("learned_dirs_rc", "plain_rc")},
         "label_seconds": round(t_labels, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
         "train_ms_per_step_batch16": round(t_train / steps * 1e3, 3),
-        "train_loss_last_epoch": round(hist[-1], 5), "heldout_rel_sq_error": round(val, 5),
+        "train_loss_last_epoch": round(hist[-1], 5), "heldout_loss": round(val, 5),
         "inference_ms": round(t_inf, 3),
     }
 
@@ -609,10 +611,11 @@ def main():
         return
     if args.workload == "c5":
         r = bench_warmstart(*ws_pairs, epochs=args.warmstart_epochs, label_pool=args.warmstart_label_pool)
-        t = r["time_to_grel_1e-2_ms"]
-        print(json.dumps({"metric": "time to ||g||/||g(0)|| <= 1e-2 at 256^2, learned warm start (config 5)",
-                          "value": t["learned_mean"], "unit": "ms", "higher_is_better": False,
-                          "plain_value": t["plain_mean"], "n_gpus": 1, "dtype": "f32 transport, bf16 network",
+        t = r["variants"]
+        print(json.dumps({"metric": "time to ||g||/||g(0)|| <= 1e-2 at 256^2, learned warm start and directions "
+                                    "(config 5)",
+                          "value": t["learned_dirs"]["ms_mean"], "unit": "ms", "higher_is_better": False,
+                          "plain_value": t["plain"]["ms_mean"], "n_gpus": 1, "dtype": "f32 transport, bf16 network",
                           "data": "synthetic", **r}))
         return
     cfg = 2 if args.workload == "c2" else 3

@@ -236,6 +236,21 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
  * field; cfl_host: host double.  Synchronises the stream. */
 reg_status reg_cfl(reg_problem* h, const double* v, double* cfl_host);
 
+/* Leading generalised eigenpairs of (H, M) at the current linearisation point, H the Hessian of
+ * reg_hessian_matvec and M the preconditioner of reg_precond_apply (an extension: the training
+ * targets of the learned low-rank correction, regnet.h).  Subspace iteration: Rayleigh-Ritz on
+ * span(U) exactly as reg_solve does for precond_U (admissible parts, orthonormal in <., M .>_W,
+ * Ritz pairs with theta <= 0 dropped), then U <- M^{-1} H z_k, repeated `iters` times (0..100);
+ * each repetition damps the components along smaller theta by their ratio to the kept ones.
+ * U: device [rank][2][n1][n2], in: the starting directions, out: the Ritz vectors in descending
+ * order of theta, M-orthonormal with plain grid sums (sum over points of z_i . M z_j = delta_ij, the
+ * M image K^{-1}-weighted for REG_MASS_SOURCE as in <., .>_W; slots of dropped directions zeroed).  theta_host
+ * (nullable): host [rank], the Ritz values, descending, then zeros.  1 <= rank <= min(8,
+ * lowrank_capacity); REG_ESTATE before reg_gradient; REG_EINVAL for REG_STOKES with
+ * REG_MASS_SOURCE.  Costs (iters + 1) rank matvecs; overwrites the low-rank correction slots and
+ * synchronises the stream. */
+reg_status reg_ritz_directions(reg_problem* h, double* U, int32_t rank, int32_t iters, double* theta_host);
+
 /* Deformation diagnostics of a velocity (appendix "Illustration of Deformation Map"): the
  * displacement u with u(0) = 0 transported by v with source v (eq. (displacement); the Eulerian map
  * is y = x - u_1) and the deformation gradient F with F(0) = I transported by v with source

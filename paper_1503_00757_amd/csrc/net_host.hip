@@ -47,6 +47,7 @@ constexpr long OFF_Q2 = OFF_q1 + FNO_H;
 constexpr long OFF_q2 = OFF_Q2 + FNO_OUT * FNO_H;
 constexpr long N_PARAMS = OFF_q2 + FNO_OUT;
 static_assert(N_PARAMS == REG_FNO_PARAMS, "parameter layout");
+static_assert(FNO_OUT == REG_FNO_OUT && FNO_RANK == REG_FNO_RANK, "output channels");
 
 constexpr int KSPLIT_MAX = 1024;   // weight gradients: K = P split into chunks of >= 512
 constexpr long PART_FLOATS = (long)KSPLIT_MAX * FNO_H * FNO_C;
@@ -92,7 +93,7 @@ NetLayout net_layout(int n, int B) {
     L.dB = take(FNO_C * P * f);
     L.part = take(PART_FLOATS * f);
     L.rsum = take((size_t)FNO_H * RS_CHUNKS * sizeof(double));
-    L.sums = take(2 * (size_t)B * sizeof(double));
+    L.sums = take((size_t)FNO_LOSS_SUMS * B * sizeof(double));
     L.loss = take(sizeof(double));
     L.red = take(RED_BLOCKS * sizeof(double));
     L.sq = take(sizeof(double));
@@ -350,7 +351,7 @@ reg_status backward_impl(reg_fno* F, const float* th, const float* target, float
     const NetLayout& L = F->L;
     float *Y = F->f(L.Y), *Yp = F->f(L.Yp), *T = F->f(L.T), *O = F->f(L.O), *dZ = F->f(L.dZ);
     float *dy = F->f(L.dy), *dzq = F->f(L.dzq);
-    CK(launch_fno_loss(FNO_OUT, B, (long)n * n, F->f(L.y), target, F->at<double>(L.sums), dy, loss, F->stream));
+    CK(launch_fno_loss(B, (long)n * n, F->f(L.y), target, F->at<double>(L.sums), dy, loss, F->stream));
     CKS(band_limit_T(F, dy, F->f(L.du), FNO_OUT));
     dy = F->f(L.du);   // from here on: the gradient with respect to u
     // projection
@@ -572,10 +573,10 @@ reg_status reg_fno_features(reg_fno* h, const double* m_T, const double* m_R, fl
     return REG_OK;
 }
 
-reg_status reg_fno_target(reg_fno* h, const double* v, const double* scale, float* out) {
+reg_status reg_fno_target(reg_fno* h, const double* v, const double* scale, const double* dirs, float* out) {
     CKS(check_handle(h));
     if (!v || !scale || !out) return fail(REG_EINVAL, "NULL array");
-    CK(launch_fno_target(FNO_OUT * (long)h->n * h->n, v, scale, out, h->stream));
+    CK(launch_fno_target((long)h->n * h->n, v, scale, dirs, out, h->stream));
     return REG_OK;
 }
 
@@ -588,11 +589,14 @@ reg_status reg_fno_gather(reg_fno* h, const float* set, int64_t nset, int32_t ch
     if (channels == FNO_IN) {
         const int k[FNO_IN] = {0, 1, 2, 3, 4, 5, 0, 1, 2};   // features: m_T, grad, tensor, r, r grad
         std::memcpy(kinds.k, k, sizeof k);
-    } else if (channels == FNO_OUT) {
-        kinds.k[0] = 1;   // a velocity field
-        kinds.k[1] = 2;
+    } else if (channels == FNO_OUT || channels == 2) {
+        for (int c = 0; c < channels; c += 2) {   // vector fields: the velocity, then the directions
+            kinds.k[c] = 1;
+            kinds.k[c + 1] = 2;
+        }
     } else if (sym) {
-        return fail(REG_EINVAL, "symmetry transforms need the feature (9) or velocity (2) channel layout");
+        return fail(REG_EINVAL, "symmetry transforms need the feature (9), velocity (2) or output (%d) channel layout",
+                    FNO_OUT);
     }
     CK(launch_fno_gather(set, nset, channels, h->n, idx, sym, kinds, h->B, out, h->stream));
     return REG_OK;
@@ -629,13 +633,14 @@ reg_status reg_fno_train_step(reg_fno* h, float* params, const float* in, const 
     return reg_fno_adam(h, params, grad, m, v, step, lr, 0.9f, 0.999f, 1e-8f);
 }
 
-reg_status reg_fno_predict(reg_fno* h, const float* params, const double* m_T, const double* m_R, double* v0) {
+reg_status reg_fno_predict(reg_fno* h, const float* params, const double* m_T, const double* m_R, double* v0,
+                           double* dirs) {
     CKS(check_handle(h));
     if (h->B != 1) return fail(REG_EINVAL, "reg_fno_predict needs a handle with batch 1");
     if (!params || !m_T || !m_R || !v0) return fail(REG_EINVAL, "NULL array");
     CKS(features_impl(h, m_T, m_R, h->f(h->L.in)));
     CKS(forward_impl(h, params));
-    CK(launch_fno_unscale(FNO_OUT * h->P, h->f(h->L.y), h->at<double>(h->L.scale), v0, h->stream));
+    CK(launch_fno_unscale(h->P, h->f(h->L.y), h->at<double>(h->L.scale), v0, dirs, h->stream));
     return REG_OK;
 }
 

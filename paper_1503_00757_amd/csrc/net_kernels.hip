@@ -42,17 +42,23 @@ __global__ void scale_kernel(long nn, const double* __restrict__ sq, double* __r
     if (threadIdx.x == 0 && blockIdx.x == 0) scale[0] = sqrt(2.0 * sq[0] / (double)nn);
 }
 
-__global__ void target_kernel(long count, const double* __restrict__ v, const double* __restrict__ scale,
-                              float* __restrict__ out) {
+__global__ void target_kernel(long nn, const double* __restrict__ v, const double* __restrict__ scale,
+                              const double* __restrict__ dirs, float* __restrict__ out) {
     const double sc = scale[0];
     const double inv_s = sc > 0.0 ? 1.0 / sc : 0.0;
-    GRID_STRIDE(i, count) out[i] = (float)(v[i] * inv_s);
+    GRID_STRIDE(i, FNO_OUT * nn) {
+        if (i < 2 * nn) out[i] = (float)(v[i] * inv_s);
+        else out[i] = dirs ? (float)dirs[i - 2 * nn] : 0.0f;
+    }
 }
 
-__global__ void unscale_kernel(long count, const float* __restrict__ y, const double* __restrict__ scale,
-                               double* __restrict__ v) {
+__global__ void unscale_kernel(long nn, const float* __restrict__ y, const double* __restrict__ scale,
+                               double* __restrict__ v, double* __restrict__ dirs) {
     const double sc = scale[0];
-    GRID_STRIDE(i, count) v[i] = sc * (double)y[i];
+    GRID_STRIDE(i, FNO_OUT * nn) {
+        if (i < 2 * nn) v[i] = sc * (double)y[i];
+        else if (dirs) dirs[i - 2 * nn] = (double)y[i];
+    }
 }
 
 __global__ void gather_kernel(const float* __restrict__ set, long nset, int channels, int n,
@@ -202,41 +208,69 @@ __global__ void rowsum_final_kernel(int rows, const double* __restrict__ part, f
     out[r] = (float)s;
 }
 
-// block b: sample b's squared error and squared target over all channels
-__global__ __launch_bounds__(TB) void loss_sums_kernel(int ch, int B, long npos, const float* __restrict__ y,
+// block (b, g): sample b's sums over one channel pair.  g = 0, the velocity: squared error and squared
+// target; g = 1 + k, direction k: ||t||^2, ||y||^2, <t, y>.  sums[(b (1 + R) + g) 3 + 0..2].
+__global__ __launch_bounds__(TB) void loss_sums_kernel(int B, long npos, const float* __restrict__ y,
                                                        const float* __restrict__ t, double* __restrict__ sums) {
     __shared__ double sh[TB / 64];
-    double num = 0.0, den = 0.0;
-    for (int c = 0; c < ch; ++c) {
+    const int g = blockIdx.y;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int c = 2 * g; c < 2 * g + 2; ++c) {
         const long base = ((long)c * B + blockIdx.x) * npos;
         for (long i = threadIdx.x; i < npos; i += TB) {
-            const double tv = t[base + i], d = (double)y[base + i] - tv;
-            num += d * d;
-            den += tv * tv;
+            const double tv = t[base + i], yv = y[base + i];
+            if (g == 0) {
+                const double d = yv - tv;
+                s0 += d * d;
+                s1 += tv * tv;
+            } else {
+                s0 += tv * tv;
+                s1 += yv * yv;
+                s2 += tv * yv;
+            }
         }
     }
-    const double sn = block_sum<TB>(num, sh);
-    const double sd = block_sum<TB>(den, sh);
+    const double r0 = block_sum<TB>(s0, sh);
+    const double r1 = block_sum<TB>(s1, sh);
+    const double r2 = block_sum<TB>(s2, sh);
     if (threadIdx.x == 0) {
-        sums[2 * blockIdx.x] = sn;
-        sums[2 * blockIdx.x + 1] = sd;
+        double* o = sums + ((long)blockIdx.x * (1 + FNO_RANK) + g) * 3;
+        o[0] = r0;
+        o[1] = r1;
+        o[2] = r2;
     }
 }
 
-__global__ void loss_grad_kernel(int ch, int B, long npos, const float* __restrict__ y, const float* __restrict__ t,
+__global__ void loss_grad_kernel(int B, long npos, const float* __restrict__ y, const float* __restrict__ t,
                                  const double* __restrict__ sums, float* __restrict__ dy) {
-    const long total = (long)ch * B * npos;
+    const long total = (long)FNO_OUT * B * npos;
     GRID_STRIDE(i, total) {
         const int b = (int)((i / npos) % B);
-        const double den = sums[2 * b + 1];
-        dy[i] = den > 0.0 ? (float)(2.0 * ((double)y[i] - (double)t[i]) / (B * den)) : 0.0f;
+        const int c = (int)(i / (npos * B));
+        if (c < 2) {
+            const double den = sums[(long)b * (1 + FNO_RANK) * 3 + 1];
+            dy[i] = den > 0.0 ? (float)(2.0 * ((double)y[i] - (double)t[i]) / (B * den)) : 0.0f;
+        } else {
+            const double* S = sums + ((long)b * (1 + FNO_RANK) + 1 + (c - 2) / 2) * 3;
+            const double a = S[0], bb = fmax(S[1], 1e-30), cc = S[2];
+            const double f = FNO_DIR_WEIGHT / ((double)B * FNO_RANK);
+            dy[i] = a > 0.0 ? (float)(f * (-2.0 * cc * (double)t[i] / (a * bb) + 2.0 * cc * cc * (double)y[i] / (a * bb * bb)))
+                            : 0.0f;
+        }
     }
 }
 
 __global__ void loss_value_kernel(int B, const double* __restrict__ sums, double* __restrict__ loss) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double L = 0.0;
-    for (int b = 0; b < B; ++b) L += sums[2 * b + 1] > 0.0 ? sums[2 * b] / sums[2 * b + 1] : 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double* S = sums + (long)b * (1 + FNO_RANK) * 3;
+        L += S[1] > 0.0 ? S[0] / S[1] : 0.0;
+        for (int k = 0; k < FNO_RANK; ++k) {
+            const double* D = S + 3 * (1 + k);
+            if (D[0] > 0.0) L += (FNO_DIR_WEIGHT / FNO_RANK) * (1.0 - D[2] * D[2] / (D[0] * fmax(D[1], 1e-30)));
+        }
+    }
     *loss = L / B;
 }
 
@@ -265,13 +299,14 @@ hipError_t launch_fno_scale(long nn, const double* sq, double* scale, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_fno_target(long count, const double* v, const double* scale, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(target_kernel, dim3(blocks_for(count)), dim3(TB), 0, s, count, v, scale, out);
+hipError_t launch_fno_target(long nn, const double* v, const double* scale, const double* dirs, float* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(target_kernel, dim3(blocks_for(FNO_OUT * nn)), dim3(TB), 0, s, nn, v, scale, dirs, out);
     return hipGetLastError();
 }
 
-hipError_t launch_fno_unscale(long count, const float* y, const double* scale, double* v, hipStream_t s) {
-    hipLaunchKernelGGL(unscale_kernel, dim3(blocks_for(count)), dim3(TB), 0, s, count, y, scale, v);
+hipError_t launch_fno_unscale(long nn, const float* y, const double* scale, double* v, double* dirs, hipStream_t s) {
+    hipLaunchKernelGGL(unscale_kernel, dim3(blocks_for(FNO_OUT * nn)), dim3(TB), 0, s, nn, y, scale, v, dirs);
     return hipGetLastError();
 }
 
@@ -326,10 +361,10 @@ hipError_t launch_rowsum(int rows, long len, const float* x, double* part, float
     return hipGetLastError();
 }
 
-hipError_t launch_fno_loss(int ch, int B, long npos, const float* y, const float* t, double* sums, float* dy,
-                           double* loss, hipStream_t s) {
-    hipLaunchKernelGGL(loss_sums_kernel, dim3(B), dim3(TB), 0, s, ch, B, npos, y, t, sums);
-    hipLaunchKernelGGL(loss_grad_kernel, dim3(blocks_for((long)ch * B * npos)), dim3(TB), 0, s, ch, B, npos, y, t,
+hipError_t launch_fno_loss(int B, long npos, const float* y, const float* t, double* sums, float* dy, double* loss,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(loss_sums_kernel, dim3(B, 1 + FNO_RANK), dim3(TB), 0, s, B, npos, y, t, sums);
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(blocks_for((long)FNO_OUT * B * npos)), dim3(TB), 0, s, B, npos, y, t,
                        sums, dy);
     if (loss) hipLaunchKernelGGL(loss_value_kernel, dim3(1), dim3(64), 0, s, B, sums, loss);
     return hipGetLastError();

@@ -17,7 +17,9 @@ constexpr int FNO_M = 16;        // retained modes per axis (k1 rows: 2M, k2 col
 constexpr int FNO_MODES = 2 * FNO_M * FNO_M;   // 512 retained (k1, k2) pairs
 constexpr int FNO_L = 4;         // Fourier layers
 constexpr int FNO_IN = 9;
-constexpr int FNO_OUT = 2;
+constexpr int FNO_RANK = 4;                    // direction fields of the low-rank head
+constexpr int FNO_OUT = 2 + 2 * FNO_RANK;      // channels 0, 1: v / s; 2 + 2k, 3 + 2k: direction k
+constexpr double FNO_DIR_WEIGHT = 0.1;         // weight of the direction terms in the loss
 constexpr int FNO_H = 64;        // projection width
 constexpr int FNO_RADIUS = 12;   // output band: retained modes with |k| <= 12
 
@@ -68,10 +70,13 @@ hipError_t launch_fno_features(int n, const double* mT, const double* mR, const 
                                hipStream_t s);
 // scale[0] = s = sqrt(2 sq / nn)
 hipError_t launch_fno_scale(long nn, const double* sq, double* scale, hipStream_t s);
-// out[i] = v[i] / s (0 if s = 0), i < count (normalised training target)
-hipError_t launch_fno_target(long count, const double* v, const double* scale, float* out, hipStream_t s);
-// v[i] = s y[i] (warm start from the normalised network output)
-hipError_t launch_fno_unscale(long count, const float* y, const double* scale, double* v, hipStream_t s);
+// training target of one pair, out[FNO_OUT][nn]: channels 0, 1 = v / s (0 if s = 0); channels 2.. =
+// dirs[k][2][nn] as float (zeros if dirs is NULL)
+hipError_t launch_fno_target(long nn, const double* v, const double* scale, const double* dirs, float* out,
+                             hipStream_t s);
+// v[i] = s y[i], i < 2 nn (warm start from the normalised network output); dirs (nullable) = the
+// direction channels y[2 nn ..] widened to double
+hipError_t launch_fno_unscale(long nn, const float* y, const double* scale, double* v, double* dirs, hipStream_t s);
 // out[c][b][p] = set[idx[b]][c'][q] for 0 <= idx[b] < nset (zeros otherwise), where sym[b] (nullable:
 // identity) is a symmetry of the periodic square grid: bit 0 swaps the axes, bits 1 and 2 flip axis
 // 1 and 2 (i -> (n - i) mod n); output point i reads source point P(F(i)).  kind[c] says how channel c
@@ -100,10 +105,13 @@ hipError_t launch_fno_fold_w(const float* dW, float* gR, hipStream_t s);
 // (rows * RS_CHUNKS doubles), a second pass adds them in a fixed order
 constexpr int RS_CHUNKS = 64;
 hipError_t launch_rowsum(int rows, long len, const float* x, double* part, float* out, hipStream_t s);
-// per-sample sums over channels of y - t and t (layout [ch][B][npos]); then dy = 2 (y - t) / (B den_b)
-// and loss = (1/B) sum_b num_b / den_b (device double, nullable)
-hipError_t launch_fno_loss(int ch, int B, long npos, const float* y, const float* t, double* sums, float* dy,
-                           double* loss, hipStream_t s);
+// Loss of a batch (layout [FNO_OUT][B][npos]): per sample b the relative squared error of the two
+// velocity channels, num_b / den_b, plus (FNO_DIR_WEIGHT / FNO_RANK) sum_k (1 - c^2 / (a max(bb, 1e-30)))
+// over the direction slots k with a = ||t_k||^2 > 0 (bb = ||y_k||^2, c = <t_k, y_k>).  sums holds
+// 3 (1 + FNO_RANK) B doubles; dy = dL/dy; loss = L (device double, nullable), averaged over B.
+constexpr int FNO_LOSS_SUMS = 3 * (1 + FNO_RANK);
+hipError_t launch_fno_loss(int B, long npos, const float* y, const float* t, double* sums, float* dy, double* loss,
+                           hipStream_t s);
 // Adam with bias corrections c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t)
 hipError_t launch_adam(long n, float* p, const float* g, float* m, float* v, float lr, float beta1, float beta2,
                        float eps, float c1, float c2, hipStream_t s);

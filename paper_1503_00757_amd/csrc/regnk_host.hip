@@ -203,6 +203,7 @@ struct reg_problem {
     };
     static constexpr int NGRAPH = 4;
     MvGraph graph[NGRAPH];
+    hipGraphExec_t lr_graph[LR_MIX_MAX] = {};   // H z_k of the Rayleigh-Ritz basis slots (fixed pointers)
     int graph_next = 0;
     bool use_graphs = true;
     hipStream_t capture_stream = nullptr;
@@ -675,6 +676,10 @@ void drop_graphs(reg_problem* P) {
     P->pcg_iter_graph = nullptr;
     if (P->pcg_iter_graph_lr) (void)hipGraphExecDestroy(P->pcg_iter_graph_lr);
     P->pcg_iter_graph_lr = nullptr;
+    for (auto& g : P->lr_graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
 // Capture the work `enqueue` puts on the problem's stream into an executable graph (on the private
@@ -840,6 +845,28 @@ reg_status lr_gram(reg_problem* P, int setx, int sety, int r, double* G) {
     return REG_OK;
 }
 
+// H z_k for Rayleigh-Ritz basis slot k (and K^{-1} H z_k for the mass-source model), replayed from a
+// graph captured once per slot: the slots' pointers are fixed, like the matvec's.
+template <typename T>
+reg_status lr_matvec(reg_problem* P, int k) {
+    const bool ms = P->p.constraint == REG_MASS_SOURCE;
+    const double* in = P->lr_slot(0, k);
+    double* out = P->lr_slot(1, k);
+    double* kout = ms ? P->lr_slot(3, k) : nullptr;
+    if (P->use_graphs) {
+        hipGraphExec_t& g = P->lr_graph[k];
+        if (!g) g = capture_graph(P, [&]() { return matvec_t<T>(P, in, out, kout, false); });
+        if (g) {
+            CK(hipGraphLaunch(g, P->stream));
+            P->matvec_done = true;
+            return REG_OK;
+        }
+        P->use_graphs = false;
+        drop_graphs(P);
+    }
+    return matvec_t<T>(P, in, out, kout, false);
+}
+
 // Rayleigh-Ritz on the caller directions U (r <= LR_MIX_MAX) at the current linearisation point:
 // admissible parts Z, orthonormalised in <., M .>_W (Gram eigenvalues <= 1e-10 of the largest
 // dropped), H applied to that basis, the projected Hessian diagonalised, Ritz pairs with theta <= 0
@@ -872,7 +899,7 @@ reg_status lr_setup_t(reg_problem* P, const double* U, int r, double* theta_out,
     if (r1 == 0) return lr_set_count(P, 0);
     CK(launch_lr_mix(n, P->lr_set(0), n, r, r1, C, P->stream));
     for (int k = 0; k < r1; ++k) {
-        CKS(matvec_t<T>(P, P->lr_slot(0, k), P->lr_slot(1, k), ms ? P->lr_slot(3, k) : nullptr));
+        CKS(lr_matvec<T>(P, k));
         if (nmv) ++*nmv;
     }
     double Tm[LR_MIX_MAX * LR_MIX_MAX], th[LR_MIX_MAX], V[LR_MIX_MAX * LR_MIX_MAX];
@@ -901,6 +928,33 @@ reg_status lr_setup_t(reg_problem* P, const double* U, int r, double* theta_out,
     CK(hipMemcpyAsync(P->lr_sc() + LRS_E, e, sizeof(double) * r2, hipMemcpyHostToDevice, P->stream));
     CK(hipStreamSynchronize(P->stream));   // e is a host stack array
     return lr_set_count(P, r2);
+}
+
+// Subspace iteration for the leading generalised eigenpairs of (H, M) at the current linearisation
+// point: Rayleigh-Ritz on span(U), then U <- M^{-1} H z_k, repeated `iters` times (the caller's U
+// holds each new basis).  Leaves the Ritz vectors in U in descending order of theta (dropped slots
+// zeroed) and the values in theta (host, descending, zeros after the kept ones).
+template <typename T>
+reg_status ritz_t(reg_problem* P, double* U, int rank, int iters, double* theta) {
+    const long n = 2 * P->nn;
+    double th[LR_MIX_MAX];
+    CKS(lr_setup_t<T>(P, U, rank, th, nullptr));
+    for (int it = 0; it < iters && P->lr_count > 0; ++it) {
+        const int r = P->lr_count;
+        for (int k = 0; k < r; ++k) CKS(precond_t(P, P->lr_slot(1, k), U + (size_t)k * n, nullptr));
+        CKS(lr_setup_t<T>(P, U, r, th, nullptr));
+    }
+    const int kept = P->lr_count;   // lr_setup_t leaves theta ascending in th[0, kept)
+    for (int k = 0; k < rank; ++k) {
+        if (k < kept)
+            CK(hipMemcpyAsync(U + (size_t)k * n, P->lr_slot(0, kept - 1 - k), n * 8, hipMemcpyDeviceToDevice, P->stream));
+        else
+            CK(launch_fill(n, 0.0, U + (size_t)k * n, P->stream));
+        if (theta) theta[k] = k < kept ? th[kept - 1 - k] : 0.0;
+    }
+    CKS(lr_set_count(P, 0));
+    CK(hipStreamSynchronize(P->stream));
+    return REG_OK;
 }
 
 // ---- PCG (Alg. 2) -----------------------------------------------------------------------------
@@ -1740,6 +1794,18 @@ reg_status reg_batch_solve(int32_t count, reg_problem* const* problems, const re
     for (int i = 0; i < count; ++i)
         if (status[i] == REG_ENOTCONV) return fail(REG_ENOTCONV, "pair %d: %s", i, errs[i].c_str());
     return REG_OK;
+}
+
+reg_status reg_ritz_directions(reg_problem* h, double* U, int32_t rank, int32_t iters, double* theta_host) {
+    if (!h || !U) return fail(REG_EINVAL, "NULL argument");
+    if (!h->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
+    if (rank < 1 || rank > LR_MIX_MAX || rank > h->p.lowrank_capacity)
+        return fail(REG_EINVAL, "rank=%d out of [1, min(%d, lowrank_capacity=%d)]", rank, LR_MIX_MAX,
+                    h->p.lowrank_capacity);
+    if (iters < 0 || iters > 100) return fail(REG_EINVAL, "iters=%d out of [0, 100]", iters);
+    if (h->p.norm == REG_STOKES && h->p.constraint == REG_MASS_SOURCE)
+        return fail(REG_EINVAL, "no low-rank directions for the shear-control model with a mass source");
+    return DISPATCH(h, ritz_t<float>(h, U, rank, iters, theta_host), ritz_t<double>(h, U, rank, iters, theta_host));
 }
 
 reg_status reg_cfl(reg_problem* h, const double* v, double* cfl_host) {

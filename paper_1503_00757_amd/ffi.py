@@ -81,13 +81,13 @@ def lib():
         L.reg_fno_create.argtypes = [i32, i32, vp, sz, vp, C.POINTER(vp)]
         L.reg_fno_destroy.argtypes = [vp]
         L.reg_fno_features.argtypes = [vp, vp, vp, vp, vp]
-        L.reg_fno_target.argtypes = [vp, vp, vp, vp]
+        L.reg_fno_target.argtypes = [vp, vp, vp, vp, vp]
         L.reg_fno_gather.argtypes = [vp, vp, i64, i32, vp, vp, vp]
         L.reg_fno_forward.argtypes = [vp, vp, vp, vp]
         L.reg_fno_backward.argtypes = [vp, vp, vp, vp, vp]
         L.reg_fno_adam.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32]
         L.reg_fno_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, f32, vp]
-        L.reg_fno_predict.argtypes = [vp, vp, vp, vp, vp]
+        L.reg_fno_predict.argtypes = [vp, vp, vp, vp, vp, vp]
         L.reg_set_stream.argtypes = [vp, vp]
         L.reg_state_forward.argtypes = [vp, vp, vp]
         L.reg_objective.argtypes = [vp, vp, dp, dp]
@@ -103,6 +103,7 @@ def lib():
         L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
         L.reg_deformation_workspace_bytes.argtypes = [C.POINTER(RegParams), C.POINTER(sz)]
         L.reg_cfl.argtypes = [vp, vp, dp]
+        L.reg_ritz_directions.argtypes = [vp, vp, i32, i32, dp]
         L.reg_deformation.argtypes = [vp, vp, vp, sz, vp, vp, vp, dp]
         L.reg_deformation_static.argtypes = [vp, vp, vp, vp, vp, dp]
         L.reg_last_error.argtypes = []
@@ -110,7 +111,8 @@ def lib():
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
                      "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve",
-                     "reg_deformation_workspace_bytes", "reg_deformation", "reg_cfl", "reg_deformation_static"):
+                     "reg_deformation_workspace_bytes", "reg_deformation", "reg_cfl", "reg_deformation_static",
+                     "reg_ritz_directions"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -217,6 +219,13 @@ def reg_batch_solve(handles, opts, v_outs, raise_on_error: bool = True):
     return status, [S[i] for i in range(n)]
 
 
+def reg_ritz_directions(h, U: int, rank: int, iters: int):
+    """Subspace iteration in place on the device directions U; returns the Ritz values (descending)."""
+    th = (C.c_double * rank)()
+    _check(lib().reg_ritz_directions(h, U, rank, iters, th))
+    return list(th)
+
+
 def reg_cfl(h, v: int) -> float:
     c = C.c_double(0)
     _check(lib().reg_cfl(h, v, C.byref(c)))
@@ -248,7 +257,9 @@ def reg_set_images(h, m_T: int, m_R: int):
 
 
 # ---- learned warm start (include/regnet.h) -------------------------------------------------------
-REG_FNO_PARAMS = 4201090
+REG_FNO_PARAMS = 4201610
+REG_FNO_RANK = 4
+REG_FNO_OUT = 2 + 2 * REG_FNO_RANK
 REG_FNO_SYMMETRIES = 8
 
 
@@ -278,8 +289,8 @@ def reg_fno_features(h, m_T: int, m_R: int, out: int, scale=None):
     _check(lib().reg_fno_features(h, m_T, m_R, out, scale))
 
 
-def reg_fno_target(h, v: int, scale: int, out: int):
-    _check(lib().reg_fno_target(h, v, scale, out))
+def reg_fno_target(h, v: int, scale: int, dirs, out: int):
+    _check(lib().reg_fno_target(h, v, scale, dirs, out))
 
 
 def reg_fno_gather(h, data_set: int, nset: int, channels: int, idx: int, sym, out: int):
@@ -304,5 +315,5 @@ def reg_fno_train_step(h, params: int, inp: int, target: int, grad: int, m: int,
     _check(lib().reg_fno_train_step(h, params, inp, target, grad, m, v, step, lr, loss))
 
 
-def reg_fno_predict(h, params: int, m_T: int, m_R: int, v0: int):
-    _check(lib().reg_fno_predict(h, params, m_T, m_R, v0))
+def reg_fno_predict(h, params: int, m_T: int, m_R: int, v0: int, dirs=None):
+    _check(lib().reg_fno_predict(h, params, m_T, m_R, v0, dirs))

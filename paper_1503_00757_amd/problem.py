@@ -149,6 +149,13 @@ class Problem:
         self.nt = d["nt"]
         return v, d
 
+    def ritz_directions(self, U, iters=8):
+        """Leading generalised eigenpairs of (H, M) at the current linearisation point by subspace
+        iteration from the directions U [r][2][n1][n2] (reg_ritz_directions): (Ritz vectors, values)."""
+        U = self._c(U).clone()
+        theta = ffi.reg_ritz_directions(self.h, U.data_ptr(), int(U.shape[0]), iters)
+        return U, theta
+
     def cfl(self, v):
         """CFL number of v for this problem's n_t (reg_cfl)."""
         return ffi.reg_cfl(self.h, self._c(v).data_ptr())

@@ -1,5 +1,6 @@
 """Learned warm start (``include/regnet.h``): a Fourier neural operator predicts the initial velocity of
-the Gauss-Newton solve (Alg. 1) from (m_T, m_R).  It is trained on the GPU by the library's own
+the Gauss-Newton solve (Alg. 1) from (m_T, m_R), and directions for the low-rank correction of its
+PCG preconditioner.  It is trained on the GPU by the library's own
 forward, reverse-pass and Adam kernels on registrations that the plain solver produced, and the
 plain solver has the last word: ``reg_solve`` drops a warm start that does not lower the objective.
 
@@ -54,10 +55,12 @@ class Network:
                              scale.data_ptr() if scale is not None else None)
         return out
 
-    def target(self, v, scale, out=None):
-        """[2][n][n] float32 training target v / s of a solved velocity (FP64) and its pair's scale."""
-        out = self._f32(2, self.n, self.n) if out is None else out
-        ffi.reg_fno_target(self.h, v.contiguous().data_ptr(), scale.data_ptr(), out.data_ptr())
+    def target(self, v, scale, dirs=None, out=None):
+        """[REG_FNO_OUT][n][n] float32 training target: v / s of a solved velocity (FP64) and its pair's
+        scale, then the direction targets dirs [REG_FNO_RANK][2][n][n] (FP64; None: zeros, not trained)."""
+        out = self._f32(ffi.REG_FNO_OUT, self.n, self.n) if out is None else out
+        ffi.reg_fno_target(self.h, v.contiguous().data_ptr(), scale.data_ptr(),
+                           dirs.contiguous().data_ptr() if dirs is not None else None, out.data_ptr())
         return out
 
     def gather(self, data_set, idx, out=None, sym=None):
@@ -73,7 +76,7 @@ class Network:
         return out
 
     def forward(self, params, inp, out=None):
-        out = self._f32(2, self.batch, self.n, self.n) if out is None else out
+        out = self._f32(ffi.REG_FNO_OUT, self.batch, self.n, self.n) if out is None else out
         ffi.reg_fno_forward(self.h, params.data_ptr(), inp.contiguous().data_ptr(), out.data_ptr())
         return out
 
@@ -91,12 +94,14 @@ class Network:
         ffi.reg_fno_train_step(self.h, params.data_ptr(), inp.data_ptr(), target.data_ptr(), grad.data_ptr(),
                                m.data_ptr(), v.data_ptr(), step, lr, loss.data_ptr() if loss is not None else None)
 
-    def predict(self, params, mT, mR, out=None):
-        """FP64 [2][n][n] velocity for one pair (batch-1 handle)."""
-        out = self.torch.empty((2, self.n, self.n), dtype=self.torch.float64, device=self.device) if out is None else out
+    def predict(self, params, mT, mR):
+        """(v0 FP64 [2][n][n], directions FP64 [REG_FNO_RANK][2][n][n]) for one pair (batch-1 handle)."""
+        t = self.torch
+        v0 = t.empty((2, self.n, self.n), dtype=t.float64, device=self.device)
+        dirs = t.empty((ffi.REG_FNO_RANK, 2, self.n, self.n), dtype=t.float64, device=self.device)
         ffi.reg_fno_predict(self.h, params.data_ptr(), mT.contiguous().data_ptr(), mR.contiguous().data_ptr(),
-                            out.data_ptr())
-        return out
+                            v0.data_ptr(), dirs.data_ptr())
+        return v0, dirs
 
 
 class WarmStart:
@@ -117,9 +122,9 @@ class WarmStart:
         self._pred = {}
 
     def train(self, feats, targets, epochs, batch=16, lr=1e-3, lr_final=5e-5, seed=0, log=None, augment=True):
-        """Adam on (1/B) sum ||y - t||^2 / ||t||^2 over shuffled batches; cosine learning-rate decay from
-        lr to lr_final.  feats: [N][9][n][n], targets: [N][2][n][n] normalised velocities v / s
-        (float32, device).  With augment, every sample of a batch is mapped by a random one of the 8
+        """Adam on the network loss (regnet.h) over shuffled batches; cosine learning-rate decay from
+        lr to lr_final.  feats: [N][9][n][n], targets: [N][REG_FNO_OUT][n][n] (normalised velocities
+        v / s, then the direction targets; float32, device).  With augment, every sample of a batch is mapped by a random one of the 8
         symmetries of the periodic square grid (exact for the discrete problem).  Returns the mean
         training loss of every epoch."""
         torch = self.torch
@@ -128,7 +133,7 @@ class WarmStart:
             raise ValueError("fewer samples than one batch")
         net = Network(n, batch, self.device)
         inp = net._f32(feats.shape[1], batch, n, n)
-        tgt = net._f32(2, batch, n, n)
+        tgt = net._f32(targets.shape[1], batch, n, n)
         steps_per_epoch = N // batch
         total = epochs * steps_per_epoch
         losses = torch.zeros(steps_per_epoch, dtype=torch.float64, device=self.device)
@@ -163,7 +168,7 @@ class WarmStart:
         N, n = feats.shape[0], feats.shape[-1]
         b = min(batch, N)
         net = Network(n, b, self.device)
-        inp, tgt = net._f32(feats.shape[1], b, n, n), net._f32(2, b, n, n)
+        inp, tgt = net._f32(feats.shape[1], b, n, n), net._f32(targets.shape[1], b, n, n)
         grad = torch.empty_like(self.params)
         nb = N // b
         losses = torch.zeros(nb, dtype=torch.float64, device=self.device)
@@ -177,11 +182,12 @@ class WarmStart:
         net.close()
         return out
 
-    def predict(self, mT, mR, out=None):
+    def predict(self, mT, mR):
+        """(v0, directions) for one pair."""
         n = mT.shape[-1]
         if n not in self._pred:
             self._pred[n] = Network(n, 1, self.device)
-        return self._pred[n].predict(self.params, mT, mR, out)
+        return self._pred[n].predict(self.params, mT, mR)
 
 
 # ---- data set and evaluation helpers ---------------------------------------------------------------
@@ -207,20 +213,37 @@ def tune_shapes(P, device):
     return P.autotune(reps=20)["chosen"]
 
 
-def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settings):
+RITZ_BLOCK = 8     # subspace-iteration block for the direction targets (the leading 4 are kept)
+RITZ_ITERS = 6
+
+
+def direction_targets(P, v, seed):
+    """Leading REG_FNO_RANK generalised eigenvectors of (H, M) at v (reg_ritz_directions, block of
+    RITZ_BLOCK from seeded white noise, RITZ_ITERS steps), FP64 [REG_FNO_RANK][2][n1][n2]."""
+    import torch
+    P.gradient(v, want_J=False)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U0 = torch.as_tensor(rng.standard_normal((RITZ_BLOCK, 2, P.n1, P.n2)), device=v.device)
+    U, _ = P.ritz_directions(U0, RITZ_ITERS)
+    return U[:ffi.REG_FNO_RANK]
+
+
+def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, directions=True, seed=0, **settings):
     """Features and plain-solver labels for a list of (m_T, v*) numpy pairs of one grid size.
 
-    Returns (feats [N][9][n][n], labels [N][2][n][n], stats list); the labels are the velocities of the
-    plain solves (v0 = 0) to ||g|| / ||g(0)|| <= label_gtol divided by each pair's misfit scale,
-    solved `pool` at a time with reg_batch_solve on handles reused through reg_set_images (pool 1:
-    one after another on the calling thread)."""
+    Returns (feats [N][9][n][n], labels [N][REG_FNO_OUT][n][n], stats list); the labels are the
+    velocities of the plain solves (v0 = 0) to ||g|| / ||g(0)|| <= label_gtol divided by each pair's
+    misfit scale, solved `pool` at a time with reg_batch_solve on handles reused through
+    reg_set_images (pool 1: one after another on the calling thread), then (with directions) the
+    leading generalised eigenvectors of (H, M) at that velocity (``direction_targets``)."""
     import torch
     s = dict(SOLVER, **settings)
+    s["lowrank_capacity"] = max(s.get("lowrank_capacity", 0), RITZ_BLOCK)
     N = len(pairs)
     n = pairs[0][0].shape[0]
     feats = torch.empty((N, 9, n, n), dtype=torch.float32, device=device)
     scale = torch.empty(1, dtype=torch.float64, device=device)
-    labels = torch.empty((N, 2, n, n), dtype=torch.float32, device=device)
+    labels = torch.empty((N, ffi.REG_FNO_OUT, n, n), dtype=torch.float32, device=device)
     net = Network(n, 1, device)
     gen = None
     probs = []
@@ -253,7 +276,8 @@ def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settin
                 st.append(s_)
         for i, (v, (mT, mR)) in enumerate(zip(vs_out, imgs)):
             net.features(mT, mR, feats[c0 + i], scale)
-            net.target(v, scale, labels[c0 + i])
+            dirs = direction_targets(probs[i], v, seed + c0 + i) if directions else None
+            net.target(v, scale, dirs, labels[c0 + i])
         all_stats += st
         if log and (c0 // pool) % max(1, 1024 // pool) == 0:
             log(f"labels {c0 + len(chunk)}/{N} ({time.perf_counter() - t0:.1f} s)")
@@ -267,17 +291,29 @@ def build_dataset(pairs, nt, device, label_gtol=1e-2, pool=8, log=None, **settin
 
 def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup=1, log=None, recycle=0,
                              **settings):
-    """Time to ||g|| / ||g(0)|| <= gtol for every (m_T, v*) pair: plain solve (v0 = 0) and learned solve
-    (network inference + solve from its v0, which includes g(0) and g(v0)) on one problem handle.
-    recycle > 0 also times both with that many PCG directions of each Newton step recycled into the
-    low-rank correction of the preconditioner.  Returns per-pair records."""
+    """Time to ||g|| / ||g(0)|| <= gtol for every (m_T, v*) pair on one problem handle: the plain solve
+    (v0 = 0), the learned warm start (network inference + solve from its v0, which includes g(0) and
+    g(v0)) and the learned warm start with the network's directions in the low-rank correction of
+    the preconditioner (precond_U).  recycle > 0 also times all three with that many PCG directions
+    of each Newton step recycled into the correction.  Returns per-pair records."""
     import torch
     s = dict(SOLVER, **settings)
-    if recycle > 0:
-        s.setdefault("lowrank_capacity", 16)
+    s["lowrank_capacity"] = max(s.get("lowrank_capacity", 0), ffi.REG_FNO_RANK + (16 if recycle > 0 else 0))
     recs = []
     P = None
     gen = None
+
+    def timed(**kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kw.pop("learned", False):
+            v0, dirs = ws.predict(mT, mR)
+            if kw.pop("dirs", False):
+                kw["precond_U"] = dirs
+            kw["v0"] = v0
+        _, st = P.solve(gtol_rel=gtol, raise_on_error=False, **kw)
+        return time.perf_counter() - t0, st
+
     for i, (mT_np, vs) in enumerate(pairs):
         mT = torch.as_tensor(mT_np, dtype=torch.float64, device=device)
         if gen is None:
@@ -288,32 +324,28 @@ def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup
             P = Problem(mT, mR, nt, **s)
             tune_shapes(P, device)   # launch shapes for this grid (untimed; kept by the handle)
             for _ in range(warmup):   # graph capture and first-touch costs, not timed
-                P.solve(gtol_rel=gtol, raise_on_error=False)
+                timed()
+                timed(learned=True, dirs=True)
                 if recycle > 0:
-                    P.solve(gtol_rel=gtol, raise_on_error=False, recycle=recycle)
-                ws.predict(mT, mR)
+                    timed(recycle=recycle)
+                    timed(learned=True, dirs=True, recycle=recycle)
         P.set_images(mT, mR)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, sp = P.solve(gtol_rel=gtol, raise_on_error=False)
-        t1 = time.perf_counter()
-        v0 = ws.predict(mT, mR)
-        _, sl = P.solve(gtol_rel=gtol, v0=v0, raise_on_error=False)
-        t2 = time.perf_counter()
-        rec = {"plain_s": t1 - t0, "learned_s": t2 - t1, "plain": sp, "learned": sl}
+        tp, sp = timed()
+        tl, sl = timed(learned=True)
+        td, sd = timed(learned=True, dirs=True)
+        rec = {"plain_s": tp, "learned_s": tl, "learned_dirs_s": td, "plain": sp, "learned": sl, "learned_dirs": sd}
         if recycle > 0:
-            t0 = time.perf_counter()
-            _, spr = P.solve(gtol_rel=gtol, raise_on_error=False, recycle=recycle)
-            t1 = time.perf_counter()
-            v0 = ws.predict(mT, mR)
-            _, slr = P.solve(gtol_rel=gtol, v0=v0, raise_on_error=False, recycle=recycle)
-            t2 = time.perf_counter()
-            rec.update({"plain_rc_s": t1 - t0, "learned_rc_s": t2 - t1, "plain_rc": spr, "learned_rc": slr})
+            tp, spr = timed(recycle=recycle)
+            tl, slr = timed(learned=True, recycle=recycle)
+            td, sdr = timed(learned=True, dirs=True, recycle=recycle)
+            rec.update({"plain_rc_s": tp, "learned_rc_s": tl, "learned_dirs_rc_s": td, "plain_rc": spr,
+                        "learned_rc": slr, "learned_dirs_rc": sdr})
         recs.append(rec)
         if log and i % 32 == 0:
-            log(f"pair {i}: plain {1e3 * (t1 - t0):.1f} ms ({sp['newton_iters']} GN, {sp['pcg_iters']} PCG), "
-                f"learned {1e3 * (t2 - t1):.1f} ms ({sl['newton_iters']} GN, {sl['pcg_iters']} PCG, "
-                f"fallback {sl['fallback_used']})")
+            log(f"pair {i}: plain {1e3 * rec['plain_s']:.1f} ms ({sp['newton_iters']} GN, {sp['pcg_iters']} PCG), "
+                f"learned {1e3 * rec['learned_s']:.1f} ms ({sl['newton_iters']} GN, {sl['pcg_iters']} PCG, "
+                f"fallback {sl['fallback_used']}), with directions {1e3 * rec['learned_dirs_s']:.1f} ms "
+                f"({sd['newton_iters']} GN, {sd['pcg_iters']} PCG)")
     if P is not None:
         P.close()
     if gen is not None:
@@ -322,32 +354,24 @@ def compare_plain_vs_learned(pairs, nt, ws: WarmStart, device, gtol=1e-2, warmup
 
 
 def summarize(recs):
+    """Means over the pairs for every variant in the records (plain, learned, learned with
+    directions; with and without recycling), and how often the learned variants beat the plain one."""
     import statistics as stt
-    f = lambda k, sub: [r[sub][k] for r in recs]   # noqa: E731
-    out = {}
-    if recs and "plain_rc" in recs[0]:
-        ok = lambda sub: sum(1 for r in recs if r[sub]["g_rel"] <= 1e-2 and r[sub]["status"] == 0)  # noqa: E731
-        out["recycle"] = {
-            "plain_ms_mean": round(1e3 * stt.mean(r["plain_rc_s"] for r in recs), 3),
-            "learned_ms_mean": round(1e3 * stt.mean(r["learned_rc_s"] for r in recs), 3),
-            "plain_pcg_mean": stt.mean(f("pcg_iters", "plain_rc")),
-            "learned_pcg_mean": stt.mean(f("pcg_iters", "learned_rc")),
-            "plain_newton_mean": stt.mean(f("newton_iters", "plain_rc")),
-            "learned_newton_mean": stt.mean(f("newton_iters", "learned_rc")),
-            "plain_converged": ok("plain_rc"), "learned_converged": ok("learned_rc"),
+    out = {"pairs": len(recs)}
+    variants = [k for k in ("plain", "learned", "learned_dirs", "plain_rc", "learned_rc", "learned_dirs_rc")
+                if recs and k in recs[0]]
+    for k in variants:
+        sts = [r[k] for r in recs]
+        out[k] = {
+            "ms_mean": round(1e3 * stt.mean(r[k + "_s"] for r in recs), 3),
+            "ms_median": round(1e3 * stt.median(r[k + "_s"] for r in recs), 3),
+            "newton_mean": stt.mean(st["newton_iters"] for st in sts),
+            "pcg_mean": stt.mean(st["pcg_iters"] for st in sts),
+            "converged": sum(1 for st in sts if st["g_rel"] <= 1e-2 and st["status"] == 0),
+            "fallback_rate": stt.mean(st["fallback_used"] for st in sts),
         }
-    return out | {
-        "pairs": len(recs),
-        "plain_ms_mean": 1e3 * stt.mean(r["plain_s"] for r in recs),
-        "learned_ms_mean": 1e3 * stt.mean(r["learned_s"] for r in recs),
-        "plain_ms_median": 1e3 * stt.median(r["plain_s"] for r in recs),
-        "learned_ms_median": 1e3 * stt.median(r["learned_s"] for r in recs),
-        "plain_newton_mean": stt.mean(f("newton_iters", "plain")),
-        "learned_newton_mean": stt.mean(f("newton_iters", "learned")),
-        "plain_pcg_mean": stt.mean(f("pcg_iters", "plain")),
-        "learned_pcg_mean": stt.mean(f("pcg_iters", "learned")),
-        "plain_converged": sum(1 for r in recs if r["plain"]["g_rel"] <= 1e-2 and r["plain"]["status"] == 0),
-        "learned_converged": sum(1 for r in recs if r["learned"]["g_rel"] <= 1e-2 and r["learned"]["status"] == 0),
-        "fallback_rate": stt.mean(f("fallback_used", "learned")),
-        "faster_fraction": sum(1 for r in recs if r["learned_s"] < r["plain_s"]) / len(recs),
-    }
+    for k in variants:
+        if k.startswith("learned"):
+            base = "plain_rc" if k.endswith("_rc") else "plain"
+            out[k]["faster_than_" + base] = sum(1 for r in recs if r[k + "_s"] < r[base + "_s"]) / len(recs)
+    return out

@@ -285,7 +285,7 @@ def random_vec(n1: int, n2: int, kmax: int, seed: int, divfree: bool = False) ->
 def network_init(seed: int = BASE_SEED + 55) -> np.ndarray:
     """Initial weights of the warm-start network as one flat float32 vector, in the parameter order
     of the network's interface (lifting 9->32; four Fourier layers of width 32 with 32x16 retained
-    modes; projection 32->64->2).
+    modes; projection 32->64->10: the velocity and 4 direction fields).
 
     Draws only: pointwise weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)); spectral weights
     (real and imaginary parts) ~ U(0, 1) / (32 * 32), the usual initialisation of Fourier layers.
@@ -302,7 +302,8 @@ def network_init(seed: int = BASE_SEED + 55) -> np.ndarray:
         blocks += [rng.uniform(0.0, 1.0, size=(2 * M, M, C, C)) / (C * C),
                    rng.uniform(0.0, 1.0, size=(2 * M, M, C, C)) / (C * C),
                    uni((C, C), C), uni((C,), C)]
-    blocks += [uni((H, C), C), uni((H,), C), uni((2, H), H), uni((2,), H)]
+    OUT = 2 + 2 * 4
+    blocks += [uni((H, C), C), uni((H,), C), uni((OUT, H), H), uni((OUT,), H)]
     return np.concatenate([b.ravel() for b in blocks]).astype(np.float32)
 
 

@@ -2,6 +2,7 @@
 // contracts in net_kernels.hpp, so that the real host driver (net_host.hip compiled with g++) can
 // run on the CPU: every operand range a launch would touch is checked against the registered
 // buffers before any access (test infrastructure only).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -168,18 +169,24 @@ hipError_t launch_fno_scale(long nn, const double* sq, double* scale, hipStream_
     return hipSuccess;
 }
 
-hipError_t launch_fno_target(long count, const double* v, const double* scale, float* out, hipStream_t) {
-    if (!mock_range_ok(v, count * 8) || !mock_range_ok(scale, 8) || !span_ok(out, {{count, 1}}))
+hipError_t launch_fno_target(long nn, const double* v, const double* scale, const double* dirs, float* out,
+                             hipStream_t) {
+    if (!mock_range_ok(v, 2 * nn * 8) || !mock_range_ok(scale, 8) || !span_ok(out, {{FNO_OUT * nn, 1}}) ||
+        (dirs && !mock_range_ok(dirs, (FNO_OUT - 2) * nn * 8)))
         return hipErrorInvalidValue;
     const double inv_s = scale[0] > 0 ? 1.0 / scale[0] : 0.0;
-    for (long i = 0; i < count; ++i) out[i] = (float)(v[i] * inv_s);
+    for (long i = 0; i < 2 * nn; ++i) out[i] = (float)(v[i] * inv_s);
+    for (long i = 2 * nn; i < FNO_OUT * nn; ++i) out[i] = dirs ? (float)dirs[i - 2 * nn] : 0.0f;
     return hipSuccess;
 }
 
-hipError_t launch_fno_unscale(long count, const float* y, const double* scale, double* v, hipStream_t) {
-    if (!span_ok(y, {{count, 1}}) || !mock_range_ok(scale, 8) || !mock_range_ok(v, count * 8))
+hipError_t launch_fno_unscale(long nn, const float* y, const double* scale, double* v, double* dirs, hipStream_t) {
+    if (!span_ok(y, {{FNO_OUT * nn, 1}}) || !mock_range_ok(scale, 8) || !mock_range_ok(v, 2 * nn * 8) ||
+        (dirs && !mock_range_ok(dirs, (FNO_OUT - 2) * nn * 8)))
         return hipErrorInvalidValue;
-    for (long i = 0; i < count; ++i) v[i] = scale[0] * (double)y[i];
+    for (long i = 0; i < 2 * nn; ++i) v[i] = scale[0] * (double)y[i];
+    if (dirs)
+        for (long i = 2 * nn; i < FNO_OUT * nn; ++i) dirs[i - 2 * nn] = (double)y[i];
     return hipSuccess;
 }
 
@@ -343,31 +350,56 @@ hipError_t launch_rowsum(int rows, long len, const float* x, double* part, float
     return hipSuccess;
 }
 
-hipError_t launch_fno_loss(int ch, int B, long npos, const float* y, const float* t, double* sums, float* dy,
-                           double* loss, hipStream_t) {
-    const long tot = (long)ch * B * npos;
+hipError_t launch_fno_loss(int B, long npos, const float* y, const float* t, double* sums, float* dy, double* loss,
+                           hipStream_t) {
+    const long tot = (long)FNO_OUT * B * npos;
+    const int G = 1 + FNO_RANK;
     if (!span_ok(y, {{tot, 1}}) || !span_ok(t, {{tot, 1}}) || !span_ok(dy, {{tot, 1}}) ||
-        !mock_range_ok(sums, 16L * B) || (loss && !mock_range_ok(loss, 8)))
+        !mock_range_ok(sums, 8L * FNO_LOSS_SUMS * B) || (loss && !mock_range_ok(loss, 8)))
         return hipErrorInvalidValue;
-    for (int b = 0; b < B; ++b) {
-        double num = 0, den = 0;
-        for (int c = 0; c < ch; ++c)
-            for (long i = 0; i < npos; ++i) {
-                const long k = ((long)c * B + b) * npos + i;
-                const double d = (double)y[k] - t[k];
-                num += d * d;
-                den += (double)t[k] * t[k];
-            }
-        sums[2 * b] = num;
-        sums[2 * b + 1] = den;
-    }
+    for (int b = 0; b < B; ++b)
+        for (int g = 0; g < G; ++g) {
+            double s0 = 0, s1 = 0, s2 = 0;
+            for (int c = 2 * g; c < 2 * g + 2; ++c)
+                for (long i = 0; i < npos; ++i) {
+                    const long k = ((long)c * B + b) * npos + i;
+                    const double tv = t[k], yv = y[k];
+                    if (g == 0) {
+                        s0 += (yv - tv) * (yv - tv);
+                        s1 += tv * tv;
+                    } else {
+                        s0 += tv * tv;
+                        s1 += yv * yv;
+                        s2 += tv * yv;
+                    }
+                }
+            double* o = sums + ((long)b * G + g) * 3;
+            o[0] = s0;
+            o[1] = s1;
+            o[2] = s2;
+        }
+    const double f = FNO_DIR_WEIGHT / ((double)B * FNO_RANK);
     for (long i = 0; i < tot; ++i) {
-        const int b = (int)((i / npos) % B);
-        dy[i] = (float)(2.0 * ((double)y[i] - t[i]) / (B * sums[2 * b + 1]));
+        const int b = (int)((i / npos) % B), c = (int)(i / (npos * B));
+        if (c < 2) {
+            const double den = sums[(long)b * G * 3 + 1];
+            dy[i] = den > 0 ? (float)(2.0 * ((double)y[i] - t[i]) / (B * den)) : 0.0f;
+        } else {
+            const double* S = sums + ((long)b * G + 1 + (c - 2) / 2) * 3;
+            const double a = S[0], bb = std::max(S[1], 1e-30), cc = S[2];
+            dy[i] = a > 0 ? (float)(f * (-2.0 * cc * t[i] / (a * bb) + 2.0 * cc * cc * y[i] / (a * bb * bb))) : 0.0f;
+        }
     }
     if (loss) {
         double L = 0;
-        for (int b = 0; b < B; ++b) L += sums[2 * b] / sums[2 * b + 1];
+        for (int b = 0; b < B; ++b) {
+            const double* S = sums + (long)b * G * 3;
+            L += S[1] > 0 ? S[0] / S[1] : 0.0;
+            for (int k = 0; k < FNO_RANK; ++k) {
+                const double* D = S + 3 * (1 + k);
+                if (D[0] > 0) L += (FNO_DIR_WEIGHT / FNO_RANK) * (1.0 - D[2] * D[2] / (D[0] * std::max(D[1], 1e-30)));
+            }
+        }
         *loss = L / B;
     }
     return hipSuccess;

@@ -166,3 +166,35 @@ def test_lowrank_options_are_checked():
     finally:
         P.close()
         P0.close()
+
+
+@pytest.mark.parametrize("case", [C1_64, MS_64, UN_64])
+def test_ritz_directions_match_oracle_subspace_iteration(case):
+    """reg_ritz_directions against the oracle's subspace iteration (same start, 4 steps, block 4):
+    Ritz values to 1e-8, each Ritz vector to 1e-6 up to sign (the values are distinct)."""
+    print(f"[case] ritz directions {case}", flush=True)
+    mT, mR, v, *_ = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    lin = reduced.gradient(g, p, mT, mR, v)
+    U0 = directions(case, 4, seed=21)
+    theta, Z = solver.ritz_directions(g, p, lambda s: reduced.hessian_matvec(g, p, lin, s), list(U0), 4)
+    assert np.all(np.diff(theta) < 0) and np.min(-np.diff(theta)) > 1e-4 * theta[0]
+    P = gpu_problem(case, lowrank_capacity=8)
+    try:
+        P.gradient(dev(v), want_J=False)
+        Ug, th_g = P.ritz_directions(dev(U0), 4)
+        assert np.allclose(th_g, theta, rtol=1e-8, atol=0)
+        W = lambda a, b: reduced.w_inner(g, p, a, b)   # noqa: E731
+        for k in range(4):
+            # the library scales z to a grid sum of z . M z equal to 1, the oracle to <z, M z>_W = 1
+            # (W carries the cell area h1 h2): compare the M-normalised directions up to sign
+            zg = host(Ug[k])
+            zg = zg / np.sqrt(W(zg, solver.precond_op(g, p, zg)))
+            c = W(zg, solver.precond_op(g, p, Z[k]))
+            assert abs(abs(c) - 1.0) < 1e-6, (k, c)
+            assert close(np.sign(c) * zg, Z[k], 1e-6)
+        with pytest.raises(Exception):
+            P.ritz_directions(dev(directions(case, 9)), 2)   # more than 8 directions
+    finally:
+        P.close()

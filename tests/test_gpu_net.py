@@ -24,7 +24,7 @@ def _theta_test():
     field whose bfloat16 rounding in the band limit sits on one rounding boundary, which turns
     FP32-versus-FP64 differences of 1e-8 into whole-ulp flips of many values at once."""
     th = synthdata.network_init().copy()
-    th[-2:] = 0.0
+    th[-fno.OUT_CH:] = 0.0
     return th
 
 
@@ -61,7 +61,8 @@ def test_forward_backward_adam_match_oracle(dev, n, B):
     theta = _theta_test()
     mTs, mRs = _pairs(B, n)
     a = np.stack([fno.features(t, r)[0] for t, r in zip(mTs, mRs)])
-    t = np.random.default_rng(11).standard_normal((B, 2, n, n)) * 0.05
+    t = np.random.default_rng(11).standard_normal((B, fno.OUT_CH, n, n)) * 0.05
+    t[0, 4:6] = 0.0                                    # a direction slot without a target
     th = torch.tensor(theta, device=dev)
     inp = torch.tensor(np.transpose(a, (1, 0, 2, 3)).astype(np.float32), device=dev)
     tgt = torch.tensor(np.transpose(t, (1, 0, 2, 3)).astype(np.float32), device=dev)
@@ -103,11 +104,12 @@ def test_predict_matches_oracle_at_256(dev):
     net = Network(n, 1, dev)
     theta = _theta_test()
     mTs, mRs = _pairs(1, n, seed0=7)
-    v0 = net.predict(torch.tensor(theta, device=dev), torch.tensor(mTs[0], device=dev),
-                     torch.tensor(mRs[0], device=dev))
-    assert v0.dtype == torch.float64
+    v0, dirs = net.predict(torch.tensor(theta, device=dev), torch.tensor(mTs[0], device=dev),
+                           torch.tensor(mRs[0], device=dev))
+    assert v0.dtype == dirs.dtype == torch.float64 and dirs.shape == (fno.RANK, 2, n, n)
     a_or, s_or = fno.features(mTs[0], mRs[0])
-    _assert_forward_parity(v0.cpu().numpy()[None] / s_or, theta.astype(np.float64), a_or[None])
+    y = np.concatenate([v0.cpu().numpy() / s_or, dirs.cpu().numpy().reshape(-1, n, n)])[None]
+    _assert_forward_parity(y, theta.astype(np.float64), a_or[None])
     feat = net.features(torch.tensor(mTs[0], device=dev), torch.tensor(mRs[0], device=dev),
                         scale=(sc := torch.zeros(1, dtype=torch.float64, device=dev)))
     np.testing.assert_allclose(feat.cpu().numpy(), a_or, rtol=1e-6, atol=1e-6 * np.abs(a_or).max())
@@ -124,6 +126,10 @@ def test_gather_and_argument_errors(dev):
     out = net.gather(data, idx)
     assert torch.equal(out[:, 0], data[4]) and torch.equal(out[:, 1], data[0])
     assert not out[:, 2].any()
+    # targets (velocity and direction fields) transform as vectors channel pair by channel pair
+    tg = torch.randn(2, fno.OUT_CH, n, n, device=dev)
+    ot = Network(n, 8, dev).gather(tg, torch.tensor([1, 0, 1, 0, 1, 0, 1, 1], dtype=torch.int32, device=dev),
+                                  sym=torch.arange(8, dtype=torch.int32, device=dev)).cpu().numpy()
     # the 8 grid symmetries: features of transformed pairs, velocities as vectors
     from test_net_host_cpu import transform_scalar, transform_vector
     net8 = Network(n, 8, dev)
@@ -139,10 +145,12 @@ def test_gather_and_argument_errors(dev):
         want, _ = fno.features(transform_scalar(mTs[p], code), transform_scalar(mRs[p], code))
         np.testing.assert_allclose(of[:, b], want, rtol=1e-6, atol=1e-6 * np.abs(want).max())
         np.testing.assert_array_equal(ov[:, b], transform_vector(vel[p].cpu().numpy(), code))
+        for c in range(0, fno.OUT_CH, 2):
+            np.testing.assert_array_equal(ot[c:c + 2, b], transform_vector(tg[p, c:c + 2].cpu().numpy(), code))
     net2 = Network(n, 2, dev)
     th = torch.zeros(R.REG_FNO_PARAMS, device=dev)
     with pytest.raises(R.RegError) as e:
-        net2.backward(th, torch.zeros(2, 2, n, n, device=dev))
+        net2.backward(th, torch.zeros(fno.OUT_CH, 2, n, n, device=dev))
     assert e.value.status == R.ffi.REG_ESTATE
 
 

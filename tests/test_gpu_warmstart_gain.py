@@ -1,10 +1,12 @@
 """What the trained warm-start network gains over the plain solver (GPU).
 
 A network is trained by the library's own kernels on plain-solver registrations of 512 seeded pairs
-at 64^2 (the warm-start data generator, labels solved to ||g|| / ||g(0)|| <= 1e-3), then both
-solvers run on 12 unseen pairs at 128^2 to ||g|| / ||g(0)|| <= 1e-2 on one handle.  The learned
-solve pays for the network inference and the extra gradient at v0, and must still need fewer PDE
-solves and less time than the plain one.
+at 64^2 (the warm-start data generator, labels solved to ||g|| / ||g(0)|| <= 1e-3, direction
+targets from reg_ritz_directions at the label), then the plain solver, the learned warm start and
+the learned warm start with the learned directions in the preconditioner correction run on 12
+unseen pairs at 128^2 to ||g|| / ||g(0)|| <= 1e-2 on one handle.  The learned solve pays for the
+network inference and the extra gradient at v0, and must still need fewer PDE solves and less time
+than the plain one; the learned directions must not add PCG iterations.
 """
 import numpy as np
 import pytest
@@ -37,8 +39,11 @@ def test_trained_network_beats_plain_solver(dev):
     recs = W.compare_plain_vs_learned(test, 16, ws, dev)
     s = W.summarize(recs)
     print(s)
-    assert s["plain_converged"] == s["learned_converged"] == len(test)
-    assert s["learned_newton_mean"] < s["plain_newton_mean"]
+    assert s["plain"]["converged"] == s["learned"]["converged"] == s["learned_dirs"]["converged"] == len(test)
+    assert s["learned"]["newton_mean"] < s["plain"]["newton_mean"]
     assert sum(r["learned"]["n_pde"] for r in recs) < sum(r["plain"]["n_pde"] for r in recs)
     ratio = np.mean([r["learned_s"] / r["plain_s"] for r in recs])
     assert ratio < 1.0, ratio
+    # the learned directions feed the preconditioner correction: no more PCG iterations than the
+    # learned warm start alone (the correction is SPD for any directions; trained ones deflate)
+    assert s["learned_dirs"]["pcg_mean"] <= s["learned"]["pcg_mean"], s

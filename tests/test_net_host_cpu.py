@@ -33,12 +33,12 @@ def lib(tmp_path_factory):
     L.reg_fno_create.argtypes = [i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
     L.reg_fno_destroy.argtypes = [vp]
     L.reg_fno_features.argtypes = [vp, vp, vp, vp, vp]
-    L.reg_fno_target.argtypes = [vp, vp, vp, vp]
+    L.reg_fno_target.argtypes = [vp, vp, vp, vp, vp]
     L.reg_fno_gather.argtypes = [vp, vp, i64, i32, vp, vp, vp]
     L.reg_fno_forward.argtypes = [vp, vp, vp, vp]
     L.reg_fno_backward.argtypes = [vp, vp, vp, vp, vp]
     L.reg_fno_adam.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
-    L.reg_fno_predict.argtypes = [vp, vp, vp, vp, vp]
+    L.reg_fno_predict.argtypes = [vp, vp, vp, vp, vp, vp]
     return L
 
 
@@ -80,7 +80,7 @@ def _theta_test():
     field whose bfloat16 rounding in the band limit sits on one rounding boundary, which turns
     FP32-versus-FP64 differences of 1e-8 into whole-ulp flips of many values at once."""
     th = synthdata.network_init().copy()
-    th[-2:] = 0.0
+    th[-fno.OUT_CH:] = 0.0
     return th
 
 
@@ -108,11 +108,12 @@ def test_forward_backward_adam_match_oracle(lib, n, B):
     mTs, mRs = _pairs(B, n)
     a = np.stack([fno.features(t, r)[0] for t, r in zip(mTs, mRs)])            # (B, 4, n, n)
     rng = np.random.default_rng(11)
-    t = rng.standard_normal((B, 2, n, n)) * 0.05
+    t = rng.standard_normal((B, fno.OUT_CH, n, n)) * 0.05
+    t[0, 4:6] = 0.0                                                            # a slot without a target
     th32 = net.buf(theta.astype(np.float32))
     a_dev = net.buf(np.transpose(a, (1, 0, 2, 3)).astype(np.float32))       # [9][B][n][n]
     t_dev = net.buf(np.transpose(t, (1, 0, 2, 3)).astype(np.float32))
-    out = net.buf(np.zeros((2, B, n, n), np.float32))
+    out = net.buf(np.zeros((fno.OUT_CH, B, n, n), np.float32))
     grad = net.buf(np.zeros(fno.param_count(), np.float32))
     loss = net.buf(np.zeros(1))
     vp = lambda x: ctypes.c_void_p(x.ctypes.data)   # noqa: E731
@@ -168,13 +169,22 @@ def test_gather_and_predict(lib):
     np.testing.assert_allclose(feat, a_or, rtol=1e-6, atol=1e-6 * np.abs(a_or).max())
     assert abs(scale[0] - s_or) < 1e-14 * s_or
     v = one.buf(np.random.default_rng(3).standard_normal((2, n, n)))
-    tgt = one.buf(np.zeros((2, n, n), np.float32))
-    one.check(lib.reg_fno_target(one.h, vp(v), vp(scale), vp(tgt)))
-    np.testing.assert_allclose(tgt, v / s_or, rtol=1e-6)
+    dirs_in = one.buf(np.random.default_rng(5).standard_normal((fno.RANK, 2, n, n)))
+    tgt = one.buf(np.full((fno.OUT_CH, n, n), 7.0, np.float32))
+    one.check(lib.reg_fno_target(one.h, vp(v), vp(scale), None, vp(tgt)))
+    np.testing.assert_allclose(tgt[:2], v / s_or, rtol=1e-6)
+    assert not tgt[2:].any()                                     # no directions: zero targets
+    one.check(lib.reg_fno_target(one.h, vp(v), vp(scale), vp(dirs_in), vp(tgt)))
+    np.testing.assert_allclose(tgt[2:], dirs_in.reshape(-1, n, n), rtol=1e-6)
     v0 = one.buf(np.zeros((2, n, n)))
-    one.check(lib.reg_fno_predict(one.h, vp(theta), vp(mT), vp(mR), vp(v0)))
-    _assert_forward_parity(v0[None] / s_or, theta.astype(np.float64), a_or[None])
-    assert lib.reg_fno_predict(net.h, vp(theta), vp(mT), vp(mR), vp(v0)) == -1   # batch 3 handle
+    dirs = one.buf(np.zeros((fno.RANK, 2, n, n)))
+    one.check(lib.reg_fno_predict(one.h, vp(theta), vp(mT), vp(mR), vp(v0), vp(dirs)))
+    y = np.concatenate([v0 / s_or, dirs.reshape(-1, n, n)])[None]
+    _assert_forward_parity(y, theta.astype(np.float64), a_or[None])
+    v0b = one.buf(np.zeros((2, n, n)))
+    one.check(lib.reg_fno_predict(one.h, vp(theta), vp(mT), vp(mR), vp(v0b), None))   # directions not wanted
+    np.testing.assert_array_equal(v0b, v0)
+    assert lib.reg_fno_predict(net.h, vp(theta), vp(mT), vp(mR), vp(v0), None) == -1   # batch 3 handle
 
 
 def transform_scalar(m, code):
@@ -214,6 +224,14 @@ def test_gather_symmetries_match_transformed_images(lib):
         want, _ = fno.features(transform_scalar(mTs[p], code), transform_scalar(mRs[p], code))
         np.testing.assert_allclose(out[:, b], want, rtol=1e-6, atol=1e-6 * np.abs(want).max())
         np.testing.assert_array_equal(outv[:, b], transform_vector(vel[p], code))
+    # the target layout (velocity, then the direction fields): every channel pair is a vector
+    tg = net.buf(np.random.default_rng(6).standard_normal((2, fno.OUT_CH, n, n)).astype(np.float32))
+    outt = net.buf(np.zeros((fno.OUT_CH, B, n, n), np.float32))
+    net.check(lib.reg_fno_gather(net.h, vp(tg), 2, fno.OUT_CH, vp(idx), vp(sym), vp(outt)))
+    for b in range(B):
+        p, code = idx[b], sym[b]
+        for c in range(0, fno.OUT_CH, 2):
+            np.testing.assert_array_equal(outt[c:c + 2, b], transform_vector(tg[p, c:c + 2], code))
     bad = net.buf(np.zeros((3, 2, n, n), np.float32))
     assert lib.reg_fno_gather(net.h, vp(bad), 3, 2, vp(idx), vp(sym), vp(outv)) == 0   # velocity layout
     assert lib.reg_fno_gather(net.h, vp(feats), 2, 3, vp(idx), vp(sym), vp(out)) == -1  # unknown layout

@@ -58,6 +58,7 @@ def build_mock(out):
     L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp, dp]
     L.reg_autotune.argtypes = [vp, i32, C.c_char_p, sz]
     L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
+    L.reg_ritz_directions.argtypes = [vp, vp, i32, i32, dp]
     L.reg_last_error.restype = C.c_char_p
     return L
 
@@ -146,6 +147,14 @@ def run_all(L, p, solve=True):
     var = (C.c_int32 * 7)(*[k % 12 for k in range(7)])
     H.check(L.reg_set_pass_variants(H.h, var, 7))
     H.check(L.reg_hessian_matvec(H.h, H.ptr(vt), H.ptr(Hv)))
+    if p.lowrank_capacity:
+        rank = min(p.lowrank_capacity, 8)
+        U = H.buf(rank * 2 * nn)
+        th = (dbl * rank)()
+        ok = (-1,) if p.norm == REG_STOKES and p.constraint == REG_MASS_SOURCE else (0,)
+        H.check(L.reg_ritz_directions(H.h, H.ptr(U), rank, 3, th), ok=ok)
+    else:
+        H.check(L.reg_ritz_directions(H.h, H.ptr(v), 1, 3, None), ok=(-1,))   # no correction slots
     u1, F1, det = H.buf(2 * nn), H.buf(4 * nn), H.buf(nn)
     stats = (dbl * 8)()
     nb = C.c_size_t()
