@@ -479,6 +479,9 @@ def bench_warmstart(train, val, test, epochs=60, label_gtol=1e-3, label_pool=16)
     log(f"comparing plain vs learned on {len(test)} unseen pairs")
     recs = W.compare_plain_vs_learned(test, 16, ws, dev, log=log, recycle=4)
     s = W.summarize(recs)
+    # tighter solves (more PCG iterations per Newton step, the same fixed set-up cost of the directions)
+    log("tight tolerance 1e-3 on 64 of the test pairs")
+    tight = W.summarize(W.compare_plain_vs_learned(test[:64], 16, ws, dev, gtol=1e-3))
     ratio = lambda a, b: round(s[b]["ms_mean"] / s[a]["ms_mean"], 3)   # noqa: E731  (speed-up of a over b)
     return {
         "protocol": f"train {len(train)} pairs at {train[0][0].shape[0]}^2 (a separate {nval} held out), "
@@ -495,6 +498,9 @@ def bench_warmstart(train, val, test, epochs=60, label_gtol=1e-3, label_pool=16)
                          "learned_rc_vs_plain_rc": ratio("learned_rc", "plain_rc"),
                          "learned_dirs_rc_vs_learned_rc": ratio("learned_dirs_rc", "learned_rc"),
                          "learned_dirs_rc_vs_plain_rc": ratio("learned_dirs_rc", "plain_rc")},
+        "tight_grel_1e-3_64_pairs": {k: {"ms_mean": tight[k]["ms_mean"], "pcg_mean": tight[k]["pcg_mean"],
+                                         "newton_mean": tight[k]["newton_mean"]}
+                                     for k in ("plain", "learned", "learned_dirs")},
         "label_seconds": round(t_labels, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
         "train_ms_per_step_batch16": round(t_train / steps * 1e3, 3),
         "train_loss_last_epoch": round(hist[-1], 5), "heldout_loss": round(val, 5),
