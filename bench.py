@@ -465,6 +465,8 @@ def bench_warmstart(train, val, test, epochs=60, label_gtol=1e-3, label_pool=16)
     t_train = time.perf_counter() - t0
     steps = epochs * (len(train) // 16)
     val = ws.evaluate(vfeats, vlabels)
+    vlabels[:, 2:] = 0.0   # without direction targets the loss is the velocity term alone
+    val_v = ws.evaluate(vfeats, vlabels)
     del feats, labels, vfeats, vlabels
     # inference latency at the test size (features + network + rescale), events on the current stream
     mT = torch.tensor(test[0][0], device=dev)
@@ -504,6 +506,10 @@ def bench_warmstart(train, val, test, epochs=60, label_gtol=1e-3, label_pool=16)
         "label_seconds": round(t_labels, 2), "train_seconds": round(t_train, 2), "train_steps": steps,
         "train_ms_per_step_batch16": round(t_train / steps * 1e3, 3),
         "train_loss_last_epoch": round(hist[-1], 5), "heldout_loss": round(val, 5),
+        # split of the held-out loss: velocity relative squared error, and the mean cos^2 between a
+        # predicted direction and its target (angle terms = DIR_WEIGHT (1 - mean cos^2))
+        "heldout_velocity_rel_sq_error": round(val_v, 5),
+        "heldout_direction_mean_cos2": round(1.0 - (val - val_v) / W.ffi.REG_FNO_DIR_WEIGHT, 4),
         "inference_ms": round(t_inf, 3),
     }
 

@@ -259,6 +259,7 @@ def reg_set_images(h, m_T: int, m_R: int):
 # ---- learned warm start (include/regnet.h) -------------------------------------------------------
 REG_FNO_PARAMS = 4201610
 REG_FNO_RANK = 4
+REG_FNO_DIR_WEIGHT = 0.1
 REG_FNO_OUT = 2 + 2 * REG_FNO_RANK
 REG_FNO_SYMMETRIES = 8
 
