@@ -299,7 +299,7 @@ reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms
 reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes);
 
 /* Apply launch shapes chosen earlier (e.g. cached from a reg_autotune report): one shape index in
- * [0, 12) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
+ * [0, 20) per stage op {state 1, state 2, adjoint 1, adjoint 2, incremental state 1, incremental
  * state 2, gradient}; count must be 7.  A shape that does not fit the grid's line length (too few
  * threads for a 2048-point line, say) runs as the grid's default shape. */
 reg_status reg_set_pass_variants(reg_problem* h, const int32_t* variants, int32_t count);

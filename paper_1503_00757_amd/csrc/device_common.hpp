@@ -285,12 +285,12 @@ __device__ __forceinline__ void fft_stages(cpx<T> (&x)[E], cpx<T>* __restrict__ 
     }
 }
 
-// Length-N FFT, E elements per thread (E in {4, 8, 16}, E <= N/2); W from load_tw<T, N, E, 1, 0>;
+// Length-N FFT, E elements per thread (E in {2, 4, 8, 16}, E <= N/2); W from load_tw<T, N, E, 1, 0>;
 // see fft4 for `buf`.
 template <typename T, int N, int E, bool INV, int NW>
 __device__ __forceinline__ void fftE(cpx<T> (&x)[E], cpx<T>* __restrict__ lds0, cpx<T>* __restrict__ lds1, int t,
                                      const cpx<T> (&W)[NW], int& buf) {
-    static_assert(E == 4 || E == 8 || E == 16, "E");
+    static_assert(E == 2 || E == 4 || E == 8 || E == 16, "E");
     static_assert(N >= 2 * E, "N >= 2E");
     fft_stages<T, N, E, 1, INV, 0, NW>(x, lds0, lds1, t, W, buf);
 }

@@ -59,7 +59,7 @@ struct StageArgs {
 // clk[2 i] = ~0, clk[2 i + 1] = 0 for i < pairs (before timed stages)
 hipError_t launch_clk_init(unsigned long long* clk, int pairs, hipStream_t s);
 
-constexpr int NUM_STAGE_VARIANTS = 12;
+constexpr int NUM_STAGE_VARIANTS = 20;
 // var: launch-shape variant (0 = default; see transport_kernels.hpp).  FP32 stages exist for the
 // matvec ops (OP_A1, OP_A2, OP_I1, OP_I2); the state ops run in FP64.
 // t0 / t1 (nullable): events stamped by the dispatch itself at the stage's start and end (timing).

@@ -677,10 +677,12 @@ __global__ void body_last_kernel(long nn, T w, bool first, const T* __restrict__
 // G = BS/(N/EC) column pairs per block).  Variant 0 is the default; an autotuner may pick another.
 // FP64 and non-square or short grids use one fixed shape.
 // ---------------------------------------------------------------------------------------------
-// variant:                 0    1    2    3    4    5    6    7    8   9  10  11
-constexpr int VAR_ER[] = {8, 4, 4, 8, 8, 4, 8, 16, 4, 4, 8, 16};
-constexpr int VAR_EC[] = {16, 16, 8, 8, 8, 4, 16, 16, 4, 4, 8, 16};
-constexpr int VAR_BS[] = {128, 256, 256, 128, 256, 256, 256, 128, 512, 64, 64, 64};   // 9-11: one wave per block
+// variant:                 0    1    2    3    4    5    6    7    8   9  10  11   12   13   14   15   16   17    18   19
+constexpr int VAR_ER[] = {8, 4, 4, 8, 8, 4, 8, 16, 4, 4, 8, 16, 2, 2, 2, 2, 2, 2, 2, 4};
+constexpr int VAR_EC[] = {16, 16, 8, 8, 8, 4, 16, 16, 4, 4, 8, 16, 2, 4, 2, 4, 4, 8, 4, 2};
+constexpr int VAR_BS[] = {128, 256, 256, 128, 256, 256, 256, 128, 512, 64, 64, 64, 128, 128, 256, 256, 512, 512, 1024, 128};
+// 9-11: one wave per block; 12-19: two elements per thread on at least one axis (more waves per transform)
+static_assert(sizeof(VAR_ER) / sizeof(int) == NUM_STAGE_VARIANTS, "one shape per variant");
 constexpr int var_ER(int v) { return VAR_ER[v]; }
 constexpr int var_EC(int v) { return VAR_EC[v]; }
 constexpr int var_BS(int v) { return VAR_BS[v]; }
@@ -757,6 +759,14 @@ constexpr bool var_ok(int v) {
         case 9: return fused_ok<T, N, var_ER(9), var_EC(9), var_BS(9)>();
         case 10: return fused_ok<T, N, var_ER(10), var_EC(10), var_BS(10)>();
         case 11: return fused_ok<T, N, var_ER(11), var_EC(11), var_BS(11)>();
+        case 12: return fused_ok<T, N, var_ER(12), var_EC(12), var_BS(12)>();
+        case 13: return fused_ok<T, N, var_ER(13), var_EC(13), var_BS(13)>();
+        case 14: return fused_ok<T, N, var_ER(14), var_EC(14), var_BS(14)>();
+        case 15: return fused_ok<T, N, var_ER(15), var_EC(15), var_BS(15)>();
+        case 16: return fused_ok<T, N, var_ER(16), var_EC(16), var_BS(16)>();
+        case 17: return fused_ok<T, N, var_ER(17), var_EC(17), var_BS(17)>();
+        case 18: return fused_ok<T, N, var_ER(18), var_EC(18), var_BS(18)>();
+        case 19: return fused_ok<T, N, var_ER(19), var_EC(19), var_BS(19)>();
     }
     return false;
 }
@@ -793,6 +803,14 @@ static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s, h
             case 9: return launch_fused<T, N, OP, var_ER(9), var_EC(9), var_BS(9)>(a, s, t0, t1);
             case 10: return launch_fused<T, N, OP, var_ER(10), var_EC(10), var_BS(10)>(a, s, t0, t1);
             case 11: return launch_fused<T, N, OP, var_ER(11), var_EC(11), var_BS(11)>(a, s, t0, t1);
+            case 12: return launch_fused<T, N, OP, var_ER(12), var_EC(12), var_BS(12)>(a, s, t0, t1);
+            case 13: return launch_fused<T, N, OP, var_ER(13), var_EC(13), var_BS(13)>(a, s, t0, t1);
+            case 14: return launch_fused<T, N, OP, var_ER(14), var_EC(14), var_BS(14)>(a, s, t0, t1);
+            case 15: return launch_fused<T, N, OP, var_ER(15), var_EC(15), var_BS(15)>(a, s, t0, t1);
+            case 16: return launch_fused<T, N, OP, var_ER(16), var_EC(16), var_BS(16)>(a, s, t0, t1);
+            case 17: return launch_fused<T, N, OP, var_ER(17), var_EC(17), var_BS(17)>(a, s, t0, t1);
+            case 18: return launch_fused<T, N, OP, var_ER(18), var_EC(18), var_BS(18)>(a, s, t0, t1);
+            case 19: return launch_fused<T, N, OP, var_ER(19), var_EC(19), var_BS(19)>(a, s, t0, t1);
         }
         return hipErrorInvalidValue;
     }

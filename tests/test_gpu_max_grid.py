@@ -38,8 +38,10 @@ def test_2048sq_gradient_matvec_parity_symmetry_positivity():
         assert float((vt * Hx).sum()) >= p.beta_v * xAx * (1 - 1e-6)
         # the autotuner only times shapes that fit 2048-point lines (256+ threads per transform), and
         # the tuned matvec is the same operator
+        from test_gpu_parity import expected_shapes
         rep = P.autotune(reps=3)
-        fits = {4, 6, 7, 8}
+        fits = expected_shapes(2048, 2048)
+        assert fits == {4, 6, 7, 8, 18}
         for op in ("A1", "A2", "I1", "I2"):
             assert {v for v, _ in rep[op]} <= fits, rep[op]
         assert set(rep["chosen"][2:6]) <= fits

@@ -174,7 +174,8 @@ def test_constant_template_hessian_is_regulariser(problems):
 # both transforms fit (E <= N/2, a block holds at least one transform of each kind, at most 1024
 # threads) and the transforms' LDS fits in 160 KiB; smaller or other grids have one fixed shape.
 SHAPES = [(8, 16, 128), (4, 16, 256), (4, 8, 256), (8, 8, 128), (8, 8, 256), (4, 4, 256), (8, 16, 256),
-          (16, 16, 128), (4, 4, 512), (4, 4, 64), (8, 8, 64), (16, 16, 64)]
+          (16, 16, 128), (4, 4, 512), (4, 4, 64), (8, 8, 64), (16, 16, 64),
+          (2, 2, 128), (2, 4, 128), (2, 2, 256), (2, 4, 256), (2, 4, 512), (2, 8, 512), (2, 4, 1024), (4, 2, 128)]
 
 
 def expected_shapes(n1, n2):
@@ -217,4 +218,4 @@ def test_every_launch_shape_matches_oracle(problems, name):
         assert close(host(H), ref["H"], tol), v
     P.set_pass_variants([0] * 7)
     with pytest.raises(R.RegError):
-        P.set_pass_variants([12] * 7)
+        P.set_pass_variants([len(SHAPES)] * 7)
