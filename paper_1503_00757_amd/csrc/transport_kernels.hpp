@@ -729,14 +729,15 @@ constexpr int min_block(int want) { return (N / E) >= want ? 1 : want / (N / E);
 
 template <typename T, int N, int OP>
 static hipError_t launch_row_fixed(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    constexpr int E = sizeof(T) == 8 ? 4 : small_E<N>();
+    // 64..512-point lines: two elements per thread (latency-bound lengths, as the fused shapes)
+    constexpr int E = (N >= 64 && N <= 512) ? 2 : (sizeof(T) == 8 ? 4 : small_E<N>());
     constexpr int FPW = min_block<N, E>(64);
     launch_k(stage_row_kernel<T, N, E, FPW, OP>, dim3((a.n1 / 2 + FPW - 1) / FPW), dim3(FPW * N / E), s, t0, t1, a);
     return hipGetLastError();
 }
 template <typename T, int N, int OP>
 static hipError_t launch_col_fixed(const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    constexpr int E = sizeof(T) == 8 ? (N >= 16 ? 8 : 4) : small_E<N>();
+    constexpr int E = (N >= 64 && N <= 512) ? 4 : (sizeof(T) == 8 ? (N >= 16 ? 8 : 4) : small_E<N>());
     constexpr int G0 = min_block<N, E>(64);
     constexpr int G = G0 < 2 ? 2 : G0;
     launch_k(stage_col_kernel<T, N, E, G, OP>, dim3((a.n2 + 2 * G - 1) / (2 * G)), dim3(G * N / E), s, t0, t1, a);
@@ -783,8 +784,11 @@ template <typename T, int N, int OP>
 static hipError_t launch_square(int var, const StageArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if constexpr (sizeof(T) == 8 || N < 64) {
         (void)var;
-        constexpr int ER = sizeof(T) == 8 ? 4 : small_E<N>();
-        constexpr int EC = sizeof(T) == 8 ? (N >= 16 ? 8 : 4) : small_E<N>();
+        // FP64 lines of 64..512 points: two elements per thread on the rows (a shorter per-thread
+        // chain where the stage is latency-bound); longer lines are bandwidth-bound
+        constexpr bool E2 = sizeof(T) == 8 && N >= 64 && N <= 512;
+        constexpr int ER = E2 ? 2 : (sizeof(T) == 8 ? 4 : small_E<N>());
+        constexpr int EC = E2 ? 4 : (sizeof(T) == 8 ? (N >= 16 ? 8 : 4) : small_E<N>());
         constexpr int BS0 = (N / ER) > (N / EC) ? (N / ER) : (N / EC);
         constexpr int BS = BS0 < 64 ? 64 : BS0;
         return launch_fused<T, N, OP, ER, EC, BS>(a, s, t0, t1);
