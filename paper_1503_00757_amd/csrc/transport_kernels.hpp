@@ -538,14 +538,14 @@ __device__ __forceinline__ void mr_col_part(const StageArgs<T>& a, int cb, int t
 }
 
 template <typename T, int OP, int EM>
-__global__ __launch_bounds__(256) void stage_mr_row_kernel(StageArgs<T> a, int tpt, int fpw, int twl) {
+__global__ __launch_bounds__(512) void stage_mr_row_kernel(StageArgs<T> a, int tpt, int fpw, int twl) {
     extern __shared__ unsigned char dsm[];
     clk_start(a.clk);
     mr_row_part<T, OP, EM>(a, blockIdx.x, tpt, fpw, reinterpret_cast<cpx<T>*>(dsm), fpw, twl != 0);
     clk_end(a.clk);
 }
 template <typename T, int OP, int EM>
-__global__ __launch_bounds__(256) void stage_mr_col_kernel(StageArgs<T> a, int tpt, int G, int twl) {
+__global__ __launch_bounds__(512) void stage_mr_col_kernel(StageArgs<T> a, int tpt, int G, int twl) {
     extern __shared__ unsigned char dsm[];
     clk_start(a.clk);
     mr_col_part<T, OP, EM>(a, blockIdx.x, tpt, G, reinterpret_cast<cpx<T>*>(dsm), G, twl != 0);
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void stage_mr_col_kernel(StageArgs<T> a, int t
 }
 // Square grids of such a length: both parts in one launch (blocks [0, nrb) rows, the rest columns).
 template <typename T, int OP, int EMR, int EMC>
-__global__ __launch_bounds__(256) void stage_mr_fused_kernel(StageArgs<T> a, int nrb, int tpt_r, int fpw, int tpt_c,
+__global__ __launch_bounds__(512) void stage_mr_fused_kernel(StageArgs<T> a, int nrb, int tpt_r, int fpw, int tpt_c,
                                                             int G, int twl) {
     extern __shared__ unsigned char dsm[];
     const int nlines = fpw > G ? fpw : G;
@@ -575,15 +575,16 @@ inline size_t mr_lds_bytes(int n, int nlines, int& twl) {
 }
 
 // Launch shape of a mixed-radix axis of length n: EM elements per thread, tpt threads per transform
-// (tpt * EM >= n), and transforms per block (at most 256 threads and 64 KiB of LDS per block).
+// (tpt * EM >= n), and transforms per block (at most 256 threads for lines of up to 256 points, 512
+// for longer ones, and 64 KiB of LDS per block).
 struct MrShape {
     int em, tpt, per_block;
 };
 template <typename T>
 inline MrShape mr_shape(int n, bool column) {
-    const int em = n > 1024 ? 8 : (n > 256 || column ? (n > 512 && column ? 8 : 4) : 2);
+    const int em = n > 1024 ? 8 : (n > 256 || column ? 4 : 2);
     const int tpt = (n + em - 1) / em;
-    int pb = 256 / tpt;
+    int pb = (n > 256 ? 512 : 256) / tpt;
     const int lds_line = 2 * n * (int)sizeof(cpx<T>);
     while (pb > 1 && pb * lds_line > 64 * 1024) --pb;
     if (pb < 1) pb = 1;
