@@ -109,6 +109,20 @@ hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1
 template <typename TI0, typename TI1>
 hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* in1, cpx<double>* spec,
                                 const cpx<double>* tw2, hipStream_t s);
+// The last adjoint step's body-force term (see launch_body_last) deferred to the assembly: the
+// body force entering the transform is (first ? 0 : B) + w ((Q + C) G + X G2) (G, G2 vector fields).
+template <typename T>
+struct BodyLast {
+    const T *Q, *C, *X, *G, *G2;   // Q == nullptr: nothing deferred
+    T w;
+    int first;
+};
+// launch_spec_row_fwd2 with field 1 = the body force B completed by `bl` on the fly (B is read, not
+// written; power-of-two n2 fuse the term into the row pass, other lengths run launch_body_last
+// first and then leave the completed body force in B).
+template <typename T>
+hipError_t launch_spec_row_fwd_body(const SpecParams& p, const double* in0, T* B, const BodyLast<T>& bl,
+                                    cpx<double>* spec, const cpx<double>* tw2, hipStream_t s);
 // Column pass: forward FFT along x1 of the needed spectra, Fourier multiplier of `mode`, inverse
 // FFT; in place in spec (outputs: field 0 = first result, field 1 = second result if want2).
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,

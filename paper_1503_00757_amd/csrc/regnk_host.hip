@@ -355,10 +355,12 @@ reg_status state_forward(reg_problem* P, const double* v, bool store, double* m1
 // Terminal value lam(1) = sign (TA + TB) (TB nullable).  B: body force (vector, overwritten) in the
 // selected quadrature, using the stored trajectory.  Full Newton: keep = true stores the stage values
 // lam_{j+1}, lam*_j (the gradient's adjoint sweep); vt != nullptr runs the full-Newton incremental
-// adjoint (stages OP_A1F / OP_A2F with the stored lam and grad m~).
+// adjoint (stages OP_A1F / OP_A2F with the stored lam and grad m~).  defer (nullable): the last
+// step's body-force term of the exact-transpose quadrature is returned there instead of launched,
+// for the assembly to apply while it loads B (launch_spec_row_fwd_body).
 template <typename T>
 reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB, bool negate, T* B,
-                            bool keep = false, const T* vt = nullptr) {
+                            bool keep = false, const T* vt = nullptr, BodyLast<T>* defer = nullptr) {
     TV<T> tv{P};
     const long nn = P->nn;
     const T h = T(1.0 / P->nt);
@@ -397,6 +399,10 @@ reg_status adjoint_backward(reg_problem* P, const T* v, const T* TA, const T* TB
             s2.GT2 = tv.Gm(P->nt + j);
         }
         if (j == 0 && !paper && !vt && B) {   // lam_0 is not needed: body force only
+            if (defer && !keep) {
+                *defer = BodyLast<T>{s2.A, s2.Bf, s2.X, s2.G, s2.G2, s2.bw, first ? 1 : 0};
+                return REG_OK;
+            }
             CK(launch_body_last<T>(nn, s2.bw, first, s2.A, s2.Bf, s2.X, s2.G, s2.G2, B, keep ? s2.UOUT : nullptr,
                                    P->stream));
             return REG_OK;
@@ -621,14 +627,15 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
         CKS(data_term(P, P->sF(7), &d));
         CKS(reg_terms(P, v64, &rv, &rw));
     }
+    BodyLast<T> bl{};
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(8), (const T*)nullptr, false, tv.B(),
-                            P->p.hessian == REG_HESS_FULL));
+                            P->p.hessian == REG_HESS_FULL, (const T*)nullptr, &bl));
     const double* x0 = v64;
     if (P->p.norm == REG_STOKES) {   // the regularisation term is formed in real space
         CKS(stokes_first(P, v64));
         x0 = stk(P, STK_R);
     }
-    CK((launch_spec_row_fwd2<double, T>(P->sp, x0, tv.B(), P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream)));
+    CK(launch_spec_row_fwd_body<T>(P->sp, x0, tv.B(), bl, P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream));
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
     CKS(spec_col(P, SPEC_HESS, true, ms && kg));
     CKS(spec_inv2(P, g, (ms && kg) ? kg : nullptr));
@@ -651,15 +658,16 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     const bool full = P->p.hessian == REG_HESS_FULL;
     CKS(inc_state_forward<T>(P, tv.vT(), tv.vtT(), &mt, full));
     // lam~(1) = -m~(1)
+    BodyLast<T> bl{};
     CKS(adjoint_backward<T>(P, tv.vT(), tv.F(mt.r), tv.F(mt.c), true, tv.Bt(), false,
-                            full ? (const T*)tv.vtT() : (const T*)nullptr));
+                            full ? (const T*)tv.vtT() : (const T*)nullptr, &bl));
     const double* x0 = vt64;
     if (P->p.norm == REG_STOKES) {
         CKS(stokes_second(P, vt64));
         x0 = stk(P, STK_R);
     }
-    // both fields' row transforms in one launch
-    CK((launch_spec_row_fwd2<double, T>(P->sp, x0, tv.Bt(), P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream)));
+    // both fields' row transforms in one launch, the last adjoint step's body force folded in
+    CK(launch_spec_row_fwd_body<T>(P->sp, x0, tv.Bt(), bl, P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
     CKS(spec_inv2(P, out, kout));
     P->matvec_done = true;
@@ -1451,10 +1459,43 @@ const char* op_name(int op) {
     return n[op];
 }
 
+// Best of three batches of `reps` graph-replayed matvecs on the last projected input (ms per matvec).
+reg_status matvec_batch_ms(reg_problem* P, int reps, double* ms) {
+    double* in = P->at<double>(P->o.vt64);
+    double* out = P->pcg(PST);
+    CKS(matvec_run<float>(P, in, out, nullptr));   // capture with the current shapes, warm-up
+    double best = 1e30;
+    for (int b = 0; b < 3; ++b) {
+        hipEvent_t e0, e1;
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        CK(hipEventRecord(e0, P->stream));
+        reg_status st = REG_OK;
+        for (int i = 0; i < reps && st == REG_OK; ++i) st = matvec_run<float>(P, in, out, nullptr);
+        CK(hipEventRecord(e1, P->stream));
+        CK(hipEventSynchronize(e1));
+        float t = 0;
+        CK(hipEventElapsedTime(&t, e0, e1));
+        CK(hipEventDestroy(e0));
+        CK(hipEventDestroy(e1));
+        CKS(st);
+        best = std::min(best, (double)t / reps);
+    }
+    *ms = best;
+    return REG_OK;
+}
+
+// Two rounds: every shape that fits, timed per stage op in isolation (repeated launches of one
+// stage on the same operands), then whole graph-replayed matvecs decide among the isolated sweep's
+// four fastest shapes of each op, one op at a time (coordinate descent; a change is kept when it
+// saves more than 0.1%).  In a matvec each step reads other trajectory fields and follows other
+// stages, which the isolated timings do not see.
 reg_status autotune_f32(reg_problem* P, int reps, char* report, size_t cap) {
     if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before tuning");
     if (reps < 1) return fail(REG_EINVAL, "reps must be >= 1");
     std::string js = "{";
+    std::vector<std::pair<double, int>> iso[4];
+    int ops[4] = {};
     for (int which = 0; which < 4; ++which) {
         StageArgs<float> a;
         int op;
@@ -1473,11 +1514,38 @@ reg_status autotune_f32(reg_problem* P, int reps, char* report, size_t cap) {
             snprintf(buf, sizeof buf, "%s[%d, %.3f]", firstv ? "" : ", ", v, ms * 1e3);
             js += buf;
             firstv = false;
+            iso[which].push_back({ms, v});
             if (ms < best_ms) { best_ms = ms; best = v; }
         }
         js += "]";
         P->var[op] = best;
+        ops[which] = op;
     }
+    drop_graphs(P);
+    const int mreps = P->nn >= 512L * 512 ? 3 : 10;
+    double cur = 0;
+    CKS(matvec_batch_ms(P, mreps, &cur));
+    char buf[96];
+    snprintf(buf, sizeof buf, ", \"matvec_ms_isolated_choice\": %.4f", cur);
+    js += buf;
+    for (int which = 0; which < 4; ++which) {
+        std::sort(iso[which].begin(), iso[which].end());
+        const int op = ops[which];
+        for (size_t c = 0; c < iso[which].size() && c < 4; ++c) {
+            const int v = iso[which][c].second;
+            if (v == P->var[op]) continue;
+            const int prev = P->var[op];
+            P->var[op] = v;
+            drop_graphs(P);
+            double ms = 0;
+            CKS(matvec_batch_ms(P, mreps, &ms));
+            if (ms < cur * 0.999) cur = ms;
+            else P->var[op] = prev;
+        }
+    }
+    drop_graphs(P);
+    snprintf(buf, sizeof buf, ", \"matvec_ms\": %.4f", cur);
+    js += buf;
     js += ", \"chosen\": [";
     for (int op = 0; op < NUM_TUNED_OPS; ++op) js += std::to_string(P->var[op]) + (op < NUM_TUNED_OPS - 1 ? ", " : "");
     js += "]}";

@@ -28,11 +28,14 @@ template <int N>
 constexpr int spec_nf() { return (N / 4) >= 32 ? 2 : 128 / (N / 4); }
 
 // ---------------------------------------------------------------------------------------------
+// bl.Q != nullptr (field 1 only): the body force in1 is completed by the deferred last adjoint step,
+// with the arithmetic of body_last_kernel.
 template <typename TI0, typename TI1, int N, int FPW>
 __global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const TI0* __restrict__ in0,
                                                                   const TI1* __restrict__ in1,
                                                                   cpx<double>* __restrict__ spec,
-                                                                  const cpx<double>* __restrict__ tw) {
+                                                                  const cpx<double>* __restrict__ tw,
+                                                                  BodyLast<TI1> bl) {
     constexpr int Q = N / 4, H = N / 2;
     constexpr int L = LdsSize<N>::value;
     __shared__ cpx<double> lds[FPW][L];   // one buffer per transform: more resident blocks
@@ -45,10 +48,21 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_fwd_kernel(int n1, const
     cpx<double> x[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int e = t + r * Q;
-        if (!valid) x[r] = cpx<double>{0.0, 0.0};
-        else if (field) x[r] = cpx<double>{(double)in1[row + e], (double)in1[nn + row + e]};
-        else x[r] = cpx<double>{(double)in0[row + e], (double)in0[nn + row + e]};
+        const long i = row + t + r * Q;
+        if (!valid) {
+            x[r] = cpx<double>{0.0, 0.0};
+        } else if (field && bl.Q) {
+            TI1 u = bl.Q[i];
+            u += bl.C[i];
+            const TI1 xv = bl.X[i];
+            const TI1 b0 = u * bl.G[i] + xv * bl.G2[i], b1 = u * bl.G[nn + i] + xv * bl.G2[nn + i];
+            const TI1 o0 = bl.first ? TI1(0) : in1[i], o1 = bl.first ? TI1(0) : in1[nn + i];
+            x[r] = cpx<double>{(double)(o0 + bl.w * b0), (double)(o1 + bl.w * b1)};
+        } else if (field) {
+            x[r] = cpx<double>{(double)in1[i], (double)in1[nn + i]};
+        } else {
+            x[r] = cpx<double>{(double)in0[i], (double)in0[nn + i]};
+        }
     }
     int buf = 0;
     fft4<double, N, false, true>(x, lds[f], lds[f], t, tw, buf);
@@ -621,15 +635,16 @@ __global__ __launch_bounds__(MR_THREADS) void spec_mr_row_inv_kernel(SpecParams 
 static inline bool pow2(int n) { return (n & (n - 1)) == 0; }
 
 // ---------------------------------------------------------------------------------------------
+// bl.Q != nullptr only with a power-of-two n2 (see launch_spec_row_fwd_body)
 template <typename TI0, typename TI1>
-hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* in1, cpx<double>* spec,
-                                const cpx<double>* tw2, hipStream_t s) {
+static hipError_t row_fwd(const SpecParams& p, const TI0* in0, const TI1* in1, const BodyLast<TI1>& bl,
+                          cpx<double>* spec, const cpx<double>* tw2, hipStream_t s) {
     const int nf = in1 ? 2 : 1;
 #define ROWF(NN)                                                                                       \
     case NN: {                                                                                         \
         constexpr int FPW = spec_fpw<NN>();                                                            \
         hipLaunchKernelGGL((spec_row_fwd_kernel<TI0, TI1, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf), \
-                           dim3(FPW * NN / 4), 0, s, p.n1, in0, in1, spec, tw2);                       \
+                           dim3(FPW * NN / 4), 0, s, p.n1, in0, in1, spec, tw2, bl);                   \
         break;                                                                                         \
     }
     if (!pow2(p.n2) && p.mr2.ns > 0) {
@@ -652,10 +667,26 @@ hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* 
     return hipGetLastError();
 }
 
+template <typename TI0, typename TI1>
+hipError_t launch_spec_row_fwd2(const SpecParams& p, const TI0* in0, const TI1* in1, cpx<double>* spec,
+                                const cpx<double>* tw2, hipStream_t s) {
+    return row_fwd<TI0, TI1>(p, in0, in1, BodyLast<TI1>{}, spec, tw2, s);
+}
+
 template <typename TI>
 hipError_t launch_spec_row_fwd(const SpecParams& p, const TI* in0, const TI* in1, cpx<double>* spec,
                                const cpx<double>* tw2, hipStream_t s) {
     return launch_spec_row_fwd2<TI, TI>(p, in0, in1, spec, tw2, s);
+}
+
+template <typename T>
+hipError_t launch_spec_row_fwd_body(const SpecParams& p, const double* in0, T* B, const BodyLast<T>& bl,
+                                    cpx<double>* spec, const cpx<double>* tw2, hipStream_t s) {
+    if (!bl.Q || pow2(p.n2)) return row_fwd<double, T>(p, in0, B, bl, spec, tw2, s);
+    const hipError_t e = launch_body_last<T>((long)p.n1 * p.n2, bl.w, bl.first != 0, bl.Q, bl.C, bl.X, bl.G, bl.G2,
+                                             B, (T*)nullptr, s);
+    if (e != hipSuccess) return e;
+    return row_fwd<double, T>(p, in0, B, BodyLast<T>{}, spec, tw2, s);
 }
 
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
@@ -792,57 +823,65 @@ __global__ __launch_bounds__(NYQ_THREADS) void nyq_tile_kernel(int n1, int n2, c
     }
 }
 
-// pass 2: a(i1) and b(i2) from the partial sums and c from the corner sums (fixed order); the last
-// block computes c
-__global__ __launch_bounds__(NYQ_THREADS) void nyq_sums_kernel(int n1, int n2, int ncb, int nrb,
-                                                               const double* __restrict__ rowp,
-                                                               const double* __restrict__ colp,
-                                                               const double* __restrict__ cpart, double* __restrict__ a,
-                                                               double* __restrict__ b, double* __restrict__ c) {
-    __shared__ double sh[NYQ_THREADS / 64];
-    const int comp = blockIdx.y;
-    if ((int)blockIdx.x == (int)gridDim.x - 1) {
-        const double* cp = cpart + (long)comp * nrb * ncb;
-        double acc = 0.0;
-        for (int k = threadIdx.x; k < nrb * ncb; k += NYQ_THREADS) acc += cp[k];
-        const double t = block_sum<NYQ_THREADS>(acc, sh);
-        if (threadIdx.x == 0) c[comp] = t / ((double)n1 * (double)n2);
-        return;
-    }
-    const int t = blockIdx.x * NYQ_THREADS + threadIdx.x;
-    if (t < n1) {
-        const double* rp = rowp + (long)comp * ncb * n1;
-        double r = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < ncb; ++k) r += rp[(long)k * n1 + t];
-        a[(long)comp * n1 + t] = r / n2;
-    } else if (t < n1 + n2) {
-        const int j = t - n1;
-        const double* cp = colp + (long)comp * nrb * n2;
-        double r = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < nrb; ++k) r += cp[(long)k * n2 + j];
-        b[(long)comp * n2 + j] = r / n1;
-    }
-}
-
-// pass 3: the projected field, one row per block
+// pass 2, per 32 x 64 tile: a(i1) of the tile's rows and b(i2) of its columns from the partial sums,
+// c from the corner sums (every block forms them in the same fixed order, so all agree), and the
+// projected tile.  The tile's loads are issued first and overlap the sums.
 template <typename TO>
 __global__ __launch_bounds__(NYQ_THREADS) void nyq_apply_kernel(int n1, int n2, const double* __restrict__ in,
-                                                                const double* __restrict__ a,
-                                                                const double* __restrict__ b,
-                                                                const double* __restrict__ c, double* __restrict__ out_d,
-                                                                TO* __restrict__ out_t) {
-    const int i = blockIdx.x, comp = blockIdx.y;
-    const double si = (i & 1) ? -1.0 : 1.0;
-    const double ai = a[(long)comp * n1 + i], ci = si * c[comp];
-    const double* bc = b + (long)comp * n2;
-    const long row = ((long)comp * n1 + i) * n2;
-    for (int j = threadIdx.x; j < n2; j += NYQ_THREADS) {
-        const double sj = (j & 1) ? -1.0 : 1.0;
-        const double y = in[row + j] - sj * ai - si * bc[j] + sj * ci;
-        if (out_d) out_d[row + j] = y;
-        if (out_t) out_t[row + j] = (TO)y;
+                                                                const double* __restrict__ rowp,
+                                                                const double* __restrict__ colp,
+                                                                const double* __restrict__ cpart,
+                                                                double* __restrict__ out_d, TO* __restrict__ out_t) {
+    constexpr int RG = NYQ_THREADS / NYQ_TC, K = NYQ_TR / RG;
+    __shared__ double sa[NYQ_TR], sb[NYQ_TC], sh[NYQ_THREADS / 64], sc;
+    const int cb = blockIdx.x, rb = blockIdx.y, comp = blockIdx.z, ncb = gridDim.x, nrb = gridDim.y;
+    const int tx = threadIdx.x % NYQ_TC, ty = threadIdx.x / NYQ_TC, t = threadIdx.x;
+    const int j = cb * NYQ_TC + tx;
+    const bool jv = j < n2;
+    const long base = (long)comp * n1 * n2;
+    double x[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {   // clamped addresses: every load in bounds, masked below
+        const int i = rb * NYQ_TR + ty + RG * k;
+        x[k] = in[base + (long)(i < n1 ? i : 0) * n2 + (jv ? j : 0)];
+    }
+    const double* cp = cpart + (long)comp * nrb * ncb;
+    double acc = 0.0;
+    for (int k = t; k < nrb * ncb; k += NYQ_THREADS) acc += cp[k];
+    const double csum = block_sum<NYQ_THREADS>(acc, sh);
+    if (t == 0) sc = csum / ((double)n1 * (double)n2);
+    if (t < NYQ_TR) {
+        const int i = rb * NYQ_TR + t;
+        double r = 0.0;
+        if (i < n1) {
+            const double* rp = rowp + (long)comp * ncb * n1;
+#pragma unroll 8
+            for (int k = 0; k < ncb; ++k) r += rp[(long)k * n1 + i];
+        }
+        sa[t] = r / n2;
+    } else if (t < NYQ_TR + NYQ_TC) {
+        const int jj = cb * NYQ_TC + (t - NYQ_TR);
+        double r = 0.0;
+        if (jj < n2) {
+            const double* q = colp + (long)comp * nrb * n2;
+#pragma unroll 8
+            for (int k = 0; k < nrb; ++k) r += q[(long)k * n2 + jj];
+        }
+        sb[t - NYQ_TR] = r / n1;
+    }
+    __syncthreads();
+    if (!jv) return;
+    const double sj = (j & 1) ? -1.0 : 1.0;
+    const double bj = sb[tx];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int r = ty + RG * k, i = rb * NYQ_TR + r;
+        if (i >= n1) continue;
+        const double si = (i & 1) ? -1.0 : 1.0;
+        const double y = x[k] - sj * sa[r] - si * bj + sj * (si * sc);
+        const long idx = base + (long)i * n2 + j;
+        if (out_d) out_d[idx] = y;
+        if (out_t) out_t[idx] = (TO)y;
     }
 }
 
@@ -850,23 +889,18 @@ template <typename TO>
 hipError_t launch_nyquist_project(int n1, int n2, const double* in, double* out_d, TO* out_t, double* scratch,
                                   hipStream_t s) {
     const int ncb = (n2 + NYQ_TC - 1) / NYQ_TC, nrb = (n1 + NYQ_TR - 1) / NYQ_TR;
-    double* a = scratch;
-    double* b = a + 2 * n1;
-    double* c = b + 2 * n2;
-    double* rowp = c + 2;
+    double* rowp = scratch;
     double* colp = rowp + 2L * ncb * n1;
     double* cpart = colp + 2L * nrb * n2;
     hipLaunchKernelGGL(nyq_tile_kernel, dim3(ncb, nrb, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, rowp, colp, cpart);
-    hipLaunchKernelGGL(nyq_sums_kernel, dim3((n1 + n2 + NYQ_THREADS - 1) / NYQ_THREADS + 1, 2), dim3(NYQ_THREADS), 0,
-                       s, n1, n2, ncb, nrb, rowp, colp, cpart, a, b, c);
-    hipLaunchKernelGGL((nyq_apply_kernel<TO>), dim3(n1, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, a, b, c, out_d,
-                       out_t);
+    hipLaunchKernelGGL((nyq_apply_kernel<TO>), dim3(ncb, nrb, 2), dim3(NYQ_THREADS), 0, s, n1, n2, in, rowp, colp,
+                       cpart, out_d, out_t);
     return hipGetLastError();
 }
 
 size_t nyquist_scratch_doubles(int n1, int n2) {
     const size_t ncb = (n2 + NYQ_TC - 1) / NYQ_TC, nrb = (n1 + NYQ_TR - 1) / NYQ_TR;
-    return 2 * (size_t)n1 + 2 * (size_t)n2 + 2 + 2 * ncb * n1 + 2 * nrb * n2 + 2 * nrb * ncb;
+    return 2 * ncb * n1 + 2 * nrb * n2 + 2 * nrb * ncb;
 }
 
 template hipError_t launch_spec_row_fwd<float>(const SpecParams&, const float*, const float*, cpx<double>*,
@@ -877,6 +911,11 @@ template hipError_t launch_spec_row_fwd2<double, float>(const SpecParams&, const
                                                         cpx<double>*, const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_fwd2<double, double>(const SpecParams&, const double*, const double*,
                                                          cpx<double>*, const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_fwd_body<float>(const SpecParams&, const double*, float*, const BodyLast<float>&,
+                                                    cpx<double>*, const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_fwd_body<double>(const SpecParams&, const double*, double*,
+                                                     const BodyLast<double>&, cpx<double>*, const cpx<double>*,
+                                                     hipStream_t);
 template hipError_t launch_nyquist_project<float>(int, int, const double*, double*, float*, double*, hipStream_t);
 template hipError_t launch_nyquist_project<double>(int, int, const double*, double*, double*, double*, hipStream_t);
 

@@ -121,45 +121,57 @@ __device__ __forceinline__ T row_load(const StageArgs<T>& a, long idx, Rp<T>& p)
     return is_adj(OP) ? p.v * p.u : p.u;
 }
 
-template <typename T, int OP>
+// Row-part results at 1024+ points per FP32 line are written through the XCD's L2 (a relaxed
+// agent-scope atomic store is a plain vector store with the device-coherence policy): the rows are
+// whole cache lines, and the kernel-end release then has little left to publish (1024^2 matvec 0.7%
+// faster; at 256^2, where a stage is latency-bound, 5% slower, so shorter lines keep plain stores).
+template <typename T, int N>
+constexpr bool rows_write_through() { return sizeof(T) == 4 && N >= 1024; }
+template <bool WT, typename S>
+__device__ __forceinline__ void st1(S* p, S v) {
+    if constexpr (WT) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
+template <typename T, int OP, bool WT>
 __device__ __forceinline__ void row_store(const StageArgs<T>& a, long idx, T d, const Rp<T>& p) {
     const long nn = a.nn;
     const T h = a.h;
     const T hh = T(0.5) * a.h;
     if constexpr (OP == OP_S1 || OP == OP_S2 || OP == OP_GRAD || is_inc(OP)) {   // d = d2 u: component 1 of grad u
-        if (a.GOUT) a.GOUT[nn + idx] = d;
-        if (a.GOUTF) a.GOUTF[nn + idx] = (float)d;
+        if (a.GOUT) st1<WT>(a.GOUT + (nn + idx), d);
+        if (a.GOUTF) st1<WT>(a.GOUTF + (nn + idx), (float)d);
     }
     if constexpr (OP == OP_S1) {
-        a.ROUT[idx] = p.u - h * p.v * d;                               // R of m*
-        a.UOUT[idx] = p.u;                                             // m_j
+        st1<WT>(a.ROUT + idx, p.u - h * p.v * d);                               // R of m*
+        st1<WT>(a.UOUT + idx, p.u);                                             // m_j
     } else if constexpr (OP == OP_S2) {
-        a.ROUT[idx] = T(0.5) * (p.x + p.u) - hh * p.v * d;             // R of m_{j+1}
+        st1<WT>(a.ROUT + idx, T(0.5) * (p.x + p.u) - hh * p.v * d);             // R of m_{j+1}
     } else if constexpr (is_a1(OP)) {
-        a.ROUT[idx] = p.u + h * d;                                     // R of l*
-        a.UOUT[idx] = p.u;                                             // l_{j+1}
+        st1<WT>(a.ROUT + idx, p.u + h * d);                                     // R of l*
+        st1<WT>(a.UOUT + idx, p.u);                                             // l_{j+1}
         if (a.B) {                                                     // trapezoid: w_{j+1} h l_{j+1} G_{j+1}
             const T w = a.bw * p.u;
-            a.B[idx] = p.b0 + w * p.g0;
-            a.B[nn + idx] = p.b1 + w * p.g1;
+            st1<WT>(a.B + idx, p.b0 + w * p.g0);
+            st1<WT>(a.B + (nn + idx), p.b1 + w * p.g1);
         }
     } else if constexpr (is_a2(OP)) {
-        a.ROUT[idx] = T(0.5) * (p.x + p.u) + hh * d;                   // R of l_j (x = l_{j+1}, u = l*)
-        if (a.UOUT) a.UOUT[idx] = p.u;                                 // l*_j, kept for full Newton
+        st1<WT>(a.ROUT + idx, T(0.5) * (p.x + p.u) + hh * d);                   // R of l_j (x = l_{j+1}, u = l*)
+        if (a.UOUT) st1<WT>(a.UOUT + idx, p.u);                                 // l*_j, kept for full Newton
         if (a.B) {                                                     // (h/2)(l* G_j + l_{j+1} G*_j)
             T b0 = p.u * p.g0 + p.x * p.h0, b1 = p.u * p.g1 + p.x * p.h1;
             if constexpr (OP == OP_A2F) {                              // + lam*_j grad m~_j + lam_{j+1} grad m~*_j
                 b0 += p.l * p.t0 + p.l2 * p.s0;
                 b1 += p.l * p.t1 + p.l2 * p.s1;
             }
-            a.B[idx] = p.b0 + a.bw * b0;
-            a.B[nn + idx] = p.b1 + a.bw * b1;
+            st1<WT>(a.B + idx, p.b0 + a.bw * b0);
+            st1<WT>(a.B + (nn + idx), p.b1 + a.bw * b1);
         }
     } else if constexpr (OP == OP_I1) {
-        a.ROUT[idx] = p.u - h * (p.v * d + p.g0 * p.h0 + p.g1 * p.h1); // R of m~*
-        a.UOUT[idx] = p.u;                                             // m~_j
+        st1<WT>(a.ROUT + idx, p.u - h * (p.v * d + p.g0 * p.h0 + p.g1 * p.h1));  // R of m~*
+        st1<WT>(a.UOUT + idx, p.u);                                             // m~_j
     } else if constexpr (OP == OP_I2) {
-        a.ROUT[idx] = T(0.5) * (p.x + p.u) - hh * (p.v * d + p.g0 * p.h0 + p.g1 * p.h1);   // R of m~_{j+1}
+        st1<WT>(a.ROUT + idx, T(0.5) * (p.x + p.u) - hh * (p.v * d + p.g0 * p.h0 + p.g1 * p.h1));  // R of m~_{j+1}
     }
 }
 
@@ -267,8 +279,8 @@ __device__ __forceinline__ void row_part(const StageArgs<T>& a, int rb, cpx<T>* 
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int e = t + TT * m;
-        row_store<T, OP>(a, row0 + e, x[m].x, q0[m]);
-        row_store<T, OP>(a, row1 + e, x[m].y, q1[m]);
+        row_store<T, OP, rows_write_through<T, N>()>(a, row0 + e, x[m].x, q0[m]);
+        row_store<T, OP, rows_write_through<T, N>()>(a, row1 + e, x[m].y, q1[m]);
     }
 }
 
@@ -389,8 +401,8 @@ __global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_row_kernel(St
         Rp<T> q0, q1;
         row_load<T, OP>(a, row0 + e, q0);
         row_load<T, OP>(a, row1 + e, q1);
-        row_store<T, OP>(a, row0 + e, dx, q0);
-        row_store<T, OP>(a, row1 + e, dy, q1);
+        row_store<T, OP, false>(a, row0 + e, dx, q0);
+        row_store<T, OP, false>(a, row1 + e, dy, q1);
     }
     clk_end(a.clk);
 }
@@ -486,8 +498,8 @@ __device__ __forceinline__ void mr_row_part(const StageArgs<T>& a, int rb, int t
             const int e = t + tpt * m;
             if (e < N) {
                 const cpx<T> y = Y[e];
-                row_store<T, OP>(a, row0 + e, y.x, q0[m]);
-                row_store<T, OP>(a, row1 + e, y.y, q1[m]);
+                row_store<T, OP, false>(a, row0 + e, y.x, q0[m]);
+                row_store<T, OP, false>(a, row1 + e, y.y, q1[m]);
             }
         }
     }

@@ -162,6 +162,25 @@ template hipError_t launch_spec_row_fwd2<double, float>(const SpecParams&, const
                                                         const cpx<double>*, hipStream_t);
 template hipError_t launch_spec_row_fwd2<double, double>(const SpecParams&, const double*, const double*,
                                                          cpx<double>*, const cpx<double>*, hipStream_t);
+template <typename T>
+hipError_t launch_spec_row_fwd_body(const SpecParams& p, const double* in0, T* B, const BodyLast<T>& bl,
+                                    cpx<double>* spec, const cpx<double>* tw2, hipStream_t s) {
+    const size_t nn = (size_t)p.n1 * p.n2;
+    if (bl.Q && !(chk(bl.Q, nn, "row_fwd_body Q") && chk(bl.C, nn, "row_fwd_body C") &&
+                  chk(bl.X, nn, "row_fwd_body X") && chk(bl.G, 2 * nn, "row_fwd_body G") &&
+                  chk(bl.G2, 2 * nn, "row_fwd_body G2")))
+        return done(false);
+    if (!B) {
+        mock_fail("row_fwd_body: NULL body force");
+        return done(false);
+    }
+    return launch_spec_row_fwd2<double, T>(p, in0, B, spec, tw2, s);
+}
+template hipError_t launch_spec_row_fwd_body<float>(const SpecParams&, const double*, float*, const BodyLast<float>&,
+                                                    cpx<double>*, const cpx<double>*, hipStream_t);
+template hipError_t launch_spec_row_fwd_body<double>(const SpecParams&, const double*, double*,
+                                                     const BodyLast<double>&, cpx<double>*, const cpx<double>*,
+                                                     hipStream_t);
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
                            const cpx<double>* tw1, hipStream_t) {
     const bool mode_ok = mode >= SPEC_PROJ && mode <= SPEC_LR;
@@ -178,7 +197,7 @@ hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, do
 
 size_t nyquist_scratch_doubles(int n1, int n2) {   // the real launcher's formula (32 x 64 tiles)
     const size_t ncb = (n2 + 63) / 64, nrb = (n1 + 31) / 32;
-    return 2 * (size_t)n1 + 2 * (size_t)n2 + 2 + 2 * ncb * n1 + 2 * nrb * n2 + 2 * nrb * ncb;
+    return 2 * ncb * n1 + 2 * nrb * n2 + 2 * nrb * ncb;
 }
 template <typename TO>
 hipError_t launch_nyquist_project(int n1, int n2, const double* in, double* out_d, TO* out_t, double* scratch,
