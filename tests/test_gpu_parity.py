@@ -46,6 +46,11 @@ CASES = {
     "600sq_nt3_H1_divfree_fp32": Case(600, 600, 3, "H1", "divfree", 1e-3, 0.0, "fp32", seed=25),
     "1200sq_nt2_H1_none_fp32": Case(1200, 1200, 2, "H1", "none", 1e-3, 0.0, "fp32", seed=26),
     "90sq_nt3_H1_divfree_fp64": Case(90, 90, 3, "H1", "divfree", 1e-2, 0.0, "fp64", seed=27),
+    # one time step with the exact-transpose quadrature: the only adjoint step is both the first and
+    # the last, so the assembly's row pass completes the body force from nothing (power-of-two rows)
+    # and the pointwise last-step pass does it before a mixed-radix row pass (24 points)
+    "32sq_nt1_H1_divfree_fp32": Case(32, 32, 1, "H1", "divfree", 1e-2, 0.0, "fp32", seed=28),
+    "32x24_nt1_H2_mass_fp64": Case(32, 24, 1, "H2", "mass_source", 1e-2, 1e-3, "fp64", seed=29),
 }
 
 
@@ -210,6 +215,8 @@ def test_every_launch_shape_matches_oracle(problems, name):
     for op in ("A2", "I2", "A1", "I1"):
         assert {v for v, _ in rep[op]} == want, (op, rep[op])
     assert all(c in want for c in rep["chosen"][2:6])
+    # the whole-matvec round only keeps a change that made the matvec faster
+    assert 0 < rep["matvec_ms"] <= rep["matvec_ms_isolated_choice"], rep
     H = P.hessian_matvec(dev(vt))
     assert close(host(H), ref["H"], tol)
     for v in sorted(want):

@@ -6,6 +6,7 @@ that runs past its buffer fails the call.  Kernels compute nothing here (they re
 scalars), so these tests cover addressing and control flow of every entry point, not values; the
 values are covered by the GPU parity tests.  No GPU involved."""
 import ctypes as C
+import json
 import os
 import subprocess
 
@@ -144,6 +145,9 @@ def run_all(L, p, solve=True):
                 ok=(0,) if p.hessian == REG_HESS_GN else (-1,))
     rep = C.create_string_buffer(4096)
     H.check(L.reg_autotune(H.h, 1, rep, len(rep)))
+    if p.precision == REG_FP32_TRANSPORT:   # both rounds ran (isolated stage launches, whole matvecs)
+        r = json.loads(rep.value.decode())
+        assert len(r["chosen"]) == 7 and "matvec_ms" in r and "matvec_ms_isolated_choice" in r, r
     var = (C.c_int32 * 7)(*[k % 12 for k in range(7)])
     H.check(L.reg_set_pass_variants(H.h, var, 7))
     H.check(L.reg_hessian_matvec(H.h, H.ptr(vt), H.ptr(Hv)))
