@@ -156,6 +156,10 @@ def roofline(P, reps=None, workload="c2"):
     dispatch stamps (reg_time_pass)."""
     ms, by, ex = P.time_pass(0, reps or max(1, 256 // P.nt))   # ~256 timed launches
     achieved = by / (ms * 1e-3) / 1e9
+    # phase mode (reg_time_phases): every block stamps its loads' arrival and the end of its
+    # transforms after waiting for them, so the phases run one after another; their lengths, not
+    # the overlapped launch above
+    phases = {k: round(v, 3) for k, v in P.time_phases(0, max(1, 128 // P.nt)).items()}
     return {"kernel": "stage_fused_kernel<float, N, ..., OP_A2> (GN incremental adjoint, RK2 stage 2)",
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload),
@@ -163,7 +167,8 @@ def roofline(P, reps=None, workload="c2"):
             # the blocks' own execution interval (device clock), without the dispatch ramp and the
             # end-of-kernel completion that the launch duration above includes
             "exec_us_per_launch": round(ex * 1e3, 3),
-            "exec_achieved": round(by / (ex * 1e-3) / 1e9, 2)}
+            "exec_achieved": round(by / (ex * 1e-3) / 1e9, 2),
+            "phase_mode_us_per_launch": phases}
 
 
 LOWRANK_CAPACITY = 16   # directions of the preconditioner correction the bench problems can hold
@@ -171,12 +176,14 @@ LOWRANK_CAPACITY = 16   # directions of the preconditioner correction the bench 
 
 def moved_bytes_per_matvec(nt, nn):
     """Compulsory bytes the implemented GN matvec moves (each operand read once, each result written
-    once), incompressible H1 case: 4 fused stage launches per time step with 13 + 13 + 9 + 17 = 52 FP32
-    fields (208 N), except that the last adjoint stage is the body-force-only pass (11 fields instead
-    of 17); the real-space Nyquist projection of the input (two FP64 reads, FP64 and FP32 writes: 56 N)
-    and the FP64 assembly (row forward 24 N in, 32 N out; column pass 32 N in, 16 N out; row inverse
-    16 N in, 16 N out: 136 N)."""
-    return (208 * nt - 24 + 56 + 136) * nn
+    once), incompressible H1 case, in FP32 fields of 4 N bytes: incremental state stage 1 13 fields
+    (none at j = 0, where m~_0 = 0 makes it pointwise), stage 2 13 (14 at j = 0, which forms m~*_0
+    from v~ . grad m_0), GN adjoint stage 1 9 and stage 2 17 (none at j = 0: its body-force term is
+    folded into the assembly): 52 n_t - 29 fields.  The real-space Nyquist projection of the input
+    (two FP64 reads, FP64 and FP32 writes: 56 N) and the FP64 assembly (row forward: v~ 16 N and
+    the nine FP32 fields of the last body-force term 36 N in, 32 N out; column pass 32 N in, 16 N out;
+    row inverse 16 N in, 16 N out: 164 N)."""
+    return (4 * (52 * nt - 29) + 56 + 164) * nn
 
 
 def bench_solve(P, recycle=0, diagnostics=False):

@@ -288,6 +288,17 @@ reg_status reg_deformation_static(reg_problem* h, const double* v, double* u1, d
 reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms_per_launch_host,
                          double* bytes_per_launch_host, double* exec_ms_host);
 
+/* Measurement hook, phase mode: as reg_time_pass (same `which`; reps * nt <= 256), but every block of
+ * the timed launches also stamps, on the device wall clock, the arrival of all its loads and the end
+ * of its transforms, each after waiting for all its waves' memory operations, so the three phases
+ * run one after another instead of overlapping.  phase_us_host[6] receives, in microseconds per
+ * launch: [0] dispatch interval, [1] block execution interval, [2] spread of the block starts (latest
+ * minus earliest), and the means over blocks of [3] start -> loads arrived, [4] -> forward and inverse
+ * transforms done, [5] -> stores acknowledged.  [3..5] cover the one-launch stages of square
+ * power-of-two FP32 grids (64+ points) and are 0 for the others.  REG_ESTATE before the first reg_hessian_matvec.  Synchronises
+ * the stream. */
+reg_status reg_time_phases(reg_problem* h, int32_t which, int32_t reps, double* phase_us_host);
+
 /* Launch-shape autotuner for the FP32 transport stages on square grids of 64+ points (elements per
  * thread of the row and column register FFTs, threads per block), at the current linearisation
  * point and on the last reg_hessian_matvec input.  Round 1 times every shape that fits the grid's

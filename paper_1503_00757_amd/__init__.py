@@ -10,7 +10,7 @@ from .ffi import (  # noqa: F401
     REG_H1, REG_H2, REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE, REG_FP64, REG_FP32_TRANSPORT,
     REG_ADJ_DISCRETE, REG_ADJ_PAPER,
     reg_workspace_bytes, reg_create, reg_destroy, reg_set_stream, reg_state_forward, reg_objective,
-    reg_gradient, reg_hessian_matvec, reg_precond_apply, reg_pcg, reg_solve, reg_time_pass,
+    reg_gradient, reg_hessian_matvec, reg_precond_apply, reg_pcg, reg_solve, reg_time_pass, reg_time_phases,
     reg_autotune, reg_set_pass_variants, reg_batch_solve, reg_set_images, reg_deformation,
     reg_deformation_workspace_bytes, reg_cfl, REG_H3,
     reg_fno_param_count, reg_fno_workspace_bytes, reg_fno_create, reg_fno_destroy, reg_fno_features, reg_fno_target,

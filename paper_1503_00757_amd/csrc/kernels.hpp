@@ -17,7 +17,8 @@ struct cpx;
 enum PassOp { OP_S1 = 0, OP_S2, OP_A1, OP_A2, OP_I1, OP_I2, OP_GRAD, OP_A1F, OP_A2F };
 constexpr int NUM_TUNED_OPS = 7;
 constexpr int op_base(int op) { return op == OP_A1F ? OP_A1 : (op == OP_A2F ? OP_A2 : op); }
-enum PassFlags { F_ZERO = 1, F_FIRST = 2, F_NEG = 4 };
+// F_PHASES (timing only, with clk): four stamps per block instead of two (see transport_kernels.hpp).
+enum PassFlags { F_ZERO = 1, F_FIRST = 2, F_NEG = 4, F_PHASES = 8 };
 
 // One RK2 stage: input u = A + Bf (Bf nullable; negated with F_NEG; with F_ZERO u = -h v~ . G2).
 // Row blocks write ROUT (and UOUT = u, gradient component 1, body force); column blocks write COUT
@@ -54,7 +55,10 @@ struct StageArgs {
     MrPlan mr1, mr2;         // mixed-radix plans of the two axis lengths (ns = 0: power of two, or a
                              // length with another prime factor, which takes the circulant)
     unsigned long long* clk; // timing (nullable): block b stores its start / end (device wall clock)
-                             // to clk[2b], clk[2b+1]; a stage has at most (n1 + n2) / 2 blocks
+                             // to clk[2b], clk[2b+1]; a stage has at most (n1 + n2) / 2 blocks.
+                             // With F_PHASES: clk[4b .. 4b+3] = start, loads arrived, transforms
+                             // done, stores acknowledged (one-launch FP32 Gauss-Newton stages of
+                             // square grids; the others leave the middle two at their initial values)
 };
 // clk[2 i] = ~0, clk[2 i + 1] = 0 for i < pairs (before timed stages)
 hipError_t launch_clk_init(unsigned long long* clk, int pairs, hipStream_t s);

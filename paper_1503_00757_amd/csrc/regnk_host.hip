@@ -214,6 +214,8 @@ struct reg_problem {
     // measurement hook: hipEvents around every launch of one stage op during real matvecs
     int timing_op = -1;
     int clk_used = 0;   // timed launches recorded so far (reg_time_pass)
+    int clk_max = 0;    // timed launches the stamp buffer holds in the current mode
+    bool clk_phases = false;   // four stamps per block (reg_time_phases)
     size_t clk_stride = 0;
     std::vector<hipEvent_t> tev;   // dispatch-stamped start / end events of the timed launches
 
@@ -289,9 +291,10 @@ StageArgs<T> base_args(const reg_problem* P) {
 template <typename T>
 reg_status stage(reg_problem* P, int op, const StageArgs<T>& a) {
     const int var = P->var[op_base(op)];
-    if (op == P->timing_op && P->clk_used < MAX_TIMED && 2 * (size_t)P->clk_used + 2 <= P->tev.size()) {
+    if (op == P->timing_op && P->clk_used < P->clk_max && 2 * (size_t)P->clk_used + 2 <= P->tev.size()) {
         StageArgs<T> t = a;   // the blocks stamp their own start and end; the dispatch stamps two events
         t.clk = P->at<unsigned long long>(P->o.clk) + P->clk_stride * P->clk_used;
+        if (P->clk_phases) t.flags |= F_PHASES;
         CK(launch_stage<T>(op, var, t, P->stream, P->tev[2 * P->clk_used], P->tev[2 * P->clk_used + 1]));
         ++P->clk_used;
     } else {
@@ -1391,6 +1394,63 @@ reg_status time_launches(reg_problem* P, int op, int var, const StageArgs<T>& a,
     return REG_OK;
 }
 
+// Timed matvecs with the selected stage's launches stamped (direct launches).  phases: four stamps
+// per block (F_PHASES) and at most MAX_TIMED / 2 timed launches.  Leaves the host copy of the stamps
+// in h (slots per launch = stamps * (n1 + n2) / 2) and the events' mean dispatch interval in ev_ms.
+template <typename T>
+reg_status timed_matvecs(reg_problem* P, int which, int reps, bool phases, std::vector<unsigned long long>& h,
+                         int* timed_out, double* ev_ms_out, double* fields_out, int* khz_out) {
+    if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
+    if (P->p.hessian != REG_HESS_GN) return fail(REG_EINVAL, "the timing hook covers the Gauss-Newton stages");
+    if (reps < 1 || reps > 1000) return fail(REG_EINVAL, "reps must be in [1, 1000]");
+    const int cap = phases ? MAX_TIMED / 2 : MAX_TIMED;
+    if ((long)reps * P->nt > cap)
+        return fail(REG_EINVAL, "reps * nt = %ld timed launches exceed %d", (long)reps * P->nt, cap);
+    StageArgs<T> a;
+    int op;
+    CKS(stage_spec<T>(P, which, a, op, *fields_out));
+    int dev = 0, khz = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(REG_EDEVICE, "device wall-clock rate unavailable");
+    *khz_out = khz;
+    const int stamps = phases ? 4 : 2;
+    const size_t slots = clk_slots(&P->p);
+    P->clk_stride = stamps * slots;
+    const int launches = reps * P->nt;
+    while (P->tev.size() < 2 * (size_t)launches) {
+        hipEvent_t e;
+        CK(hipEventCreate(&e));
+        P->tev.push_back(e);
+    }
+    unsigned long long* clk = P->at<unsigned long long>(P->o.clk);
+    CK(launch_clk_init(clk, (int)(launches * slots * stamps / 2), P->stream));
+    P->timing_op = op;
+    P->clk_used = 0;
+    P->clk_max = cap;
+    P->clk_phases = phases;
+    reg_status st = REG_OK;
+    for (int r = 0; r < reps && st == REG_OK; ++r)
+        st = matvec_t<T>(P, P->at<double>(P->o.vt64), P->pcg(PST), nullptr);
+    P->timing_op = -1;
+    P->clk_phases = false;
+    CKS(st);
+    const int timed = P->clk_used;
+    if (timed == 0) return fail(REG_EINVAL, "no launches of the selected stage");
+    h.assign((size_t)timed * stamps * slots, 0);
+    CK(hipMemcpyAsync(h.data(), clk, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, P->stream));
+    CK(hipStreamSynchronize(P->stream));
+    double ev_ms = 0;
+    for (int i = 0; i < timed; ++i) {
+        float t = 0;
+        CK(hipEventElapsedTime(&t, P->tev[2 * i], P->tev[2 * i + 1]));
+        ev_ms += t;
+    }
+    *timed_out = timed;
+    *ev_ms_out = ev_ms / timed;
+    return REG_OK;
+}
+
 // Mean device time of the selected stage's launches inside `reps` real matvecs (direct launches):
 //  * ms: the dispatch interval, from start / end events that the dispatch itself stamps
 //    (hipExtLaunchKernelGGL) -- what a profiler reports as the kernel's duration;
@@ -1399,46 +1459,13 @@ reg_status time_launches(reg_problem* P, int op, int var, const StageArgs<T>& a,
 // The difference is the workgroup dispatch ramp and the end-of-kernel completion.
 template <typename T>
 reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* bytes, double* exec_ms) {
-    if (!P->matvec_done) return fail(REG_ESTATE, "run one reg_hessian_matvec before timing passes");
-    if (P->p.hessian != REG_HESS_GN) return fail(REG_EINVAL, "the timing hook covers the Gauss-Newton stages");
-    if (reps < 1 || reps > 1000) return fail(REG_EINVAL, "reps must be in [1, 1000]");
-    if ((long)reps * P->nt > MAX_TIMED)
-        return fail(REG_EINVAL, "reps * nt = %ld timed launches exceed %d", (long)reps * P->nt, MAX_TIMED);
-    StageArgs<T> a;
-    int op;
-    double fields;
-    CKS(stage_spec<T>(P, which, a, op, fields));
-    int dev = 0, khz = 0;
-    CK(hipGetDevice(&dev));
-    CK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    if (khz <= 0) return fail(REG_EDEVICE, "device wall-clock rate unavailable");
+    std::vector<unsigned long long> h;
+    int timed = 0, khz = 0;
+    double ev = 0, fields = 0;
+    CKS(timed_matvecs<T>(P, which, reps, false, h, &timed, &ev, &fields, &khz));
     const size_t slots = clk_slots(&P->p);
-    P->clk_stride = 2 * slots;
-    const int launches = reps * P->nt;
-    while (P->tev.size() < 2 * (size_t)launches) {
-        hipEvent_t e;
-        CK(hipEventCreate(&e));
-        P->tev.push_back(e);
-    }
-    unsigned long long* clk = P->at<unsigned long long>(P->o.clk);
-    CK(launch_clk_init(clk, (int)(launches * slots), P->stream));
-    P->timing_op = op;
-    P->clk_used = 0;
-    reg_status st = REG_OK;
-    for (int r = 0; r < reps && st == REG_OK; ++r)
-        st = matvec_t<T>(P, P->at<double>(P->o.vt64), P->pcg(PST), nullptr);
-    P->timing_op = -1;
-    CKS(st);
-    const int timed = P->clk_used;
-    if (timed == 0) return fail(REG_EINVAL, "no launches of the selected stage");
-    std::vector<unsigned long long> h((size_t)timed * 2 * slots);
-    CK(hipMemcpyAsync(h.data(), clk, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, P->stream));
-    CK(hipStreamSynchronize(P->stream));
-    double ticks = 0, ev_ms = 0;
+    double ticks = 0;
     for (int i = 0; i < timed; ++i) {
-        float t = 0;
-        CK(hipEventElapsedTime(&t, P->tev[2 * i], P->tev[2 * i + 1]));
-        ev_ms += t;
         unsigned long long t0 = ~0ull, t1 = 0;
         for (size_t b = 0; b < slots; ++b) {
             const unsigned long long s0 = h[(i * slots + b) * 2], s1 = h[(i * slots + b) * 2 + 1];
@@ -1448,9 +1475,49 @@ reg_status time_pass_t(reg_problem* P, int which, int reps, double* ms, double* 
         if (t0 == ~0ull || t1 < t0) return fail(REG_EDEVICE, "timed launch %d recorded no interval", i);
         ticks += (double)(t1 - t0);
     }
-    *ms = ev_ms / timed;
+    *ms = ev;
     if (exec_ms) *exec_ms = ticks / timed / (double)khz;   // khz ticks per millisecond
     *bytes = fields * (double)P->nn * sizeof(T);
+    return REG_OK;
+}
+
+// Phase mode (F_PHASES): us[0] dispatch interval, us[1] block execution interval, us[2] spread of
+// the block starts (latest minus earliest), and the per-block means of us[3] start -> loads arrived,
+// us[4] -> transforms done, us[5] -> stores acknowledged, over the blocks that stamped all four
+// (the one-launch FP32 stages of square grids; 0 where none did).  Microseconds per launch.
+template <typename T>
+reg_status time_phases_t(reg_problem* P, int which, int reps, double* us) {
+    std::vector<unsigned long long> h;
+    int timed = 0, khz = 0;
+    double ev = 0, fields = 0;
+    CKS(timed_matvecs<T>(P, which, reps, true, h, &timed, &ev, &fields, &khz));
+    const size_t slots = clk_slots(&P->p);
+    double exec = 0, spread = 0, ph[3] = {0, 0, 0};
+    long nb = 0;
+    for (int i = 0; i < timed; ++i) {
+        unsigned long long t0 = ~0ull, t1 = 0, s_last = 0;
+        for (size_t b = 0; b < slots; ++b) {
+            const unsigned long long* q = &h[(i * slots + b) * 4];
+            if (q[0] == ~0ull) continue;   // no such block
+            t0 = std::min(t0, q[0]);
+            s_last = std::max(s_last, q[0]);
+            t1 = std::max(t1, q[3]);
+            if (q[1] != 0ull && q[2] != ~0ull && q[0] <= q[1] && q[1] <= q[2] && q[2] <= q[3]) {
+                ph[0] += (double)(q[1] - q[0]);
+                ph[1] += (double)(q[2] - q[1]);
+                ph[2] += (double)(q[3] - q[2]);
+                ++nb;
+            }
+        }
+        if (t0 == ~0ull || t1 < t0) return fail(REG_EDEVICE, "timed launch %d recorded no interval", i);
+        exec += (double)(t1 - t0);
+        spread += (double)(s_last - t0);
+    }
+    const double us_per_tick = 1e3 / (double)khz;
+    us[0] = ev * 1e3;
+    us[1] = exec / timed * us_per_tick;
+    us[2] = spread / timed * us_per_tick;
+    for (int k = 0; k < 3; ++k) us[3 + k] = nb ? ph[k] / nb * us_per_tick : 0.0;
     return REG_OK;
 }
 
@@ -1948,6 +2015,12 @@ reg_status reg_time_pass(reg_problem* h, int32_t which, int32_t reps, double* ms
     if (!h || !ms || !bytes) return fail(REG_EINVAL, "NULL argument");
     return DISPATCH(h, time_pass_t<float>(h, which, reps, ms, bytes, exec_ms),
                     time_pass_t<double>(h, which, reps, ms, bytes, exec_ms));
+}
+
+reg_status reg_time_phases(reg_problem* h, int32_t which, int32_t reps, double* phase_us_host) {
+    if (!h || !phase_us_host) return fail(REG_EINVAL, "NULL argument");
+    return DISPATCH(h, time_phases_t<float>(h, which, reps, phase_us_host),
+                    time_phases_t<double>(h, which, reps, phase_us_host));
 }
 
 reg_status reg_autotune(reg_problem* h, int32_t reps, char* report, size_t report_bytes) {

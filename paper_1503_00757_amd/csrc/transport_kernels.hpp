@@ -242,7 +242,7 @@ __device__ __forceinline__ void col_store2(const StageArgs<T>& a, long idx, T d0
 // ---------------------------------------------------------------------------------------------
 // Row part: FPW transforms per block, each = one pair of rows (2r, 2r+1), length N = n2, E elements
 // per thread.  lds: FPW * 2 * LdsSize<N> entries.
-template <typename T, int N, int E, int FPW, int OP>
+template <typename T, int N, int E, int FPW, int OP, bool PH = false>
 __device__ __forceinline__ void row_part(const StageArgs<T>& a, int rb, cpx<T>* lds) {
     constexpr int TT = N / E;
     constexpr int L = LdsSize<N>::value;
@@ -265,6 +265,7 @@ __device__ __forceinline__ void row_part(const StageArgs<T>& a, int rb, cpx<T>* 
     }
     cpx<T> W[tw_regs<N, E>()];
     load_tw<T, N, E, 1, 0>(W, t, a.tw2);
+    if constexpr (PH) clk_phase(a, 1);
     cpx<T>* l0 = lds + f * 2 * L;
     int buf = 0;
     fftE<T, N, E, false>(x, l0, l0 + L, t, W, buf);
@@ -275,6 +276,7 @@ __device__ __forceinline__ void row_part(const StageArgs<T>& a, int rb, cpx<T>* 
         x[m] = {-x[m].y * k, x[m].x * k};   // times i k / N
     }
     fftE<T, N, E, true>(x, l0, l0 + L, t, W, buf);
+    if constexpr (PH) clk_phase(a, 2);
     if (!valid) return;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -285,7 +287,7 @@ __device__ __forceinline__ void row_part(const StageArgs<T>& a, int rb, cpx<T>* 
 }
 
 // Column part: a block owns TW = 2G adjacent columns (G transforms of length N = n1).
-template <typename T, int N, int E, int G, int OP>
+template <typename T, int N, int E, int G, int OP, bool PH = false>
 __device__ __forceinline__ void col_part(const StageArgs<T>& a, int cb, int ncb, cpx<T>* lds) {
     constexpr int TT = N / E;
     constexpr int L = LdsSize<N>::value;
@@ -305,6 +307,7 @@ __device__ __forceinline__ void col_part(const StageArgs<T>& a, int cb, int ncb,
     }
     cpx<T> W[tw_regs<N, E>()];
     load_tw<T, N, E, 1, 0>(W, t, a.tw1);
+    if constexpr (PH) clk_phase(a, 1);
     cpx<T>* l0 = lds + f * 2 * L;
     int buf = 0;
     fftE<T, N, E, false>(x, l0, l0 + L, t, W, buf);
@@ -315,6 +318,7 @@ __device__ __forceinline__ void col_part(const StageArgs<T>& a, int cb, int ncb,
         x[m] = {-x[m].y * k, x[m].x * k};
     }
     fftE<T, N, E, true>(x, l0, l0 + L, t, W, buf);
+    if constexpr (PH) clk_phase(a, 2);
     if (!valid) return;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -328,44 +332,66 @@ __device__ __forceinline__ void col_part(const StageArgs<T>& a, int cb, int ncb,
 // contention); the end is taken after every wave's stores were acknowledged (s_waitcnt 0: stores
 // count in vmcnt; no cache write-back, unlike a device-scope fence, which costs an L2 flush per
 // block here).  The caller takes the earliest start and the latest end.
-__device__ __forceinline__ void clk_start(unsigned long long* clk) {
-    if (clk && threadIdx.x == 0) clk[2 * blockIdx.x] = wall_clock64();
+// Phase mode (F_PHASES): four slots per block, and the phase-mode build of the fused square FP32
+// Gauss-Newton stages (PH) also stamps the arrival of all its loads and the end of its transforms,
+// each after waiting for every wave's memory operations; the phases then run one after another (no
+// overlap of loads with transforms), so they show each phase's length rather than the overlapped
+// launch.  The stamps are compiled only into that build: a branch on the flag in the production
+// kernels cost 1-1.4% (it splits the code the scheduler interleaves).
+template <typename T>
+__device__ __forceinline__ int clk_slots_per_block(const StageArgs<T>& a) {
+    return (a.flags & F_PHASES) ? 4 : 2;
 }
-__device__ __forceinline__ void clk_end(unsigned long long* clk) {
-    if (clk) {
+template <typename T>
+__device__ __forceinline__ void clk_start(const StageArgs<T>& a) {
+    if (a.clk && threadIdx.x == 0) a.clk[clk_slots_per_block(a) * blockIdx.x] = wall_clock64();
+}
+template <typename T>
+__device__ __forceinline__ void clk_end(const StageArgs<T>& a) {
+    if (a.clk) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (threadIdx.x == 0) clk[2 * blockIdx.x + 1] = wall_clock64();
+        const int k = clk_slots_per_block(a);
+        if (threadIdx.x == 0) a.clk[k * blockIdx.x + k - 1] = wall_clock64();
+    }
+}
+template <typename T>
+__device__ __forceinline__ void clk_phase(const StageArgs<T>& a, int slot) {
+    if (a.clk && (a.flags & F_PHASES)) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) a.clk[4 * blockIdx.x + slot] = wall_clock64();
     }
 }
 
 // Square grids: one launch, blocks [0, nrb) do row pairs, the rest column tiles.
-template <typename T, int N, int ER, int FPW, int EC, int G, int OP>
+// PH: the phase-mode build of the kernel (timing only; launched when F_PHASES is set).
+template <typename T, int N, int ER, int FPW, int EC, int G, int OP, bool PH = false>
 __global__ __launch_bounds__(FPW * N / ER) void stage_fused_kernel(StageArgs<T> a, int nrb) {
     static_assert(FPW * (N / ER) == G * (N / EC), "row and column blocks must have the same size");
     constexpr int LR = FPW * 2 * LdsSize<N>::value;
     constexpr int LC = G * 2 * LdsSize<N>::value;
     __shared__ cpx<T> lds[LR > LC ? LR : LC];
-    clk_start(a.clk);
-    if ((int)blockIdx.x < nrb) row_part<T, N, ER, FPW, OP>(a, blockIdx.x, lds);
-    else col_part<T, N, EC, G, OP>(a, blockIdx.x - nrb, gridDim.x - nrb, lds);
-    clk_end(a.clk);
+    clk_start(a);
+    if ((int)blockIdx.x < nrb) row_part<T, N, ER, FPW, OP, PH>(a, blockIdx.x, lds);
+    else col_part<T, N, EC, G, OP, PH>(a, blockIdx.x - nrb, gridDim.x - nrb, lds);
+    clk_end(a);
 }
 
 // Non-square grids: the two parts as two launches.
 template <typename T, int N, int E, int FPW, int OP>
 __global__ __launch_bounds__(FPW * N / E) void stage_row_kernel(StageArgs<T> a) {
     __shared__ cpx<T> lds[FPW * 2 * LdsSize<N>::value];
-    clk_start(a.clk);
+    clk_start(a);
     row_part<T, N, E, FPW, OP>(a, blockIdx.x, lds);
-    clk_end(a.clk);
+    clk_end(a);
 }
 template <typename T, int N, int E, int G, int OP>
 __global__ __launch_bounds__(G * N / E) void stage_col_kernel(StageArgs<T> a) {
     __shared__ cpx<T> lds[G * 2 * LdsSize<N>::value];
-    clk_start(a.clk);
+    clk_start(a);
     col_part<T, N, E, G, OP>(a, blockIdx.x, gridDim.x, lds);
-    clk_end(a.clk);
+    clk_end(a);
 }
 
 // Axis lengths that are not powers of two: the derivative along the axis is the product with the
@@ -381,7 +407,7 @@ __global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_row_kernel(St
     cpx<T>* f = reinterpret_cast<cpx<T>*>(dsm);
     const int N = a.n2;
     const long row0 = (long)(2 * blockIdx.x) * N, row1 = row0 + N;
-    clk_start(a.clk);
+    clk_start(a);
     for (int e = threadIdx.x; e < N; e += DENSE_STAGE_THREADS) {
         Rp<T> q0, q1;
         const T p0 = row_load<T, OP>(a, row0 + e, q0);
@@ -404,7 +430,7 @@ __global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_row_kernel(St
         row_store<T, OP, false>(a, row0 + e, dx, q0);
         row_store<T, OP, false>(a, row1 + e, dy, q1);
     }
-    clk_end(a.clk);
+    clk_end(a);
 }
 
 template <typename T, int OP>
@@ -413,7 +439,7 @@ __global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_col_kernel(St
     cpx<T>* f = reinterpret_cast<cpx<T>*>(dsm);
     const int N = a.n1;
     const long c = 2 * (long)blockIdx.x, n2 = a.n2;
-    clk_start(a.clk);
+    clk_start(a);
     for (int r = threadIdx.x; r < N; r += DENSE_STAGE_THREADS) {
         Cp<T> q0, q1;
         f[r] = col_load2<T, OP>(a, (long)r * n2 + c, q0, q1);
@@ -433,7 +459,7 @@ __global__ __launch_bounds__(DENSE_STAGE_THREADS) void stage_dense_col_kernel(St
         col_load2<T, OP>(a, idx, q0, q1);
         col_store2<T, OP>(a, idx, dx, dy, q0, q1);
     }
-    clk_end(a.clk);
+    clk_end(a);
 }
 
 // Axis lengths 2^a 3^b 5^c that are not powers of two: the same stage with the mixed-radix FFT in LDS
@@ -552,16 +578,16 @@ __device__ __forceinline__ void mr_col_part(const StageArgs<T>& a, int cb, int t
 template <typename T, int OP, int EM>
 __global__ __launch_bounds__(512) void stage_mr_row_kernel(StageArgs<T> a, int tpt, int fpw, int twl) {
     extern __shared__ unsigned char dsm[];
-    clk_start(a.clk);
+    clk_start(a);
     mr_row_part<T, OP, EM>(a, blockIdx.x, tpt, fpw, reinterpret_cast<cpx<T>*>(dsm), fpw, twl != 0);
-    clk_end(a.clk);
+    clk_end(a);
 }
 template <typename T, int OP, int EM>
 __global__ __launch_bounds__(512) void stage_mr_col_kernel(StageArgs<T> a, int tpt, int G, int twl) {
     extern __shared__ unsigned char dsm[];
-    clk_start(a.clk);
+    clk_start(a);
     mr_col_part<T, OP, EM>(a, blockIdx.x, tpt, G, reinterpret_cast<cpx<T>*>(dsm), G, twl != 0);
-    clk_end(a.clk);
+    clk_end(a);
 }
 // Square grids of such a length: both parts in one launch (blocks [0, nrb) rows, the rest columns).
 template <typename T, int OP, int EMR, int EMC>
@@ -569,11 +595,11 @@ __global__ __launch_bounds__(512) void stage_mr_fused_kernel(StageArgs<T> a, int
                                                             int G, int twl) {
     extern __shared__ unsigned char dsm[];
     const int nlines = fpw > G ? fpw : G;
-    clk_start(a.clk);
+    clk_start(a);
     if ((int)blockIdx.x < nrb)
         mr_row_part<T, OP, EMR>(a, blockIdx.x, tpt_r, fpw, reinterpret_cast<cpx<T>*>(dsm), nlines, twl != 0);
     else mr_col_part<T, OP, EMC>(a, blockIdx.x - nrb, tpt_c, G, reinterpret_cast<cpx<T>*>(dsm), nlines, twl != 0);
-    clk_end(a.clk);
+    clk_end(a);
 }
 
 // LDS of a mixed-radix stage launch: `nlines` line pairs, plus the twiddle table when the total stays
@@ -728,6 +754,14 @@ static hipError_t launch_fused(const StageArgs<T>& a, hipStream_t s, hipEvent_t 
         constexpr int G = BS / (N / EC);
         const int nrb = (a.n1 / 2 + FPW - 1) / FPW;
         const int ncb = (a.n2 + 2 * G - 1) / (2 * G);
+        // the phase-mode build exists for the FP32 Gauss-Newton stages (the timed matvec launches)
+        if constexpr (sizeof(T) == 4 && (OP == OP_A1 || OP == OP_A2 || OP == OP_I1 || OP == OP_I2)) {
+            if (a.flags & F_PHASES) {
+                launch_k(stage_fused_kernel<T, N, ER, FPW, EC, G, OP, true>, dim3(nrb + ncb), dim3(BS), s, t0, t1,
+                         a, nrb);
+                return hipGetLastError();
+            }
+        }
         launch_k(stage_fused_kernel<T, N, ER, FPW, EC, G, OP>, dim3(nrb + ncb), dim3(BS), s, t0, t1, a, nrb);
         return hipGetLastError();
     } else {
@@ -895,7 +929,7 @@ hipError_t launch_stage_op(int var, const StageArgs<T>& a, hipStream_t s, hipEve
                                      : launch_dense_axis<T, OP>(2, a, s, t0, nullptr);
     if (e != hipSuccess) return e;
     StageArgs<T> ac = a;
-    if (ac.clk) ac.clk += 2 * (a.n1 / 2);
+    if (ac.clk) ac.clk += ((a.flags & F_PHASES) ? 4 : 2) * (a.n1 / 2);
     return is_pow2_len(a.n1) ? launch_axis<T, OP, 1>(ac, s, nullptr, t1) : launch_dense_axis<T, OP>(1, ac, s, nullptr, t1);
 }
 

@@ -97,6 +97,7 @@ def lib():
         L.reg_pcg.argtypes = [vp, vp, d, i32, i32, vp, C.POINTER(i32), dp]
         L.reg_solve.argtypes = [vp, C.POINTER(RegSolveOpts), vp, C.POINTER(RegSolveStats)]
         L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp, dp]
+        L.reg_time_phases.argtypes = [vp, i32, i32, dp]
         L.reg_autotune.argtypes = [vp, i32, C.c_char_p, sz]
         L.reg_batch_solve.argtypes = [i32, C.POINTER(vp), C.POINTER(RegSolveOpts), C.POINTER(vp),
                                       C.POINTER(RegSolveStats)]
@@ -110,7 +111,7 @@ def lib():
         L.reg_last_error.restype = C.c_char_p
         for name in ("reg_workspace_bytes", "reg_create", "reg_destroy", "reg_set_stream", "reg_state_forward",
                      "reg_objective", "reg_gradient", "reg_hessian_matvec", "reg_precond_apply", "reg_pcg",
-                     "reg_solve", "reg_time_pass", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve",
+                     "reg_solve", "reg_time_pass", "reg_time_phases", "reg_autotune", "reg_set_pass_variants", "reg_batch_solve",
                      "reg_deformation_workspace_bytes", "reg_deformation", "reg_cfl", "reg_deformation_static",
                      "reg_ritz_directions"):
             getattr(L, name).restype = C.c_int
@@ -194,6 +195,14 @@ def reg_time_pass(h, which: int, reps: int):
     ex = C.c_double(0)
     _check(lib().reg_time_pass(h, which, reps, C.byref(ms), C.byref(by), C.byref(ex)))
     return ms.value, by.value, ex.value
+
+
+def reg_time_phases(h, which: int, reps: int):
+    """Phase-mode stage timing (microseconds per launch): dispatch, block execution, start spread,
+    loads, transforms, stores."""
+    out = (C.c_double * 6)()
+    _check(lib().reg_time_phases(h, which, reps, out))
+    return list(out)
 
 
 def reg_autotune(h, reps: int = 50) -> str:

@@ -177,6 +177,11 @@ class Problem:
     def time_pass(self, which, reps=100):
         return ffi.reg_time_pass(self.h, which, reps)
 
+    def time_phases(self, which, reps=8):
+        """reg_time_phases as a dict (microseconds per launch)."""
+        keys = ("dispatch", "exec", "start_spread", "loads", "transforms", "stores")
+        return dict(zip(keys, ffi.reg_time_phases(self.h, which, reps)))
+
     def autotune(self, reps=50):
         """Pick the fastest launch shape of each FP32 transport pass; returns the JSON timing report."""
         import json

@@ -93,7 +93,8 @@ hipError_t launch_stage(int op, int var, const StageArgs<T>& a, hipStream_t, hip
     ok &= chk(a.GOUT, n2, "stage GOUT") && chk(a.GOUTF, n2, "stage GOUTF") && chk(a.B, n2, "stage B");
     ok &= chk(a.tw1, (size_t)a.n1, "stage tw1") && chk(a.tw2, (size_t)a.n2, "stage tw2");
     ok &= chk(a.dc1, (size_t)a.n1, "stage dc1") && chk(a.dc2, (size_t)a.n2, "stage dc2");
-    ok &= chk(a.clk, (size_t)(a.n1 + a.n2), "stage clk");   // 2 slots per block, at most (n1 + n2) / 2 blocks
+    // 2 slots per block (4 with F_PHASES), at most (n1 + n2) / 2 blocks
+    ok &= chk(a.clk, (size_t)((a.flags & F_PHASES) ? 2 : 1) * (a.n1 + a.n2), "stage clk");
     return done(ok);
 }
 template hipError_t launch_stage<float>(int, int, const StageArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);

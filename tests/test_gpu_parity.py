@@ -226,3 +226,29 @@ def test_every_launch_shape_matches_oracle(problems, name):
     P.set_pass_variants([0] * 7)
     with pytest.raises(R.RegError):
         P.set_pass_variants([len(SHAPES)] * 7)
+
+
+@pytest.mark.parametrize("name", ["c2_256sq_nt16_H2_mass_fp32", "250sq_nt4_H2_mass_fp32", "128x32_nt3_H1_none_fp32"])
+def test_timing_hooks(problems, name):
+    """reg_time_pass and the phase mode of reg_time_phases on real matvecs: positive intervals, the
+    phase stamps only from the one-launch stages of square power-of-two FP32 grids, and the timed
+    matvecs leave the matvec's result bitwise unchanged."""
+    case = CASES[name]
+    P = get(problems, name)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    P.gradient(dev(vlin), want_J=False)
+    before = host(P.hessian_matvec(dev(vt)))
+    stamped = case.n1 == case.n2 and case.n1 & (case.n1 - 1) == 0 and case.n1 >= 64 and case.precision == "fp32"
+    for which in range(4):
+        ms, by, ex = P.time_pass(which, 2)
+        assert ms > 0 and ex > 0 and by > 0, (which, ms, ex, by)
+        ph = P.time_phases(which, 2)
+        assert ph["dispatch"] > 0 and ph["exec"] > 0 and ph["start_spread"] >= 0, ph
+        parts = [ph["loads"], ph["transforms"], ph["stores"]]
+        if stamped:
+            assert all(p > 0 for p in parts), ph
+            # a block's phases follow one another inside the launch's execution interval
+            assert sum(parts) <= ph["exec"] * 1.001, ph
+        else:
+            assert parts == [0.0, 0.0, 0.0], ph
+    assert np.array_equal(host(P.hessian_matvec(dev(vt))), before)

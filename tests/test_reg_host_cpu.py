@@ -57,6 +57,7 @@ def build_mock(out):
     L.reg_deformation.argtypes = [vp, vp, vp, sz, vp, vp, vp, dp]
     L.reg_deformation_static.argtypes = [vp, vp, vp, vp, vp, dp]
     L.reg_time_pass.argtypes = [vp, i32, i32, dp, dp, dp]
+    L.reg_time_phases.argtypes = [vp, i32, i32, dp]
     L.reg_autotune.argtypes = [vp, i32, C.c_char_p, sz]
     L.reg_set_pass_variants.argtypes = [vp, C.POINTER(i32), i32]
     L.reg_ritz_directions.argtypes = [vp, vp, i32, i32, dp]
@@ -143,6 +144,8 @@ def run_all(L, p, solve=True):
     for which in range(4):   # the timing hook covers the Gauss-Newton stages only
         H.check(L.reg_time_pass(H.h, which, 2, C.byref(ms), C.byref(by), C.byref(ex)),
                 ok=(0,) if p.hessian == REG_HESS_GN else (-1,))
+        ph = (dbl * 6)()
+        H.check(L.reg_time_phases(H.h, which, 2, ph), ok=(0,) if p.hessian == REG_HESS_GN else (-1,))
     rep = C.create_string_buffer(4096)
     H.check(L.reg_autotune(H.h, 1, rep, len(rep)))
     if p.precision == REG_FP32_TRANSPORT:   # both rounds ran (isolated stage launches, whole matvecs)
