@@ -198,7 +198,26 @@ typedef struct {
      * n_t; g(0) does not).  n_t never decreases; the new n_t stays with the handle after the solve.
      * 0 = n_t fixed. */
     double cfl_max;
+    /* Per-Newton-step records (nullable): step k < max_steps fills steps[k] (host memory) once the
+     * step ends, also a step whose line search fails (alpha = 0).  Costs one host round trip per
+     * step for C(v). */
+    struct reg_step_record* steps;
+    int32_t max_steps;        /* >= 0; 0 = no records */
 } reg_solve_opts;
+
+/* One Newton step of reg_solve (Alg. 1): the quantities the paper reports per iteration and the
+ * step's cost. */
+typedef struct reg_step_record {
+    int32_t newton_iter;      /* k, from 0 */
+    int32_t pcg_iters;        /* PCG iterations of the step's Newton system */
+    int32_t backtracks;       /* Armijo reductions of the step length */
+    int32_t nt;               /* n_t after the step's CFL check */
+    double J;                 /* objective at the new iterate (the old one if the search failed) */
+    double g_rel;             /* ||g|| / ||g(0)|| at that iterate */
+    double alpha;             /* accepted step length; 0 if the line search failed */
+    double cfl;               /* C(v) of that iterate at n_t (see reg_cfl) */
+    double ms;                /* host wall time of the step, host round trips included */
+} reg_step_record;
 
 typedef struct {
     int32_t newton_iters, pcg_iters, n_matvec, n_pde, backtracks, status;

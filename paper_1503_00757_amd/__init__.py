@@ -6,7 +6,7 @@ marshals arguments to it.  ``ffi`` holds the raw C functions with the names of `
 There is no CPU fallback: if the library is not built, importing ``ffi.lib()`` raises.
 """
 from .ffi import (  # noqa: F401
-    RegParams, RegSolveOpts, RegSolveStats, RegError, lib, library_path,
+    RegParams, RegSolveOpts, RegSolveStats, RegStepRecord, RegError, lib, library_path,
     REG_H1, REG_H2, REG_UNCONSTRAINED, REG_DIVFREE, REG_MASS_SOURCE, REG_FP64, REG_FP32_TRANSPORT,
     REG_ADJ_DISCRETE, REG_ADJ_PAPER,
     reg_workspace_bytes, reg_create, reg_destroy, reg_set_stream, reg_state_forward, reg_objective,

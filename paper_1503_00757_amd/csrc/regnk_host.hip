@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <mutex>
@@ -1182,10 +1183,26 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
     int k = 0;
     reg_status status = REG_OK;
     double grel = 0;
+    using clock = std::chrono::steady_clock;
+    // per-step record k (o->steps): the current iterate's J, ||g||_rel and C(v) after the step
+    auto record = [&](int kk, int its, int nbt, double alpha, clock::time_point t0) -> reg_status {
+        if (!o->steps || kk >= o->max_steps) return REG_OK;
+        reg_step_record& R = o->steps[kk];
+        R.ms = std::chrono::duration<double, std::milli>(clock::now() - t0).count();
+        R.newton_iter = kk;
+        R.pcg_iters = its;
+        R.backtracks = nbt;
+        R.nt = P->nt;
+        R.J = J;
+        R.g_rel = g0 > 0 ? std::sqrt(gg) / g0 : 0.0;
+        R.alpha = alpha;
+        return cfl_t(P, P->at<double>(P->o.v64), &R.cfl);   // v64: the projected iterate
+    };
     while (true) {
         grel = g0 > 0 ? std::sqrt(gg) / g0 : 0.0;
         if (!std::isfinite(grel) || !std::isfinite(J)) { status = REG_ENONFINITE; break; }
         if (grel <= o->gtol_rel || k >= o->max_newton) break;
+        const clock::time_point t_step = clock::now();
         const double eta = std::min(0.5, std::sqrt(grel));
         CK(launch_fill(n, 0.0, rhs, P->stream));
         CK(launch_axpby(n, -1.0, g, 0.0, rhs, P->stream));   // rhs = -g
@@ -1225,7 +1242,11 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
         }
         if (nbt > o->max_backtracks) nbt = o->max_backtracks;
         S.backtracks += nbt;
-        if (!accepted) { status = REG_ENOTCONV; break; }
+        if (!accepted) {
+            status = REG_ENOTCONV;
+            CKS(record(k, its, nbt, 0.0, t_step));
+            break;
+        }
         CK(launch_add_scaled(n, v, alpha, vt, v, P->stream));
         {
             bool changed = false;
@@ -1237,6 +1258,7 @@ reg_status solve_t(reg_problem* P, const reg_solve_opts* o, double* vout, reg_so
             const double* a[1] = {g};
             CKS(dots(P, 1, a, a, &gg));
         }
+        CKS(record(k, its, nbt, alpha, t_step));
         ++k;
     }
     S.newton_iters = k;
@@ -1853,6 +1875,8 @@ static reg_status check_opts(const reg_problem* h, const reg_solve_opts* opts) {
         return fail(REG_EINVAL, "no preconditioner correction for REG_STOKES with REG_MASS_SOURCE (its W-product "
                                 "moves with the linearisation point)");
     if (!(opts->cfl_max >= 0.0) || !std::isfinite(opts->cfl_max)) return fail(REG_EINVAL, "cfl_max must be >= 0");
+    if (opts->max_steps < 0 || (opts->max_steps > 0 && !opts->steps))
+        return fail(REG_EINVAL, "max_steps=%d needs a record array", opts->max_steps);
     return REG_OK;
 }
 

@@ -30,12 +30,21 @@ class RegParams(C.Structure):
                 ("stokes_eps", C.c_double)]
 
 
+class RegStepRecord(C.Structure):
+    _fields_ = [("newton_iter", C.c_int32), ("pcg_iters", C.c_int32), ("backtracks", C.c_int32),
+                ("nt", C.c_int32), ("J", C.c_double), ("g_rel", C.c_double), ("alpha", C.c_double),
+                ("cfl", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class RegSolveOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("fixed_pcg_iters", C.c_int32),
                 ("max_backtracks", C.c_int32), ("gtol_rel", C.c_double), ("armijo_c1", C.c_double),
                 ("armijo_rho", C.c_double), ("v0", C.c_void_p), ("precond_U", C.c_void_p),
                 ("precond_d", C.POINTER(C.c_double)), ("rank", C.c_int32), ("recycle", C.c_int32),
-                ("cfl_max", C.c_double)]
+                ("cfl_max", C.c_double), ("steps", C.POINTER(RegStepRecord)), ("max_steps", C.c_int32)]
 
 
 class RegSolveStats(C.Structure):

@@ -118,28 +118,35 @@ class Problem:
 
     def solve_opts(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
                    armijo_c1=1e-4, armijo_rho=0.5, v0=None, precond_U=None, recycle=0, ritz_out=None,
-                   cfl_max=0.0):
+                   cfl_max=0.0, steps=None):
         """reg_solve_opts; v0 / precond_U must be contiguous float64 device tensors kept alive by the
-        caller, ritz_out a ctypes double array of len(precond_U) (or None)."""
+        caller, ritz_out a ctypes double array of len(precond_U) (or None), steps a ctypes array of
+        RegStepRecord (or None)."""
+        import ctypes
         rank = 0 if precond_U is None else int(precond_U.shape[0])
+        rec = ctypes.cast(steps, ctypes.POINTER(ffi.RegStepRecord)) if steps is not None else None
         return ffi.RegSolveOpts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
                                 armijo_rho, v0.data_ptr() if v0 is not None else None,
                                 precond_U.data_ptr() if precond_U is not None else None, ritz_out, rank,
-                                int(recycle), float(cfl_max))
+                                int(recycle), float(cfl_max), rec, len(steps) if steps is not None else 0)
 
     def solve(self, max_newton=50, max_pcg=100, fixed_pcg_iters=0, max_backtracks=10, gtol_rel=1e-2,
               armijo_c1=1e-4, armijo_rho=0.5, v0=None, raise_on_error=True, precond_U=None, recycle=0,
-              cfl_max=0.0):
+              cfl_max=0.0, log=None):
         """Alg. 1 (reg_solve).  precond_U: (r, 2, n1, n2) float64 directions of the preconditioner
         correction; recycle: PCG directions kept per Newton step (both need lowrank_capacity > 0);
         cfl_max > 0: n_t raised (up to nt_max) whenever the iterate's CFL number exceeds it.
-        The stats dict carries the Ritz values of precond_U as "ritz"."""
+        The stats dict carries the Ritz values of precond_U as "ritz" and, with `log`, the
+        per-Newton-step records as "steps" (J, ||g||_rel, PCG iterations, step length, C(v), n_t and
+        the step's wall time; reg_step_record).  log: a path (one JSON line per step is appended,
+        with the grid and the step) or a callable taking each record."""
         import ctypes
         v0c = self._c(v0) if v0 is not None else None
         Uc = self._c(precond_U) if precond_U is not None else None
         ritz = (ctypes.c_double * int(Uc.shape[0]))() if Uc is not None and Uc.shape[0] > 0 else None
+        steps = (ffi.RegStepRecord * max(1, max_newton + 1))() if log is not None else None
         opts = self.solve_opts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
-                               armijo_rho, v0c, Uc, recycle, ritz, cfl_max)
+                               armijo_rho, v0c, Uc, recycle, ritz, cfl_max, steps)
         v = self.vec()
         status, st = ffi.reg_solve(self.h, opts, v.data_ptr(), raise_on_error)
         d = st.as_dict()
@@ -147,6 +154,11 @@ class Problem:
         if ritz is not None:
             d["ritz"] = list(ritz)
         self.nt = d["nt"]
+        if steps is not None:
+            # the failed step of a line search that gave up also has a record
+            n_rec = min(len(steps), d["newton_iters"] + (1 if status == ffi.REG_ENOTCONV else 0))
+            d["steps"] = [steps[k].as_dict() for k in range(n_rec)]
+            write_step_log(log, d["steps"], {"n1": self.n1, "n2": self.n2})
         return v, d
 
     def ritz_directions(self, U, iters=8):
@@ -198,3 +210,16 @@ def batch_solve(problems, raise_on_error=True, v0s=None, **opts):
     o = [p.solve_opts(v0=v0, **opts) for p, v0 in zip(problems, v0s)]
     status, st = ffi.reg_batch_solve([p.h for p in problems], o, [v.data_ptr() for v in outs], raise_on_error)
     return outs, [s.as_dict() for s in st]
+
+
+def write_step_log(log, records, context):
+    """Per-Newton-step records: appended to the file `log` as JSON lines ({**context, **record}), or
+    passed one by one to the callable `log`."""
+    import json
+    if callable(log):
+        for r in records:
+            log(dict(context, **r))
+        return
+    with open(log, "a") as fh:
+        for r in records:
+            fh.write(json.dumps(dict(context, **r)) + "\n")

@@ -121,12 +121,15 @@ class WarmStart:
         self.step = 0
         self._pred = {}
 
-    def train(self, feats, targets, epochs, batch=16, lr=1e-3, lr_final=5e-5, seed=0, log=None, augment=True):
+    def train(self, feats, targets, epochs, batch=16, lr=1e-3, lr_final=5e-5, seed=0, log=None, augment=True,
+              start_epoch=0, end_epoch=None):
         """Adam on the network loss (regnet.h) over shuffled batches; cosine learning-rate decay from
         lr to lr_final.  feats: [N][9][n][n], targets: [N][REG_FNO_OUT][n][n] (normalised velocities
         v / s, then the direction targets; float32, device).  With augment, every sample of a batch is mapped by a random one of the 8
-        symmetries of the periodic square grid (exact for the discrete problem).  Returns the mean
-        training loss of every epoch."""
+        symmetries of the periodic square grid (exact for the discrete problem).  Runs epochs
+        [start_epoch, end_epoch) of an `epochs`-long schedule (same shuffling and learning rates as
+        one uninterrupted run; resume from a checkpoint.save_training state).  Returns the mean
+        training loss of every epoch run."""
         torch = self.torch
         N, n = feats.shape[0], feats.shape[-1]
         if N < batch:
@@ -139,11 +142,17 @@ class WarmStart:
         losses = torch.zeros(steps_per_epoch, dtype=torch.float64, device=self.device)
         rng = np.random.Generator(np.random.PCG64(seed))
         history = []
-        done = 0
-        for ep in range(epochs):
-            order = torch.tensor(rng.permutation(N)[:steps_per_epoch * batch].astype(np.int32), device=self.device)
-            syms = torch.tensor(rng.integers(0, ffi.REG_FNO_SYMMETRIES, steps_per_epoch * batch).astype(np.int32),
-                                device=self.device) if augment else None
+        end_epoch = epochs if end_epoch is None else end_epoch
+        if not 0 <= start_epoch <= end_epoch <= epochs:
+            raise ValueError("need 0 <= start_epoch <= end_epoch <= epochs")
+        done = start_epoch * steps_per_epoch
+        for ep in range(end_epoch):
+            perm = rng.permutation(N)[:steps_per_epoch * batch].astype(np.int32)
+            sy = rng.integers(0, ffi.REG_FNO_SYMMETRIES, steps_per_epoch * batch).astype(np.int32) if augment else None
+            if ep < start_epoch:   # the draws of the epochs already run
+                continue
+            order = torch.tensor(perm, device=self.device)
+            syms = torch.tensor(sy, device=self.device) if augment else None
             for i in range(steps_per_epoch):
                 idx = order[i * batch:(i + 1) * batch]
                 sym = syms[i * batch:(i + 1) * batch] if augment else None

@@ -40,7 +40,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(R.RegParams) == 10 * 4 + 4 * 8
-    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(R.RegSolveOpts) == 4 * 4 + 3 * 8 + 3 * 8 + 2 * 4 + 8 + 8 + 8   # steps, max_steps (padded)
+    assert ctypes.sizeof(R.RegStepRecord) == 4 * 4 + 5 * 8
     assert ctypes.sizeof(R.RegSolveStats) == 8 * 4 + 4 * 8 + 2 * 4
 
 
@@ -158,3 +159,25 @@ def test_even_grids_that_are_not_powers_of_two_are_accepted():
     """The paper's 128 x 150 slice (and 96^2 = 2^5 3 squared) take the mixed-radix transforms."""
     for n1, n2 in ((128, 150), (96, 96), (150, 128)):
         assert R.reg_workspace_bytes(make_params(n1, n2, 4)) > 0
+
+
+def test_struct_offsets_match_header(tmp_path):
+    """Every field of the ctypes mirrors sits where a C compiler puts it (gcc on include/regnk.h)."""
+    structs = {"reg_params": R.RegParams, "reg_solve_opts": R.RegSolveOpts, "reg_solve_stats": R.RegSolveStats,
+               "reg_step_record": R.RegStepRecord}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "regnk.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "offsets.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "offsets"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)

@@ -15,7 +15,8 @@ import pytest
 
 from paper_1503_00757_amd.ffi import (REG_DIVFREE, REG_EDEVICE, REG_FP32_TRANSPORT, REG_FP64, REG_H1, REG_H2,
                                       REG_H3, REG_HESS_FULL, REG_HESS_GN, REG_MASS_SOURCE, REG_STOKES,
-                                      REG_UNCONSTRAINED, RegParams, RegSolveOpts, RegSolveStats)
+                                      REG_UNCONSTRAINED, RegParams, RegSolveOpts, RegSolveStats,
+                                      RegStepRecord)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 DEF_STATIC_MAX_POINTS = 65536
@@ -178,8 +179,12 @@ def run_all(L, p, solve=True):
         o.recycle = 1 if p.lowrank_capacity else 0
         st = RegSolveStats()
         vout = H.buf(2 * nn)
+        recs = (RegStepRecord * 3)()   # fewer records than steps: the first three are kept
+        o.steps, o.max_steps = C.cast(recs, C.POINTER(RegStepRecord)), 3
         H.check(L.reg_solve(H.h, C.byref(o), H.ptr(vout), C.byref(st)), ok=(0, -4, -5))
         assert st.newton_iters == 4   # the placeholder scalars let every line search succeed
+        assert [r.newton_iter for r in recs] == [0, 1, 2] and all(r.alpha > 0 and r.nt >= p.nt for r in recs)
+        o.steps, o.max_steps = None, 0
         if p.lowrank_capacity:
             assert st.lowrank_dim == p.lowrank_capacity
         o.fixed_pcg_iters = 3
