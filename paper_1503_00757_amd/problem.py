@@ -144,7 +144,7 @@ class Problem:
         v0c = self._c(v0) if v0 is not None else None
         Uc = self._c(precond_U) if precond_U is not None else None
         ritz = (ctypes.c_double * int(Uc.shape[0]))() if Uc is not None and Uc.shape[0] > 0 else None
-        steps = (ffi.RegStepRecord * max(1, max_newton + 1))() if log is not None else None
+        steps = (ffi.RegStepRecord * max(1, min(max_newton + 1, 4096)))() if log is not None else None
         opts = self.solve_opts(max_newton, max_pcg, fixed_pcg_iters, max_backtracks, gtol_rel, armijo_c1,
                                armijo_rho, v0c, Uc, recycle, ritz, cfl_max, steps)
         v = self.vec()
