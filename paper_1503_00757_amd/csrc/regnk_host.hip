@@ -718,10 +718,11 @@ hipGraphExec_t capture_graph(reg_problem* P, F enqueue) {
 }
 
 // (reg_hessian_matvec only: vt64 comes from the projection, which also wrote its T copy.)
-// The matvec is a fixed chain of ~12 n_t + 10 kernels whose arguments depend only on workspace
-// pointers, so it is captured once into a HIP graph (on a private stream) and replayed on the
-// problem's stream; this removes the host launch cost per pass.  Falls back to direct launches if
-// capture is unavailable.
+// The matvec is a fixed chain of 4 n_t + 1 kernels (four stage launches per time step, less the
+// pointwise first and the folded last one, and three assembly passes; power-of-two grids, GN, no
+// shear-control term) whose arguments depend only on workspace pointers, so it is captured once
+// into a HIP graph (on a private stream) and replayed on the problem's stream; this removes the
+// host launch cost per pass.  Falls back to direct launches if capture is unavailable.
 template <typename T>
 reg_status matvec_run(reg_problem* P, const double* vt64, double* out, double* kout) {
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
