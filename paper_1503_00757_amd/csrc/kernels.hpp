@@ -135,6 +135,17 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
 // 0 only) in one launch.
 hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
                                 const cpx<double>* tw2, hipStream_t s);
+// The same pass forming partial sums of <s, out_field> (field 0: out0, 1: out1; both components)
+// while it writes: partial[b] for the rows of block b, in a fixed order; *count receives the number
+// of partials (0 where the pass for this length does not form them: the caller then sums itself).
+struct RowDot {
+    const double* s;
+    int field;
+    double* partial;
+    int* count;
+};
+hipError_t launch_spec_row_inv2_dot(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
+                                    const cpx<double>* tw2, const RowDot& d, hipStream_t s);
 
 // Nyquist projection of a real vector field in real space (every mode with k1 = n1/2 or k2 = n2/2
 // removed): out_d (double, nullable), out_t (TO, nullable); `in` may equal out_d.  scratch: at
@@ -231,6 +242,10 @@ enum PcgSlot {
     NUM_PCG_SLOTS
 };
 enum PcgScalarMode { PCG_INIT = 0, PCG_KAPPA, PCG_MU };
+// Second level of `nk` sums of `count` partials each (partial[k * count + i]) and the PCG scalar step
+// `mode` (out = sc + slot), one block.
+hipError_t launch_finalize_scalar(int nk, int count, const double* partial, double* out, int mode, double* scal,
+                                  hipStream_t s);
 // launch_dots (FP64) followed by the PCG scalar step `mode`, the latter fused into the second level.
 hipError_t launch_dots_scalar(int nk, const double* const* a, const double* const* b, long n, double* partial,
                               double* out, int mode, double* scal, hipStream_t s);

@@ -159,6 +159,7 @@ Offsets layout(const reg_params* p) {
     o.rhs = L.take(2 * nn * 8);
     for (int i = 0; i < NPCG; ++i) o.pcg[i] = L.take(2 * nn * 8);
     o.spec = L.take(4 * (size_t)p->n1 * (p->n2 / 2) * 16);
+    static_assert(4 * RED_BLOCKS >= 2048, "partials: one per row of the largest grid (RowDot)");
     o.partial = L.take(4 * RED_BLOCKS * 8);
     o.scal = L.take(NSCAL * 8);
     o.clk = L.take((size_t)MAX_TIMED * 2 * clk_slots(p) * sizeof(unsigned long long));
@@ -467,8 +468,9 @@ reg_status spec_col(reg_problem* P, int mode, bool have_y, bool want2) {
 }
 
 // Both result fields of the last column pass (the second only with out1) in one launch.
-reg_status spec_inv2(reg_problem* P, double* out0, double* out1) {
-    CK(launch_spec_row_inv2(P->sp, P->spec(), out0, out1, P->at<cpx<double>>(P->o.tw2d), P->stream));
+reg_status spec_inv2(reg_problem* P, double* out0, double* out1, const RowDot* dot = nullptr) {
+    if (dot) CK(launch_spec_row_inv2_dot(P->sp, P->spec(), out0, out1, P->at<cpx<double>>(P->o.tw2d), *dot, P->stream));
+    else CK(launch_spec_row_inv2(P->sp, P->spec(), out0, out1, P->at<cpx<double>>(P->o.tw2d), P->stream));
     return REG_OK;
 }
 
@@ -653,8 +655,10 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
 
 // ---- GN Hessian matvec on a projected FP64 input ------------------------------------------------
 // converted: the caller already wrote vt64 in T to tv.vtT().
+// dot (nullable): the assembly's inverse row pass also forms the partial sums of <s, out> (RowDot).
 template <typename T>
-reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kout, bool converted = false) {
+reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kout, bool converted = false,
+                    const RowDot* dot = nullptr) {
     TV<T> tv{P};
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
     if (!converted) CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
@@ -673,7 +677,7 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     // both fields' row transforms in one launch, the last adjoint step's body force folded in
     CK(launch_spec_row_fwd_body<T>(P->sp, x0, tv.Bt(), bl, P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream));
     CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
-    CKS(spec_inv2(P, out, kout));
+    CKS(spec_inv2(P, out, kout, dot));
     P->matvec_done = true;
     return REG_OK;
 }
@@ -982,8 +986,13 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
     double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
     double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
     double* sc = P->scal();
-    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr, true));   // s in T: written with s
-    {
+    // <s, H s>_W: partial sums from the assembly's last pass where it forms them
+    int parts = 0;
+    const RowDot rd{s, W ? 1 : 0, P->partial(), &parts};
+    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr, true, &rd));   // s in T: written with s
+    if (parts > 0) {
+        CK(launch_finalize_scalar(1, parts, P->partial(), sc + S_SHS, PCG_KAPPA, sc, P->stream));
+    } else {
         const double* a[1] = {s};
         const double* b[1] = {W ? kst : st};
         CK(launch_dots_scalar(1, a, b, n, P->partial(), sc + S_SHS, PCG_KAPPA, sc, P->stream));

@@ -293,12 +293,13 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
 
 // ---------------------------------------------------------------------------------------------
 template <typename TO, int N, int FPW>
-// blockIdx.y = 1: the next field of spec (out_d1; no T copy)
+// blockIdx.y = 1: the next field of spec (out_d1; no T copy).  d.s != nullptr: the blocks of field
+// d.field also write partial sums of <d.s, out> (see RowDot).
 __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const cpx<double>* __restrict__ spec,
                                                                   double* __restrict__ out_d0,
                                                                   TO* __restrict__ out_t0,
                                                                   double* __restrict__ out_d1,
-                                                                  const cpx<double>* __restrict__ tw) {
+                                                                  const cpx<double>* __restrict__ tw, RowDot d) {
     constexpr int Q = N / 4, H = N / 2;
     constexpr int L = LdsSize<N>::value;
     __shared__ cpx<double> lds[FPW][L];   // one buffer per transform: more resident blocks
@@ -329,9 +330,22 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
     }
     int buf = 0;
     fft4<double, N, true, true>(x, lds[f], lds[f], t, tw, buf);
-    if (!valid) return;
     const long nn = (long)n1 * N;
     const long row = (long)i1 * N;
+    if (d.s && field == d.field) {   // uniform over the block
+        __shared__ double dsh[FPW * N / 4 / 64];
+        double acc = 0.0;
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = t + r * Q;
+                acc += d.s[row + e] * x[r].x + d.s[nn + row + e] * x[r].y;
+            }
+        }
+        const double tot = block_sum<FPW * N / 4>(acc, dsh);
+        if (threadIdx.x == 0) d.partial[blockIdx.x] = tot;
+    }
+    if (!valid) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int e = t + r * Q;
@@ -730,13 +744,16 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
 // field 0 of spec at `spec` -> out_d / out_t; with out_d1, field 1 -> out_d1 in the same launch
 template <typename TO>
 static hipError_t row_inv_fields(const SpecParams& p, const cpx<double>* spec, double* out_d, TO* out_t,
-                                 double* out_d1, const cpx<double>* tw2, hipStream_t s) {
+                                 double* out_d1, const cpx<double>* tw2, hipStream_t s, const RowDot& d = RowDot{}) {
     const int nf = out_d1 ? 2 : 1;
+    if (d.count) *d.count = 0;
 #define ROWI(NN)                                                                                       \
     case NN: {                                                                                         \
         constexpr int FPW = spec_fpw<NN>();                                                            \
-        hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3((p.n1 + FPW - 1) / FPW, nf),      \
-                           dim3(FPW * NN / 4), 0, s, p.n1, spec, out_d, out_t, out_d1, tw2);           \
+        const int nb = (p.n1 + FPW - 1) / FPW;                                                         \
+        hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3(nb, nf), dim3(FPW * NN / 4), 0, s, \
+                           p.n1, spec, out_d, out_t, out_d1, tw2, d);                                  \
+        if (d.s && d.count) *d.count = nb;                                                             \
         break;                                                                                         \
     }
     if (!pow2(p.n2) && p.mr2.ns > 0) {
@@ -762,6 +779,12 @@ static hipError_t row_inv_fields(const SpecParams& p, const cpx<double>* spec, d
 hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
                                 const cpx<double>* tw2, hipStream_t s) {
     return row_inv_fields<double>(p, spec, out0, (double*)nullptr, out1, tw2, s);
+}
+
+hipError_t launch_spec_row_inv2_dot(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
+                                    const cpx<double>* tw2, const RowDot& d, hipStream_t s) {
+    if (!d.s || !d.partial || !d.count || d.field < 0 || d.field > (out1 ? 1 : 0)) return hipErrorInvalidValue;
+    return row_inv_fields<double>(p, spec, out0, (double*)nullptr, out1, tw2, s, d);
 }
 
 // ---------------------------------------------------------------------------------------------

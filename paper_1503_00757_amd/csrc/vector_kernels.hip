@@ -172,12 +172,13 @@ __device__ __forceinline__ void pcg_scalar_step(int mode, double* sc) {
 // finalize_kernel), then the PCG scalar step of `mode`: one launch instead of two.  `out` points into
 // `sc` (out = sc + slot), and the scalar step reads the sums just stored through `out`, so neither
 // pointer is declared non-aliasing.
-__global__ __launch_bounds__(RED_THREADS) void finalize_scalar_kernel(int nk, const double* __restrict__ partial,
+__global__ __launch_bounds__(RED_THREADS) void finalize_scalar_kernel(int nk, int count,
+                                                                      const double* __restrict__ partial,
                                                                       double* out, int mode, double* sc) {
     __shared__ double sh[RED_THREADS / 64];
     for (int k = 0; k < nk; ++k) {
         double acc = 0.0;
-        for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partial[k * RED_BLOCKS + i];
+        for (int i = threadIdx.x; i < count; i += RED_THREADS) acc += partial[(long)k * count + i];
         const double t = block_sum<RED_THREADS>(acc, sh);
         if (threadIdx.x == 0) out[k] = t;
     }
@@ -214,7 +215,15 @@ hipError_t launch_dots_scalar(int nk, const double* const* a, const double* cons
         p.b[k] = b[k];
     }
     hipLaunchKernelGGL((dots_kernel<double>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, nk, p, n, partial);
-    hipLaunchKernelGGL(finalize_scalar_kernel, dim3(1), dim3(RED_THREADS), 0, s, nk, partial, out, mode, scal);
+    hipLaunchKernelGGL(finalize_scalar_kernel, dim3(1), dim3(RED_THREADS), 0, s, nk, RED_BLOCKS, partial, out, mode,
+                       scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_scalar(int nk, int count, const double* partial, double* out, int mode, double* scal,
+                                  hipStream_t s) {
+    if (nk < 1 || count < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finalize_scalar_kernel, dim3(1), dim3(RED_THREADS), 0, s, nk, count, partial, out, mode, scal);
     return hipGetLastError();
 }
 

@@ -195,6 +195,20 @@ hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, do
     return done(spec_ok(p, spec, out1 ? 4 : 2, "spec_row_inv spec") && chk(out0, n2f, "spec_row_inv out0") &&
                 chk(out1, n2f, "spec_row_inv out1") && chk(tw2, (size_t)p.n2, "spec_row_inv tw2"));
 }
+// one partial per row at most (the real pass writes one per block of rows, only for power-of-two n2)
+hipError_t launch_spec_row_inv2_dot(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
+                                    const cpx<double>* tw2, const RowDot& d, hipStream_t s) {
+    const size_t n2f = 2 * (size_t)p.n1 * p.n2;
+    if (!d.s || !d.partial || !d.count || d.field < 0 || d.field > (out1 ? 1 : 0)) {
+        mock_fail("spec_row_inv dot: bad arguments");
+        return done(false);
+    }
+    const bool p2 = (p.n2 & (p.n2 - 1)) == 0;
+    *d.count = p2 ? p.n1 : 0;
+    if (!(chk(d.s, n2f, "spec_row_inv dot s") && chk(d.partial, (size_t)*d.count, "spec_row_inv dot partial")))
+        return done(false);
+    return launch_spec_row_inv2(p, spec, out0, out1, tw2, s);
+}
 
 size_t nyquist_scratch_doubles(int n1, int n2) {   // the real launcher's formula (32 x 64 tiles)
     const size_t ncb = (n2 + 63) / 64, nrb = (n1 + 31) / 32;
@@ -211,6 +225,24 @@ template hipError_t launch_nyquist_project<float>(int, int, const double*, doubl
 template hipError_t launch_nyquist_project<double>(int, int, const double*, double*, double*, double*, hipStream_t);
 
 // ---- reductions and vector updates ----
+hipError_t launch_finalize_scalar(int nk, int count, const double* partial, double* out, int mode, double* scal,
+                                  hipStream_t) {
+    bool ok = nk >= 1 && count >= 1 && mode >= PCG_INIT && mode <= PCG_MU;
+    if (!ok) mock_fail("finalize_scalar: bad counts or mode");
+    ok = ok && chk(partial, (size_t)nk * count, "finalize_scalar partial") && chk(out, (size_t)nk, "finalize_scalar out") &&
+         chk(scal, (size_t)NUM_PCG_SLOTS, "finalize_scalar scalars");
+    if (ok) {   // the placeholders of launch_dots_scalar
+        for (int k = 0; k < nk; ++k) out[k] = 1.0;
+        if (mode == PCG_INIT) {
+            scal[S_ACTIVE] = 1.0;
+            scal[S_ITER] = 0.0;
+            scal[S_BREAK] = 0.0;
+        } else if (mode == PCG_KAPPA) {
+            scal[S_ITER] += 1.0;
+        }
+    }
+    return done(ok);
+}
 template <typename TI>
 hipError_t launch_dots(int nk, const TI* const* a, const TI* const* b, long n, double* partial, double* out,
                        hipStream_t) {
