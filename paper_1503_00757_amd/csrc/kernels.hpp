@@ -89,7 +89,14 @@ hipError_t launch_body_last(long nn, T w, bool first, const T* Q, const T* C, co
 // ---- 2D spectral operators (FP64) -----------------------------------------------------------
 // SPEC_LR: first result = admissible part of x (Leray projection for w = 0, x otherwise), second
 // result = K^{-1} P^ of that part (the preconditioner operator, weighted for <., .>_W).
-enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG, SPEC_LR };
+// SPEC_HESS_P: SPEC_HESS and the preconditioner (beta_v A)^{-1} of its result, for the PCG
+// recurrence of P^{-1} r: with want2 fields 0..2 = H x, K^{-1} H x, P^{-1} H x (spec holds 6 half
+// spectra), without it fields 0, 1 = H x, P^{-1} H x.  Column lengths 64..512 only
+// (spec_col_hess_p_ok).
+enum SpecMode { SPEC_PROJ = 0, SPEC_HESS, SPEC_PREC, SPEC_REG, SPEC_LR, SPEC_HESS_P };
+inline bool spec_col_hess_p_ok(int n1, int n2) {
+    return (n1 & (n1 - 1)) == 0 && n1 >= 64 && n1 <= 512 && (n2 & (n2 - 1)) == 0;
+}
 
 struct SpecParams {
     int n1, n2;
@@ -145,6 +152,10 @@ struct RowDot {
     int* count;
 };
 hipError_t launch_spec_row_inv2_dot(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
+                                    const cpx<double>* tw2, const RowDot& d, hipStream_t s);
+// The inverse row pass of fields 0..nf-1 (nf <= 4) into out[0..nf-1] in one launch (power-of-two n2),
+// with the partial sums of `d`.
+hipError_t launch_spec_row_inv4_dot(const SpecParams& p, const cpx<double>* spec, double* const* out, int nf,
                                     const cpx<double>* tw2, const RowDot& d, hipStream_t s);
 
 // Nyquist projection of a real vector field in real space (every mode with k1 = n1/2 or k2 = n2/2
@@ -252,6 +263,12 @@ hipError_t launch_dots_scalar(int nk, const double* const* a, const double* cons
 // x += kappa s, r -= kappa s~ (kappa from scal)
 hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
                              hipStream_t stream);
+// The same, and while the iteration is active z -= kappa pst (pst = P^{-1} s~: the preconditioned
+// residual by recurrence) and kr -= kappa kst (kst = K^{-1} s~: the weighted residual; kr, kst
+// nullable).
+hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
+                               const double* pst, double* kr, const double* kst, const double* scal,
+                               hipStream_t stream);
 // s = z + mu s (scal == nullptr: s = z) and its copy sT = (T) s for the next matvec
 template <typename T>
 hipError_t launch_pcg_dir_copy(long n, double* s, T* sT, const double* z, const double* scal, hipStream_t stream);

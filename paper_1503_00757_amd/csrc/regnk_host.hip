@@ -45,7 +45,7 @@ namespace {
 
 constexpr int NFIELD = 9;    // scalar scratch fields in transport precision
 constexpr int NSFIELD = 8;   // FP64 state-solve scratch fields
-constexpr int NPCG = 7;      // x, r, z, kr, s, st, kst
+constexpr int NPCG = 8;      // x, r, z, kr, s, st, kst, P^{-1} st
 constexpr int NSCAL = 32;
 constexpr int MAX_TIMED = 512;   // timed stage launches per reg_time_pass call
 // shear-control model, FP64 fields: partials dv (4), stress (3), stress gradients (6), E (3) and eta (1)
@@ -158,7 +158,7 @@ Offsets layout(const reg_params* p) {
     o.vtry = L.take(2 * nn * 8);
     o.rhs = L.take(2 * nn * 8);
     for (int i = 0; i < NPCG; ++i) o.pcg[i] = L.take(2 * nn * 8);
-    o.spec = L.take(4 * (size_t)p->n1 * (p->n2 / 2) * 16);
+    o.spec = L.take(6 * (size_t)p->n1 * (p->n2 / 2) * 16);   // 6 half spectra (SPEC_HESS_P)
     static_assert(4 * RED_BLOCKS >= 2048, "partials: one per row of the largest grid (RowDot)");
     o.partial = L.take(4 * RED_BLOCKS * 8);
     o.scal = L.take(NSCAL * 8);
@@ -656,9 +656,10 @@ reg_status gradient_t(reg_problem* P, const double* v, double* g, double* kg, do
 // ---- GN Hessian matvec on a projected FP64 input ------------------------------------------------
 // converted: the caller already wrote vt64 in T to tv.vtT().
 // dot (nullable): the assembly's inverse row pass also forms the partial sums of <s, out> (RowDot).
+// pout (nullable; spec_col_hess_p_ok grids): also P^{-1} out (SPEC_HESS_P).
 template <typename T>
 reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kout, bool converted = false,
-                    const RowDot* dot = nullptr) {
+                    const RowDot* dot = nullptr, double* pout = nullptr) {
     TV<T> tv{P};
     if (!P->linearized) return fail(REG_ESTATE, "no linearisation point: call reg_gradient first");
     if (!converted) CK(launch_convert<T>(2 * P->nn, vt64, tv.vtT(), P->stream));
@@ -676,8 +677,21 @@ reg_status matvec_t(reg_problem* P, const double* vt64, double* out, double* kou
     }
     // both fields' row transforms in one launch, the last adjoint step's body force folded in
     CK(launch_spec_row_fwd_body<T>(P->sp, x0, tv.Bt(), bl, P->spec(), P->at<cpx<double>>(P->o.tw2d), P->stream));
-    CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
-    CKS(spec_inv2(P, out, kout, dot));
+    if (pout) {
+        CKS(spec_col(P, SPEC_HESS_P, true, kout != nullptr));
+        double* outs[4] = {out, pout, nullptr, nullptr};   // fields: H s, P^{-1} H s
+        int nf = 2;
+        if (kout) {   // H s, K^{-1} H s, P^{-1} H s
+            outs[1] = kout;
+            outs[2] = pout;
+            nf = 3;
+        }
+        CK(launch_spec_row_inv4_dot(P->sp, P->spec(), outs, nf, P->at<cpx<double>>(P->o.tw2d),
+                                    dot ? *dot : RowDot{}, P->stream));
+    } else {
+        CKS(spec_col(P, SPEC_HESS, true, kout != nullptr));
+        CKS(spec_inv2(P, out, kout, dot));
+    }
     P->matvec_done = true;
     return REG_OK;
 }
@@ -975,7 +989,7 @@ reg_status ritz_t(reg_problem* P, double* U, int rank, int iters, double* theta)
 }
 
 // ---- PCG (Alg. 2) -----------------------------------------------------------------------------
-enum { PX = 0, PR, PZ, PKR, PS, PST, PKST };
+enum { PX = 0, PR, PZ, PKR, PS, PST, PKST, PPST };
 
 // One PCG iteration with device-side scalars: s~ = H s, kappa, x and r updates, z = P^{-1} r,
 // the new <r, z>_W and ||r||^2, mu, s = z + mu s.  No host synchronisation inside.
@@ -986,10 +1000,14 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
     double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
     double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
     double* sc = P->scal();
+    // the preconditioned residual by recurrence, z -= kappa P^{-1} H s, with P^{-1} H s formed by the
+    // assembly's column pass (the corrected preconditioner of the low-rank extension is applied to r)
+    const bool rec = !P->lr_active && spec_col_hess_p_ok(P->n1, P->n2);
+    double* pst = P->pcg(PPST);
     // <s, H s>_W: partial sums from the assembly's last pass where it forms them
     int parts = 0;
     const RowDot rd{s, W ? 1 : 0, P->partial(), &parts};
-    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr, true, &rd));   // s in T: written with s
+    CKS(matvec_t<T>(P, s, st, W ? kst : nullptr, true, &rd, rec ? pst : nullptr));
     if (parts > 0) {
         CK(launch_finalize_scalar(1, parts, P->partial(), sc + S_SHS, PCG_KAPPA, sc, P->stream));
     } else {
@@ -997,8 +1015,13 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
         const double* b[1] = {W ? kst : st};
         CK(launch_dots_scalar(1, a, b, n, P->partial(), sc + S_SHS, PCG_KAPPA, sc, P->stream));
     }
-    CK(launch_pcg_update(n, x, r, s, st, sc, P->stream));
-    CKS(precond_pcg(P, r, z, W ? kr : nullptr));
+    if (rec) {
+        // kr = K^{-1} r (the weighted residual of <., .>_W) follows r with K^{-1} H s
+        CK(launch_pcg_update_z(n, x, r, s, st, z, pst, W ? kr : nullptr, W ? kst : nullptr, sc, P->stream));
+    } else {
+        CK(launch_pcg_update(n, x, r, s, st, sc, P->stream));
+        CKS(precond_pcg(P, r, z, W ? kr : nullptr));
+    }
     {
         const double* a[2] = {r, W ? kr : r};
         const double* b[2] = {r, z};

@@ -171,6 +171,15 @@ __device__ __forceinline__ void spec_multiplier(const SpecParams& p, int mode, d
     }
 }
 
+// 1 / P^ at (k1, k2) (App. E.2; SPEC_PREC's scale): 1 / (beta_v A^), or 1 / beta_v where A^ = 0; the
+// vector Laplacian's symbol for the shear-control model.
+__device__ __forceinline__ double prec_inv(const SpecParams& p, double k1, double k2d) {
+    const double kk = k1 * k1 + k2d * k2d;
+    const double A = (p.norm == 1) ? kk : (p.norm == 2 ? kk * kk : (p.norm == 3 ? kk * kk * kk : 0.0));
+    const double Ap = p.norm == 4 ? kk : A;
+    return 1.0 / (p.beta_v * (Ap > 0.0 ? Ap : 1.0));
+}
+
 template <int N, int NF>
 __global__ __launch_bounds__(NF * N / 4) void spec_col_kernel(SpecParams p, int mode, int have_y, int want2,
                                                               cpx<double>* __restrict__ spec,
@@ -267,39 +276,72 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
 #pragma unroll
     for (int r = 0; r < 4; ++r) lds[c][b][lpad(t + r * Q)] = x[r];
     __syncthreads();
+    const bool hp = mode == SPEC_HESS_P;
+    cpx<double> r2[4] = {};   // SPEC_HESS_P with want2: the second round's values of this thread's wavenumber
     {
         const int e = threadIdx.x;   // one wavenumber per thread
         const double k1 = (double)kwave<N>(e);
         cpx<double> o0, o1, q0, q1;
-        spec_multiplier(p, mode, k1, (double)k2, lds[0][b][lpad(e)], lds[1][b][lpad(e)], lds[2][b][lpad(e)],
-                        lds[3][b][lpad(e)], o0, o1, q0, q1, eb);
+        spec_multiplier(p, hp ? SPEC_HESS : mode, k1, (double)k2, lds[0][b][lpad(e)], lds[1][b][lpad(e)],
+                        lds[2][b][lpad(e)], lds[3][b][lpad(e)], o0, o1, q0, q1, eb);
         const double sc = (e == N / 2) ? 0.0 : 1.0 / ((double)N * (double)p.n2);   // Nyquist row projected out
+        if (hp) {   // P^{-1} H x: into the second field, or with want2 into the third (second round)
+            const double pi = prec_inv(p, k1, (double)k2);
+            const cpx<double> p0 = {pi * o0.x, pi * o0.y}, p1 = {pi * o1.x, pi * o1.y};
+            if (want2) {
+                r2[0] = p0;
+                r2[1] = p1;
+            } else {
+                q0 = p0;
+                q1 = p1;
+            }
+        }
         __syncthreads();
         lds[0][b][lpad(e)] = {o0.x * sc, o0.y * sc};
         lds[1][b][lpad(e)] = {o1.x * sc, o1.y * sc};
         lds[2][b][lpad(e)] = {q0.x * sc, q0.y * sc};
         lds[3][b][lpad(e)] = {q1.x * sc, q1.y * sc};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r2[k] = {r2[k].x * sc, r2[k].y * sc};
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) x[r] = lds[c][b][lpad(t + r * Q)];
     buf = b ^ 1;   // the inverse's first exchange must not overwrite the buffer just read
     fft4<double, N, true>(x, lds[c][0], lds[c][1], t, tw, buf);
-    if (c < 2 || want2) {
+    if (c < 2 || want2 || hp) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) spec[c * hn + (long)(t + r * Q) * H + k2] = x[r];
+    }
+    if (hp && want2) {   // second round: field 2 (half spectra 4, 5; groups 2 and 3 only join the exchanges)
+        const int b2 = buf ^ 1;   // not the buffer the inverse's last exchange may still be read from
+        __syncthreads();
+        const int e = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lds[k][b2][lpad(e)] = r2[k];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = lds[c][b2][lpad(t + r * Q)];
+        buf = b2 ^ 1;
+        fft4<double, N, true>(x, lds[c][0], lds[c][1], t, tw, buf);
+        if (c < 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) spec[(4 + c) * hn + (long)(t + r * Q) * H + k2] = x[r];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------------------------
 template <typename TO, int N, int FPW>
-// blockIdx.y = 1: the next field of spec (out_d1; no T copy).  d.s != nullptr: the blocks of field
-// d.field also write partial sums of <d.s, out> (see RowDot).
+// blockIdx.y = f > 0: field f of spec into out_d1..3 (no T copy).  d.s != nullptr: the blocks of
+// field d.field also write partial sums of <d.s, out> (see RowDot).
 __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const cpx<double>* __restrict__ spec,
                                                                   double* __restrict__ out_d0,
                                                                   TO* __restrict__ out_t0,
                                                                   double* __restrict__ out_d1,
-                                                                  const cpx<double>* __restrict__ tw, RowDot d) {
+                                                                  const cpx<double>* __restrict__ tw, RowDot d,
+                                                                  double* __restrict__ out_d2,
+                                                                  double* __restrict__ out_d3) {
     constexpr int Q = N / 4, H = N / 2;
     constexpr int L = LdsSize<N>::value;
     __shared__ cpx<double> lds[FPW][L];   // one buffer per transform: more resident blocks
@@ -308,7 +350,7 @@ __global__ __launch_bounds__(FPW * N / 4) void spec_row_inv_kernel(int n1, const
     const bool valid = i1 < n1;
     const long hn = (long)n1 * H;
     const int field = blockIdx.y;
-    double* out_d = field ? out_d1 : out_d0;
+    double* out_d = field == 0 ? out_d0 : (field == 1 ? out_d1 : (field == 2 ? out_d2 : out_d3));
     TO* out_t = field ? nullptr : out_t0;
     const cpx<double>* s0 = spec + (long)(2 * field) * hn + (long)(valid ? i1 : 0) * H;
     const cpx<double>* s1 = s0 + hn;
@@ -706,6 +748,7 @@ hipError_t launch_spec_row_fwd_body(const SpecParams& p, const double* in0, T* B
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
                            const cpx<double>* tw1, hipStream_t s) {
     const int H = p.n2 / 2;
+    if (mode == SPEC_HESS_P && !spec_col_hess_p_ok(p.n1, p.n2)) return hipErrorInvalidValue;   // four-spectra kernel only
 #define COLF(NN)                                                                                       \
     case NN: {                                                                                         \
         constexpr int NF = spec_nf<NN>();                                                              \
@@ -742,17 +785,20 @@ hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want
 }
 
 // field 0 of spec at `spec` -> out_d / out_t; with out_d1, field 1 -> out_d1 in the same launch
+// out_d2 / out_d3 (fields 2, 3: power-of-two n2 only) with out_d1
 template <typename TO>
 static hipError_t row_inv_fields(const SpecParams& p, const cpx<double>* spec, double* out_d, TO* out_t,
-                                 double* out_d1, const cpx<double>* tw2, hipStream_t s, const RowDot& d = RowDot{}) {
-    const int nf = out_d1 ? 2 : 1;
+                                 double* out_d1, const cpx<double>* tw2, hipStream_t s, const RowDot& d = RowDot{},
+                                 double* out_d2 = nullptr, double* out_d3 = nullptr) {
+    const int nf = out_d3 ? 4 : (out_d2 ? 3 : (out_d1 ? 2 : 1));
     if (d.count) *d.count = 0;
+    if (out_d2 && !pow2(p.n2)) return hipErrorInvalidValue;
 #define ROWI(NN)                                                                                       \
     case NN: {                                                                                         \
         constexpr int FPW = spec_fpw<NN>();                                                            \
         const int nb = (p.n1 + FPW - 1) / FPW;                                                         \
         hipLaunchKernelGGL((spec_row_inv_kernel<TO, NN, FPW>), dim3(nb, nf), dim3(FPW * NN / 4), 0, s, \
-                           p.n1, spec, out_d, out_t, out_d1, tw2, d);                                  \
+                           p.n1, spec, out_d, out_t, out_d1, tw2, d, out_d2, out_d3);                  \
         if (d.s && d.count) *d.count = nb;                                                             \
         break;                                                                                         \
     }
@@ -785,6 +831,16 @@ hipError_t launch_spec_row_inv2_dot(const SpecParams& p, const cpx<double>* spec
                                     const cpx<double>* tw2, const RowDot& d, hipStream_t s) {
     if (!d.s || !d.partial || !d.count || d.field < 0 || d.field > (out1 ? 1 : 0)) return hipErrorInvalidValue;
     return row_inv_fields<double>(p, spec, out0, (double*)nullptr, out1, tw2, s, d);
+}
+
+hipError_t launch_spec_row_inv4_dot(const SpecParams& p, const cpx<double>* spec, double* const* out, int nf,
+                                    const cpx<double>* tw2, const RowDot& d, hipStream_t s) {
+    if (nf < 1 || nf > 4) return hipErrorInvalidValue;
+    if (d.s && (!d.partial || !d.count || d.field < 0 || d.field >= nf)) return hipErrorInvalidValue;
+    for (int f = 0; f < nf; ++f)
+        if (!out[f]) return hipErrorInvalidValue;
+    return row_inv_fields<double>(p, spec, out[0], (double*)nullptr, nf > 1 ? out[1] : nullptr, tw2, s, d,
+                                  nf > 2 ? out[2] : nullptr, nf > 3 ? out[3] : nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -195,6 +195,22 @@ __global__ void pcg_update_kernel(long n, double* __restrict__ x, double* __rest
     }
 }
 
+__global__ void pcg_update_z_kernel(long n, double* __restrict__ x, double* __restrict__ r,
+                                    const double* __restrict__ s, const double* __restrict__ st,
+                                    double* __restrict__ z, const double* __restrict__ pst, double* __restrict__ kr,
+                                    const double* __restrict__ kst, const double* __restrict__ sc) {
+    const double kappa = sc[S_KAPPA];
+    const bool upd = sc[S_ACTIVE] != 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        x[i] += kappa * s[i];
+        if (upd) {
+            r[i] -= kappa * st[i];
+            z[i] -= kappa * pst[i];
+            if (kr) kr[i] -= kappa * kst[i];
+        }
+    }
+}
+
 template <typename T>
 __global__ void pcg_dir_copy_kernel(long n, double* __restrict__ s, T* __restrict__ sT, const double* __restrict__ z,
                                     const double* __restrict__ sc) {
@@ -230,6 +246,13 @@ hipError_t launch_finalize_scalar(int nk, int count, const double* partial, doub
 hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
                              hipStream_t stream) {
     hipLaunchKernelGGL(pcg_update_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, x, r, s, st, scal);
+    return hipGetLastError();
+}
+hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
+                               const double* pst, double* kr, const double* kst, const double* scal,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(pcg_update_z_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, x, r, s, st, z, pst, kr, kst,
+                       scal);
     return hipGetLastError();
 }
 template <typename T>

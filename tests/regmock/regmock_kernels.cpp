@@ -184,10 +184,25 @@ template hipError_t launch_spec_row_fwd_body<double>(const SpecParams&, const do
                                                      hipStream_t);
 hipError_t launch_spec_col(const SpecParams& p, int mode, bool have_y, bool want2, cpx<double>* spec,
                            const cpx<double>* tw1, hipStream_t) {
-    const bool mode_ok = mode >= SPEC_PROJ && mode <= SPEC_LR;
-    if (!mode_ok) mock_fail("spec_col: bad mode");
-    return done(mode_ok && spec_ok(p, spec, (have_y || want2) ? 4 : 2, "spec_col spec") &&
-                chk(tw1, (size_t)p.n1, "spec_col tw1") && chk(p.eta_sum, 1, "spec eta_sum"));
+    bool mode_ok = mode >= SPEC_PROJ && mode <= SPEC_HESS_P;
+    if (mode == SPEC_HESS_P) mode_ok &= spec_col_hess_p_ok(p.n1, p.n2);
+    if (!mode_ok) mock_fail("spec_col: bad mode (or SPEC_HESS_P on a grid without the four-spectra kernel)");
+    const int slots = (mode == SPEC_HESS_P && want2) ? 6 : ((have_y || want2) ? 4 : 2);
+    return done(mode_ok && spec_ok(p, spec, slots, "spec_col spec") && chk(tw1, (size_t)p.n1, "spec_col tw1") &&
+                chk(p.eta_sum, 1, "spec eta_sum"));
+}
+hipError_t launch_spec_row_inv4_dot(const SpecParams& p, const cpx<double>* spec, double* const* out, int nf,
+                                    const cpx<double>* tw2, const RowDot& d, hipStream_t) {
+    const size_t n2f = 2 * (size_t)p.n1 * p.n2;
+    const bool p2 = (p.n2 & (p.n2 - 1)) == 0;
+    bool ok = nf >= 1 && nf <= 4 && p2 && (!d.s || (d.partial && d.count && d.field >= 0 && d.field < nf));
+    if (!ok) mock_fail("spec_row_inv4: bad field count, grid or dot");
+    for (int f = 0; ok && f < nf; ++f) ok &= out[f] != nullptr && chk(out[f], n2f, "spec_row_inv4 out");
+    if (ok && d.s) {
+        *d.count = p.n1;
+        ok &= chk(d.s, n2f, "spec_row_inv4 dot s") && chk(d.partial, (size_t)p.n1, "spec_row_inv4 dot partial");
+    }
+    return done(ok && spec_ok(p, spec, 2 * nf, "spec_row_inv4 spec") && chk(tw2, (size_t)p.n2, "spec_row_inv4 tw2"));
 }
 hipError_t launch_spec_row_inv2(const SpecParams& p, const cpx<double>* spec, double* out0, double* out1,
                                 const cpx<double>* tw2, hipStream_t) {
@@ -370,6 +385,15 @@ hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, cons
                              hipStream_t) {
     return done(chk(x, n, "pcg_update x") && chk(r, n, "pcg_update r") && chk(s, n, "pcg_update s") &&
                 chk(st, n, "pcg_update st") && chk(scal, NUM_PCG_SLOTS, "pcg_update scal"));
+}
+hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
+                               const double* pst, double* kr, const double* kst, const double* scal, hipStream_t) {
+    const bool ok_k = (kr == nullptr) == (kst == nullptr);
+    if (!ok_k) mock_fail("pcg_update_z: kr and kst must come together");
+    return done(ok_k && chk(x, n, "pcg_update_z x") && chk(r, n, "pcg_update_z r") && chk(s, n, "pcg_update_z s") &&
+                chk(st, n, "pcg_update_z st") && chk(z, n, "pcg_update_z z") && chk(pst, n, "pcg_update_z pst") &&
+                chk(kr, n, "pcg_update_z kr") && chk(kst, n, "pcg_update_z kst") &&
+                chk(scal, NUM_PCG_SLOTS, "pcg_update_z scal"));
 }
 template <typename T>
 hipError_t launch_pcg_dir_copy(long n, double* s, T* sT, const double* z, const double* scal, hipStream_t) {
