@@ -211,6 +211,7 @@ struct reg_problem {
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t pcg_iter_graph = nullptr;   // one PCG iteration (matvec + scalar updates)
     hipGraphExec_t pcg_iter_graph_lr = nullptr;   // the same with the low-rank correction
+    hipGraphExec_t pcg_iter_graph_ex = nullptr;   // the iteration that forms z = P^{-1} r afresh
     bool lr_active = false;   // PCG applies the low-rank correction (inside reg_solve only)
     int lr_count = 0;         // valid directions (host copy of the device count)
     // measurement hook: hipEvents around every launch of one stage op during real matvecs
@@ -706,6 +707,8 @@ void drop_graphs(reg_problem* P) {
     P->pcg_iter_graph = nullptr;
     if (P->pcg_iter_graph_lr) (void)hipGraphExecDestroy(P->pcg_iter_graph_lr);
     P->pcg_iter_graph_lr = nullptr;
+    if (P->pcg_iter_graph_ex) (void)hipGraphExecDestroy(P->pcg_iter_graph_ex);
+    P->pcg_iter_graph_ex = nullptr;
     for (auto& g : P->lr_graph) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
@@ -991,18 +994,25 @@ reg_status ritz_t(reg_problem* P, double* U, int rank, int iters, double* theta)
 // ---- PCG (Alg. 2) -----------------------------------------------------------------------------
 enum { PX = 0, PR, PZ, PKR, PS, PST, PKST, PPST };
 
+// Every PCG_Z_REFRESH-th iteration forms z = P^{-1} r (and K^{-1} r) from r itself; the others
+// update them by recurrence.  The recurrence carries rounding of the size of the largest z seen so
+// far; once ||z|| has fallen by about the unit roundoff, <r, z>_W is that rounding and the iteration
+// breaks down.  Replacing z every few iterations bounds the drift by the decrease over that many
+// iterations (a factor 10 per iteration at most over 8 still leaves eight digits).
+constexpr int PCG_Z_REFRESH = 8;
+
 // One PCG iteration with device-side scalars: s~ = H s, kappa, x and r updates, z = P^{-1} r,
-// the new <r, z>_W and ||r||^2, mu, s = z + mu s.  No host synchronisation inside.
+// the new <r, z>_W and ||r||^2, mu, s = z + mu s.  No host synchronisation inside.  rec: the
+// preconditioned residual by recurrence, z -= kappa P^{-1} H s, with P^{-1} H s formed by the
+// assembly's column pass (the caller checks that the grid has that pass and the low-rank extension,
+// whose corrected preconditioner is applied to r, is off).
 template <typename T>
-reg_status pcg_iter_enqueue(reg_problem* P) {
+reg_status pcg_iter_enqueue(reg_problem* P, bool rec) {
     const long n = 2 * P->nn;
     const bool W = P->p.constraint == REG_MASS_SOURCE;
     double *x = P->pcg(PX), *r = P->pcg(PR), *z = P->pcg(PZ), *kr = P->pcg(PKR);
     double *s = P->pcg(PS), *st = P->pcg(PST), *kst = P->pcg(PKST);
     double* sc = P->scal();
-    // the preconditioned residual by recurrence, z -= kappa P^{-1} H s, with P^{-1} H s formed by the
-    // assembly's column pass (the corrected preconditioner of the low-rank extension is applied to r)
-    const bool rec = !P->lr_active && spec_col_hess_p_ok(P->n1, P->n2);
     double* pst = P->pcg(PPST);
     // <s, H s>_W: partial sums from the assembly's last pass where it forms them
     int parts = 0;
@@ -1031,11 +1041,16 @@ reg_status pcg_iter_enqueue(reg_problem* P) {
     return REG_OK;
 }
 
+// Iteration l (from 0) of a PCG solve.
 template <typename T>
-reg_status pcg_iter_run(reg_problem* P) {
-    hipGraphExec_t& graph = P->lr_active ? P->pcg_iter_graph_lr : P->pcg_iter_graph;
+reg_status pcg_iter_run(reg_problem* P, int l) {
+    const bool can_rec = !P->lr_active && spec_col_hess_p_ok(P->n1, P->n2);
+    const bool rec = can_rec && (l + 1) % PCG_Z_REFRESH != 0;
+    hipGraphExec_t& graph = P->lr_active          ? P->pcg_iter_graph_lr
+                            : (can_rec && !rec) ? P->pcg_iter_graph_ex
+                                                : P->pcg_iter_graph;
     if (P->use_graphs && !graph) {
-        graph = capture_graph(P, [&]() { return pcg_iter_enqueue<T>(P); });
+        graph = capture_graph(P, [&]() { return pcg_iter_enqueue<T>(P, rec); });
         if (!graph) P->use_graphs = false;
     }
     if (graph) {
@@ -1043,7 +1058,7 @@ reg_status pcg_iter_run(reg_problem* P) {
         P->matvec_done = true;
         return REG_OK;
     }
-    return pcg_iter_enqueue<T>(P);
+    return pcg_iter_enqueue<T>(P, rec);
 }
 
 // record > 0: the first `record` search directions s_l that complete a step are copied with H s_l
@@ -1079,7 +1094,7 @@ reg_status pcg_t(reg_problem* P, const double* rhs, double eta, int max_iters, i
     while (l < nit) {
         const int slot = P->lr_count + l;
         if (l < record) CK(hipMemcpyAsync(P->lr_slot(0, slot), s, n * 8, hipMemcpyDeviceToDevice, P->stream));
-        CKS(pcg_iter_run<T>(P));
+        CKS(pcg_iter_run<T>(P, l));
         if (l < record) {
             CK(hipMemcpyAsync(P->lr_slot(1, slot), P->pcg(PST), n * 8, hipMemcpyDeviceToDevice, P->stream));
             if (W) CK(hipMemcpyAsync(P->lr_slot(3, slot), P->pcg(PKST), n * 8, hipMemcpyDeviceToDevice, P->stream));

@@ -50,6 +50,56 @@ def test_pcg_fixed_iterations_parity(case, tol):
         P.close()
 
 
+MS_128 = Case(128, 32, 5, "H2", "mass_source", 1e-3, 1e-4, "fp64", "dto", 1)   # z and K^{-1} r by recurrence
+
+
+@pytest.mark.parametrize("case,tol", [(C1_64, 1e-9), (MS_128, 1e-8)])
+def test_pcg_parity_across_preconditioned_residual_refresh(case, tol):
+    """10 fixed iterations: the preconditioned residual (and K^{-1} r) follow their recurrences, are
+    formed afresh from r at the eighth iteration and follow the recurrences again; the iterate matches
+    the oracle's textbook PCG.  CG amplifies rounding as it proceeds: a relative perturbation of 1e-13
+    in the oracle's own matvec moves its 10-iteration iterate by 2.6e-10 (64^2, H1) and 4.1e-10
+    (128 x 32, mass source), and by up to 3e-4 at 20 iterations, so parity is taken at 10."""
+    print(f"[case] pcg refresh {case}", flush=True)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    p = params(case)
+    g = Grid(case.n1, case.n2)
+    lin = reduced.gradient(g, p, mT, mR, vlin)
+    x_ref, it_ref, rr_ref = solver.pcg(lambda s: reduced.hessian_matvec(g, p, lin, s),
+                                       lambda r: reduced.precond(g, p, r),
+                                       lambda a, b: reduced.w_inner(g, p, a, b), g.norm, -lin.g, 0.0, 100,
+                                       fixed_iters=10)
+    P = gpu_problem(case)
+    try:
+        P.gradient(dev(vlin), want_J=False)
+        x, it, rr = P.pcg(dev(-lin.g), eta=0.0, max_iters=100, fixed_iters=10)
+        assert it == it_ref == 10
+        assert close(host(x), x_ref, tol)
+        assert abs(rr - rr_ref) <= 10 * tol * max(rr_ref, 1e-3)
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("case", [C1_64, MS_128, C2])
+def test_pcg_long_fixed_schedule_completes(case):
+    """300 iterations at eta = 0, far past convergence (the benchmark's schedule): every iteration
+    completes, since <r, z>_W stays positive while z follows its recurrence between refreshes, and
+    the true residual ||H x + g|| / ||g|| is at the level the precision of H allows."""
+    print(f"[case] pcg 300 {case}", flush=True)
+    mT, mR, vlin, vt, vtr = inputs(case)
+    P = gpu_problem(case)
+    try:
+        g, _ = P.gradient(dev(vlin), want_J=False)
+        x, it, rr = P.pcg(-g, eta=0.0, max_iters=300, fixed_iters=300)
+        assert it == 300
+        assert np.isfinite(rr) and rr <= 1e-6
+        Hx = P.hessian_matvec(x)
+        true_res = float((Hx + g).norm() / g.norm())
+        assert true_res <= (1e-8 if case.precision == "fp64" else 1e-3), true_res
+    finally:
+        P.close()
+
+
 @pytest.mark.parametrize("case,newton,pcg,tol", [(C1_64, 5, 10, 1e-10), (MS_64, 3, 6, 1e-9), (C2, 3, 8, 1e-4),
                                                   (NP2_64, 3, 6, 1e-9), (NP2_32, 3, 6, 1e-4)])
 def test_solve_fixed_schedule_parity(case, newton, pcg, tol):
