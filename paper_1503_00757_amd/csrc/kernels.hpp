@@ -265,9 +265,10 @@ hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, cons
                              hipStream_t stream);
 // The same, and while the iteration is active z -= kappa pst (pst = P^{-1} s~: the preconditioned
 // residual by recurrence) and kr -= kappa kst (kst = K^{-1} s~: the weighted residual; kr, kst
-// nullable).
+// nullable together); partial (2 * RED_BLOCKS) receives the block sums of ||r||^2 and <r, z>_W over
+// the updated vectors, those of launch_dots with a = {r, kr or r}, b = {r, z}.
 hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
-                               const double* pst, double* kr, const double* kst, const double* scal,
+                               const double* pst, double* kr, const double* kst, const double* scal, double* partial,
                                hipStream_t stream);
 // s = z + mu s (scal == nullptr: s = z) and its copy sT = (T) s for the next matvec
 template <typename T>

@@ -1026,13 +1026,14 @@ reg_status pcg_iter_enqueue(reg_problem* P, bool rec) {
         CK(launch_dots_scalar(1, a, b, n, P->partial(), sc + S_SHS, PCG_KAPPA, sc, P->stream));
     }
     if (rec) {
-        // kr = K^{-1} r (the weighted residual of <., .>_W) follows r with K^{-1} H s
-        CK(launch_pcg_update_z(n, x, r, s, st, z, pst, W ? kr : nullptr, W ? kst : nullptr, sc, P->stream));
+        // kr = K^{-1} r (the weighted residual of <., .>_W) follows r with K^{-1} H s; the update
+        // forms the partial sums of ||r||^2 and <r, z>_W as it writes them
+        CK(launch_pcg_update_z(n, x, r, s, st, z, pst, W ? kr : nullptr, W ? kst : nullptr, sc, P->partial(),
+                               P->stream));
+        CK(launch_finalize_scalar(2, RED_BLOCKS, P->partial(), sc + S_RR, PCG_MU, sc, P->stream));
     } else {
         CK(launch_pcg_update(n, x, r, s, st, sc, P->stream));
         CKS(precond_pcg(P, r, z, W ? kr : nullptr));
-    }
-    {
         const double* a[2] = {r, W ? kr : r};
         const double* b[2] = {r, z};
         CK(launch_dots_scalar(2, a, b, n, P->partial(), sc + S_RR, PCG_MU, sc, P->stream));

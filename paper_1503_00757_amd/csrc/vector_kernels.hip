@@ -195,20 +195,46 @@ __global__ void pcg_update_kernel(long n, double* __restrict__ x, double* __rest
     }
 }
 
-__global__ void pcg_update_z_kernel(long n, double* __restrict__ x, double* __restrict__ r,
-                                    const double* __restrict__ s, const double* __restrict__ st,
-                                    double* __restrict__ z, const double* __restrict__ pst, double* __restrict__ kr,
-                                    const double* __restrict__ kst, const double* __restrict__ sc) {
+// pcg_update_kernel with the recurrences z -= kappa pst and kr -= kappa kst, and the block partial
+// sums of ||r||^2 and <r, z>_W (kr . z with the weighting, r . z without) over the updated vectors,
+// in the contiguous chunks, thread order and tree of dots_kernel: the sums are those dots_kernel
+// would form, one launch earlier.
+__global__ __launch_bounds__(RED_THREADS) void pcg_update_z_kernel(
+    long n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ s,
+    const double* __restrict__ st, double* __restrict__ z, const double* __restrict__ pst, double* __restrict__ kr,
+    const double* __restrict__ kst, const double* __restrict__ sc, double* __restrict__ partial) {
+    __shared__ double sh[RED_THREADS / 64];
     const double kappa = sc[S_KAPPA];
     const bool upd = sc[S_ACTIVE] != 0.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
+    const long lo = (long)blockIdx.x * chunk;
+    const long hi = lo + chunk < n ? lo + chunk : n;
+    double rr = 0.0, rz = 0.0;
+    for (long i = lo + threadIdx.x; i < hi; i += RED_THREADS) {
         x[i] += kappa * s[i];
+        double ri = r[i], zi = z[i];
+        double wi = ri;
         if (upd) {
-            r[i] -= kappa * st[i];
-            z[i] -= kappa * pst[i];
-            if (kr) kr[i] -= kappa * kst[i];
+            ri -= kappa * st[i];
+            zi -= kappa * pst[i];
+            r[i] = ri;
+            z[i] = zi;
+            wi = ri;
         }
+        if (kr) {
+            wi = kr[i];
+            if (upd) {
+                wi -= kappa * kst[i];
+                kr[i] = wi;
+            }
+        }
+        rr += ri * ri;
+        rz += wi * zi;
     }
+    const double t0 = block_sum<RED_THREADS>(rr, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t0;
+    const double t1 = block_sum<RED_THREADS>(rz, sh);
+    if (threadIdx.x == 0) partial[RED_BLOCKS + blockIdx.x] = t1;
 }
 
 template <typename T>
@@ -249,10 +275,11 @@ hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, cons
     return hipGetLastError();
 }
 hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
-                               const double* pst, double* kr, const double* kst, const double* scal,
+                               const double* pst, double* kr, const double* kst, const double* scal, double* partial,
                                hipStream_t stream) {
-    hipLaunchKernelGGL(pcg_update_z_kernel, dim3(grid_for(n)), dim3(256), 0, stream, n, x, r, s, st, z, pst, kr, kst,
-                       scal);
+    if ((kr == nullptr) != (kst == nullptr)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pcg_update_z_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, stream, n, x, r, s, st, z, pst,
+                       kr, kst, scal, partial);
     return hipGetLastError();
 }
 template <typename T>

@@ -387,13 +387,15 @@ hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, cons
                 chk(st, n, "pcg_update st") && chk(scal, NUM_PCG_SLOTS, "pcg_update scal"));
 }
 hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
-                               const double* pst, double* kr, const double* kst, const double* scal, hipStream_t) {
+                               const double* pst, double* kr, const double* kst, const double* scal, double* partial,
+                               hipStream_t) {
     const bool ok_k = (kr == nullptr) == (kst == nullptr);
     if (!ok_k) mock_fail("pcg_update_z: kr and kst must come together");
     return done(ok_k && chk(x, n, "pcg_update_z x") && chk(r, n, "pcg_update_z r") && chk(s, n, "pcg_update_z s") &&
                 chk(st, n, "pcg_update_z st") && chk(z, n, "pcg_update_z z") && chk(pst, n, "pcg_update_z pst") &&
                 chk(kr, n, "pcg_update_z kr") && chk(kst, n, "pcg_update_z kst") &&
-                chk(scal, NUM_PCG_SLOTS, "pcg_update_z scal"));
+                chk(scal, NUM_PCG_SLOTS, "pcg_update_z scal") &&
+                chk(partial, 2 * RED_BLOCKS, "pcg_update_z partial"));
 }
 template <typename T>
 hipError_t launch_pcg_dir_copy(long n, double* s, T* sT, const double* z, const double* scal, hipStream_t) {
