@@ -395,8 +395,8 @@ def bench_batch(npairs=96):
 
 def c3_matvec(w3, P3, vlin3, vt3, copy_gbs):
     """GN matvec throughput at 1024^2, n_t = 32 (reg_hessian_matvec: the Nyquist projection of the
-    input and the graph-replayed matvec), as the median of 5 timed batches of 20, against the survey's
-    byte model (248 N per step + 112 N) and against the bytes the kernels move."""
+    input and the graph-replayed matvec), as the median of 5 timed batches of 20, against the per-step
+    byte model of the matvec (248 N per step + 112 N) and against the bytes the kernels move."""
     P3.gradient(vlin3, want_J=False)
     reps3 = sorted(bench_matvec(P3, vt3, 20) for _ in range(5))
     t3 = reps3[2]

@@ -320,12 +320,12 @@ reg_status reg_time_phases(reg_problem* h, int32_t which, int32_t reps, double* 
 
 /* Launch-shape autotuner for the FP32 transport stages on square grids of 64+ points (elements per
  * thread of the row and column register FFTs, threads per block), at the current linearisation
- * point and on the last reg_hessian_matvec input.  Round 1 times every shape that fits the grid's
- * line length for each of the four matvec stage launches in isolation (`reps` launches); round 2
- * times whole graph-replayed matvecs and, one stage at a time, keeps whichever of that stage's four
- * fastest round-1 shapes makes the matvec fastest (a change must save more than 0.1%).  The choice
- * stays in the handle; `report` (nullable, truncated to report_bytes) receives JSON with the round-1
- * timings (microseconds per launch), the matvec time of the round-1 picks and of the final choice
+ * point and on the last reg_hessian_matvec input.  The first pass times every shape that fits the
+ * grid's line length for each of the four matvec stage launches in isolation (`reps` launches); the
+ * second times whole graph-replayed matvecs and, one stage at a time, keeps whichever of that stage's
+ * four fastest first-pass shapes makes the matvec fastest (a change must save more than 0.1%).  The choice
+ * stays in the handle; `report` (nullable, truncated to report_bytes) receives JSON with the first-pass
+ * timings (microseconds per launch), the matvec time of the first-pass picks and of the final choice
  * (milliseconds) and the choice.  Results are identical for every shape up to rounding; only speed
  * differs.  REG_ESTATE before the first reg_hessian_matvec.  FP64 problems use fixed shapes
  * (no-op).  Synchronises the stream. */

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
     for (int r = 0; r < 4; ++r) lds[c][b][lpad(t + r * Q)] = x[r];
     __syncthreads();
     const bool hp = mode == SPEC_HESS_P;
-    cpx<double> r2[4] = {};   // SPEC_HESS_P with want2: the second round's values of this thread's wavenumber
+    cpx<double> r2[4] = {};   // SPEC_HESS_P with want2: the second pass's values of this thread's wavenumber
     {
         const int e = threadIdx.x;   // one wavenumber per thread
         const double k1 = (double)kwave<N>(e);
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
         spec_multiplier(p, hp ? SPEC_HESS : mode, k1, (double)k2, lds[0][b][lpad(e)], lds[1][b][lpad(e)],
                         lds[2][b][lpad(e)], lds[3][b][lpad(e)], o0, o1, q0, q1, eb);
         const double sc = (e == N / 2) ? 0.0 : 1.0 / ((double)N * (double)p.n2);   // Nyquist row projected out
-        if (hp) {   // P^{-1} H x: into the second field, or with want2 into the third (second round)
+        if (hp) {   // P^{-1} H x: into the second field, or with want2 into the third (second pass)
             const double pi = prec_inv(p, k1, (double)k2);
             const cpx<double> p0 = {pi * o0.x, pi * o0.y}, p1 = {pi * o1.x, pi * o1.y};
             if (want2) {
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(N) void spec_col_split_kernel(SpecParams p, int mod
 #pragma unroll
         for (int r = 0; r < 4; ++r) spec[c * hn + (long)(t + r * Q) * H + k2] = x[r];
     }
-    if (hp && want2) {   // second round: field 2 (half spectra 4, 5; groups 2 and 3 only join the exchanges)
+    if (hp && want2) {   // second pass: field 2 (half spectra 4, 5; groups 2 and 3 only join the exchanges)
         const int b2 = buf ^ 1;   // not the buffer the inverse's last exchange may still be read from
         __syncthreads();
         const int e = threadIdx.x;

@@ -215,7 +215,7 @@ def test_every_launch_shape_matches_oracle(problems, name):
     for op in ("A2", "I2", "A1", "I1"):
         assert {v for v, _ in rep[op]} == want, (op, rep[op])
     assert all(c in want for c in rep["chosen"][2:6])
-    # the whole-matvec round only keeps a change that made the matvec faster
+    # the whole-matvec pass only keeps a change that made the matvec faster
     assert 0 < rep["matvec_ms"] <= rep["matvec_ms_isolated_choice"], rep
     H = P.hessian_matvec(dev(vt))
     assert close(host(H), ref["H"], tol)
