@@ -157,6 +157,11 @@ reg_status reg_precond_apply(reg_problem* h, const double* r, double* z);
 /* Newton step of Alg. 2: PCG on H x = rhs at the current linearisation point, x_0 = 0, stopping at
  * ||r|| <= eta ||rhs|| or after max_iters iterations; fixed_iters > 0 runs exactly that many.
  * For REG_MASS_SOURCE the PCG inner product is <K^{-1} a, b>, in which H is self-adjoint.
+ * Where the assembly's column pass can form P^{-1} H s (power-of-two grids with 64..512-point
+ * columns, no low-rank correction), z = P^{-1} r and K^{-1} r follow r by recurrence and are formed
+ * from r afresh at the start and every eighth iteration; the iterates equal those of the textbook
+ * iteration up to rounding.  If <s, H s>_W <= 0 the iteration stops (a fixed schedule keeps
+ * launching with x and r held).
  * x: device vector field (output).  iters_host, relres_host: host outputs (nullable).
  * Synchronises the stream. */
 reg_status reg_pcg(reg_problem* h, const double* rhs, double eta, int32_t max_iters,
