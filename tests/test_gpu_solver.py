@@ -51,15 +51,18 @@ def test_pcg_fixed_iterations_parity(case, tol):
 
 
 MS_128 = Case(128, 32, 5, "H2", "mass_source", 1e-3, 1e-4, "fp64", "dto", 1)   # z and K^{-1} r by recurrence
+H3_64 = Case(64, 64, 4, "H3", "mass_source", 1e-4, 1e-4, "fp64", seed=5)
+ST_64 = Case(64, 64, 4, "stokes", "divfree", 1e-2, 0.0, "fp64", seed=5, nu=1.7, stokes_eps=1e-4)
 
 
-@pytest.mark.parametrize("case,tol", [(C1_64, 1e-9), (MS_128, 1e-8)])
+@pytest.mark.parametrize("case,tol", [(C1_64, 1e-9), (MS_128, 1e-8), (H3_64, 1e-9), (ST_64, 1e-9)])
 def test_pcg_parity_across_preconditioned_residual_refresh(case, tol):
     """10 fixed iterations: the preconditioned residual (and K^{-1} r) follow their recurrences, are
     formed afresh from r at the eighth iteration and follow the recurrences again; the iterate matches
-    the oracle's textbook PCG.  CG amplifies rounding as it proceeds: a relative perturbation of 1e-13
-    in the oracle's own matvec moves its 10-iteration iterate by 2.6e-10 (64^2, H1) and 4.1e-10
-    (128 x 32, mass source), and by up to 3e-4 at 20 iterations, so parity is taken at 10."""
+    the oracle's textbook PCG (H1, H2 and H3 symbols, the shear-control operator).  CG amplifies
+    rounding as it proceeds: a relative perturbation of 1e-13 in the oracle's own matvec moves its
+    10-iteration iterate by 2.6e-10 (64^2, H1), 4.1e-10 (128 x 32, mass source), 2.5e-12 (H3) and
+    1.1e-13 (shear control), and by up to 3e-4 at 20 iterations, so parity is taken at 10."""
     print(f"[case] pcg refresh {case}", flush=True)
     mT, mR, vlin, vt, vtr = inputs(case)
     p = params(case)
