@@ -189,8 +189,9 @@ __global__ void pcg_update_kernel(long n, double* __restrict__ x, double* __rest
                                   const double* __restrict__ st, const double* __restrict__ sc) {
     const double kappa = sc[S_KAPPA];
     const bool upd_r = sc[S_ACTIVE] != 0.0;
+    // kappa = 0 (after a breakdown) leaves x as it is, also where s is no longer finite
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        x[i] += kappa * s[i];
+        if (kappa != 0.0) x[i] += kappa * s[i];
         if (upd_r) r[i] -= kappa * st[i];
     }
 }
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(RED_THREADS) void pcg_update_z_kernel(
     const long hi = lo + chunk < n ? lo + chunk : n;
     double rr = 0.0, rz = 0.0;
     for (long i = lo + threadIdx.x; i < hi; i += RED_THREADS) {
-        x[i] += kappa * s[i];
+        if (kappa != 0.0) x[i] += kappa * s[i];
         double ri = r[i], zi = z[i];
         double wi = ri;
         if (upd) {
