@@ -27,6 +27,7 @@ std::string g_err;
 std::mutex g_err_mu;
 std::atomic<long> g_launches{0};
 std::atomic<long> g_sqdiff_calls{0};
+std::atomic<long> g_pcg_update{0}, g_pcg_update_z{0};   // launches of the two PCG update forms
 }  // namespace
 
 bool mock_range_ok(const void* p, size_t bytes) {
@@ -50,9 +51,13 @@ void mock_reset() {
     g_err.clear();
     g_launches = 0;
     g_sqdiff_calls = 0;
+    g_pcg_update = 0;
+    g_pcg_update_z = 0;
 }
 const char* mock_last_error() { return g_err.c_str(); }
 long mock_launches() { return g_launches.load(); }
+// launches of launch_pcg_update (z = 0) or launch_pcg_update_z (z = 1) since mock_reset
+long mock_pcg_updates(int z) { return z ? g_pcg_update_z.load() : g_pcg_update.load(); }
 }
 
 namespace regnk {
@@ -383,12 +388,14 @@ hipError_t launch_dots_scalar(int nk, const double* const* a, const double* cons
 }
 hipError_t launch_pcg_update(long n, double* x, double* r, const double* s, const double* st, const double* scal,
                              hipStream_t) {
+    ++g_pcg_update;
     return done(chk(x, n, "pcg_update x") && chk(r, n, "pcg_update r") && chk(s, n, "pcg_update s") &&
                 chk(st, n, "pcg_update st") && chk(scal, NUM_PCG_SLOTS, "pcg_update scal"));
 }
 hipError_t launch_pcg_update_z(long n, double* x, double* r, const double* s, const double* st, double* z,
                                const double* pst, double* kr, const double* kst, const double* scal, double* partial,
                                hipStream_t) {
+    ++g_pcg_update_z;
     const bool ok_k = (kr == nullptr) == (kst == nullptr);
     if (!ok_k) mock_fail("pcg_update_z: kr and kst must come together");
     return done(ok_k && chk(x, n, "pcg_update_z x") && chk(r, n, "pcg_update_z r") && chk(s, n, "pcg_update_z s") &&
