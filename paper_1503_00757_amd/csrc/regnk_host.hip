@@ -788,7 +788,7 @@ reg_status precond_t(reg_problem* P, const double* r, double* z, double* kr) {
 // It is symmetric positive definite in <., .>_W for any such set.  For the mass-source model the
 // W-products use the stored K^{-1} images and K^{-1} r = K^{-1} r~ + sum a_k K^{-1} H z_k.
 reg_status precond_pcg(reg_problem* P, const double* r, double* z, double* kr) {
-    if (!P->lr_active) return precond_t(P, r, z, kr);
+    if (!P->lr_active || P->lr_count == 0) return precond_t(P, r, z, kr);   // no directions: the plain form
     const long n = 2 * P->nn;
     const bool ms = P->p.constraint == REG_MASS_SOURCE;
     const int cap = P->p.lowrank_capacity;
@@ -1045,9 +1045,12 @@ reg_status pcg_iter_enqueue(reg_problem* P, bool rec) {
 // Iteration l (from 0) of a PCG solve.
 template <typename T>
 reg_status pcg_iter_run(reg_problem* P, int l) {
-    const bool can_rec = !P->lr_active && spec_col_hess_p_ok(P->n1, P->n2);
+    // a correction without directions yet (the first Newton step of a recycling solve) is the plain
+    // preconditioner; the set does not change within one PCG solve
+    const bool lr = P->lr_active && P->lr_count > 0;
+    const bool can_rec = !lr && spec_col_hess_p_ok(P->n1, P->n2);
     const bool rec = can_rec && (l + 1) % PCG_Z_REFRESH != 0;
-    hipGraphExec_t& graph = P->lr_active          ? P->pcg_iter_graph_lr
+    hipGraphExec_t& graph = lr                    ? P->pcg_iter_graph_lr
                             : (can_rec && !rec) ? P->pcg_iter_graph_ex
                                                 : P->pcg_iter_graph;
     if (P->use_graphs && !graph) {

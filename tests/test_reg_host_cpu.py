@@ -282,24 +282,23 @@ def test_static_scratch_limit_on_the_host(lib):
 @pytest.mark.parametrize("n1,n2,lowrank,recurrence", [
     (64, 64, 0, True), (512, 256, 0, True), (256, 256, 4, True),    # column pass forms P^{-1} H s
     (1024, 1024, 0, False), (32, 128, 0, False), (64, 96, 0, False),   # no such column pass
-    (256, 256, 4, False),                                             # low-rank correction active
+    (256, 256, 4, None),                                              # recycling solve
 ])
 def test_pcg_preconditioned_residual_schedule(lib, n1, n2, lowrank, recurrence):
     """Which update each PCG iteration launches: with the recurrence every iteration but each eighth
     updates z (and K^{-1} r) from P^{-1} H s, and each eighth forms them from r (the refresh); without
     it (no such column pass, or the low-rank-corrected preconditioner of a solve with caller
-    directions) every iteration applies the preconditioner to r."""
+    directions) every iteration applies the preconditioner to r.  A recycling solve runs its first
+    Newton step, before any direction is held, with the plain preconditioner and the recurrence."""
     p = params(n1, n2, constraint=REG_MASS_SOURCE, lowrank=lowrank)
     H = Host(lib, p)
     nn = H.nn
     v, g, x = H.buf(2 * nn), H.buf(2 * nn), H.buf(2 * nn)
     H.check(lib.reg_gradient(H.h, H.ptr(v), H.ptr(g), None))
     before = (lib.mock_pcg_updates(0), lib.mock_pcg_updates(1))
-    iters = 20
-    if lowrank and not recurrence:
-        # two Newton steps of 20 PCG iterations, recycling directions: the corrected preconditioner
-        # (with no directions yet in the first step) is applied to r in every iteration
-        iters = 40
+    if recurrence is None:
+        # two Newton steps of 20 PCG iterations, recycling directions: the first step with the plain
+        # preconditioner by recurrence, the second with the correction its directions switched on
         o = RegSolveOpts()
         o.max_newton, o.max_pcg, o.fixed_pcg_iters, o.max_backtracks = 2, 20, 20, 3
         o.gtol_rel, o.armijo_c1, o.armijo_rho, o.recycle = 0.0, 1e-4, 0.5, 2
@@ -311,5 +310,6 @@ def test_pcg_preconditioned_residual_schedule(lib, n1, n2, lowrank, recurrence):
         H.check(lib.reg_pcg(H.h, H.ptr(g), 0.0, 20, 20, H.ptr(x), C.byref(it), C.byref(rel)))
     plain = lib.mock_pcg_updates(0) - before[0]
     rec = lib.mock_pcg_updates(1) - before[1]
-    assert (plain, rec) == ((iters // 8, iters - iters // 8) if recurrence else (iters, 0))
+    want = {True: (2, 18), False: (20, 0), None: (2 + 20, 18)}[recurrence]
+    assert (plain, rec) == want
     H.close()
